@@ -1,0 +1,189 @@
+/*
+ * dme.h -- C ABI of the MI355X (gfx950) low-rank splitting solver for
+ * differential Lyapunov and Riccati equations.
+ *
+ * Problem (Mena, Pfurtscheller, Stillfjord 2018, Sec. 1 and Sec. 2):
+ *
+ *     dP/dt = A^T P + P A + Q + G(P),   P(0) = P0 = L0 D0 L0^T,   Q = C^T C,
+ *     G = 0                      differential Lyapunov equation (Sec. 2.1)
+ *     G = -P B R^-1 B^T P        differential Riccati equation (Sec. 2.2)
+ *     plus S P S^T when S is given  (generalized equations, Sec. 2.3 / 2.4)
+ *
+ * The solution is carried as P = L D L^T (Sec. 2, low-rank paragraph) and
+ * advanced by Lie or Strang compositions of the subflows T1, T2, T12, T3, T4
+ * (Sec. 2 and the scheme list of Sec. 3), with column compression after every
+ * concatenation (Alg. 1, 2, 4).  The dense operator e^{tA^T} is formed once by
+ * scaling and squaring with a diagonal Pade approximant (Higham 2005, Alg. 2.3)
+ * and applied to L by FP64 (or split-BF16) MFMA GEMMs.
+ *
+ * Conventions for every entry point:
+ *   - All matrices are FP64 and column-major; leading dimension = row count
+ *     unless an ld argument says otherwise.
+ *   - "host" pointers are read during the call only and stay owned by the
+ *     caller; "device" pointers are HBM addresses on the context's device,
+ *     also caller-owned; results (dme_result) are owned by the library until
+ *     dme_result_free.
+ *   - Return value: DME_OK (0) or a negative error code; dme_last_error()
+ *     returns a message for the calling thread's most recent failure.
+ *   - A context is used by one host thread at a time.  Step-level calls are
+ *     enqueued on the context's stream; solve-level calls synchronise it.
+ */
+#ifndef DME_H
+#define DME_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---------------------------------------------------------------- errors */
+#define DME_OK 0
+#define DME_EINVAL (-1)    /* bad dimensions, T/h not an integer, tol <= 0, R not SPD */
+#define DME_ENOMEM (-2)    /* device allocation failed or memory budget exceeded */
+#define DME_ERANK (-3)     /* compressed rank exceeds max_rank */
+#define DME_ENUMERIC (-4)  /* NaN/Inf, singular Pade denominator, non-SPD Riccati block */
+#define DME_EAGAIN (-5)    /* result not ready yet (serving) */
+#define DME_EHIP (-6)      /* HIP runtime error */
+#define DME_EINTERNAL (-7) /* internal invariant violated */
+
+typedef struct dme_ctx dme_ctx;
+typedef struct dme_result dme_result;
+typedef struct dme_solver dme_solver;
+
+/* Problem data (Sec. 1 equation; Sec. 2.2 Riccati term; Sec. 2.3 S term).
+ * All pointers are host pointers, n x n / n x m / p x n / m x m / n x r0 / r0 x r0. */
+typedef struct {
+  int64_t n, m, p, r0;
+  const double *A;  /* n x n, required                                   */
+  const double *B;  /* n x m, NULL iff m == 0                             */
+  const double *C;  /* p x n, Q = C^T C, required (p >= 1)                */
+  const double *R;  /* m x m SPD, NULL iff m == 0                         */
+  const double *S;  /* n x n or NULL (adds S P S^T)                       */
+  const double *L0; /* n x r0 (NULL iff r0 == 0, i.e. P0 = 0)             */
+  const double *D0; /* r0 x r0 symmetric                                  */
+} dme_problem;
+
+/* Composition order (operators act right to left, Sec. 2):
+ *   DME_LIE:    one step = T_last(h) ... T_first(h)
+ *   DME_STRANG: palindromic, outer subflows over h/2, the middle over h.   */
+typedef enum { DME_LIE = 0, DME_STRANG = 1 } dme_scheme;
+
+/* Which subflows:
+ *   DME_SPLIT_F12:    linear part A^T P + P A + Q solved with the quadrature
+ *                     formula (Alg. 2); DRE adds T3 (Sec. 3, first scheme);
+ *                     with S the generalized DRE scheme T12 T3 T4 T3 T12.
+ *   DME_SPLIT_F1F2:   T1 / T2 split of Alg. 1; with B (or S) the three-term
+ *                     scheme T1 T2 T3 T2 T1 (Sec. 3, second scheme).
+ *   DME_SPLIT_F1F3F2: reversed three-term scheme T1 T3 T2 T3 T1 (Sec. 3). */
+typedef enum { DME_SPLIT_F12 = 0, DME_SPLIT_F1F2 = 1, DME_SPLIT_F1F3F2 = 2 } dme_split;
+
+/* DME_FP64: every product in FP64 MFMA.
+ * DME_MIXED: the e^{tA^T} L and quadrature products in split BF16 MFMA with
+ *            FP32 accumulation flushed to FP64; Pade, squaring, LU and the
+ *            compression stay FP64.                                        */
+typedef enum { DME_FP64 = 0, DME_MIXED = 1 } dme_precision;
+
+typedef struct {
+  double T;        /* final time                                            */
+  double h;        /* step; N = round(T/h) with |N h - T| <= 1e-12 T          */
+  double tol;      /* compression: keep |lambda_i| > tol * max |lambda|      */
+  int scheme;      /* dme_scheme                                            */
+  int split;       /* dme_split                                             */
+  int precision;   /* dme_precision                                         */
+  int quad_nodes;  /* Gauss-Legendre nodes K for T12 (0 -> 7)               */
+  int64_t max_rank;/* rank cap (0 -> min(n, 512))                           */
+} dme_opts;
+
+/* ------------------------------------------------------------- context */
+/* Create a context on HIP device `device`.  `stream` is a hipStream_t to
+ * enqueue on, or NULL for a library-owned stream. */
+int dme_create(dme_ctx **ctx, int device, void *stream);
+void dme_destroy(dme_ctx *ctx);
+const char *dme_strerror(int code);
+const char *dme_last_error(void);
+
+/* --------------------------------------------------------- whole solves */
+/* G = 0 (Sec. 2.1; Alg. 1 and Alg. 2). B, R are ignored. */
+int dle_solve(dme_ctx *ctx, const dme_problem *prob, const dme_opts *opts, dme_result **out);
+/* G = -P B R^-1 B^T P (Sec. 2.2; Alg. 3 inside the Sec. 3 schemes). */
+int dre_solve(dme_ctx *ctx, const dme_problem *prob, const dme_opts *opts, dme_result **out);
+
+/* Stepwise form of the same solves: create = upload + operator setup
+ * (e^{tA^T}, quadrature factor), step = advance `nsteps` time steps with all
+ * data resident in HBM, result = copy of the current (L, D).
+ * is_dre: 0 -> DLE, 1 -> DRE.  A solver owns its device memory. */
+int dme_solver_create(dme_ctx *ctx, const dme_problem *prob, const dme_opts *opts, int is_dre,
+                      dme_solver **out);
+int dme_solver_step(dme_solver *sv, int64_t nsteps);
+/* steps taken, total steps N, current rank r. */
+int dme_solver_state(const dme_solver *sv, int64_t *step, int64_t *nsteps_total, int64_t *rank);
+/* Setup timing (ms): e^{tA^T} formation, quadrature factor; rank of the
+ * quadrature factor. */
+int dme_solver_setup_info(const dme_solver *sv, double *expm_ms, double *quad_ms, int64_t *rank_quad);
+int dme_solver_result(dme_solver *sv, dme_result **out);
+
+/* Phase timing with HIP events recorded on the solver's stream around each
+ * launch group of a phase (enable = 1 turns it on and clears the totals).
+ * Phases: DME_PHASE_STEP_GEMM (e^{tA^T} L products), DME_PHASE_COMPRESS
+ * (QR + eigen compression), DME_PHASE_RICCATI (T3), DME_PHASE_S (S L, S^2 L).
+ * For each: number of launches, summed device milliseconds, and the
+ * algorithmic flops and HBM bytes of the method's operation (not counting
+ * split-precision emulation). */
+#define DME_PHASE_STEP_GEMM 0
+#define DME_PHASE_COMPRESS 1
+#define DME_PHASE_RICCATI 2
+#define DME_PHASE_S 3
+int dme_solver_profile(dme_solver *sv, int enable);
+int dme_solver_profile_get(dme_solver *sv, int phase, int64_t *count, double *ms, double *flops,
+                           double *bytes);
+void dme_solver_free(dme_solver *sv);
+
+/* ------------------------------------------------------------- results */
+int dme_result_info(const dme_result *res, int64_t *n, int64_t *r, int64_t *steps);
+/* L: n x r host buffer, D: r x r host buffer, both caller-allocated. */
+int dme_result_copy(const dme_result *res, double *L, double *D);
+void dme_result_free(dme_result *res);
+
+/* ------------------------------------------ step-level calls (device)  */
+/* Each is one row of the method's hot path, on device pointers, enqueued on
+ * the context's stream.  Used by the solvers above and by parity tests.     */
+
+/* E = e^{t X} for an n x n X (Higham 2005 Alg. 2.3: Pade degree m and
+ * scaling s from ||tX||_1, [m/m] Pade numerator/denominator, LU solve, s
+ * squarings).  Writes m and s to *m_out, *s_out (host) when non-NULL.
+ * X and E device, n x n, must not alias.  Synchronises the stream.          */
+int dme_expm(dme_ctx *ctx, int64_t n, const double *X, double t, double *E, int *m_out, int *s_out);
+
+/* C = alpha op(A) op(B) + beta C with FP64 MFMA; trans = 'N' or 'T'. */
+int dme_gemm_f64(dme_ctx *ctx, char transa, char transb, int64_t M, int64_t N, int64_t K,
+                 double alpha, const double *A, int64_t lda, const double *B, int64_t ldb,
+                 double beta, double *C, int64_t ldc);
+
+/* Column compression (Sec. 3 after Alg. 2): Householder QR W = Q R,
+ * M = R Dhat R^T, M = V Lam V^T, keep |lam_i| > tol max|lam| (sorted by |lam|
+ * descending), L = Q V_I, D = diag(lam_I).
+ * W: n x k device (destroyed), Dhat: k x k device, L: n x max_rank device
+ * (ld n), D: max_rank x max_rank device (ld max_rank).  *r_out (host) gets the
+ * kept rank; DME_ERANK if it exceeds max_rank.  Synchronises the stream.    */
+int dme_compress(dme_ctx *ctx, int64_t n, int64_t k, double *W, const double *Dhat, double tol,
+                 int64_t max_rank, double *L, double *D, int64_t *r_out);
+
+/* Riccati subflow T3(t) of Sec. 2.2 on the small factor: with W_B = L^T B,
+ * D <- (I + t D W_B R^-1 W_B^T)^-1 D, evaluated as the symmetric m x m
+ * Woodbury form D - t D W_B (R + t W_B^T D W_B)^-1 W_B^T D.
+ * L: n x r, B: n x m, R: m x m, D: r x r (in place), all device.           */
+int dme_riccati(dme_ctx *ctx, int64_t n, int64_t r, int64_t m, const double *L, const double *B,
+                const double *R, double t, double *D);
+
+/* Symmetric eigen-decomposition of a k x k matrix M (device), eigenvalues
+ * ordered by |lambda| descending; eigenvectors only for the kept ones
+ * (|lambda| > tol max|lambda|, at most max_keep).  lam: k, V: k x max_keep. */
+int dme_syev(dme_ctx *ctx, int64_t k, const double *M, double tol, int64_t max_keep, double *lam,
+             double *V, int64_t *keep_out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DME_H */

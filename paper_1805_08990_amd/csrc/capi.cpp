@@ -1,0 +1,376 @@
+// C ABI (include/dme.h): argument checking, error codes, ownership.
+#include <cstring>
+#include <memory>
+#include <new>
+
+#include "solver.h"
+
+namespace dme {
+
+thread_local std::string g_last_error;
+
+void fail(int code, const std::string& msg) { throw Error{code, msg}; }
+
+void DevBuf::alloc(size_t b) {
+  if (b == 0) b = 256;
+  hipError_t e = hipMalloc(&p, b);
+  if (e != hipSuccess) {
+    p = nullptr;
+    bytes = 0;
+    (void)hipGetLastError();
+    fail(DME_ENOMEM, "hipMalloc of " + std::to_string(b) + " bytes failed: " + hipGetErrorString(e));
+  }
+  bytes = b;
+}
+
+void DevBuf::release() {
+  if (p) (void)hipFree(p);
+  p = nullptr;
+  bytes = 0;
+}
+
+}  // namespace dme
+
+struct dme_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  dme::Arena ws;
+  dme::DevBuf flags;
+};
+
+struct dme_result {
+  int64_t n = 0, r = 0, steps = 0;
+  std::vector<double> L, D;
+};
+
+struct dme_solver {
+  dme_ctx* ctx = nullptr;
+  dme::Solver sv;
+};
+
+namespace {
+
+template <class F>
+int guarded(F&& f) {
+  try {
+    f();
+    return DME_OK;
+  } catch (const dme::Error& e) {
+    dme::g_last_error = e.msg;
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    dme::g_last_error = "host allocation failed";
+    return DME_ENOMEM;
+  } catch (const std::exception& e) {
+    dme::g_last_error = e.what();
+    return DME_EINTERNAL;
+  } catch (...) {
+    dme::g_last_error = "unknown exception";
+    return DME_EINTERNAL;
+  }
+}
+
+int* ctx_flags(dme_ctx* c) { return c->flags.as<int>(); }
+int64_t* ctx_rank(dme_ctx* c) { return reinterpret_cast<int64_t*>(c->flags.as<char>() + 16); }
+
+void ctx_reset_flags(dme_ctx* c) { dme::fill_f64(c->stream, c->flags.as<double>(), 8, 1, 8, 0.0); }
+
+void ctx_read_flags(dme_ctx* c, int* h) {
+  DME_HIP(hipMemcpyAsync(h, c->flags.p, 4 * sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  DME_HIP(hipStreamSynchronize(c->stream));
+}
+
+void require_ctx(dme_ctx* c) { DME_REQUIRE(c != nullptr, DME_EINVAL, "null context"); }
+
+void make_result(dme::Solver& sv, dme_result** out) {
+  auto res = std::make_unique<dme_result>();
+  res->n = sv.n;
+  res->r = sv.r;
+  res->steps = sv.step;
+  res->L.resize((size_t)sv.n * sv.r);
+  res->D.resize((size_t)sv.r * sv.r);
+  if (sv.r > 0) {
+    DME_HIP(hipMemcpyAsync(res->L.data(), sv.Lc(), res->L.size() * sizeof(double),
+                           hipMemcpyDeviceToHost, sv.s));
+    DME_HIP(hipMemcpyAsync(res->D.data(), sv.Dc(), res->D.size() * sizeof(double),
+                           hipMemcpyDeviceToHost, sv.s));
+  }
+  DME_HIP(hipStreamSynchronize(sv.s));
+  *out = res.release();
+}
+
+int solve_impl(dme_ctx* ctx, const dme_problem* prob, const dme_opts* opts, int is_dre,
+               dme_result** out) {
+  return guarded([&] {
+    require_ctx(ctx);
+    DME_REQUIRE(prob && opts && out, DME_EINVAL, "null argument");
+    *out = nullptr;
+    DME_HIP(hipSetDevice(ctx->device));
+    dme::Solver sv;
+    sv.s = ctx->stream;
+    sv.device = ctx->device;
+    sv.setup(*prob, *opts, is_dre != 0);
+    sv.advance(sv.N);
+    make_result(sv, out);
+  });
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* dme_strerror(int code) {
+  switch (code) {
+    case DME_OK: return "ok";
+    case DME_EINVAL: return "invalid argument";
+    case DME_ENOMEM: return "out of memory";
+    case DME_ERANK: return "rank exceeds max_rank";
+    case DME_ENUMERIC: return "numerical failure";
+    case DME_EAGAIN: return "not ready";
+    case DME_EHIP: return "HIP runtime error";
+    case DME_EINTERNAL: return "internal error";
+    default: return "unknown error";
+  }
+}
+
+const char* dme_last_error(void) { return dme::g_last_error.c_str(); }
+
+int dme_create(dme_ctx** ctx, int device, void* stream) {
+  return guarded([&] {
+    DME_REQUIRE(ctx != nullptr, DME_EINVAL, "null ctx pointer");
+    *ctx = nullptr;
+    int ndev = 0;
+    DME_HIP(hipGetDeviceCount(&ndev));
+    DME_REQUIRE(device >= 0 && device < ndev, DME_EINVAL, "no such HIP device");
+    DME_HIP(hipSetDevice(device));
+    auto c = std::make_unique<dme_ctx>();
+    c->device = device;
+    if (stream) {
+      c->stream = static_cast<hipStream_t>(stream);
+    } else {
+      DME_HIP(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
+      c->own_stream = true;
+    }
+    c->flags.ensure(64);
+    *ctx = c.release();
+  });
+}
+
+void dme_destroy(dme_ctx* ctx) {
+  if (!ctx) return;
+  (void)hipSetDevice(ctx->device);
+  (void)hipStreamSynchronize(ctx->stream);
+  if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
+  delete ctx;
+}
+
+int dle_solve(dme_ctx* ctx, const dme_problem* prob, const dme_opts* opts, dme_result** out) {
+  return solve_impl(ctx, prob, opts, 0, out);
+}
+
+int dre_solve(dme_ctx* ctx, const dme_problem* prob, const dme_opts* opts, dme_result** out) {
+  return solve_impl(ctx, prob, opts, 1, out);
+}
+
+int dme_solver_create(dme_ctx* ctx, const dme_problem* prob, const dme_opts* opts, int is_dre,
+                      dme_solver** out) {
+  return guarded([&] {
+    require_ctx(ctx);
+    DME_REQUIRE(prob && opts && out, DME_EINVAL, "null argument");
+    *out = nullptr;
+    DME_HIP(hipSetDevice(ctx->device));
+    auto sv = std::make_unique<dme_solver>();
+    sv->ctx = ctx;
+    sv->sv.s = ctx->stream;
+    sv->sv.device = ctx->device;
+    sv->sv.setup(*prob, *opts, is_dre != 0);
+    *out = sv.release();
+  });
+}
+
+int dme_solver_step(dme_solver* sv, int64_t nsteps) {
+  return guarded([&] {
+    DME_REQUIRE(sv != nullptr && nsteps >= 0, DME_EINVAL, "bad solver or step count");
+    DME_HIP(hipSetDevice(sv->sv.device));
+    sv->sv.advance(nsteps);
+  });
+}
+
+int dme_solver_state(const dme_solver* sv, int64_t* step, int64_t* nsteps_total, int64_t* rank) {
+  return guarded([&] {
+    DME_REQUIRE(sv != nullptr, DME_EINVAL, "null solver");
+    if (step) *step = sv->sv.step;
+    if (nsteps_total) *nsteps_total = sv->sv.N;
+    if (rank) *rank = sv->sv.r;
+  });
+}
+
+int dme_solver_setup_info(const dme_solver* sv, double* expm_ms, double* quad_ms, int64_t* rank_quad) {
+  return guarded([&] {
+    DME_REQUIRE(sv != nullptr, DME_EINVAL, "null solver");
+    if (expm_ms) *expm_ms = sv->sv.expm_ms;
+    if (quad_ms) *quad_ms = sv->sv.quad_ms;
+    if (rank_quad) *rank_quad = sv->sv.rank_quad;
+  });
+}
+
+int dme_solver_result(dme_solver* sv, dme_result** out) {
+  return guarded([&] {
+    DME_REQUIRE(sv != nullptr && out != nullptr, DME_EINVAL, "null argument");
+    DME_HIP(hipSetDevice(sv->sv.device));
+    make_result(sv->sv, out);
+  });
+}
+
+int dme_solver_profile(dme_solver* sv, int enable) {
+  return guarded([&] {
+    DME_REQUIRE(sv != nullptr, DME_EINVAL, "null solver");
+    DME_HIP(hipSetDevice(sv->sv.device));
+    sv->sv.flush_timings();
+    sv->sv.profiling = (enable != 0);
+    for (auto& a : sv->sv.phase) a = dme::PhaseAcc{};
+  });
+}
+
+int dme_solver_profile_get(dme_solver* sv, int phase, int64_t* count, double* ms, double* flops,
+                           double* bytes) {
+  return guarded([&] {
+    DME_REQUIRE(sv != nullptr && phase >= 0 && phase < 4, DME_EINVAL, "bad solver or phase");
+    DME_HIP(hipSetDevice(sv->sv.device));
+    sv->sv.flush_timings();
+    const dme::PhaseAcc& a = sv->sv.phase[phase];
+    if (count) *count = a.count;
+    if (ms) *ms = a.ms;
+    if (flops) *flops = a.flops;
+    if (bytes) *bytes = a.bytes;
+  });
+}
+
+void dme_solver_free(dme_solver* sv) {
+  if (!sv) return;
+  (void)hipSetDevice(sv->sv.device);
+  (void)hipStreamSynchronize(sv->sv.s);
+  delete sv;
+}
+
+int dme_result_info(const dme_result* res, int64_t* n, int64_t* r, int64_t* steps) {
+  return guarded([&] {
+    DME_REQUIRE(res != nullptr, DME_EINVAL, "null result");
+    if (n) *n = res->n;
+    if (r) *r = res->r;
+    if (steps) *steps = res->steps;
+  });
+}
+
+int dme_result_copy(const dme_result* res, double* L, double* D) {
+  return guarded([&] {
+    DME_REQUIRE(res != nullptr, DME_EINVAL, "null result");
+    if (L && !res->L.empty()) std::memcpy(L, res->L.data(), res->L.size() * sizeof(double));
+    if (D && !res->D.empty()) std::memcpy(D, res->D.data(), res->D.size() * sizeof(double));
+  });
+}
+
+void dme_result_free(dme_result* res) { delete res; }
+
+int dme_expm(dme_ctx* ctx, int64_t n, const double* X, double t, double* E, int* m_out, int* s_out) {
+  return guarded([&] {
+    require_ctx(ctx);
+    DME_REQUIRE(n >= 0 && (n == 0 || (X && E)), DME_EINVAL, "bad expm arguments");
+    DME_REQUIRE(X != E || n == 0, DME_EINVAL, "expm: X and E must not alias");
+    DME_REQUIRE(std::isfinite(t), DME_EINVAL, "expm: t must be finite");
+    DME_HIP(hipSetDevice(ctx->device));
+    if (n == 0) return;
+    ctx->ws.reserve(dme::expm_workspace(n));
+    ctx_reset_flags(ctx);
+    dme::expm_f64(ctx->stream, n, X, t, E, ctx->ws, m_out, s_out, ctx_flags(ctx) + 1);
+    int h[4];
+    ctx_read_flags(ctx, h);
+    DME_REQUIRE(h[1] == 0, DME_ENUMERIC, "expm: singular Pade denominator");
+  });
+}
+
+int dme_gemm_f64(dme_ctx* ctx, char transa, char transb, int64_t M, int64_t N, int64_t K,
+                 double alpha, const double* A, int64_t lda, const double* B, int64_t ldb,
+                 double beta, double* C, int64_t ldc) {
+  return guarded([&] {
+    require_ctx(ctx);
+    const bool ta = (transa == 'T' || transa == 't'), tb = (transb == 'T' || transb == 't');
+    DME_REQUIRE((transa == 'N' || transa == 'n' || ta) && (transb == 'N' || transb == 'n' || tb),
+                DME_EINVAL, "gemm: trans must be 'N' or 'T'");
+    DME_REQUIRE(M >= 0 && N >= 0 && K >= 0, DME_EINVAL, "gemm: negative dimension");
+    DME_REQUIRE(ldc >= std::max<int64_t>(1, M), DME_EINVAL, "gemm: ldc < M");
+    DME_REQUIRE(lda >= std::max<int64_t>(1, ta ? K : M), DME_EINVAL, "gemm: lda too small");
+    DME_REQUIRE(ldb >= std::max<int64_t>(1, tb ? N : K), DME_EINVAL, "gemm: ldb too small");
+    DME_HIP(hipSetDevice(ctx->device));
+    ctx->ws.reserve(dme::gemm_f64_workspace(M, N, K) + 1024);
+    dme::gemm_f64(ctx->stream, ta ? 'T' : 'N', tb ? 'T' : 'N', M, N, K, alpha, A, lda, B, ldb, beta,
+                  C, ldc, &ctx->ws);
+  });
+}
+
+int dme_compress(dme_ctx* ctx, int64_t n, int64_t k, double* W, const double* Dhat, double tol,
+                 int64_t max_rank, double* L, double* D, int64_t* r_out) {
+  return guarded([&] {
+    require_ctx(ctx);
+    DME_REQUIRE(n >= 0 && k >= 0 && max_rank >= 0, DME_EINVAL, "compress: negative size");
+    DME_REQUIRE(tol > 0, DME_EINVAL, "compress: tol must be positive");
+    DME_REQUIRE(k == 0 || (W && Dhat && L && D), DME_EINVAL, "compress: null pointer");
+    DME_HIP(hipSetDevice(ctx->device));
+    int64_t r = 0;
+    if (k > 0 && n > 0) {
+      ctx->ws.reserve(dme::compress_workspace(n, k));
+      ctx_reset_flags(ctx);
+      r = dme::compress_f64(ctx->stream, n, k, W, Dhat, tol, std::min(max_rank, std::min(n, k)), L,
+                            n, D, max_rank, ctx_rank(ctx), ctx_flags(ctx), ctx->ws);
+      int h[4];
+      ctx_read_flags(ctx, h);
+      DME_REQUIRE((h[0] & 1) == 0, DME_ENUMERIC, "compress: non-finite values");
+      if (r_out) *r_out = r;
+      DME_REQUIRE((h[0] & 2) == 0, DME_ERANK, "compress: rank exceeds max_rank");
+    }
+    if (r_out) *r_out = r;
+  });
+}
+
+int dme_riccati(dme_ctx* ctx, int64_t n, int64_t r, int64_t m, const double* L, const double* B,
+                const double* R, double t, double* D) {
+  return guarded([&] {
+    require_ctx(ctx);
+    DME_REQUIRE(n >= 0 && r >= 0 && m >= 0, DME_EINVAL, "riccati: negative size");
+    DME_HIP(hipSetDevice(ctx->device));
+    if (r == 0 || m == 0) return;
+    DME_REQUIRE(L && B && R && D, DME_EINVAL, "riccati: null pointer");
+    ctx->ws.reserve(dme::gemm_f64_workspace(r, m, n) + (size_t)r * (r + 2 * m) * sizeof(double) + 8192);
+    ctx_reset_flags(ctx);
+    double* WB = ctx->ws.get<double>((size_t)r * m);
+    dme::gemm_f64(ctx->stream, 'T', 'N', r, m, n, 1.0, L, n, B, n, 0.0, WB, r, &ctx->ws);
+    dme::riccati_update_f64(ctx->stream, r, m, D, r, WB, r, R, m, t, ctx_flags(ctx), ctx->ws);
+    int h[4];
+    ctx_read_flags(ctx, h);
+    DME_REQUIRE((h[0] & 4) == 0, DME_ENUMERIC, "riccati: R + t W^T D W is not SPD");
+  });
+}
+
+int dme_syev(dme_ctx* ctx, int64_t k, const double* M, double tol, int64_t max_keep, double* lam,
+             double* V, int64_t* keep_out) {
+  return guarded([&] {
+    require_ctx(ctx);
+    DME_REQUIRE(k >= 0 && max_keep >= 0, DME_EINVAL, "syev: negative size");
+    DME_REQUIRE(tol >= 0, DME_EINVAL, "syev: tol must be >= 0");
+    DME_HIP(hipSetDevice(ctx->device));
+    int64_t keep = 0;
+    if (k > 0) {
+      DME_REQUIRE(M && lam && V, DME_EINVAL, "syev: null pointer");
+      ctx->ws.reserve(dme::syev_workspace(k));
+      ctx_reset_flags(ctx);
+      dme::syev_trunc_f64(ctx->stream, k, M, k, tol, std::min(max_keep, k), lam, V, k,
+                          ctx_rank(ctx), ctx_flags(ctx), ctx->ws);
+      DME_HIP(hipMemcpyAsync(&keep, ctx_rank(ctx), sizeof(int64_t), hipMemcpyDeviceToHost, ctx->stream));
+      DME_HIP(hipStreamSynchronize(ctx->stream));
+    }
+    if (keep_out) *keep_out = keep;
+  });
+}
+
+}  // extern "C"

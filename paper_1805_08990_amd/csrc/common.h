@@ -1,0 +1,146 @@
+// Shared host/device helpers for the differential-matrix-equation library.
+// All matrices are FP64 (or BF16 pieces of FP64 values) in column-major order.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cfloat>
+#include <cmath>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/dme.h"
+
+namespace dme {
+
+struct Error {
+  int code;
+  std::string msg;
+};
+
+[[noreturn]] void fail(int code, const std::string& msg);
+
+#define DME_HIP(expr)                                                          \
+  do {                                                                         \
+    hipError_t e_ = (expr);                                                    \
+    if (e_ != hipSuccess)                                                      \
+      ::dme::fail(DME_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+#define DME_REQUIRE(cond, code, msg)                                           \
+  do {                                                                         \
+    if (!(cond)) ::dme::fail((code), (msg));                                   \
+  } while (0)
+
+inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// Device buffer owned by the library (hipMalloc / hipFree).
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  DevBuf() = default;
+  explicit DevBuf(size_t b) { alloc(b); }
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  DevBuf(DevBuf&& o) noexcept : p(o.p), bytes(o.bytes) { o.p = nullptr; o.bytes = 0; }
+  DevBuf& operator=(DevBuf&& o) noexcept {
+    if (this != &o) { release(); p = o.p; bytes = o.bytes; o.p = nullptr; o.bytes = 0; }
+    return *this;
+  }
+  ~DevBuf() { release(); }
+  void alloc(size_t b);
+  void ensure(size_t b) { if (b > bytes) { release(); alloc(b); } }
+  void release();
+  template <class T> T* as() const { return static_cast<T*>(p); }
+};
+
+// Scratch arena that grows on demand; the pointers it hands out are valid
+// until the next reset().  Used for per-call temporaries of the step-level
+// entry points.
+struct Arena {
+  DevBuf buf;
+  size_t used = 0;
+  void reset() { used = 0; }
+  // Reserve `bytes` of capacity up front (invalidates earlier pointers).
+  void reserve(size_t bytes) { buf.ensure(bytes); used = 0; }
+  template <class T> T* get(size_t count) {
+    size_t b = (count * sizeof(T) + 255) & ~size_t(255);
+    DME_REQUIRE(used + b <= buf.bytes, DME_EINTERNAL, "arena overflow");
+    T* out = reinterpret_cast<T*>(static_cast<char*>(buf.p) + used);
+    used += b;
+    return out;
+  }
+};
+
+// ---------------------------------------------------------------------------
+// Kernel launchers (each in its own .hip file)
+// ---------------------------------------------------------------------------
+
+// C = alpha * op(A) * op(B) + beta * C, FP64 MFMA.  op(X) = X ('N') or X^T ('T').
+// M x N result, inner dimension K.  beta == 0 never reads C.
+void gemm_f64(hipStream_t s, char ta, char tb, int64_t M, int64_t N, int64_t K,
+              double alpha, const double* A, int64_t lda, const double* B, int64_t ldb,
+              double beta, double* C, int64_t ldc, Arena* ws = nullptr);
+
+// Workspace (bytes) gemm_f64 may need for a split-K launch of this shape.
+size_t gemm_f64_workspace(int64_t M, int64_t N, int64_t K);
+
+// Elementwise / small helpers (elementwise.hip)
+void fill_f64(hipStream_t s, double* X, int64_t rows, int64_t cols, int64_t ld, double v);
+void copy_f64(hipStream_t s, const double* X, int64_t ldx, double* Y, int64_t ldy,
+              int64_t rows, int64_t cols);
+// Y = alpha * X^T (X rows x cols -> Y cols x rows)
+void transpose_f64(hipStream_t s, const double* X, int64_t ldx, double* Y, int64_t ldy,
+                   int64_t rows, int64_t cols, double alpha);
+// Y = a*X1 + b*X2 + c*X3 + d*I   (any of X1..X3 may be null when its coefficient is 0)
+void lincomb3_f64(hipStream_t s, int64_t n, double a, const double* X1, double b,
+                  const double* X2, double c, const double* X3, double d, double* Y);
+// X *= alpha (n x n, contiguous)
+void scale_f64(hipStream_t s, double* X, int64_t count, double alpha);
+// (U, V) -> (V - U, V + U) in place: U <- V - U, V <- V + U
+void pade_pm_f64(hipStream_t s, double* U, double* V, int64_t count);
+// column absolute sums -> colsum[n]; then device max -> out (1 double)
+void norm1_f64(hipStream_t s, const double* X, int64_t rows, int64_t cols, int64_t ld,
+               double* colsum, double* out);
+// D <- blkdiag(D1 (k1 x k1, ld1), w * I_p) style assembly into a k x k matrix
+void blkdiag2_f64(hipStream_t s, const double* D1, int64_t k1, int64_t ld1, const double* D2,
+                  int64_t k2, int64_t ld2, double scale2, double* out, int64_t ldo);
+// Scaled column block copy: Y[:, j] = alpha * X[:, j]
+void copy_scaled_f64(hipStream_t s, const double* X, int64_t ldx, double* Y, int64_t ldy,
+                     int64_t rows, int64_t cols, double alpha);
+// NaN/Inf scan: sets *flag = 1 if any entry of X is not finite.
+void finite_check_f64(hipStream_t s, const double* X, int64_t rows, int64_t cols, int64_t ld,
+                      int* flag);
+
+// LU with partial pivoting and the Pade solve (lu.hip)
+struct LuWork;
+// Solve P X = Q in place (Q <- P^-1 Q); P is destroyed.  n x n contiguous.
+// Returns through *info_dev (device int): 0 ok, j+1 if pivot j is exactly zero.
+void lu_solve_f64(hipStream_t s, int64_t n, double* P, double* Q, Arena& ws, int* info_dev);
+size_t lu_solve_workspace(int64_t n);
+
+// Householder QR + eigen compression (compress.hip)
+size_t compress_workspace(int64_t n, int64_t k);
+// W (n x k, ld n) is destroyed.  Dhat k x k (ld k).  Output L (n x r, ld ldl), Dout (r x r, ld ldd).
+// rank_dev: device int64 receiving r; flag_dev: device int receiving error flags
+// (1: non-finite, 2: rank capped at max_rank).  Synchronises the stream and returns r.
+int64_t compress_f64(hipStream_t s, int64_t n, int64_t k, double* W, const double* Dhat, double tol,
+                  int64_t max_rank, double* L, int64_t ldl, double* Dout, int64_t ldd,
+                  int64_t* rank_dev, int* flag_dev, Arena& ws);
+
+// Symmetric eigen-decomposition of a k x k matrix (syev.hip).
+// Eigenvalues sorted by |lambda| descending; only those with |lambda| > tol*max|lambda|
+// (at most max_keep) get eigenvectors.  Writes kept count to *keep_dev.
+size_t syev_workspace(int64_t k);
+void syev_trunc_f64(hipStream_t s, int64_t k, const double* M, int64_t ldm, double tol,
+                    int64_t max_keep, double* lam_out, double* V_out, int64_t ldv,
+                    int64_t* keep_dev, int* flag_dev, Arena& ws);
+
+// Riccati subflow (riccati.hip): D (r x r) <- D - t D W (R + t W^T D W)^-1 W^T D, W = L^T B.
+void riccati_update_f64(hipStream_t s, int64_t r, int64_t m, double* D, int64_t ldd,
+                        const double* WB, int64_t ldw, const double* R, int64_t ldr, double t,
+                        int* flag_dev, Arena& ws);
+
+}  // namespace dme

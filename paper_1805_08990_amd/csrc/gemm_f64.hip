@@ -1,0 +1,261 @@
+// FP64 MFMA GEMM for gfx950: C = alpha * op(A) op(B) + beta * C, column-major.
+//
+// Used for every dense product of the method: the Pade powers and the
+// squaring phase of e^{tX} (n x n x n), the LU trailing update and the
+// triangular solves, the step product e^{tA^T} L (n x n x r) and the
+// tall-skinny products of the Householder compression (split-K).
+//
+// Tile structure: a 256-thread workgroup (4 wave64s as 2 x 2) owns a BM x BN
+// block of C; op(A) and op(B) slabs of depth BK are staged through LDS with
+// the next slab prefetched into registers while the current one feeds
+// v_mfma_f64_16x16x4_f64.  The MFMA is fed with op(B) as its first operand
+// and op(A) as its second so that the accumulator lanes hold 16 consecutive
+// rows of C: the epilogue stores are then contiguous 128-byte runs of a C
+// column.  Split-K writes partial tiles to a workspace and a second kernel
+// adds them in fixed order, so results are deterministic.
+#include "common.h"
+
+namespace dme {
+namespace {
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+constexpr int kThreads = 256;
+constexpr int kPad = 16;  // LDS row padding in doubles (staggers the 4 k-rows of a fragment read)
+
+template <int BM, int BN, int BK, bool TA, bool TB>
+__global__ __launch_bounds__(kThreads) void gemm_f64_kernel(
+    int M, int N, int K, int kchunk, double alpha, const double* __restrict__ A, int64_t lda,
+    const double* __restrict__ B, int64_t ldb, double beta, double* __restrict__ C, int64_t ldc,
+    double* __restrict__ partial) {
+  constexpr int WTM = BM / 2, WTN = BN / 2;  // wave tile
+  constexpr int TM = WTM / 16, TN = WTN / 16;
+  constexpr int LA = BM * BK / kThreads;  // A elements per thread per slab
+  constexpr int LB = BN * BK / kThreads;
+  static_assert(LA * kThreads == BM * BK && LB * kThreads == BN * BK, "tile/thread mismatch");
+
+  __shared__ double sA[BK][BM + kPad];
+  __shared__ double sB[BK][BN + kPad];
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wm = wave & 1, wn = wave >> 1;
+  const int m0 = blockIdx.x * BM;
+  const int n0 = blockIdx.y * BN;
+  const int kbeg = blockIdx.z * kchunk;
+  const int kend = min(K, kbeg + kchunk);
+
+  v4d acc[TM][TN];
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j) acc[i][j] = v4d{0.0, 0.0, 0.0, 0.0};
+
+  double ra[LA], rb[LB];
+
+  auto load = [&](int k0) {
+#pragma unroll
+    for (int i = 0; i < LA; ++i) {
+      const int idx = tid + i * kThreads;
+      int ml, kl;
+      if (!TA) { ml = idx % BM; kl = idx / BM; }
+      else     { kl = idx % BK; ml = idx / BK; }
+      const int m = m0 + ml, k = k0 + kl;
+      double v = 0.0;
+      if (m < M && k < kend) v = TA ? A[k + (int64_t)m * lda] : A[m + (int64_t)k * lda];
+      ra[i] = v;
+    }
+#pragma unroll
+    for (int i = 0; i < LB; ++i) {
+      const int idx = tid + i * kThreads;
+      int nl, kl;
+      if (!TB) { kl = idx % BK; nl = idx / BK; }
+      else     { nl = idx % BN; kl = idx / BN; }
+      const int n = n0 + nl, k = k0 + kl;
+      double v = 0.0;
+      if (n < N && k < kend) v = TB ? B[n + (int64_t)k * ldb] : B[k + (int64_t)n * ldb];
+      rb[i] = v;
+    }
+  };
+  auto store = [&]() {
+#pragma unroll
+    for (int i = 0; i < LA; ++i) {
+      const int idx = tid + i * kThreads;
+      int ml, kl;
+      if (!TA) { ml = idx % BM; kl = idx / BM; }
+      else     { kl = idx % BK; ml = idx / BK; }
+      sA[kl][ml] = ra[i];
+    }
+#pragma unroll
+    for (int i = 0; i < LB; ++i) {
+      const int idx = tid + i * kThreads;
+      int nl, kl;
+      if (!TB) { kl = idx % BK; nl = idx / BK; }
+      else     { nl = idx % BN; kl = idx / BN; }
+      sB[kl][nl] = rb[i];
+    }
+  };
+
+  const int r16 = lane & 15;
+  const int kq = lane >> 4;
+
+  if (kbeg < kend) load(kbeg);
+  for (int k0 = kbeg; k0 < kend; k0 += BK) {
+    __syncthreads();
+    store();
+    __syncthreads();
+    if (k0 + BK < kend) load(k0 + BK);
+#pragma unroll
+    for (int kk = 0; kk < BK / 4; ++kk) {
+      double fa[TN], fb[TM];
+#pragma unroll
+      for (int j = 0; j < TN; ++j) fa[j] = sB[kk * 4 + kq][wn * WTN + j * 16 + r16];
+#pragma unroll
+      for (int i = 0; i < TM; ++i) fb[i] = sA[kk * 4 + kq][wm * WTM + i * 16 + r16];
+#pragma unroll
+      for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[j], fb[i], acc[i][j], 0, 0, 0);
+    }
+  }
+
+  // Epilogue: lane holds C(m = base_m + r16, n = base_n + 4*kq + v).
+#pragma unroll
+  for (int i = 0; i < TM; ++i) {
+    const int m = m0 + wm * WTM + i * 16 + r16;
+#pragma unroll
+    for (int j = 0; j < TN; ++j) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int n = n0 + wn * WTN + j * 16 + kq * 4 + v;
+        if (m < M && n < N) {
+          if (partial) {
+            partial[(int64_t)blockIdx.z * M * N + m + (int64_t)n * M] = acc[i][j][v];
+          } else {
+            double* c = C + m + (int64_t)n * ldc;
+            const double out = alpha * acc[i][j][v];
+            *c = (beta == 0.0) ? out : out + beta * (*c);
+          }
+        }
+      }
+    }
+  }
+}
+
+// C = alpha * sum_z partial[z] + beta * C, summed in z order.
+__global__ void splitk_reduce_kernel(int M, int N, int nsplit, double alpha,
+                                     const double* __restrict__ partial, double beta,
+                                     double* __restrict__ C, int64_t ldc) {
+  const int64_t total = (int64_t)M * N;
+  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    double s = 0.0;
+    for (int z = 0; z < nsplit; ++z) s += partial[(int64_t)z * total + idx];
+    const int64_t m = idx % M, n = idx / M;
+    double* c = C + m + n * ldc;
+    const double out = alpha * s;
+    *c = (beta == 0.0) ? out : out + beta * (*c);
+  }
+}
+
+template <int BM, int BN, int BK, bool TA, bool TB>
+void launch_tile(hipStream_t s, int M, int N, int K, int nsplit, int kchunk, double alpha,
+                 const double* A, int64_t lda, const double* B, int64_t ldb, double beta,
+                 double* C, int64_t ldc, double* partial) {
+  dim3 grid((unsigned)cdiv(M, BM), (unsigned)cdiv(N, BN), (unsigned)nsplit);
+  hipLaunchKernelGGL((gemm_f64_kernel<BM, BN, BK, TA, TB>), grid, dim3(kThreads), 0, s, M, N, K,
+                     kchunk, alpha, A, lda, B, ldb, beta, C, ldc, partial);
+}
+
+template <int BM, int BN, int BK>
+void dispatch_trans(hipStream_t s, char ta, char tb, int M, int N, int K, int nsplit, int kchunk,
+                    double alpha, const double* A, int64_t lda, const double* B, int64_t ldb,
+                    double beta, double* C, int64_t ldc, double* partial) {
+  const bool TA = (ta == 'T' || ta == 't');
+  const bool TB = (tb == 'T' || tb == 't');
+  if (!TA && !TB)
+    launch_tile<BM, BN, BK, false, false>(s, M, N, K, nsplit, kchunk, alpha, A, lda, B, ldb, beta, C, ldc, partial);
+  else if (TA && !TB)
+    launch_tile<BM, BN, BK, true, false>(s, M, N, K, nsplit, kchunk, alpha, A, lda, B, ldb, beta, C, ldc, partial);
+  else if (!TA && TB)
+    launch_tile<BM, BN, BK, false, true>(s, M, N, K, nsplit, kchunk, alpha, A, lda, B, ldb, beta, C, ldc, partial);
+  else
+    launch_tile<BM, BN, BK, true, true>(s, M, N, K, nsplit, kchunk, alpha, A, lda, B, ldb, beta, C, ldc, partial);
+}
+
+struct Plan {
+  int bm, bn, nsplit, kchunk;
+};
+
+constexpr int kBK = 16;
+constexpr int kTargetBlocks = 1024;  // ~4 workgroups per CU on 256 CUs
+constexpr int kMinKChunk = 256;
+
+Plan plan_for(int64_t M, int64_t N, int64_t K) {
+  Plan p;
+  if (M >= 128 && N >= 128) { p.bm = 128; p.bn = 128; }
+  else if (M >= 128)        { p.bm = 128; p.bn = 64; }
+  else                      { p.bm = 64;  p.bn = 64; }
+  const int64_t tiles = cdiv(M, p.bm) * cdiv(N, p.bn);
+  int64_t nsplit = 1;
+  if (tiles < kTargetBlocks && K >= 2 * kMinKChunk) {
+    nsplit = std::min<int64_t>(cdiv(kTargetBlocks, tiles), K / kMinKChunk);
+    nsplit = std::max<int64_t>(1, std::min<int64_t>(nsplit, 256));
+  }
+  int64_t kchunk = cdiv(cdiv(K, nsplit), kBK) * kBK;
+  if (kchunk <= 0) kchunk = kBK;
+  nsplit = std::max<int64_t>(1, cdiv(K, kchunk));
+  p.nsplit = (int)nsplit;
+  p.kchunk = (int)kchunk;
+  return p;
+}
+
+}  // namespace
+
+size_t gemm_f64_workspace(int64_t M, int64_t N, int64_t K) {
+  Plan p = plan_for(M, N, K);
+  if (p.nsplit <= 1) return 0;
+  return (size_t)p.nsplit * (size_t)M * (size_t)N * sizeof(double) + 256;
+}
+
+void gemm_f64(hipStream_t s, char ta, char tb, int64_t M, int64_t N, int64_t K, double alpha,
+              const double* A, int64_t lda, const double* B, int64_t ldb, double beta, double* C,
+              int64_t ldc, Arena* ws) {
+  if (M <= 0 || N <= 0) return;
+  DME_REQUIRE(M < (1ll << 31) && N < (1ll << 31) && K < (1ll << 31), DME_EINVAL, "gemm dims too large");
+  if (K <= 0) {
+    // C = beta * C
+    if (beta == 0.0) fill_f64(s, C, M, N, ldc, 0.0);
+    else if (beta != 1.0) copy_scaled_f64(s, C, ldc, C, ldc, M, N, beta);
+    return;
+  }
+  Plan p = plan_for(M, N, K);
+  double* partial = nullptr;
+  if (p.nsplit > 1) {
+    if (ws == nullptr) {
+      p.nsplit = 1;
+      p.kchunk = (int)(cdiv(K, kBK) * kBK);
+    } else {
+      partial = ws->get<double>((size_t)p.nsplit * M * N);
+    }
+  }
+  const int iM = (int)M, iN = (int)N, iK = (int)K;
+  if (p.bm == 128 && p.bn == 128)
+    dispatch_trans<128, 128, kBK>(s, ta, tb, iM, iN, iK, p.nsplit, p.kchunk, alpha, A, lda, B, ldb, beta, C, ldc, partial);
+  else if (p.bm == 128)
+    dispatch_trans<128, 64, kBK>(s, ta, tb, iM, iN, iK, p.nsplit, p.kchunk, alpha, A, lda, B, ldb, beta, C, ldc, partial);
+  else
+    dispatch_trans<64, 64, kBK>(s, ta, tb, iM, iN, iK, p.nsplit, p.kchunk, alpha, A, lda, B, ldb, beta, C, ldc, partial);
+  DME_HIP(hipGetLastError());
+  if (partial) {
+    const int64_t total = M * N;
+    const int blocks = (int)std::min<int64_t>(cdiv(total, 256), 4096);
+    hipLaunchKernelGGL(splitk_reduce_kernel, dim3(blocks), dim3(256), 0, s, iM, iN, p.nsplit, alpha,
+                       partial, beta, C, ldc);
+    DME_HIP(hipGetLastError());
+  }
+}
+
+}  // namespace dme

@@ -1,0 +1,112 @@
+// Solver state for one differential Lyapunov / Riccati solve: operators and
+// factors resident in HBM, stepped by the splitting schemes of Sec. 2 / Sec. 3.
+#pragma once
+
+#include <map>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "common.h"
+
+namespace dme {
+
+// Host helpers shared by the driver (defined in expm.hip / solver.hip).
+void expm_params(double nrm1, int* m, int* s);
+size_t expm_workspace(int64_t n);
+void expm_f64(hipStream_t s, int64_t n, const double* X, double t, double* E, Arena& ws, int* m_out,
+              int* s_out, int* info_dev);
+// K-point Gauss-Legendre nodes and weights on [0, t] (ascending nodes).
+void gauss_legendre(int K, double t, std::vector<double>& nodes, std::vector<double>& weights);
+
+enum class Sub { T1, T2, T12, T3, T4 };
+
+struct Stage {
+  Sub sub;
+  double frac;  // fraction of h
+};
+
+// Subflows of one step in application order (operators act right to left).
+std::vector<Stage> step_sequence(bool is_dre, bool has_S, int split, int scheme);
+
+struct QuadFactor {
+  DevBuf L;  // n x r
+  DevBuf D;  // r x r
+  int64_t r = 0;
+};
+
+struct MixedOp;  // split-BF16 copy of an operator (gemm_mixed.hip)
+
+struct PhaseAcc {
+  int64_t count = 0;
+  double ms = 0.0, flops = 0.0, bytes = 0.0;
+};
+
+struct PendingTiming {
+  int phase;
+  hipEvent_t a, b;
+  double flops, bytes;
+};
+
+struct Solver {
+  hipStream_t s = nullptr;
+  int device = 0;
+  int64_t n = 0, m = 0, p = 0;
+  bool is_dre = false, has_S = false;
+  dme_opts opts{};
+  int64_t N = 0, step = 0;
+  std::vector<Stage> seq;
+  int64_t max_rank = 0, kmax = 0;
+
+  DevBuf AT;   // n x n, A^T
+  DevBuf B;    // n x m
+  DevBuf CT;   // n x p, C^T
+  DevBuf R;    // m x m
+  DevBuf S;    // n x n
+  std::map<double, DevBuf> E;                       // t -> e^{t A^T}
+  std::map<double, std::shared_ptr<MixedOp>> Emix;  // t -> split-BF16 pieces
+  std::map<double, QuadFactor> Q;                   // t -> (L_I, D_I)
+
+  DevBuf L[2], D[2];
+  int cur = 0;
+  int64_t r = 0;
+  DevBuf W, Dhat, WB, SL;
+  DevBuf flags;  // int flags[4]; int64 rank at offset 16
+  Arena ws;
+
+  double expm_ms = 0.0, quad_ms = 0.0;
+  int64_t rank_quad = 0;
+
+  bool profiling = false;
+  PhaseAcc phase[4];
+  std::vector<PendingTiming> pending;
+  std::vector<hipEvent_t> event_pool;
+  hipEvent_t mark_begin();
+  void mark_end(int ph, hipEvent_t a, double flops, double bytes);
+  void flush_timings();
+  ~Solver();
+
+  double* Lc() { return L[cur].as<double>(); }
+  double* Dc() { return D[cur].as<double>(); }
+  double* Ln() { return L[cur ^ 1].as<double>(); }
+  double* Dn() { return D[cur ^ 1].as<double>(); }
+  int* flag_dev() { return flags.as<int>(); }
+  int64_t* rank_dev() { return reinterpret_cast<int64_t*>(flags.as<char>() + 16); }
+
+  void setup(const dme_problem& prob, const dme_opts& o, bool dre);
+  void advance(int64_t nsteps);
+  void check_flags(const char* where);
+
+ private:
+  void apply_T1(double t);
+  void apply_T2(double t);
+  void apply_T12(double t);
+  void apply_T3(double t);
+  void apply_T4(double t);
+  void compress_into(int64_t k);  // W (n x k), Dhat (k x k) -> new (L, D)
+  void apply_E(double t, const double* X, int64_t r, double* Y, int64_t ldy);
+  void build_operator(double t);
+  void build_quadrature(double t);
+};
+
+}  // namespace dme

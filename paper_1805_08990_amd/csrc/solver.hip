@@ -1,0 +1,418 @@
+// Splitting-scheme driver: operator setup and the step loop.
+//
+// Subflows on P = L D L^T (Sec. 2.1 - 2.4, Alg. 1 - 4):
+//   T1(t)  L <- e^{tA^T} L                                      (Sec. 2.1)
+//   T2(t)  L <- [L, C^T], D <- blkdiag(D, t I), compress         (Sec. 2.1, Alg. 1)
+//   T12(t) L <- [e^{tA^T} L, L_I], D <- blkdiag(D, D_I), compress (Alg. 2)
+//          with (L_I, D_I) the compressed Gauss-Legendre factor of
+//          int_0^t e^{sA^T} C^T C e^{sA} ds                          (Sec. 2.1 eq. for P(t))
+//   T3(t)  D <- (I + t D L^T B R^-1 B^T L)^-1 D                    (Sec. 2.2, Alg. 3)
+//   T4(t)  L <- [L, sqrt(t) S L, t/sqrt(2) S^2 L], D <- blkdiag(D, D, D),
+//          compress                                                (Sec. 2.3, Alg. 4)
+// composed as Lie or Strang steps in the orders listed in Sec. 3.  Every
+// product runs on the device; the host only sequences launches and reads back
+// the rank after each compression.
+#include "solver.h"
+
+#include <cmath>
+
+namespace dme {
+
+void gauss_legendre(int K, double t, std::vector<double>& nodes, std::vector<double>& weights) {
+  // Newton iteration on the Legendre polynomial P_K (three-term recurrence),
+  // starting from the standard cosine guesses; weights 2 / ((1 - x^2) P_K'(x)^2).
+  nodes.assign(K, 0.0);
+  weights.assign(K, 0.0);
+  for (int i = 0; i < K; ++i) {
+    long double x = std::cos(M_PI * (i + 0.75) / (K + 0.5));
+    long double dp = 1.0L;
+    for (int it = 0; it < 100; ++it) {
+      long double p0 = 1.0L, p1 = x;
+      for (int j = 2; j <= K; ++j) {
+        const long double p2 = ((2.0L * j - 1.0L) * x * p1 - (j - 1.0L) * p0) / j;
+        p0 = p1;
+        p1 = p2;
+      }
+      long double pk = (K == 0) ? 1.0L : p1;
+      long double pkm1 = (K == 1) ? 1.0L : p0;
+      if (K == 1) { pk = x; pkm1 = 1.0L; }
+      dp = K * (x * pk - pkm1) / (x * x - 1.0L);
+      const long double dx = pk / dp;
+      x -= dx;
+      if (std::fabs((double)dx) < 1e-19) break;
+    }
+    const long double w = 2.0L / ((1.0L - x * x) * dp * dp);
+    // ascending order: i = 0 gives the largest root
+    nodes[K - 1 - i] = (double)(0.5L * t * (x + 1.0L));
+    weights[K - 1 - i] = (double)(0.5L * t * w);
+  }
+}
+
+std::vector<Stage> step_sequence(bool is_dre, bool has_S, int split, int scheme) {
+  const bool strang = (scheme == DME_STRANG);
+  DME_REQUIRE(scheme == DME_LIE || scheme == DME_STRANG, DME_EINVAL, "unknown scheme");
+  std::vector<Sub> inner;
+  if (is_dre) inner.push_back(Sub::T3);
+  if (has_S) inner.push_back(Sub::T4);
+  std::vector<Stage> seq;
+  if (split == DME_SPLIT_F12) {
+    if (inner.empty()) return {{Sub::T12, 1.0}};
+    if (!strang) {
+      seq.push_back({Sub::T12, 1.0});
+      for (Sub x : inner) seq.push_back({x, 1.0});
+      return seq;
+    }
+    if (inner.size() == 1) return {{Sub::T12, 0.5}, {inner[0], 1.0}, {Sub::T12, 0.5}};
+    return {{Sub::T12, 0.5}, {Sub::T3, 0.5}, {Sub::T4, 1.0}, {Sub::T3, 0.5}, {Sub::T12, 0.5}};
+  }
+  if (split == DME_SPLIT_F1F2) {
+    DME_REQUIRE(inner.size() <= 1, DME_EINVAL, "four-term splitting is not part of the method");
+    if (inner.empty()) {
+      if (!strang) return {{Sub::T1, 1.0}, {Sub::T2, 1.0}};
+      return {{Sub::T1, 0.5}, {Sub::T2, 1.0}, {Sub::T1, 0.5}};
+    }
+    const Sub x = inner[0];
+    if (!strang) return {{Sub::T1, 1.0}, {Sub::T2, 1.0}, {x, 1.0}};
+    return {{Sub::T1, 0.5}, {Sub::T2, 0.5}, {x, 1.0}, {Sub::T2, 0.5}, {Sub::T1, 0.5}};
+  }
+  if (split == DME_SPLIT_F1F3F2) {
+    DME_REQUIRE(inner.size() == 1, DME_EINVAL, "F1F3F2 needs exactly one of B (DRE) or S");
+    const Sub x = inner[0];
+    if (!strang) return {{Sub::T1, 1.0}, {x, 1.0}, {Sub::T2, 1.0}};
+    return {{Sub::T1, 0.5}, {x, 0.5}, {Sub::T2, 1.0}, {x, 0.5}, {Sub::T1, 0.5}};
+  }
+  fail(DME_EINVAL, "unknown split");
+}
+
+namespace {
+
+struct EventTimer {
+  hipEvent_t a, b;
+  hipStream_t s;
+  explicit EventTimer(hipStream_t st) : s(st) {
+    DME_HIP(hipEventCreate(&a));
+    DME_HIP(hipEventCreate(&b));
+    DME_HIP(hipEventRecord(a, s));
+  }
+  double stop_ms() {
+    DME_HIP(hipEventRecord(b, s));
+    DME_HIP(hipEventSynchronize(b));
+    float ms = 0.f;
+    DME_HIP(hipEventElapsedTime(&ms, a, b));
+    return ms;
+  }
+  ~EventTimer() {
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+  }
+};
+
+void upload(hipStream_t s, DevBuf& dst, const double* src, size_t count) {
+  dst.ensure(std::max<size_t>(count, 1) * sizeof(double));
+  if (count) DME_HIP(hipMemcpyAsync(dst.p, src, count * sizeof(double), hipMemcpyHostToDevice, s));
+}
+
+}  // namespace
+
+hipEvent_t Solver::mark_begin() {
+  if (!profiling) return nullptr;
+  hipEvent_t e;
+  if (!event_pool.empty()) {
+    e = event_pool.back();
+    event_pool.pop_back();
+  } else {
+    DME_HIP(hipEventCreate(&e));
+  }
+  DME_HIP(hipEventRecord(e, s));
+  return e;
+}
+
+void Solver::mark_end(int ph, hipEvent_t a, double flops, double bytes) {
+  if (!profiling || a == nullptr) return;
+  hipEvent_t b = mark_begin();
+  pending.push_back({ph, a, b, flops, bytes});
+}
+
+void Solver::flush_timings() {
+  if (pending.empty()) return;
+  DME_HIP(hipStreamSynchronize(s));
+  for (const PendingTiming& t : pending) {
+    float ms = 0.f;
+    DME_HIP(hipEventElapsedTime(&ms, t.a, t.b));
+    PhaseAcc& acc = phase[t.phase];
+    acc.count += 1;
+    acc.ms += ms;
+    acc.flops += t.flops;
+    acc.bytes += t.bytes;
+    event_pool.push_back(t.a);
+    event_pool.push_back(t.b);
+  }
+  pending.clear();
+}
+
+Solver::~Solver() {
+  if (!pending.empty()) (void)hipStreamSynchronize(s);
+  for (const PendingTiming& t : pending) {
+    (void)hipEventDestroy(t.a);
+    (void)hipEventDestroy(t.b);
+  }
+  for (hipEvent_t e : event_pool) (void)hipEventDestroy(e);
+}
+
+void Solver::check_flags(const char* where) {
+  int h[4] = {0, 0, 0, 0};
+  DME_HIP(hipMemcpyAsync(h, flags.p, sizeof(h), hipMemcpyDeviceToHost, s));
+  DME_HIP(hipStreamSynchronize(s));
+  if (h[0] == 0 && h[1] == 0) return;
+  std::string w(where);
+  if (h[1] != 0) fail(DME_ENUMERIC, w + ": singular Pade denominator (zero pivot)");
+  if (h[0] & 1) fail(DME_ENUMERIC, w + ": non-finite values in the factor");
+  if (h[0] & 4) fail(DME_ENUMERIC, w + ": Riccati block R + t W^T D W is not SPD");
+  if (h[0] & 2) fail(DME_ERANK, w + ": compressed rank exceeds max_rank");
+  fail(DME_EINTERNAL, w + ": unknown device flag");
+}
+
+void Solver::setup(const dme_problem& prob, const dme_opts& o, bool dre) {
+  DME_REQUIRE(prob.n > 0 && prob.A, DME_EINVAL, "need n > 0 and A");
+  DME_REQUIRE(prob.p > 0 && prob.C, DME_EINVAL, "need p > 0 and C (Q = C^T C)");
+  DME_REQUIRE(o.h > 0 && o.T > 0, DME_EINVAL, "T and h must be positive");
+  DME_REQUIRE(o.tol > 0, DME_EINVAL, "tol must be positive");
+  DME_REQUIRE(prob.r0 >= 0, DME_EINVAL, "r0 must be >= 0");
+  DME_REQUIRE(prob.r0 == 0 || (prob.L0 && prob.D0), DME_EINVAL, "r0 > 0 needs L0 and D0");
+  n = prob.n;
+  p = prob.p;
+  is_dre = dre;
+  has_S = prob.S != nullptr;
+  opts = o;
+  if (opts.quad_nodes <= 0) opts.quad_nodes = 7;
+  DME_REQUIRE(opts.quad_nodes <= 64, DME_EINVAL, "quad_nodes must be <= 64");
+  const double Nf = std::round(o.T / o.h);
+  DME_REQUIRE(Nf >= 1 && std::fabs(Nf * o.h - o.T) <= 1e-12 * o.T, DME_EINVAL, "T/h is not an integer");
+  N = (int64_t)Nf;
+  if (dre) {
+    m = prob.m;
+    DME_REQUIRE(m > 0 && prob.B && prob.R, DME_EINVAL, "DRE needs m > 0, B and R");
+    // R must be SPD: host Cholesky of the m x m input (validation only)
+    std::vector<double> Rc(prob.R, prob.R + m * m);
+    for (int64_t j = 0; j < m; ++j) {
+      double dj = Rc[j + j * m];
+      for (int64_t q = 0; q < j; ++q) dj -= Rc[j + q * m] * Rc[j + q * m];
+      DME_REQUIRE(dj > 0, DME_EINVAL, "R is not symmetric positive definite");
+      const double l = std::sqrt(dj);
+      Rc[j + j * m] = l;
+      for (int64_t i = j + 1; i < m; ++i) {
+        double v = Rc[i + j * m];
+        for (int64_t q = 0; q < j; ++q) v -= Rc[i + q * m] * Rc[j + q * m];
+        Rc[i + j * m] = v / l;
+      }
+    }
+  } else {
+    m = 0;
+  }
+  seq = step_sequence(dre, has_S, opts.split, opts.scheme);
+  max_rank = (o.max_rank > 0) ? std::min<int64_t>(o.max_rank, n) : std::min<int64_t>(n, 512);
+  DME_REQUIRE(prob.r0 <= max_rank, DME_EINVAL, "r0 exceeds max_rank");
+  const int64_t Kp = (int64_t)opts.quad_nodes * p;
+  kmax = std::max({max_rank + p, max_rank + Kp, 3 * max_rank, Kp});
+
+  DME_HIP(hipSetDevice(device));
+  flags.ensure(64);
+  fill_f64(s, flags.as<double>(), 8, 1, 8, 0.0);
+
+  {
+    DevBuf A;
+    upload(s, A, prob.A, (size_t)n * n);
+    AT.ensure((size_t)n * n * sizeof(double));
+    transpose_f64(s, A.as<double>(), n, AT.as<double>(), n, n, n, 1.0);
+    DME_HIP(hipStreamSynchronize(s));
+  }
+  {
+    DevBuf Cd;
+    upload(s, Cd, prob.C, (size_t)p * n);
+    CT.ensure((size_t)n * p * sizeof(double));
+    transpose_f64(s, Cd.as<double>(), p, CT.as<double>(), n, p, n, 1.0);
+    DME_HIP(hipStreamSynchronize(s));
+  }
+  if (dre) {
+    upload(s, B, prob.B, (size_t)n * m);
+    upload(s, R, prob.R, (size_t)m * m);
+  }
+  if (has_S) upload(s, S, prob.S, (size_t)n * n);
+
+  for (int q = 0; q < 2; ++q) {
+    L[q].ensure((size_t)n * max_rank * sizeof(double));
+    D[q].ensure((size_t)max_rank * max_rank * sizeof(double));
+  }
+  W.ensure((size_t)n * kmax * sizeof(double));
+  Dhat.ensure((size_t)kmax * kmax * sizeof(double));
+  WB.ensure((size_t)max_rank * std::max<int64_t>(m, 1) * sizeof(double));
+  if (has_S) SL.ensure((size_t)n * max_rank * sizeof(double));
+  size_t wsb = compress_workspace(n, kmax);
+  wsb += gemm_f64_workspace(max_rank, std::max<int64_t>(m, 1), n) + 4096;
+  wsb += gemm_f64_workspace(n, max_rank, n) + 4096;
+  wsb += (size_t)max_rank * (max_rank + 64) * sizeof(double) + 4096;  // riccati scratch
+  ws.reserve(wsb);
+
+  cur = 0;
+  r = prob.r0;
+  if (r > 0) {
+    DME_HIP(hipMemcpyAsync(L[0].p, prob.L0, (size_t)n * r * sizeof(double), hipMemcpyHostToDevice, s));
+    DME_HIP(hipMemcpyAsync(D[0].p, prob.D0, (size_t)r * r * sizeof(double), hipMemcpyHostToDevice, s));
+  }
+
+  for (const Stage& st : seq) {
+    const double t = st.frac * o.h;
+    if (st.sub == Sub::T1 || st.sub == Sub::T12) {
+      if (!E.count(t)) {
+        EventTimer tm(s);
+        build_operator(t);
+        expm_ms += tm.stop_ms();
+      }
+    }
+    if (st.sub == Sub::T12 && !Q.count(t)) {
+      EventTimer tm(s);
+      build_quadrature(t);
+      quad_ms += tm.stop_ms();
+    }
+  }
+  check_flags("setup");
+  step = 0;
+}
+
+void Solver::build_operator(double t) {
+  DevBuf& Et = E[t];
+  Et.ensure((size_t)n * n * sizeof(double));
+  Arena ews;
+  ews.reserve(expm_workspace(n));
+  expm_f64(s, n, AT.as<double>(), t, Et.as<double>(), ews, nullptr, nullptr, flag_dev() + 1);
+  DME_HIP(hipStreamSynchronize(s));
+}
+
+void Solver::build_quadrature(double t) {
+  const int K = opts.quad_nodes;
+  std::vector<double> nodes, weights;
+  gauss_legendre(K, t, nodes, weights);
+  const int64_t kq = (int64_t)K * p;
+  DevBuf Ek((size_t)n * n * sizeof(double));
+  Arena ews;
+  ews.reserve(expm_workspace(n));
+  // columns [e^{s_k A^T} C^T]_k directly into W, weights into Dhat
+  double* Wd = W.as<double>();
+  for (int q = 0; q < K; ++q) {
+    ews.reset();
+    expm_f64(s, n, AT.as<double>(), nodes[q], Ek.as<double>(), ews, nullptr, nullptr, flag_dev() + 1);
+    ews.reset();
+    gemm_f64(s, 'N', 'N', n, p, n, 1.0, Ek.as<double>(), n, CT.as<double>(), n, 0.0,
+             Wd + (int64_t)q * p * n, n, &ews);
+  }
+  double* Dh = Dhat.as<double>();
+  fill_f64(s, Dh, kq, kq, kq, 0.0);
+  for (int q = 0; q < K; ++q)
+    blkdiag2_f64(s, nullptr, 0, 1, nullptr, p, 1, weights[q], Dh + (int64_t)q * p * (kq + 1), kq);
+  DME_HIP(hipStreamSynchronize(s));
+  QuadFactor& f = Q[t];
+  f.L.ensure((size_t)n * kq * sizeof(double));
+  f.D.ensure((size_t)kq * kq * sizeof(double));
+  ws.reset();
+  f.r = compress_f64(s, n, kq, Wd, Dh, opts.tol, std::min<int64_t>(kq, n), f.L.as<double>(), n,
+                     f.D.as<double>(), 0, rank_dev(), flag_dev(), ws);
+  rank_quad = std::max(rank_quad, f.r);
+  check_flags("quadrature factor");
+}
+
+void Solver::apply_E(double t, const double* X, int64_t rr, double* Y, int64_t ldy) {
+  ws.reset();
+  hipEvent_t ev = mark_begin();
+  gemm_f64(s, 'N', 'N', n, rr, n, 1.0, E.at(t).as<double>(), n, X, n, 0.0, Y, ldy, &ws);
+  // algorithmic work of Y = E X: 2 n^2 r flops; E read once, X read, Y written
+  mark_end(0, ev, 2.0 * n * n * rr, 8.0 * ((double)n * n + 2.0 * n * rr));
+}
+
+void Solver::compress_into(int64_t k) {
+  ws.reset();
+  hipEvent_t ev = mark_begin();
+  const int64_t rn = compress_f64(s, n, k, W.as<double>(), Dhat.as<double>(), opts.tol, max_rank,
+                                  Ln(), n, Dn(), 0, rank_dev(), flag_dev(), ws);
+  // Householder QR 2 n k^2 - 2/3 k^3, Q application 4 n k r', small eigenproblem ~ 10 k^3
+  const double kk = (double)k;
+  mark_end(1, ev, 2.0 * n * kk * kk + 4.0 * n * kk * rn + 10.0 * kk * kk * kk,
+           8.0 * (2.0 * n * kk + 2.0 * n * rn));
+  cur ^= 1;
+  r = rn;
+}
+
+void Solver::apply_T1(double t) {
+  if (r == 0) return;
+  apply_E(t, Lc(), r, Ln(), n);
+  copy_f64(s, Dc(), r, Dn(), r, r, r);
+  cur ^= 1;
+}
+
+void Solver::apply_T2(double t) {
+  double* Wd = W.as<double>();
+  if (r > 0) copy_f64(s, Lc(), n, Wd, n, n, r);
+  copy_f64(s, CT.as<double>(), n, Wd + r * n, n, n, p);
+  const int64_t k = r + p;
+  blkdiag2_f64(s, Dc(), r, r, nullptr, p, 1, t, Dhat.as<double>(), k);
+  compress_into(k);
+}
+
+void Solver::apply_T12(double t) {
+  const QuadFactor& f = Q.at(t);
+  double* Wd = W.as<double>();
+  if (r > 0) apply_E(t, Lc(), r, Wd, n);
+  if (f.r > 0) copy_f64(s, f.L.as<double>(), n, Wd + r * n, n, n, f.r);
+  const int64_t k = r + f.r;
+  if (k == 0) return;
+  blkdiag2_f64(s, Dc(), r, r, f.D.as<double>(), f.r, f.r, 1.0, Dhat.as<double>(), k);
+  compress_into(k);
+}
+
+void Solver::apply_T3(double t) {
+  if (r == 0) return;
+  hipEvent_t ev = mark_begin();
+  ws.reset();
+  gemm_f64(s, 'T', 'N', r, m, n, 1.0, Lc(), n, B.as<double>(), n, 0.0, WB.as<double>(), r, &ws);
+  ws.reset();
+  riccati_update_f64(s, r, m, Dc(), r, WB.as<double>(), r, R.as<double>(), m, t, flag_dev(), ws);
+  mark_end(2, ev, 2.0 * n * r * m + 2.0 * r * r * m, 8.0 * ((double)n * r + (double)n * m));
+}
+
+void Solver::apply_T4(double t) {
+  if (r == 0) return;
+  double* Wd = W.as<double>();
+  hipEvent_t ev = mark_begin();
+  ws.reset();
+  gemm_f64(s, 'N', 'N', n, r, n, 1.0, S.as<double>(), n, Lc(), n, 0.0, SL.as<double>(), n, &ws);
+  copy_f64(s, Lc(), n, Wd, n, n, r);
+  copy_scaled_f64(s, SL.as<double>(), n, Wd + r * n, n, n, r, std::sqrt(t));
+  ws.reset();
+  gemm_f64(s, 'N', 'N', n, r, n, t / std::sqrt(2.0), S.as<double>(), n, SL.as<double>(), n, 0.0,
+           Wd + 2 * r * n, n, &ws);
+  mark_end(3, ev, 4.0 * n * n * r, 8.0 * (2.0 * n * n + 4.0 * n * r));
+  const int64_t k = 3 * r;
+  double* Dh = Dhat.as<double>();
+  fill_f64(s, Dh, k, k, k, 0.0);
+  for (int q = 0; q < 3; ++q) copy_f64(s, Dc(), r, Dh + q * r * (k + 1), k, r, r);
+  compress_into(k);
+}
+
+void Solver::advance(int64_t nsteps) {
+  for (int64_t it = 0; it < nsteps; ++it) {
+    for (const Stage& st : seq) {
+      const double t = st.frac * opts.h;
+      switch (st.sub) {
+        case Sub::T1: apply_T1(t); break;
+        case Sub::T2: apply_T2(t); break;
+        case Sub::T12: apply_T12(t); break;
+        case Sub::T3: apply_T3(t); break;
+        case Sub::T4: apply_T4(t); break;
+      }
+    }
+    ++step;
+  }
+  flush_timings();
+  check_flags("step");
+}
+
+}  // namespace dme

@@ -27,3 +27,15 @@ def pytest_collection_modifyitems(config, items):
     for it in items:
         if "gpu" in it.keywords:
             it.add_marker(skip)
+
+
+@pytest.fixture(scope="session")
+def ctx():
+    """One library context on cuda:0 for the whole GPU session."""
+    import torch
+    from paper_1805_08990_amd import _binding
+    torch.cuda.init()
+    c = _binding.Context(0)
+    yield c
+    torch.cuda.synchronize()
+    c.close()

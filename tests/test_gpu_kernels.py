@@ -1,0 +1,161 @@
+"""Parity of each hot-path kernel (through the C ABI) with numpy / the oracle."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as wl
+from tests.gpu_common import announce, rel_fro, to_np
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("M,N,K,ta,tb", [
+    (64, 64, 64, "N", "N"), (200, 150, 130, "N", "N"), (129, 65, 300, "T", "N"),
+    (33, 257, 17, "N", "T"), (70, 90, 1000, "T", "T"), (1, 1, 1, "N", "N"),
+    (32, 40, 5000, "T", "N"), (1000, 7, 1000, "N", "N"), (256, 256, 0, "N", "N"),
+])
+def test_gemm_f64(ctx, M, N, K, ta, tb):
+    announce("gemm", M, N, K, ta, tb)
+    rng = np.random.default_rng(M * 7 + N * 3 + K)
+    A = rng.standard_normal((K, M) if ta == "T" else (M, K))
+    B = rng.standard_normal((N, K) if tb == "T" else (K, N))
+    C = rng.standard_normal((M, N))
+    opA = A.T if ta == "T" else A
+    opB = B.T if tb == "T" else B
+    got = to_np(ctx.gemm(A, B, alpha=0.75, beta=-0.5, C=C, transa=ta, transb=tb))
+    ref = 0.75 * opA @ opB - 0.5 * C
+    assert rel_fro(got, ref) < 1e-13
+
+
+def test_gemm_beta_zero_ignores_nan(ctx):
+    announce("gemm beta0 nan")
+    rng = np.random.default_rng(1)
+    A, B = rng.standard_normal((50, 40)), rng.standard_normal((40, 30))
+    C = np.full((50, 30), np.nan)
+    got = to_np(ctx.gemm(A, B, beta=0.0, C=C))
+    assert np.all(np.isfinite(got)) and rel_fro(got, A @ B) < 1e-14
+
+
+@pytest.mark.parametrize("nx,t", [(16, 5e-4), (16, 1e-6), (16, 2e-5), (16, 1e-3), (16, 2e-2), (10, 1e-1)])
+def test_expm_laplacian(ctx, nx, t):
+    announce("expm laplacian", nx, t)
+    A = wl.laplacian_2d(nx)
+    E, m, s = ctx.expm(A.T, t)
+    ref = oracle.expm(t * A.T)
+    mo, so = oracle.expm_params(oracle.norm1(t * A.T))
+    assert (m, s) == (mo, so)
+    assert rel_fro(to_np(E), ref) < 1e-12
+
+
+@pytest.mark.parametrize("n,t", [(100, 1.0), (130, 0.05), (1, 2.0), (257, 0.3)])
+def test_expm_nonsymmetric(ctx, n, t):
+    announce("expm nonsym", n, t)
+    X = wl.random_nonsymmetric(n, seed=n)
+    E, m, s = ctx.expm(X, t)
+    assert rel_fro(to_np(E), oracle.expm(t * X)) < 1e-12
+
+
+def _sym_with_spectrum(k, lam, seed):
+    rng = np.random.default_rng(seed)
+    Q, _ = np.linalg.qr(rng.standard_normal((k, k)))
+    return (Q * lam) @ Q.T
+
+
+@pytest.mark.parametrize("case", ["random", "graded", "clusters", "psd_lowrank", "k2", "k1", "k300"])
+def test_syev(ctx, case):
+    announce("syev", case)
+    rng = np.random.default_rng(5)
+    if case == "random":
+        k = 60
+        X = rng.standard_normal((k, k)); M = 0.5 * (X + X.T)
+    elif case == "graded":
+        k = 120
+        M = _sym_with_spectrum(k, 10.0 ** -rng.uniform(0, 12, k), 2)
+    elif case == "clusters":
+        k = 50
+        lam = np.repeat([3.0, 2.0, 1.0, 0.5, -1.0], 10)
+        M = _sym_with_spectrum(k, lam, 3)
+    elif case == "psd_lowrank":
+        k = 80
+        F = rng.standard_normal((k, 20)); M = F @ F.T
+    elif case == "k2":
+        k = 2
+        M = np.array([[2.0, 1.0], [1.0, 3.0]])
+    elif case == "k1":
+        k = 1
+        M = np.array([[-4.0]])
+    else:
+        k = 300
+        M = _sym_with_spectrum(k, np.exp(-0.1 * np.arange(k)), 4)
+    tol = 1e-12
+    lam, V, kk = ctx.syev(M, tol=tol)
+    lam, V = to_np(lam), to_np(V)
+    ref = np.linalg.eigvalsh(M)
+    ref = ref[np.argsort(-np.abs(ref), kind="stable")]
+    keep = np.abs(ref) > tol * np.abs(ref).max()
+    assert kk == int(keep.sum())
+    nrm = np.abs(ref).max()
+    assert np.max(np.abs(lam[:kk] - ref[:kk])) < 1e-13 * nrm * max(1, np.sqrt(k))
+    # kept part reproduces M up to the dropped eigenvalues
+    Mk = (V * lam[:kk]) @ V.T
+    drop = np.sqrt(np.sum(ref[kk:] ** 2))
+    assert np.linalg.norm(Mk - M) <= 1e-12 * np.linalg.norm(M) + 1.01 * drop
+    assert np.max(np.abs(V.T @ V - np.eye(kk))) < 1e-10
+
+
+def _compress_case(name):
+    rng = np.random.default_rng(11)
+    if name == "random":
+        n, k = 300, 40
+        W = rng.standard_normal((n, k)); F = rng.standard_normal((k, k)); Dh = F @ F.T / k
+    elif name == "rankdef":
+        n, k = 500, 60
+        W = rng.standard_normal((n, 20)) @ rng.standard_normal((20, k)); Dh = np.diag(rng.uniform(0.5, 2, k))
+    elif name == "wide":
+        n, k = 20, 33
+        W = rng.standard_normal((n, k)); Dh = np.diag(rng.uniform(0.1, 1, k))
+    elif name == "zero":
+        n, k = 64, 5
+        W = rng.standard_normal((n, k)); Dh = np.zeros((k, k))
+    elif name == "identity":
+        n, k = 200, 30
+        W, _ = np.linalg.qr(rng.standard_normal((n, k))); Dh = np.eye(k)
+    elif name == "graded":
+        n, k = 1000, 100
+        W = rng.standard_normal((n, k)) * (10.0 ** -np.linspace(0, 9, k)); Dh = np.eye(k)
+    elif name == "tall_multi_panel":
+        n, k = 4097, 97
+        W = rng.standard_normal((n, k)) / np.sqrt(n); Dh = np.diag(np.exp(-0.2 * np.arange(k)))
+    else:
+        raise KeyError(name)
+    return W, Dh
+
+
+@pytest.mark.parametrize("name", ["random", "rankdef", "wide", "zero", "identity", "graded",
+                                  "tall_multi_panel"])
+def test_compress_matches_oracle(ctx, name):
+    announce("compress", name)
+    W, Dh = _compress_case(name)
+    tol = 1e-10
+    L, D = ctx.compress(W, Dh, tol)
+    L, D = to_np(L), to_np(D)
+    Lo, Do = oracle.compress(W, Dh, tol)
+    assert L.shape[1] == Lo.shape[1]
+    if Lo.shape[1] == 0:
+        return
+    assert oracle.lowrank_rel_err(L, D, Lo, Do) < 1e-11
+    assert np.max(np.abs(L.T @ L - np.eye(L.shape[1]))) < 1e-8
+
+
+@pytest.mark.parametrize("n,r,m", [(200, 12, 1), (300, 40, 4), (50, 3, 2), (4096, 60, 4)])
+def test_riccati_matches_oracle(ctx, n, r, m):
+    announce("riccati", n, r, m)
+    rng = np.random.default_rng(n + r)
+    L = rng.standard_normal((n, r)) / np.sqrt(n)
+    F = rng.standard_normal((r, r)); D = F @ F.T
+    B = rng.standard_normal((n, m))
+    G = rng.standard_normal((m, m)); R = G @ G.T + m * np.eye(m)
+    t = 1e-2
+    got = to_np(ctx.riccati(L, B, R, t, D))
+    ref = oracle.t3(L, D, B, R, t)
+    assert rel_fro(got, ref) < 1e-12

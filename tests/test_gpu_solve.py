@@ -1,0 +1,108 @@
+"""Whole solves through the C ABI (dle_solve / dre_solve / stepwise solver)
+against the oracle, on seeded synthetic inputs; relative Frobenius error of
+P = L D L^T at 1e-10 (FP64)."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as wl
+from paper_1805_08990_amd import _binding as b
+from tests.gpu_common import announce
+
+pytestmark = pytest.mark.gpu
+
+TOL_FP64 = 1e-10
+
+
+def run_gpu(ctx, prob, **kw):
+    opts = b.SolveOptions(T=prob.T, h=prob.h, tol=prob.tol, scheme=prob.scheme, split=prob.split,
+                          quad_nodes=prob.quad_nodes, **kw)
+    return ctx.solve(prob.kind, opts, prob.A, prob.C, B=prob.B, R=prob.R, S=prob.S,
+                     L0=prob.L0, D0=prob.D0)
+
+
+def run_oracle(prob, **kw):
+    return oracle.solve(prob.A, prob.C, prob.T, prob.h, kind=prob.kind, B=prob.B, R=prob.R,
+                        S=prob.S, L0=prob.L0, D0=prob.D0, split=prob.split, scheme=prob.scheme,
+                        tol=prob.tol, quad_nodes=prob.quad_nodes, **kw)
+
+
+def check(ctx, prob, tol=TOL_FP64, **okw):
+    announce(prob.name, prob.kind, prob.split, prob.scheme, "n", prob.n, "h", prob.h)
+    L, D, steps = run_gpu(ctx, prob)
+    Lo, Do, info = run_oracle(prob, **okw)
+    assert steps == info["steps"]
+    err = oracle.lowrank_rel_err(L, D, Lo, Do)
+    print(f"  rank gpu {L.shape[1]} oracle {Lo.shape[1]} rel err {err:.3e}", flush=True)
+    assert err < tol
+    return L, D, Lo, Do
+
+
+def test_config_dle_strang_f1f2_n256(ctx):
+    """16 x 16 Laplacian, C = ones, P0 = 0, T = 0.1, h = 1e-3, tol 1e-12 (Alg. 1)."""
+    check(ctx, wl.config_dle_small(16))
+
+
+@pytest.mark.parametrize("scheme", ["strang", "lie"])
+@pytest.mark.parametrize("split", ["F12", "F1F2"])
+def test_dle_small(ctx, scheme, split):
+    p = wl.config_dle_small(8)
+    p.scheme, p.split, p.h, p.tol = scheme, split, 1e-2, 1e-12
+    check(ctx, p)
+
+
+@pytest.mark.parametrize("scheme", ["strang", "lie"])
+@pytest.mark.parametrize("split", ["F12", "F1F2", "F1F3F2"])
+def test_dre_small(ctx, scheme, split):
+    p = wl.config_dre_halfplane(nx=8, h=1e-2, scheme=scheme)
+    p.split = split
+    check(ctx, p)
+
+
+def test_gdre_small(ctx):
+    p = wl.config_gdre(nx=8, h=1e-2)
+    check(ctx, p)
+
+
+def test_dre_quadrant_random_C(ctx):
+    p = wl.config_dre_quadrant(nx=12, seed=0, p=8, m=4, h=1e-2)
+    check(ctx, p)
+
+
+def test_dre_nonsymmetric_A_with_P0(ctx):
+    n = 60
+    A = wl.random_nonsymmetric(n, seed=3, scale=5.0)
+    C = wl.random_C(3, n, seed=4)
+    L0, D0 = wl.random_lowrank_P0(n, 5, seed=6)
+    p = wl.Problem(name="nonsym", A=A, C=C, B=wl.random_C(2, n, seed=7).T.copy(order="F"),
+                   R=np.diag([1.0, 2.0]), L0=L0, D0=D0, T=0.05, h=5e-3, tol=1e-12)
+    check(ctx, p)
+
+
+def test_stepwise_equals_whole_solve(ctx):
+    p = wl.config_dre_halfplane(nx=8, h=1e-2)
+    announce("stepwise")
+    L, D, _ = run_gpu(ctx, p)
+    opts = b.SolveOptions(T=p.T, h=p.h, tol=p.tol, scheme=p.scheme, split=p.split)
+    sv = ctx.solver("dre", opts, p.A, p.C, B=p.B, R=p.R)
+    sv.step(3)
+    sv.step(7)
+    st, tot, r = sv.state()
+    assert (st, tot) == (10, 10)
+    L2, D2, _ = sv.result()
+    assert np.array_equal(L, L2) and np.array_equal(D, D2)
+    sv.close()
+
+
+def test_errors_are_reported(ctx):
+    p = wl.config_dre_halfplane(nx=4, h=1e-2)
+    announce("errors")
+    with pytest.raises(b.DmeError) as e:
+        ctx.solve("dre", b.SolveOptions(T=0.1, h=0.03), p.A, p.C, B=p.B, R=p.R)
+    assert e.value.code == b.DME_EINVAL
+    with pytest.raises(b.DmeError) as e:
+        ctx.solve("dre", b.SolveOptions(T=0.1, h=0.01), p.A, p.C, B=p.B, R=-np.eye(1))
+    assert e.value.code == b.DME_EINVAL
+    with pytest.raises(b.DmeError) as e:
+        ctx.solve("dle", b.SolveOptions(T=0.1, h=0.01, max_rank=1), p.A, wl.random_C(3, 16, 1))
+    assert e.value.code == b.DME_ERANK
