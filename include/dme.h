@@ -161,6 +161,17 @@ int dme_gemm_f64(dme_ctx *ctx, char transa, char transb, int64_t M, int64_t N, i
                  double alpha, const double *A, int64_t lda, const double *B, int64_t ldb,
                  double beta, double *C, int64_t ldc);
 
+/* Y = E X in the mixed-precision mode (the split-precision form of the step
+ * product e^{tA^T} L of Sec. 2.1, eq. for T1): E is rounded to FP32 and X to
+ * FP32, each is split into three BF16 pieces, the six leading piece products
+ * run on BF16 MFMA with FP32 accumulation per K chunk, and the chunks are summed
+ * in FP64.  Relative error per entry is about 2^-24 times the sum of |E||X|.
+ * E: n x n device (FP64, ld n), X: n x r device (ld ldx), Y: n x r device
+ * (ld ldy).  The FP32 copy of E is built on every call (the solver keeps its
+ * copy resident instead).  E and Y must not alias.                         */
+int dme_gemm_mixed(dme_ctx *ctx, int64_t n, int64_t r, const double *E, const double *X,
+                   int64_t ldx, double *Y, int64_t ldy);
+
 /* Column compression (Sec. 3 after Alg. 2): Householder QR W = Q R,
  * M = R Dhat R^T, M = V Lam V^T, keep |lam_i| > tol max|lam| (sorted by |lam|
  * descending), L = Q V_I, D = diag(lam_I).

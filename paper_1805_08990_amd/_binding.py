@@ -43,6 +43,12 @@ if not os.path.exists(LIB_PATH):
         f"{LIB_PATH} is missing: build the HIP library first "
         "(python -m paper_1805_08990_amd.build); there is no CPU fallback")
 
+# PyTorch supplies device memory and streams, so the library must run on the
+# HIP runtime torch has loaded: importing torch first makes the library's
+# libamdhip64.so.7 dependency resolve (by soname) to that same runtime instead
+# of loading a second one, which would not see the device.
+import torch  # noqa: E402,F401
+
 _lib = ctypes.CDLL(LIB_PATH)
 
 _p = ctypes.c_void_p
@@ -96,6 +102,7 @@ _lib_result_free = _sig("dme_result_free", None, [_p])
 _lib_expm = _sig("dme_expm", _int, [_p, _i64, _p, _dbl, _p, ctypes.POINTER(_int), ctypes.POINTER(_int)])
 _lib_gemm = _sig("dme_gemm_f64", _int, [_p, ctypes.c_char, ctypes.c_char, _i64, _i64, _i64, _dbl,
                                         _p, _i64, _p, _i64, _dbl, _p, _i64])
+_lib_gemm_mixed = _sig("dme_gemm_mixed", _int, [_p, _i64, _i64, _p, _p, _i64, _p, _i64])
 _lib_compress = _sig("dme_compress", _int, [_p, _i64, _i64, _p, _p, _dbl, _i64, _p, _p, ctypes.POINTER(_i64)])
 _lib_riccati = _sig("dme_riccati", _int, [_p, _i64, _i64, _i64, _p, _p, _p, _dbl, _p])
 _lib_syev = _sig("dme_syev", _int, [_p, _i64, _p, _dbl, _i64, _p, _p, ctypes.POINTER(_i64)])
@@ -263,6 +270,17 @@ class Context:
                          _ptr(As), max(1, ra), _ptr(Bs), max(1, rb), float(beta), _ptr(Cs), max(1, M)),
                "dme_gemm_f64")
         return from_cm(Cs)
+
+    def gemm_mixed(self, E, X):
+        """Y = E X with the split-BF16 product of the mixed-precision mode."""
+        Es, Xs = to_device_cm(E), to_device_cm(X)
+        n, r = Xs.shape[1], Xs.shape[0]
+        if Es.shape != (n, n):
+            raise ValueError("E must be n x n with n = rows of X")
+        Ys = zeros_cm(n, r)
+        _check(_lib_gemm_mixed(self._h, n, r, _ptr(Es), _ptr(Xs), max(1, n), _ptr(Ys), max(1, n)),
+               "dme_gemm_mixed")
+        return from_cm(Ys)
 
     def compress(self, W, Dhat, tol: float, max_rank: Optional[int] = None):
         Ws = to_device_cm(W)

@@ -309,6 +309,25 @@ int dme_gemm_f64(dme_ctx* ctx, char transa, char transb, int64_t M, int64_t N, i
   });
 }
 
+int dme_gemm_mixed(dme_ctx* ctx, int64_t n, int64_t r, const double* E, const double* X,
+                   int64_t ldx, double* Y, int64_t ldy) {
+  return guarded([&] {
+    require_ctx(ctx);
+    DME_REQUIRE(n >= 0 && r >= 0, DME_EINVAL, "gemm_mixed: negative size");
+    DME_REQUIRE(n == 0 || r == 0 || (E && X && Y), DME_EINVAL, "gemm_mixed: null pointer");
+    DME_REQUIRE(ldx >= std::max<int64_t>(1, n) && ldy >= std::max<int64_t>(1, n), DME_EINVAL,
+                "gemm_mixed: leading dimension < n");
+    DME_HIP(hipSetDevice(ctx->device));
+    if (n == 0 || r == 0) return;
+    std::shared_ptr<dme::MixedOp> op = dme::mixed_op_new();
+    dme::mixed_op_build(ctx->stream, n, E, *op);
+    ctx->ws.reserve(dme::gemm_mixed_workspace(n, r) + 4096);
+    dme::gemm_mixed(ctx->stream, *op, X, ldx, r, Y, ldy, ctx->ws);
+    // the operator copy is released when this call returns
+    DME_HIP(hipStreamSynchronize(ctx->stream));
+  });
+}
+
 int dme_compress(dme_ctx* ctx, int64_t n, int64_t k, double* W, const double* Dhat, double tol,
                  int64_t max_rank, double* L, double* D, int64_t* r_out) {
   return guarded([&] {

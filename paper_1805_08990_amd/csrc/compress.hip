@@ -6,13 +6,13 @@
 //   eigenpairs       M = V Lam V^T      (syev.hip), keep |lam| > tol max|lam|
 //   new factor       L = Q [V_I; 0],  D = diag(Lam_I)
 //
-// QR panel: one launch per column applies the previous reflector to the
-// panel rows (each thread owns one row of the panel) and writes per-block
-// partial sums of x^T x and x^T a_j for the next column; a one-block launch
-// reduces them in fixed order and forms beta, tau and w_j = tau v^T a_j.
-// The panel's reflectors are then aggregated into the compact WY form
-// I - V T V^T and applied to the trailing columns with three GEMMs; the same
-// form applies Q to [V_I; 0] at the end.
+// QR panel: one launch per column; each launch finishes the reflector of the
+// previous column from the partial sums the previous launch wrote (every
+// block reduces them in the same fixed order), applies it to the rows the
+// block owns (one thread per row) and writes the partial sums x^T x and
+// x^T a_j of the next column.  The panel's reflectors are then aggregated
+// into the compact WY form I - V T V^T and applied to the trailing columns
+// with three GEMMs; the same form applies Q to [V_I; 0] at the end.
 #include "common.h"
 
 namespace dme {
@@ -22,19 +22,64 @@ constexpr int kQB = 32;     // QR panel width
 constexpr int kQRT = 256;   // rows per block in the panel kernels
 constexpr int kQParts = kQB + 1;
 
-// Apply reflector p = c - 1 (when c > c0) to panel columns [c, c0 + pb) on the
-// rows this block owns, normalise v_p and place beta_p; then write partial
-// sums for column c over rows > c:  [x^T x, x^T a_{c+1}, ..., x^T a_{c0+pb-1}].
-__global__ __launch_bounds__(kQRT) void qr_col_kernel(double* W, int64_t ld, int64_t n, int64_t c0,
-                                                      int pb, int64_t c, int do_partials,
-                                                      const double* beta, const double* scale,
-                                                      const double* wbuf, double* part) {
+// One launch per column c of a panel [c0, c0 + pb):
+//  (1) if c > c0, every block reduces (in a fixed order) the partial sums of
+//      column p = c - 1 that the previous launch wrote, and forms beta_p, tau_p,
+//      the scale of v_p and w_j = tau_p v_p^T a_j for the panel columns j >= c;
+//      all blocks get identical values, block 0 stores beta_p, tau_p, scale_p;
+//  (2) applies reflector p to the panel rows this block owns;
+//  (3) if do_part, writes this block's partial sums over rows i > c of
+//      [x^T x, x^T a_{c+1}, ..., x^T a_{c0+pb-1}] (x = column c), and the
+//      thread owning row c writes that row's panel entries.
+// Partial sums and the row alternate between two buffers (launch c writes
+// set c & 1 and reads set (c - 1) & 1), so no launch overwrites what another
+// block of the same launch still reads.
+__global__ __launch_bounds__(kQRT) void qr_step_kernel(double* W, int64_t ld, int64_t n, int64_t c0,
+                                                       int pb, int64_t c, int do_part,
+                                                       const double* part_prev, int nparts_prev,
+                                                       const double* row_prev, double* part_cur,
+                                                       double* row_cur, double* beta, double* tau,
+                                                       double* scale) {
   __shared__ double red[kQRT / 64][kQParts];
+  __shared__ double tot[kQParts];
+  __shared__ double wcol[kQB];
+  __shared__ double bsc[3];  // beta, scale, tau of reflector c - 1
+  const int64_t cend = c0 + pb;
+  const int ncol = (int)(cend - c);  // panel columns >= c
+  if (c > c0) {
+    const int64_t p = c - 1;
+    const int ncp = ncol + 1;  // panel columns >= p
+    for (int q = threadIdx.x; q < ncp; q += kQRT) {
+      double sacc = 0.0;
+      for (int b = 0; b < nparts_prev; ++b) sacc += part_prev[(int64_t)b * kQParts + q];
+      tot[q] = sacc;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      const double alpha = row_prev[0];
+      const double sig2 = tot[0];
+      double b, t, sc;
+      if (sig2 == 0.0) {
+        b = alpha; t = 0.0; sc = 0.0;
+      } else {
+        b = -copysign(sqrt(alpha * alpha + sig2), alpha);
+        t = (b - alpha) / b;
+        sc = 1.0 / (alpha - b);
+      }
+      bsc[0] = b;
+      bsc[1] = sc;
+      if (blockIdx.x == 0) { beta[p] = b; tau[p] = t; scale[p] = sc; }
+      bsc[2] = t;
+    }
+    __syncthreads();
+    const double t = bsc[2];
+    const double sc = bsc[1];
+    for (int q = threadIdx.x; q < ncol; q += kQRT) wcol[q] = t * (row_prev[q + 1] + sc * tot[q + 1]);
+    __syncthreads();
+  }
   const int64_t rs = (c > c0) ? c - 1 : c;
   const int64_t i = rs + (int64_t)blockIdx.x * kQRT + threadIdx.x;
-  const int64_t cend = c0 + pb;
   double vals[kQB];
-  const int ncol = (int)(cend - c);  // panel columns >= c
 #pragma unroll
   for (int q = 0; q < kQB; ++q) vals[q] = 0.0;
   if (i < n) {
@@ -46,25 +91,26 @@ __global__ __launch_bounds__(kQRT) void qr_col_kernel(double* W, int64_t ld, int
       double vi;
       if (i == p) {
         vi = 1.0;
-        W[p + p * ld] = beta[p];
-      } else if (i > p) {
-        vi = scale[p] * W[i + p * ld];
-        W[i + p * ld] = vi;
+        W[p + p * ld] = bsc[0];
       } else {
-        vi = 0.0;
+        vi = bsc[1] * W[i + p * ld];
+        W[i + p * ld] = vi;
       }
-      if (i >= p) {
 #pragma unroll
-        for (int q = 0; q < kQB; ++q) {
-          if (q < ncol) {
-            vals[q] -= vi * wbuf[q + 1];  // wbuf[q'] is for column p + q'
-            W[i + (c + q) * ld] = vals[q];
-          }
+      for (int q = 0; q < kQB; ++q) {
+        if (q < ncol) {
+          vals[q] -= vi * wcol[q];
+          W[i + (c + q) * ld] = vals[q];
         }
       }
     }
   }
-  if (!do_partials) return;
+  if (!do_part) return;
+  if (i == c) {
+#pragma unroll
+    for (int q = 0; q < kQB; ++q)
+      if (q < ncol) row_cur[q] = vals[q];
+  }
   // partial sums over rows i > c
   const bool use = (i < n) && (i > c);
   const double x = use ? vals[0] : 0.0;
@@ -79,38 +125,9 @@ __global__ __launch_bounds__(kQRT) void qr_col_kernel(double* W, int64_t ld, int
   }
   __syncthreads();
   for (int q = threadIdx.x; q < ncol; q += kQRT) {
-    double s = 0.0;
-    for (int w = 0; w < kQRT / 64; ++w) s += red[w][q];
-    part[(int64_t)blockIdx.x * kQParts + q] = s;
-  }
-}
-
-// Reduce the partials of column c, form the reflector and w_j.
-__global__ void qr_final_kernel(const double* W, int64_t ld, int64_t c, int64_t cend,
-                                const double* part, int nparts, double* beta, double* tau,
-                                double* scale, double* wbuf) {
-  __shared__ double tot[kQParts];
-  const int ncol = (int)(cend - c);
-  for (int q = threadIdx.x; q < ncol; q += blockDim.x) {
-    double s = 0.0;
-    for (int b = 0; b < nparts; ++b) s += part[(int64_t)b * kQParts + q];
-    tot[q] = s;
-  }
-  __syncthreads();
-  const double alpha = W[c + c * ld];
-  const double sig2 = tot[0];
-  double b, t, sc;
-  if (sig2 == 0.0) {
-    b = alpha; t = 0.0; sc = 0.0;
-  } else {
-    b = -copysign(sqrt(alpha * alpha + sig2), alpha);
-    t = (b - alpha) / b;
-    sc = 1.0 / (alpha - b);
-  }
-  if (threadIdx.x == 0) { beta[c] = b; tau[c] = t; scale[c] = sc; wbuf[0] = 0.0; }
-  for (int q = 1 + threadIdx.x; q < ncol; q += blockDim.x) {
-    const double vta = W[c + (c + q) * ld] + sc * tot[q];
-    wbuf[q] = t * vta;
+    double sacc = 0.0;
+    for (int w = 0; w < kQRT / 64; ++w) sacc += red[w][q];
+    part_cur[(int64_t)blockIdx.x * kQParts + q] = sacc;
   }
 }
 
@@ -205,8 +222,8 @@ size_t compress_workspace(int64_t n, int64_t k) {
   add((size_t)n * k * sizeof(double));          // Vp (all panels)
   add((size_t)np * kQB * kQB * sizeof(double)); // T
   add(4 * (size_t)k * sizeof(double));          // beta, tau, scale, lam
-  add(kQB * sizeof(double));                    // wbuf
-  add((size_t)(cdiv(n, kQRT) + 2) * kQParts * sizeof(double));
+  add(2 * (size_t)(cdiv(n, kQRT) + 2) * kQParts * sizeof(double));  // partial sums (two sets)
+  add(2 * kQParts * sizeof(double));                                  // pivot rows (two sets)
   add(2 * (size_t)kQB * k * sizeof(double));    // Y, Y2
   add(4 * (size_t)k * k * sizeof(double));      // R, T1, M, S
   add((size_t)k * k * sizeof(double));          // V
@@ -234,8 +251,12 @@ int64_t compress_f64(hipStream_t s, int64_t n, int64_t k, double* W, const doubl
   double* tau = ws.get<double>(k);
   double* scale = ws.get<double>(k);
   double* lam = ws.get<double>(k);
-  double* wbuf = ws.get<double>(kQB);
-  double* part = ws.get<double>((size_t)(cdiv(n, kQRT) + 2) * kQParts);
+  double* part[2];
+  double* rowb[2];
+  for (int q = 0; q < 2; ++q) {
+    part[q] = ws.get<double>((size_t)(cdiv(n, kQRT) + 2) * kQParts);
+    rowb[q] = ws.get<double>(kQParts);
+  }
   double* Y = ws.get<double>((size_t)kQB * k);
   double* Y2 = ws.get<double>((size_t)kQB * k);
   double* R = ws.get<double>((size_t)k * k);
@@ -250,22 +271,16 @@ int64_t compress_f64(hipStream_t s, int64_t n, int64_t k, double* W, const doubl
     const int64_t c0 = p * kQB;
     const int pb = (int)std::min<int64_t>(kQB, k - c0);       // panel columns (incl. beyond kr)
     const int nv = (int)std::min<int64_t>(kQB, kr - c0);      // reflectors in this panel
-    int nparts = 0;
+    int nparts_prev = 0;
     for (int64_t c = c0; c <= c0 + nv; ++c) {
       const int do_part = (c < c0 + nv) ? 1 : 0;
       const int64_t rs = (c > c0) ? c - 1 : c;
       const int nb = (int)cdiv(n - rs, kQRT);
-      if (do_part || c > c0) {
-        hipLaunchKernelGGL(qr_col_kernel, dim3(nb), dim3(kQRT), 0, s, W, ld, n, c0, pb, c, do_part,
-                           beta, scale, wbuf, part);
-        DME_HIP(hipGetLastError());
-      }
-      nparts = nb;
-      if (do_part) {
-        hipLaunchKernelGGL(qr_final_kernel, dim3(1), dim3(64), 0, s, W, ld, c, c0 + pb, part,
-                           nparts, beta, tau, scale, wbuf);
-        DME_HIP(hipGetLastError());
-      }
+      const int cur = (int)(c & 1), prev = cur ^ 1;
+      hipLaunchKernelGGL(qr_step_kernel, dim3(nb), dim3(kQRT), 0, s, W, ld, n, c0, pb, c, do_part,
+                         part[prev], nparts_prev, rowb[prev], part[cur], rowb[cur], beta, tau, scale);
+      DME_HIP(hipGetLastError());
+      nparts_prev = nb;
     }
     // compact WY of this panel
     double* Vpp = Vp + c0 * n;  // panel p's V, rows [0, n - c0), ld n

@@ -35,7 +35,15 @@ struct QuadFactor {
   int64_t r = 0;
 };
 
-struct MixedOp;  // split-BF16 copy of an operator (gemm_mixed.hip)
+struct MixedOp;  // FP32 copy of an operator for the split-BF16 product (gemm_mixed.hip)
+// Build the FP32 row-major copy of E (n x n, FP64 column-major).
+void mixed_op_build(hipStream_t s, int64_t n, const double* E, MixedOp& op);
+std::shared_ptr<MixedOp> mixed_op_new();
+// Y (n x r, ld ldy) = E X on BF16 MFMA with three-piece splits, FP32 chunk
+// accumulation and an FP64 sum over chunks.
+void gemm_mixed(hipStream_t s, const MixedOp& op, const double* X, int64_t ldx, int64_t r, double* Y,
+                int64_t ldy, Arena& ws);
+size_t gemm_mixed_workspace(int64_t n, int64_t r);
 
 struct PhaseAcc {
   int64_t count = 0;

@@ -186,6 +186,8 @@ void Solver::setup(const dme_problem& prob, const dme_opts& o, bool dre) {
   opts = o;
   if (opts.quad_nodes <= 0) opts.quad_nodes = 7;
   DME_REQUIRE(opts.quad_nodes <= 64, DME_EINVAL, "quad_nodes must be <= 64");
+  DME_REQUIRE(opts.precision == DME_FP64 || opts.precision == DME_MIXED, DME_EINVAL,
+              "unknown precision");
   const double Nf = std::round(o.T / o.h);
   DME_REQUIRE(Nf >= 1 && std::fabs(Nf * o.h - o.T) <= 1e-12 * o.T, DME_EINVAL, "T/h is not an integer");
   N = (int64_t)Nf;
@@ -250,6 +252,7 @@ void Solver::setup(const dme_problem& prob, const dme_opts& o, bool dre) {
   size_t wsb = compress_workspace(n, kmax);
   wsb += gemm_f64_workspace(max_rank, std::max<int64_t>(m, 1), n) + 4096;
   wsb += gemm_f64_workspace(n, max_rank, n) + 4096;
+  if (opts.precision == DME_MIXED) wsb += gemm_mixed_workspace(n, max_rank) + 4096;
   wsb += (size_t)max_rank * (max_rank + 64) * sizeof(double) + 4096;  // riccati scratch
   ws.reserve(wsb);
 
@@ -285,6 +288,11 @@ void Solver::build_operator(double t) {
   Arena ews;
   ews.reserve(expm_workspace(n));
   expm_f64(s, n, AT.as<double>(), t, Et.as<double>(), ews, nullptr, nullptr, flag_dev() + 1);
+  if (opts.precision == DME_MIXED) {
+    std::shared_ptr<MixedOp> op = mixed_op_new();
+    mixed_op_build(s, n, Et.as<double>(), *op);
+    Emix[t] = op;
+  }
   DME_HIP(hipStreamSynchronize(s));
 }
 
@@ -323,9 +331,15 @@ void Solver::build_quadrature(double t) {
 void Solver::apply_E(double t, const double* X, int64_t rr, double* Y, int64_t ldy) {
   ws.reset();
   hipEvent_t ev = mark_begin();
-  gemm_f64(s, 'N', 'N', n, rr, n, 1.0, E.at(t).as<double>(), n, X, n, 0.0, Y, ldy, &ws);
-  // algorithmic work of Y = E X: 2 n^2 r flops; E read once, X read, Y written
-  mark_end(0, ev, 2.0 * n * n * rr, 8.0 * ((double)n * n + 2.0 * n * rr));
+  if (opts.precision == DME_MIXED) {
+    gemm_mixed(s, *Emix.at(t), X, n, rr, Y, ldy, ws);
+    // algorithmic work of Y = E X: 2 n^2 r flops; the FP32 operator read once
+    mark_end(0, ev, 2.0 * n * n * rr, 4.0 * (double)n * n + 16.0 * n * rr);
+  } else {
+    gemm_f64(s, 'N', 'N', n, rr, n, 1.0, E.at(t).as<double>(), n, X, n, 0.0, Y, ldy, &ws);
+    // algorithmic work of Y = E X: 2 n^2 r flops; E read once, X read, Y written
+    mark_end(0, ev, 2.0 * n * n * rr, 8.0 * ((double)n * n + 2.0 * n * rr));
+  }
 }
 
 void Solver::compress_into(int64_t k) {

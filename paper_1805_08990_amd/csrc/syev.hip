@@ -56,13 +56,15 @@ __global__ __launch_bounds__(kTriT) void tridiag_kernel(double* A, int64_t lda, 
   for (int j = 0; j + 2 < k; ++j) {
     const int r0 = j + 1;  // first row of x
     // sigma^2 = sum_{i >= j+2} A(i, j)^2
+    // alpha is read before the reduction's barriers: thread 0 overwrites
+    // A(r0, j) with beta below, after every wave has passed them.
+    const double alpha = A[r0 + (int64_t)j * lda];
     double part = 0.0;
     for (int i = j + 2 + t; i < k; i += kTriT) {
       const double a = A[i + (int64_t)j * lda];
       part += a * a;
     }
     const double sig2 = block_sum_1024(part, red);
-    const double alpha = A[r0 + (int64_t)j * lda];
     if (sig2 == 0.0) {
       if (t == 0) { tau[j] = 0.0; e[j] = alpha; d[j] = A[j + (int64_t)j * lda]; }
       __syncthreads();

@@ -159,3 +159,30 @@ def test_riccati_matches_oracle(ctx, n, r, m):
     got = to_np(ctx.riccati(L, B, R, t, D))
     ref = oracle.t3(L, D, B, R, t)
     assert rel_fro(got, ref) < 1e-12
+
+
+@pytest.mark.parametrize("n,r", [(1, 1), (31, 7), (257, 16), (1000, 150), (2304, 33), (1296, 300)])
+def test_gemm_mixed(ctx, n, r):
+    """Split-BF16 product: error bounded by the FP32 representation of E and X
+    plus FP32 chunk accumulation, elementwise against |E||X|."""
+    announce("gemm_mixed", n, r)
+    rng = np.random.default_rng(n + r)
+    E = rng.standard_normal((n, n)) / np.sqrt(n)
+    X = rng.standard_normal((n, r))
+    got = to_np(ctx.gemm_mixed(E, X))
+    ref = E @ X
+    scale = np.abs(E) @ np.abs(X)
+    assert np.all(np.abs(got - ref) <= 1e-5 * scale + 1e-300)
+    assert rel_fro(got, ref) < 1e-6
+
+
+def test_gemm_mixed_heat_operator(ctx):
+    """On the heat semigroup of the 2-D Laplacian (the operator the mixed mode
+    applies) the relative error of E L stays near FP32 resolution."""
+    announce("gemm_mixed heat")
+    A = wl.laplacian_2d(24)
+    E = oracle.expm(5e-4 * A.T)
+    rng = np.random.default_rng(3)
+    X, _ = np.linalg.qr(rng.standard_normal((A.shape[0], 40)))
+    got = to_np(ctx.gemm_mixed(E, X))
+    assert rel_fro(got, E @ X) < 2e-7
