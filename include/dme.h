@@ -194,6 +194,59 @@ int dme_riccati(dme_ctx *ctx, int64_t n, int64_t r, int64_t m, const double *L, 
 int dme_syev(dme_ctx *ctx, int64_t k, const double *M, double tol, int64_t max_keep, double *lam,
              double *V, int64_t *keep_out);
 
+/* ------------------------------------------------------------- serving */
+/* A request server on a context: solves submitted as they arrive run with
+ * continuous batching.  A scheduler thread admits waiting requests in
+ * arrival order whenever a slot is free and the device-memory ledger
+ * (cached operators + per-solve state) stays within the budget, advances all
+ * admitted solves one time step per tick (solves that share an operator
+ * e^{tA^T} get one product over their concatenated factors; compressions and
+ * Riccati updates of different solves overlap on their own streams), and
+ * retires finished solves.  A solve's result is the same alone and in any mix.
+ * Mixed-precision requests are re-run from the start in FP64 when a numerical
+ * guard trips (non-finite values, rank cap).                                */
+typedef struct dme_server dme_server;
+
+typedef struct {
+  int64_t completed, failed, fallbacks; /* requests                            */
+  int64_t steps;                        /* time steps advanced, all requests    */
+  int64_t cold_builds;                  /* operator sets built on demand        */
+  int64_t in_flight;                    /* submitted, not finished              */
+  int64_t peak_bytes;                   /* high-water mark of the ledger        */
+  double p50_s, p99_s;                  /* arrival-to-completion latency        */
+  double queue_p50_s, queue_p99_s;      /* arrival-to-admission                 */
+  double req_per_s, steps_per_s;        /* over first arrival .. last completion */
+  double cold_build_s;                  /* time in on-demand operator builds    */
+} dme_server_stats;
+
+/* Register an operator A (host, n x n, the A of the Sec. 1 equation) on the
+ * context: it is copied to the device once and named by *op_id in later
+ * submissions.  The registration lives as long as the context.             */
+int dme_register_operator(dme_ctx *ctx, const double *A, int64_t n, uint64_t *op_id);
+/* Start a server on ctx with a device-memory budget (bytes) for cached
+ * operators and solve state, and at most max_slots solves admitted at once. */
+int dme_server_start(dme_ctx *ctx, size_t hbm_budget_bytes, int max_slots, dme_server **srv);
+/* Build and cache the operator set of op_id for step fraction t (e^{tA^T},
+ * its FP32 copy in DME_MIXED, and the quad_nodes Gauss-Legendre node
+ * exponentials on [0, t]).  Call before submitting requests.              */
+int dme_server_warm(dme_server *srv, uint64_t op_id, double t, int precision, int quad_nodes);
+/* Submit a solve (prob.A is ignored: the operator is op_id; all host arrays
+ * are copied before return).  is_dre as in dme_solver_create.             */
+int dme_submit(dme_server *srv, uint64_t op_id, const dme_problem *prob, const dme_opts *opts,
+               int is_dre, uint64_t *ticket);
+/* DME_OK and *out (owned by the caller, free with dme_result_free) when the
+ * request finished, DME_EAGAIN while it is in flight, the request's error
+ * code if it failed.  A ticket can be collected once.                      */
+int dme_poll(dme_server *srv, uint64_t ticket, dme_result **out);
+int dme_server_stats_get(dme_server *srv, dme_server_stats *out);
+/* Finish every submitted request, stop the scheduler, free the server and
+ * results that were never collected.                                        */
+int dme_server_stop(dme_server *srv);
+/* Serving details of a result: precision used (dme_precision), whether it
+ * fell back to FP64, latency and queueing time in seconds.                 */
+int dme_result_serving(const dme_result *res, int *precision, int *fell_back, double *latency_s,
+                       double *queue_s);
+
 #ifdef __cplusplus
 }
 #endif

@@ -107,6 +107,26 @@ _lib_compress = _sig("dme_compress", _int, [_p, _i64, _i64, _p, _p, _dbl, _i64, 
 _lib_riccati = _sig("dme_riccati", _int, [_p, _i64, _i64, _i64, _p, _p, _p, _dbl, _p])
 _lib_syev = _sig("dme_syev", _int, [_p, _i64, _p, _dbl, _i64, _p, _p, ctypes.POINTER(_i64)])
 
+_lib_register = _sig("dme_register_operator", _int, [_p, _p, _i64, ctypes.POINTER(ctypes.c_uint64)])
+_lib_server_start = _sig("dme_server_start", _int, [_p, ctypes.c_size_t, _int, ctypes.POINTER(_p)])
+_lib_server_warm = _sig("dme_server_warm", _int, [_p, ctypes.c_uint64, _dbl, _int, _int])
+_lib_submit = _sig("dme_submit", _int, [_p, ctypes.c_uint64, ctypes.POINTER(Problem), ctypes.POINTER(Opts),
+                                        _int, ctypes.POINTER(ctypes.c_uint64)])
+_lib_poll = _sig("dme_poll", _int, [_p, ctypes.c_uint64, ctypes.POINTER(_p)])
+_lib_server_stop = _sig("dme_server_stop", _int, [_p])
+_lib_result_serving = _sig("dme_result_serving", _int, [_p, ctypes.POINTER(_int), ctypes.POINTER(_int),
+                                                        ctypes.POINTER(_dbl), ctypes.POINTER(_dbl)])
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [("completed", _i64), ("failed", _i64), ("fallbacks", _i64), ("steps", _i64),
+                ("cold_builds", _i64), ("in_flight", _i64), ("peak_bytes", _i64),
+                ("p50_s", _dbl), ("p99_s", _dbl), ("queue_p50_s", _dbl), ("queue_p99_s", _dbl),
+                ("req_per_s", _dbl), ("steps_per_s", _dbl), ("cold_build_s", _dbl)]
+
+
+_lib_server_stats = _sig("dme_server_stats_get", _int, [_p, ctypes.POINTER(ServerStats)])
+
 
 class DmeError(RuntimeError):
     def __init__(self, code: int, where: str):
@@ -181,15 +201,15 @@ class SolveOptions:
 class _HostProblem:
     """Keeps Fortran-ordered host copies alive for the duration of a call."""
 
-    def __init__(self, A, C, B=None, R=None, S=None, L0=None, D0=None):
-        self.A = _host_f(A)
+    def __init__(self, A, C, B=None, R=None, S=None, L0=None, D0=None, n=None):
+        self.A = _host_f(A) if n is None else None
         self.C = _host_f(C)
         self.B = _host_f(B)
         self.R = _host_f(R)
         self.S = _host_f(S)
         self.L0 = _host_f(L0)
         self.D0 = _host_f(D0)
-        n = self.A.shape[0]
+        n = self.A.shape[0] if n is None else int(n)
         p = self.C.shape[0]
         m = 0 if self.B is None else self.B.shape[1]
         r0 = 0 if self.L0 is None else self.L0.shape[1]
@@ -318,6 +338,17 @@ class Context:
         kk = int(keep.value)
         return lam[:k], from_cm(Vs)[:k, :kk], kk
 
+    def register_operator(self, A) -> int:
+        """Copy the operator A (n x n) to the device once; returns its id."""
+        Ah = _host_f(A)
+        op = ctypes.c_uint64()
+        _check(_lib_register(self._h, Ah.ctypes.data, Ah.shape[0], ctypes.byref(op)),
+               "dme_register_operator")
+        return int(op.value)
+
+    def server(self, hbm_budget_bytes: int, max_slots: int = 16) -> "Server":
+        return Server(self, hbm_budget_bytes, max_slots)
+
     # ------------------------------------------------ whole solves
     def solve(self, kind: str, opts: SolveOptions, A, C, B=None, R=None, S=None, L0=None, D0=None):
         hp = _HostProblem(A, C, B, R, S, L0, D0)
@@ -380,3 +411,63 @@ class Solver:
 
     def __del__(self):
         self.close()
+
+
+class Server:
+    """Continuous-batching request server on a context (dme_server_*)."""
+
+    def __init__(self, ctx: Context, hbm_budget_bytes: int, max_slots: int = 16):
+        self.ctx = ctx
+        h = _p()
+        _check(_lib_server_start(ctx._h, int(hbm_budget_bytes), int(max_slots), ctypes.byref(h)),
+               "dme_server_start")
+        self._h = h
+        self._keep = {}
+
+    def register_operator(self, A) -> int:
+        return self.ctx.register_operator(A)
+
+    def warm(self, op_id: int, t: float, precision: str = "mixed", quad_nodes: int = 7):
+        _check(_lib_server_warm(self._h, int(op_id), float(t), PRECISIONS[precision], int(quad_nodes)),
+               "dme_server_warm")
+
+    def submit(self, op_id: int, kind: str, opts: SolveOptions, C, n: int, B=None, R=None, S=None,
+               L0=None, D0=None) -> int:
+        hp = _HostProblem(np.zeros((n, 0)), C, B, R, S, L0, D0, n=n)
+        o = opts.to_c()
+        t = ctypes.c_uint64()
+        _check(_lib_submit(self._h, int(op_id), ctypes.byref(hp.c), ctypes.byref(o),
+                           1 if kind == "dre" else 0, ctypes.byref(t)), "dme_submit")
+        return int(t.value)
+
+    def poll(self, ticket: int):
+        """None while in flight, else (L, D, steps, info dict); raises on failure."""
+        out = _p()
+        code = _lib_poll(self._h, int(ticket), ctypes.byref(out))
+        if code == DME_EAGAIN:
+            return None
+        _check(code, "dme_poll")
+        res = Result(out)
+        prec, fb, lat, qs = _int(), _int(), _dbl(), _dbl()
+        _check(_lib_result_serving(out, ctypes.byref(prec), ctypes.byref(fb), ctypes.byref(lat),
+                                   ctypes.byref(qs)), "dme_result_serving")
+        L, D, steps = res.fetch()
+        info = {"precision": "mixed" if prec.value == DME_MIXED else "fp64", "fell_back": bool(fb.value),
+                "latency_s": lat.value, "queue_s": qs.value}
+        return L, D, steps, info
+
+    def stats(self) -> dict:
+        st = ServerStats()
+        _check(_lib_server_stats(self._h, ctypes.byref(st)), "dme_server_stats_get")
+        return {f: getattr(st, f) for f, _ in ServerStats._fields_}
+
+    def stop(self):
+        if getattr(self, "_h", None):
+            _check(_lib_server_stop(self._h), "dme_server_stop")
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.stop()
+        except Exception:
+            pass

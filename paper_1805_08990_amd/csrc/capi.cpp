@@ -3,7 +3,7 @@
 #include <memory>
 #include <new>
 
-#include "solver.h"
+#include "ctx.h"
 
 namespace dme {
 
@@ -29,20 +29,26 @@ void DevBuf::release() {
   bytes = 0;
 }
 
+dme_result* result_from_solver(Solver& sv) {
+  auto res = std::make_unique<dme_result>();
+  res->n = sv.n;
+  res->r = sv.r;
+  res->steps = sv.step;
+  res->precision = sv.opts.precision;
+  res->L.resize((size_t)sv.n * sv.r);
+  res->D.resize((size_t)sv.r * sv.r);
+  if (sv.r > 0) {
+    DME_HIP(hipMemcpyAsync(res->L.data(), sv.Lc(), res->L.size() * sizeof(double),
+                           hipMemcpyDeviceToHost, sv.s));
+    DME_HIP(hipMemcpyAsync(res->D.data(), sv.Dc(), res->D.size() * sizeof(double),
+                           hipMemcpyDeviceToHost, sv.s));
+  }
+  DME_HIP(hipStreamSynchronize(sv.s));
+  return res.release();
+}
+
 }  // namespace dme
 
-struct dme_ctx {
-  int device = 0;
-  hipStream_t stream = nullptr;
-  bool own_stream = false;
-  dme::Arena ws;
-  dme::DevBuf flags;
-};
-
-struct dme_result {
-  int64_t n = 0, r = 0, steps = 0;
-  std::vector<double> L, D;
-};
 
 struct dme_solver {
   dme_ctx* ctx = nullptr;
@@ -83,22 +89,7 @@ void ctx_read_flags(dme_ctx* c, int* h) {
 
 void require_ctx(dme_ctx* c) { DME_REQUIRE(c != nullptr, DME_EINVAL, "null context"); }
 
-void make_result(dme::Solver& sv, dme_result** out) {
-  auto res = std::make_unique<dme_result>();
-  res->n = sv.n;
-  res->r = sv.r;
-  res->steps = sv.step;
-  res->L.resize((size_t)sv.n * sv.r);
-  res->D.resize((size_t)sv.r * sv.r);
-  if (sv.r > 0) {
-    DME_HIP(hipMemcpyAsync(res->L.data(), sv.Lc(), res->L.size() * sizeof(double),
-                           hipMemcpyDeviceToHost, sv.s));
-    DME_HIP(hipMemcpyAsync(res->D.data(), sv.Dc(), res->D.size() * sizeof(double),
-                           hipMemcpyDeviceToHost, sv.s));
-  }
-  DME_HIP(hipStreamSynchronize(sv.s));
-  *out = res.release();
-}
+void make_result(dme::Solver& sv, dme_result** out) { *out = dme::result_from_solver(sv); }
 
 int solve_impl(dme_ctx* ctx, const dme_problem* prob, const dme_opts* opts, int is_dre,
                dme_result** out) {
@@ -389,6 +380,83 @@ int dme_syev(dme_ctx* ctx, int64_t k, const double* M, double tol, int64_t max_k
       DME_HIP(hipStreamSynchronize(ctx->stream));
     }
     if (keep_out) *keep_out = keep;
+  });
+}
+
+int dme_register_operator(dme_ctx* ctx, const double* A, int64_t n, uint64_t* op_id) {
+  return guarded([&] {
+    require_ctx(ctx);
+    DME_REQUIRE(A != nullptr && n > 0 && op_id != nullptr, DME_EINVAL, "bad operator arguments");
+    DME_HIP(hipSetDevice(ctx->device));
+    auto op = std::make_shared<dme::RegisteredOp>();
+    op->n = n;
+    dme::DevBuf tmp((size_t)n * n * sizeof(double));
+    DME_HIP(hipMemcpyAsync(tmp.p, A, (size_t)n * n * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
+    op->AT.ensure((size_t)n * n * sizeof(double));
+    dme::transpose_f64(ctx->stream, tmp.as<double>(), n, op->AT.as<double>(), n, n, n, 1.0);
+    DME_HIP(hipStreamSynchronize(ctx->stream));
+    std::lock_guard<std::mutex> g(ctx->ops_mu);
+    op->id = ctx->next_op++;
+    ctx->ops[op->id] = op;
+    *op_id = op->id;
+  });
+}
+
+int dme_server_start(dme_ctx* ctx, size_t hbm_budget_bytes, int max_slots, dme_server** srv) {
+  return guarded([&] {
+    DME_REQUIRE(srv != nullptr, DME_EINVAL, "null server pointer");
+    *srv = nullptr;
+    *srv = dme::server_start(ctx, hbm_budget_bytes, max_slots);
+  });
+}
+
+int dme_server_warm(dme_server* srv, uint64_t op_id, double t, int precision, int quad_nodes) {
+  return guarded([&] {
+    DME_REQUIRE(std::isfinite(t) && t > 0, DME_EINVAL, "t must be positive");
+    dme::server_warm(srv, op_id, t, precision, quad_nodes);
+  });
+}
+
+int dme_submit(dme_server* srv, uint64_t op_id, const dme_problem* prob, const dme_opts* opts,
+               int is_dre, uint64_t* ticket) {
+  return guarded([&] {
+    DME_REQUIRE(prob && opts && ticket, DME_EINVAL, "null argument");
+    *ticket = dme::server_submit(srv, op_id, *prob, *opts, is_dre);
+  });
+}
+
+int dme_poll(dme_server* srv, uint64_t ticket, dme_result** out) {
+  int code = DME_OK;
+  std::string msg;
+  const int rc = guarded([&] {
+    DME_REQUIRE(out != nullptr, DME_EINVAL, "null result pointer");
+    *out = nullptr;
+    code = dme::server_poll(srv, ticket, out, &msg);
+  });
+  if (rc != DME_OK) return rc;
+  if (code != DME_OK && code != DME_EAGAIN) dme::g_last_error = msg;
+  return code;
+}
+
+int dme_server_stats_get(dme_server* srv, dme_server_stats* out) {
+  return guarded([&] { dme::server_stats(srv, out); });
+}
+
+int dme_server_stop(dme_server* srv) {
+  return guarded([&] {
+    DME_REQUIRE(srv != nullptr, DME_EINVAL, "null server");
+    dme::server_stop(srv);
+  });
+}
+
+int dme_result_serving(const dme_result* res, int* precision, int* fell_back, double* latency_s,
+                       double* queue_s) {
+  return guarded([&] {
+    DME_REQUIRE(res != nullptr, DME_EINVAL, "null result");
+    if (precision) *precision = res->precision;
+    if (fell_back) *fell_back = res->fell_back;
+    if (latency_s) *latency_s = res->latency_s;
+    if (queue_s) *queue_s = res->queue_s;
   });
 }
 

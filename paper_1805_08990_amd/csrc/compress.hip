@@ -40,7 +40,9 @@ __global__ __launch_bounds__(kQRT) void qr_step_kernel(double* W, int64_t ld, in
                                                        const double* row_prev, double* part_cur,
                                                        double* row_cur, double* beta, double* tau,
                                                        double* scale) {
+  constexpr int kGroups = kQRT / kQB;  // partial-sum groups of the prologue reduction
   __shared__ double red[kQRT / 64][kQParts];
+  __shared__ double sred[kGroups][kQB];
   __shared__ double tot[kQParts];
   __shared__ double wcol[kQB];
   __shared__ double bsc[3];  // beta, scale, tau of reflector c - 1
@@ -48,11 +50,29 @@ __global__ __launch_bounds__(kQRT) void qr_step_kernel(double* W, int64_t ld, in
   const int ncol = (int)(cend - c);  // panel columns >= c
   if (c > c0) {
     const int64_t p = c - 1;
-    const int ncp = ncol + 1;  // panel columns >= p
-    for (int q = threadIdx.x; q < ncp; q += kQRT) {
+    const int ncp = ncol + 1;  // panel columns >= p (at most kQB here)
+    {
+      // thread (g, q) sums the partials b = g, g + kGroups, ... of entry q
+      // (independent loads, unrolled), then entry q adds the groups in order
+      const int q = threadIdx.x % kQB, g = threadIdx.x / kQB;
+      double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+      if (q < ncp) {
+        int b = g;
+        for (; b + 3 * kGroups < nparts_prev; b += 4 * kGroups) {
+          a0 += part_prev[(int64_t)b * kQParts + q];
+          a1 += part_prev[(int64_t)(b + kGroups) * kQParts + q];
+          a2 += part_prev[(int64_t)(b + 2 * kGroups) * kQParts + q];
+          a3 += part_prev[(int64_t)(b + 3 * kGroups) * kQParts + q];
+        }
+        for (; b < nparts_prev; b += kGroups) a0 += part_prev[(int64_t)b * kQParts + q];
+      }
+      sred[g][q] = (a0 + a1) + (a2 + a3);
+    }
+    __syncthreads();
+    if (threadIdx.x < ncp) {
       double sacc = 0.0;
-      for (int b = 0; b < nparts_prev; ++b) sacc += part_prev[(int64_t)b * kQParts + q];
-      tot[q] = sacc;
+      for (int g = 0; g < kGroups; ++g) sacc += sred[g][threadIdx.x];
+      tot[threadIdx.x] = sacc;
     }
     __syncthreads();
     if (threadIdx.x == 0) {

@@ -121,7 +121,9 @@ __global__ __launch_bounds__(kThreads) void gemm_f64_kernel(
     }
   }
 
-  // Epilogue: lane holds C(m = base_m + r16, n = base_n + 4*kq + v).
+  // Epilogue.  The FP64 16x16x4 MFMA leaves element v of lane l at row
+  // 4 v + l / 16, column l % 16 of its 16 x 16 result (rows of the result are
+  // columns of C here): lane holds C(m = base_m + r16, n = base_n + 4*v + kq).
 #pragma unroll
   for (int i = 0; i < TM; ++i) {
     const int m = m0 + wm * WTM + i * 16 + r16;
@@ -129,7 +131,7 @@ __global__ __launch_bounds__(kThreads) void gemm_f64_kernel(
     for (int j = 0; j < TN; ++j) {
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int n = n0 + wn * WTN + j * 16 + kq * 4 + v;
+        const int n = n0 + wn * WTN + j * 16 + v * 4 + kq;
         if (m < M && n < N) {
           if (partial) {
             partial[(int64_t)blockIdx.z * M * N + m + (int64_t)n * M] = acc[i][j][v];
@@ -185,6 +187,180 @@ void dispatch_trans(hipStream_t s, char ta, char tb, int M, int N, int K, int ns
     launch_tile<BM, BN, BK, true, true>(s, M, N, K, nsplit, kchunk, alpha, A, lda, B, ldb, beta, C, ldc, partial);
 }
 
+// Skinny product Y = E X for a tall square operator E (M x K, M, K large)
+// and a narrow X (K x N, N <= 256): the step product e^{tA^T} L.  A 256-thread
+// workgroup owns 64 rows of Y and every column (TN 16-column tiles); wave w
+// owns rows w*16 .. w*16+15, so each entry of E is read from HBM by exactly one
+// wave, straight into registers (a lane reads 16 consecutive rows of one
+// column per load).  The X slab of a K step (16 x 16 TN) is staged in LDS,
+// double-buffered, and shared by the four waves.  K is split into nsplit
+// chunks and workgroup b takes chunk b % nsplit: with nsplit = 8 each chunk
+// (and its slice of X, K/8 x N doubles) belongs to one XCD and its L2.  Every
+// column's arithmetic is the same whatever N is, so batching columns of
+// several problems does not change any result.
+constexpr int kSkBK = 16;
+constexpr int kSkRows = 64;
+
+template <int TN>
+__global__ __launch_bounds__(kThreads) void gemm_f64_skinny_kernel(
+    int M, int N, int K, int nsplit, int kchunk, const double* __restrict__ A, int64_t lda,
+    const double* __restrict__ B, int64_t ldb, double* __restrict__ partial) {
+  constexpr int NC = TN * 16;
+  constexpr int LB = (kSkBK * NC + kThreads - 1) / kThreads;  // X entries per thread per slab
+  __shared__ double sB[2][kSkBK][NC + 8];
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int split = blockIdx.x % nsplit;
+  const int rb = blockIdx.x / nsplit;
+  const int kbeg = split * kchunk;
+  const int kend = min(K, kbeg + kchunk);
+  const int r16 = lane & 15;
+  const int kq = lane >> 4;
+  const int row = rb * kSkRows + wave * 16 + r16;
+  const bool row_ok = row < M;
+
+  v4d acc[TN];
+#pragma unroll
+  for (int j = 0; j < TN; ++j) acc[j] = v4d{0.0, 0.0, 0.0, 0.0};
+
+  double ra[4], rb_[LB];
+  auto load_a = [&](int k0, double (&dst)[4]) {
+#pragma unroll
+    for (int s4 = 0; s4 < 4; ++s4) {
+      const int k = k0 + s4 * 4 + kq;
+      dst[s4] = (row_ok && k < kend) ? A[row + (int64_t)k * lda] : 0.0;
+    }
+  };
+  auto load_b = [&](int k0) {
+#pragma unroll
+    for (int i = 0; i < LB; ++i) {
+      const int idx = tid + i * kThreads;
+      const int kl = idx % kSkBK, c = idx / kSkBK;
+      const int k = k0 + kl;
+      rb_[i] = (c < N && k < kend && idx < kSkBK * NC) ? B[k + (int64_t)c * ldb] : 0.0;
+    }
+  };
+  auto store_b = [&](int buf) {
+#pragma unroll
+    for (int i = 0; i < LB; ++i) {
+      const int idx = tid + i * kThreads;
+      if (idx < kSkBK * NC) {
+        const int kl = idx % kSkBK, c = idx / kSkBK;
+        sB[buf][kl][c] = rb_[i];
+      }
+    }
+  };
+
+  if (kbeg < kend) {
+    load_b(kbeg);
+    store_b(0);
+    load_a(kbeg, ra);
+  }
+  __syncthreads();
+  int buf = 0;
+  for (int k0 = kbeg; k0 < kend; k0 += kSkBK) {
+    const bool more = (k0 + kSkBK) < kend;
+    double an[4];
+    if (more) {
+      load_b(k0 + kSkBK);
+      load_a(k0 + kSkBK, an);
+    }
+#pragma unroll
+    for (int s4 = 0; s4 < 4; ++s4) {
+#pragma unroll
+      for (int j = 0; j < TN; ++j) {
+        const double bv = sB[buf][s4 * 4 + kq][j * 16 + r16];
+        acc[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ra[s4], bv, acc[j], 0, 0, 0);
+      }
+    }
+    if (more) {
+      store_b(buf ^ 1);
+#pragma unroll
+      for (int s4 = 0; s4 < 4; ++s4) ra[s4] = an[s4];
+    }
+    __syncthreads();
+    buf ^= 1;
+  }
+
+  // element v of lane l holds row 4 v + l / 16 (of the wave's 16) of column
+  // l % 16 of each tile (FP64 16x16x4 MFMA result layout)
+  const int rowb = rb * kSkRows + wave * 16 + kq;
+#pragma unroll
+  for (int j = 0; j < TN; ++j) {
+    const int col = j * 16 + r16;
+    if (col < N) {
+      double* dst = partial + ((int64_t)split * N + col) * M;
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+        if (rowb + 4 * v < M) dst[rowb + 4 * v] = acc[j][v];
+    }
+  }
+}
+
+// C(i, j) = alpha * sum_z partial[z][j][i] + beta * C(i, j), FP64, fixed order.
+__global__ void skinny_reduce_kernel(int M, int N, int nsplit, double alpha,
+                                     const double* __restrict__ partial, double beta,
+                                     double* __restrict__ C, int64_t ldc) {
+  const int64_t total = (int64_t)M * N;
+  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    double s = 0.0;
+    for (int z = 0; z < nsplit; ++z) s += partial[(int64_t)z * total + idx];
+    const int64_t m = idx % M, n = idx / M;
+    double* c = C + m + n * ldc;
+    const double out = alpha * s;
+    *c = (beta == 0.0) ? out : out + beta * (*c);
+  }
+}
+
+constexpr int kSkMaxN = 256;
+
+bool use_skinny(char ta, char tb, int64_t M, int64_t N, int64_t K) {
+  return ta == 'N' && tb == 'N' && M >= 1024 && K >= 1024 && N >= 1 && N <= kSkMaxN;
+}
+
+int skinny_nsplit(int64_t M, int64_t K) {
+  const int64_t rowblocks = cdiv(M, kSkRows);
+  int64_t ns = 8;
+  while (rowblocks * ns < 1024 && K / (ns * 2) >= 256) ns *= 2;
+  while (ns > 1 && K / ns < kSkBK) ns /= 2;
+  return (int)ns;
+}
+
+template <int TN>
+void launch_skinny(hipStream_t s, int M, int N, int K, int ns, int kchunk, const double* A,
+                   int64_t lda, const double* B, int64_t ldb, double* partial) {
+  const int64_t rowblocks = cdiv(M, kSkRows);
+  hipLaunchKernelGGL((gemm_f64_skinny_kernel<TN>), dim3((unsigned)(rowblocks * ns)), dim3(kThreads),
+                     0, s, M, N, K, ns, kchunk, A, lda, B, ldb, partial);
+}
+
+void gemm_f64_skinny(hipStream_t s, int M, int N, int K, double alpha, const double* A, int64_t lda,
+                     const double* B, int64_t ldb, double beta, double* C, int64_t ldc,
+                     double* partial) {
+  const int ns = skinny_nsplit(M, K);
+  const int kchunk = (int)(cdiv(cdiv(K, ns), kSkBK) * kSkBK);
+  const int tn = (int)cdiv(N, 16);
+  switch (tn) {
+#define DME_SKINNY_CASE(T) \
+  case T: launch_skinny<T>(s, M, N, K, ns, kchunk, A, lda, B, ldb, partial); break;
+    DME_SKINNY_CASE(1) DME_SKINNY_CASE(2) DME_SKINNY_CASE(3) DME_SKINNY_CASE(4)
+    DME_SKINNY_CASE(5) DME_SKINNY_CASE(6) DME_SKINNY_CASE(7) DME_SKINNY_CASE(8)
+    DME_SKINNY_CASE(9) DME_SKINNY_CASE(10) DME_SKINNY_CASE(11) DME_SKINNY_CASE(12)
+    DME_SKINNY_CASE(13) DME_SKINNY_CASE(14) DME_SKINNY_CASE(15) DME_SKINNY_CASE(16)
+#undef DME_SKINNY_CASE
+    default: fail(DME_EINTERNAL, "skinny gemm: bad tile count");
+  }
+  DME_HIP(hipGetLastError());
+  const int64_t total = (int64_t)M * N;
+  const int blocks = (int)std::min<int64_t>(cdiv(total, 256), 8192);
+  hipLaunchKernelGGL(skinny_reduce_kernel, dim3(blocks), dim3(256), 0, s, M, N, ns, alpha, partial,
+                     beta, C, ldc);
+  DME_HIP(hipGetLastError());
+}
+
 struct Plan {
   int bm, bn, nsplit, kchunk;
 };
@@ -214,7 +390,19 @@ Plan plan_for(int64_t M, int64_t N, int64_t K) {
 
 }  // namespace
 
+size_t gemm_f64_workspace_tiled(int64_t M, int64_t N, int64_t K);
+
+// Largest workspace any product of at most N columns may take (the skinny
+// path serves every width up to kSkMaxN).
 size_t gemm_f64_workspace(int64_t M, int64_t N, int64_t K) {
+  size_t w = gemm_f64_workspace_tiled(M, N, K);
+  const int64_t nn = std::min<int64_t>(N, kSkMaxN);
+  if (use_skinny('N', 'N', M, nn, K))
+    w = std::max(w, (size_t)skinny_nsplit(M, K) * (size_t)M * (size_t)nn * sizeof(double) + 256);
+  return w;
+}
+
+size_t gemm_f64_workspace_tiled(int64_t M, int64_t N, int64_t K) {
   Plan p = plan_for(M, N, K);
   if (p.nsplit <= 1) return 0;
   return (size_t)p.nsplit * (size_t)M * (size_t)N * sizeof(double) + 256;
@@ -229,6 +417,12 @@ void gemm_f64(hipStream_t s, char ta, char tb, int64_t M, int64_t N, int64_t K, 
     // C = beta * C
     if (beta == 0.0) fill_f64(s, C, M, N, ldc, 0.0);
     else if (beta != 1.0) copy_scaled_f64(s, C, ldc, C, ldc, M, N, beta);
+    return;
+  }
+  if (use_skinny(ta, tb, M, N, K) && ws != nullptr) {
+    const int ns = skinny_nsplit(M, K);
+    double* partial = ws->get<double>((size_t)ns * M * N);
+    gemm_f64_skinny(s, (int)M, (int)N, (int)K, alpha, A, lda, B, ldb, beta, C, ldc, partial);
     return;
   }
   Plan p = plan_for(M, N, K);

@@ -17,7 +17,7 @@
 //
 // Layout:
 //   Et     FP32, row-major E (Et[i * lde + k] = E(i, k)), lde = n rounded up to
-//          a multiple of 32, zero padding: a lane's 8 consecutive k of one row
+//          a multiple of 64, zero padding: a lane's 8 consecutive k of one row
 //          are one 32-byte load.
 //   Xs     BF16, three planes, column-major with ld = lde and rpad = 16 TN
 //          columns, zero padded.
@@ -113,15 +113,19 @@ __global__ void mixed_split_x_kernel(const double* __restrict__ X, int64_t ldx, 
   }
 }
 
-template <int TN>
+// KS = MFMA K-steps (of 32) per main-loop iteration: 2 when the double-
+// buffered X tile fits in LDS (TN <= 8), else 1.
+template <int TN, int KS>
 __global__ __launch_bounds__(kMT) void gemm_mixed_kernel(int n, int lde, int rpad, int nsplit,
                                                          int kchunk, const float* __restrict__ Et,
                                                          const u16* __restrict__ Xs, int r,
                                                          float* __restrict__ partial) {
   constexpr int NC = TN * 16;             // columns covered
-  constexpr int CHUNKS = 3 * NC * 4;      // 16-byte chunks of one Xs tile (32 k per column)
+  constexpr int BK = kMBK * KS;           // K per iteration
+  constexpr int QPC = BK / 8;             // 16-byte chunks per column of the tile
+  constexpr int CHUNKS = 3 * NC * QPC;    // 16-byte chunks of one Xs tile
   constexpr int CPT = (CHUNKS + kMT - 1) / kMT;
-  __shared__ uint4 sX[2][3][NC][kMLdsK / 8];
+  __shared__ uint4 sX[2][3][NC][QPC + 1];
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -131,7 +135,7 @@ __global__ __launch_bounds__(kMT) void gemm_mixed_kernel(int n, int lde, int rpa
   const int kbeg = split * kchunk;
   const int kend = min(lde, kbeg + kchunk);
   const int row_l = lane & 15;
-  const int kg = lane >> 4;  // k group: k = 8 kg .. 8 kg + 7 of the step
+  const int kg = lane >> 4;  // k group: k = 8 kg .. 8 kg + 7 of a 32-wide step
   const int64_t plane = (int64_t)lde * rpad;
 
   f32x4 acc[2][TN];
@@ -140,25 +144,28 @@ __global__ __launch_bounds__(kMT) void gemm_mixed_kernel(int n, int lde, int rpa
 #pragma unroll
     for (int j = 0; j < TN; ++j) acc[t][j] = f32x4{0.f, 0.f, 0.f, 0.f};
 
-  // rows of this lane's two E fragments
   int rows[2];
 #pragma unroll
   for (int t = 0; t < 2; ++t) rows[t] = rb * kMRows + wave * kMRowsWave + t * 16 + row_l;
 
-  float ecur[2][8];
-  auto load_e = [&](int k0, float (&dst)[2][8]) {
+  // E fragments of an iteration: [substep][tile][8 consecutive k]
+  float ecur[KS][2][8];
+  auto load_e = [&](int k0, float (&dst)[KS][2][8]) {
 #pragma unroll
-    for (int t = 0; t < 2; ++t) {
-      if (rows[t] < n) {
-        const float4* src = reinterpret_cast<const float4*>(Et + (int64_t)rows[t] * lde + k0 + kg * 8);
-        const float4 a = src[0], b = src[1];
-        dst[t][0] = a.x; dst[t][1] = a.y; dst[t][2] = a.z; dst[t][3] = a.w;
-        dst[t][4] = b.x; dst[t][5] = b.y; dst[t][6] = b.z; dst[t][7] = b.w;
-      } else {
+    for (int ks = 0; ks < KS; ++ks)
 #pragma unroll
-        for (int q = 0; q < 8; ++q) dst[t][q] = 0.f;
+      for (int t = 0; t < 2; ++t) {
+        if (rows[t] < n) {
+          const float4* src =
+              reinterpret_cast<const float4*>(Et + (int64_t)rows[t] * lde + k0 + ks * kMBK + kg * 8);
+          const float4 a = src[0], b = src[1];
+          dst[ks][t][0] = a.x; dst[ks][t][1] = a.y; dst[ks][t][2] = a.z; dst[ks][t][3] = a.w;
+          dst[ks][t][4] = b.x; dst[ks][t][5] = b.y; dst[ks][t][6] = b.z; dst[ks][t][7] = b.w;
+        } else {
+#pragma unroll
+          for (int q = 0; q < 8; ++q) dst[ks][t][q] = 0.f;
+        }
       }
-    }
   };
 
   uint4 stage[CPT];
@@ -167,9 +174,9 @@ __global__ __launch_bounds__(kMT) void gemm_mixed_kernel(int n, int lde, int rpa
     for (int c = 0; c < CPT; ++c) {
       const int idx = tid + c * kMT;
       if (idx < CHUNKS) {
-        const int q = idx & 3;          // 8-k chunk within the column
-        const int col = (idx >> 2) % NC;
-        const int pc = (idx >> 2) / NC;  // piece
+        const int q = idx % QPC;
+        const int col = (idx / QPC) % NC;
+        const int pc = (idx / QPC) / NC;
         stage[c] = *reinterpret_cast<const uint4*>(Xs + pc * plane + (int64_t)col * lde + k0 + q * 8);
       }
     }
@@ -179,9 +186,9 @@ __global__ __launch_bounds__(kMT) void gemm_mixed_kernel(int n, int lde, int rpa
     for (int c = 0; c < CPT; ++c) {
       const int idx = tid + c * kMT;
       if (idx < CHUNKS) {
-        const int q = idx & 3;
-        const int col = (idx >> 2) % NC;
-        const int pc = (idx >> 2) / NC;
+        const int q = idx % QPC;
+        const int col = (idx / QPC) % NC;
+        const int pc = (idx / QPC) / NC;
         sX[buf][pc][col][q] = stage[c];
       }
     }
@@ -194,42 +201,48 @@ __global__ __launch_bounds__(kMT) void gemm_mixed_kernel(int n, int lde, int rpa
   }
   __syncthreads();
   int buf = 0;
-  for (int k0 = kbeg; k0 < kend; k0 += kMBK) {
-    const bool more = (k0 + kMBK) < kend;
-    float enext[2][8];
+  for (int k0 = kbeg; k0 < kend; k0 += BK) {
+    const bool more = (k0 + BK) < kend;
+    float enext[KS][2][8];
     if (more) {
-      load_x(k0 + kMBK);
-      load_e(k0 + kMBK, enext);
+      load_x(k0 + BK);
+      load_e(k0 + BK, enext);
     }
-    // split this step's E fragments into three BF16 pieces
-    Frag ef[2][3];
 #pragma unroll
-    for (int t = 0; t < 2; ++t)
+    for (int ks = 0; ks < KS; ++ks) {
+      // split this substep's E fragments into three BF16 pieces
+      Frag ef[2][3];
 #pragma unroll
-      for (int q = 0; q < 8; ++q) split3(ecur[t][q], ef[t][0].h[q], ef[t][1].h[q], ef[t][2].h[q]);
+      for (int t = 0; t < 2; ++t)
 #pragma unroll
-    for (int j = 0; j < TN; ++j) {
-      Frag xf[3];
+        for (int q = 0; q < 8; ++q)
+          split3(ecur[ks][t][q], ef[t][0].h[q], ef[t][1].h[q], ef[t][2].h[q]);
 #pragma unroll
-      for (int pc = 0; pc < 3; ++pc) xf[pc].q = sX[buf][pc][j * 16 + row_l][kg];
+      for (int j = 0; j < TN; ++j) {
+        Frag xf[3];
 #pragma unroll
-      for (int t = 0; t < 2; ++t) {
-        f32x4 a = acc[t][j];
-        a = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ef[t][2].v, xf[0].v, a, 0, 0, 0);
-        a = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ef[t][1].v, xf[1].v, a, 0, 0, 0);
-        a = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ef[t][0].v, xf[2].v, a, 0, 0, 0);
-        a = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ef[t][1].v, xf[0].v, a, 0, 0, 0);
-        a = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ef[t][0].v, xf[1].v, a, 0, 0, 0);
-        a = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ef[t][0].v, xf[0].v, a, 0, 0, 0);
-        acc[t][j] = a;
+        for (int pc = 0; pc < 3; ++pc) xf[pc].q = sX[buf][pc][j * 16 + row_l][ks * 4 + kg];
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+          f32x4 a = acc[t][j];
+          a = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ef[t][2].v, xf[0].v, a, 0, 0, 0);
+          a = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ef[t][1].v, xf[1].v, a, 0, 0, 0);
+          a = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ef[t][0].v, xf[2].v, a, 0, 0, 0);
+          a = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ef[t][1].v, xf[0].v, a, 0, 0, 0);
+          a = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ef[t][0].v, xf[1].v, a, 0, 0, 0);
+          a = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ef[t][0].v, xf[0].v, a, 0, 0, 0);
+          acc[t][j] = a;
+        }
       }
     }
     if (more) {
       store_x(buf ^ 1);
 #pragma unroll
-      for (int t = 0; t < 2; ++t)
+      for (int ks = 0; ks < KS; ++ks)
 #pragma unroll
-        for (int q = 0; q < 8; ++q) ecur[t][q] = enext[t][q];
+        for (int t = 0; t < 2; ++t)
+#pragma unroll
+          for (int q = 0; q < 8; ++q) ecur[ks][t][q] = enext[ks][t][q];
     }
     __syncthreads();
     buf ^= 1;
@@ -268,14 +281,17 @@ __global__ void mixed_reduce_kernel(const float* __restrict__ partial, int64_t n
 constexpr int kMaxTN = 16;
 constexpr int kMinChunk = 256;
 
-int64_t lde_for(int64_t n) { return cdiv(n, kMBK) * kMBK; }
+// K granularity: two MFMA K-steps, so every main-loop iteration is full
+constexpr int kMKGran = 2 * kMBK;
+
+int64_t lde_for(int64_t n) { return cdiv(n, kMKGran) * kMKGran; }
 
 int nsplit_for(int64_t n) {
   const int64_t lde = lde_for(n);
   const int64_t rowblocks = cdiv(n, kMRows);
   int64_t ns = 8;
   while (rowblocks * ns < 512 && lde / (ns * 2) >= kMinChunk) ns *= 2;
-  while (ns > 1 && lde / ns < kMBK) ns /= 2;
+  while (ns > 1 && lde / ns < kMKGran) ns /= 2;
   return (int)ns;
 }
 
@@ -283,8 +299,9 @@ template <int TN>
 void launch_mixed(hipStream_t s, int64_t n, int64_t lde, int64_t rpad, int nsplit, int kchunk,
                   const float* Et, const u16* Xs, int64_t r, float* partial) {
   const int64_t rowblocks = cdiv(n, kMRows);
-  hipLaunchKernelGGL((gemm_mixed_kernel<TN>), dim3((unsigned)(rowblocks * nsplit)), dim3(kMT), 0, s,
-                     (int)n, (int)lde, (int)rpad, nsplit, kchunk, Et, Xs, (int)r, partial);
+  constexpr int KS = (TN <= 8) ? 2 : 1;
+  hipLaunchKernelGGL((gemm_mixed_kernel<TN, KS>), dim3((unsigned)(rowblocks * nsplit)), dim3(kMT), 0,
+                     s, (int)n, (int)lde, (int)rpad, nsplit, kchunk, Et, Xs, (int)r, partial);
 }
 
 }  // namespace
@@ -314,7 +331,7 @@ void gemm_mixed(hipStream_t s, const MixedOp& op, const double* X, int64_t ldx, 
   if (n <= 0 || r <= 0) return;
   DME_REQUIRE(n < (1ll << 30), DME_EINVAL, "mixed gemm: n too large");
   const int ns = nsplit_for(n);
-  const int kchunk = (int)(cdiv(cdiv(op.lde, ns), kMBK) * kMBK);
+  const int kchunk = (int)(cdiv(cdiv(op.lde, ns), kMKGran) * kMKGran);
   const size_t mark = ws.used;
   for (int64_t c0 = 0; c0 < r; c0 += 16 * kMaxTN) {
     const int64_t rc = std::min<int64_t>(r - c0, 16 * kMaxTN);

@@ -2,6 +2,7 @@
 // factors resident in HBM, stepped by the splitting schemes of Sec. 2 / Sec. 3.
 #pragma once
 
+#include <functional>
 #include <map>
 #include <memory>
 #include <string>
@@ -29,13 +30,41 @@ struct Stage {
 // Subflows of one step in application order (operators act right to left).
 std::vector<Stage> step_sequence(bool is_dre, bool has_S, int split, int scheme);
 
+struct MixedOp;  // FP32 copy of an operator for the split-BF16 product (gemm_mixed.hip)
+
+// Operators derived from A for one step fraction t: e^{tA^T} in FP64 and, in
+// the mixed mode, its FP32 copy; optionally the K Gauss-Legendre node
+// exponentials e^{s_k A^T} on [0, t], kept when many right-hand sides C are
+// served from one operator (a single solve forms them one at a time while it
+// builds its quadrature factor and keeps none).
+struct OperatorSet {
+  int64_t n = 0;
+  double t = 0.0;
+  int precision = DME_FP64;
+  int K = 0;
+  DevBuf E;                      // n x n, e^{tA^T}
+  std::shared_ptr<MixedOp> mix;  // FP32 copy of E (mixed mode)
+  std::vector<DevBuf> nodes;     // e^{s_k A^T}, k = 0 .. K-1 (when kept)
+  double build_ms = 0.0;
+};
+
+// Device bytes an operator set holds.
+size_t operator_set_bytes(int64_t n, int precision, int K, bool keep_nodes);
+// Form the operator set of AT = A^T (device, n x n) on stream s (synchronous).
+// info_dev: device int receiving a nonzero LU pivot failure flag.
+std::shared_ptr<OperatorSet> build_operator_set(hipStream_t s, int64_t n, const double* AT, double t,
+                                                int precision, int K, bool keep_nodes, int* info_dev);
+
+// Supplies the operator set for a step fraction t (a cache shared by
+// several solves); null means the solve builds its own.
+using OperatorProvider = std::function<std::shared_ptr<OperatorSet>(double t)>;
+
 struct QuadFactor {
   DevBuf L;  // n x r
   DevBuf D;  // r x r
   int64_t r = 0;
 };
 
-struct MixedOp;  // FP32 copy of an operator for the split-BF16 product (gemm_mixed.hip)
 // Build the FP32 row-major copy of E (n x n, FP64 column-major).
 void mixed_op_build(hipStream_t s, int64_t n, const double* E, MixedOp& op);
 std::shared_ptr<MixedOp> mixed_op_new();
@@ -66,14 +95,13 @@ struct Solver {
   std::vector<Stage> seq;
   int64_t max_rank = 0, kmax = 0;
 
-  DevBuf AT;   // n x n, A^T
+  DevBuf AT;   // n x n, A^T (only when the solve builds its own operators)
   DevBuf B;    // n x m
   DevBuf CT;   // n x p, C^T
   DevBuf R;    // m x m
   DevBuf S;    // n x n
-  std::map<double, DevBuf> E;                       // t -> e^{t A^T}
-  std::map<double, std::shared_ptr<MixedOp>> Emix;  // t -> split-BF16 pieces
-  std::map<double, QuadFactor> Q;                   // t -> (L_I, D_I)
+  std::map<double, std::shared_ptr<OperatorSet>> ops;  // t -> e^{tA^T} (+ FP32 copy, nodes)
+  std::map<double, QuadFactor> Q;                       // t -> (L_I, D_I)
 
   DevBuf L[2], D[2];
   int cur = 0;
@@ -101,19 +129,32 @@ struct Solver {
   int* flag_dev() { return flags.as<int>(); }
   int64_t* rank_dev() { return reinterpret_cast<int64_t*>(flags.as<char>() + 16); }
 
-  void setup(const dme_problem& prob, const dme_opts& o, bool dre);
+  // Upload the problem and build (or take from `provider`) its operators.
+  // With a provider, prob.A is not read.
+  void setup(const dme_problem& prob, const dme_opts& o, bool dre,
+             const OperatorProvider* provider = nullptr);
   void advance(int64_t nsteps);
   void check_flags(const char* where);
+  // Device bytes setup() allocates for this solve (operators excluded).
+  static size_t state_bytes(int64_t n, int64_t m, int64_t p, bool has_S, const dme_opts& o);
+  static size_t workspace_bytes(int64_t n, int64_t m, int64_t max_rank, int64_t kmax, int precision);
+  static void sizes_for(int64_t n, int64_t p, const dme_opts& o, int64_t* max_rank, int64_t* kmax);
+
+  // Finer-grained stepping (used when several solves share one product):
+  // run stage `i` of the step sequence; for a T12 stage, `ext_product` says
+  // that W[:, 0:r] already holds e^{tA^T} L.
+  void run_stage(size_t i, bool ext_product = false);
+  // Called after the last stage of a step.
+  void end_step() { ++step; }
 
  private:
   void apply_T1(double t);
   void apply_T2(double t);
-  void apply_T12(double t);
+  void apply_T12(double t, bool ext_product);
   void apply_T3(double t);
   void apply_T4(double t);
   void compress_into(int64_t k);  // W (n x k), Dhat (k x k) -> new (L, D)
   void apply_E(double t, const double* X, int64_t r, double* Y, int64_t ldy);
-  void build_operator(double t);
   void build_quadrature(double t);
 };
 

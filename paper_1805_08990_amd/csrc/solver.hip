@@ -172,8 +172,9 @@ void Solver::check_flags(const char* where) {
   fail(DME_EINTERNAL, w + ": unknown device flag");
 }
 
-void Solver::setup(const dme_problem& prob, const dme_opts& o, bool dre) {
-  DME_REQUIRE(prob.n > 0 && prob.A, DME_EINVAL, "need n > 0 and A");
+void Solver::setup(const dme_problem& prob, const dme_opts& o, bool dre,
+                   const OperatorProvider* provider) {
+  DME_REQUIRE(prob.n > 0 && (prob.A || provider), DME_EINVAL, "need n > 0 and A");
   DME_REQUIRE(prob.p > 0 && prob.C, DME_EINVAL, "need p > 0 and C (Q = C^T C)");
   DME_REQUIRE(o.h > 0 && o.T > 0, DME_EINVAL, "T and h must be positive");
   DME_REQUIRE(o.tol > 0, DME_EINVAL, "tol must be positive");
@@ -212,16 +213,14 @@ void Solver::setup(const dme_problem& prob, const dme_opts& o, bool dre) {
     m = 0;
   }
   seq = step_sequence(dre, has_S, opts.split, opts.scheme);
-  max_rank = (o.max_rank > 0) ? std::min<int64_t>(o.max_rank, n) : std::min<int64_t>(n, 512);
+  sizes_for(n, p, opts, &max_rank, &kmax);
   DME_REQUIRE(prob.r0 <= max_rank, DME_EINVAL, "r0 exceeds max_rank");
-  const int64_t Kp = (int64_t)opts.quad_nodes * p;
-  kmax = std::max({max_rank + p, max_rank + Kp, 3 * max_rank, Kp});
 
   DME_HIP(hipSetDevice(device));
   flags.ensure(64);
   fill_f64(s, flags.as<double>(), 8, 1, 8, 0.0);
 
-  {
+  if (provider == nullptr) {
     DevBuf A;
     upload(s, A, prob.A, (size_t)n * n);
     AT.ensure((size_t)n * n * sizeof(double));
@@ -249,12 +248,7 @@ void Solver::setup(const dme_problem& prob, const dme_opts& o, bool dre) {
   Dhat.ensure((size_t)kmax * kmax * sizeof(double));
   WB.ensure((size_t)max_rank * std::max<int64_t>(m, 1) * sizeof(double));
   if (has_S) SL.ensure((size_t)n * max_rank * sizeof(double));
-  size_t wsb = compress_workspace(n, kmax);
-  wsb += gemm_f64_workspace(max_rank, std::max<int64_t>(m, 1), n) + 4096;
-  wsb += gemm_f64_workspace(n, max_rank, n) + 4096;
-  if (opts.precision == DME_MIXED) wsb += gemm_mixed_workspace(n, max_rank) + 4096;
-  wsb += (size_t)max_rank * (max_rank + 64) * sizeof(double) + 4096;  // riccati scratch
-  ws.reserve(wsb);
+  ws.reserve(workspace_bytes(n, m, max_rank, kmax, opts.precision));
 
   cur = 0;
   r = prob.r0;
@@ -266,9 +260,13 @@ void Solver::setup(const dme_problem& prob, const dme_opts& o, bool dre) {
   for (const Stage& st : seq) {
     const double t = st.frac * o.h;
     if (st.sub == Sub::T1 || st.sub == Sub::T12) {
-      if (!E.count(t)) {
+      if (!ops.count(t)) {
         EventTimer tm(s);
-        build_operator(t);
+        ops[t] = provider ? (*provider)(t)
+                          : build_operator_set(s, n, AT.as<double>(), t, opts.precision, 0, false,
+                                               flag_dev() + 1);
+        DME_REQUIRE(ops[t] && ops[t]->n == n && ops[t]->precision == opts.precision, DME_EINTERNAL,
+                    "operator set does not match the problem");
         expm_ms += tm.stop_ms();
       }
     }
@@ -282,18 +280,88 @@ void Solver::setup(const dme_problem& prob, const dme_opts& o, bool dre) {
   step = 0;
 }
 
-void Solver::build_operator(double t) {
-  DevBuf& Et = E[t];
-  Et.ensure((size_t)n * n * sizeof(double));
+size_t operator_set_bytes(int64_t n, int precision, int K, bool keep_nodes) {
+  const size_t nn = (size_t)n * n;
+  size_t b = nn * sizeof(double);
+  if (precision == DME_MIXED) b += (size_t)n * cdiv(n, 64) * 64 * sizeof(float);
+  if (keep_nodes) b += (size_t)K * nn * sizeof(double);
+  return b;
+}
+
+std::shared_ptr<OperatorSet> build_operator_set(hipStream_t s, int64_t n, const double* AT, double t,
+                                                int precision, int K, bool keep_nodes, int* info_dev) {
+  hipEvent_t a, b;
+  DME_HIP(hipEventCreate(&a));
+  DME_HIP(hipEventCreate(&b));
+  DME_HIP(hipEventRecord(a, s));
+  auto op = std::make_shared<OperatorSet>();
+  op->n = n;
+  op->t = t;
+  op->precision = precision;
+  op->K = keep_nodes ? K : 0;
   Arena ews;
   ews.reserve(expm_workspace(n));
-  expm_f64(s, n, AT.as<double>(), t, Et.as<double>(), ews, nullptr, nullptr, flag_dev() + 1);
-  if (opts.precision == DME_MIXED) {
-    std::shared_ptr<MixedOp> op = mixed_op_new();
-    mixed_op_build(s, n, Et.as<double>(), *op);
-    Emix[t] = op;
+  op->E.ensure((size_t)n * n * sizeof(double));
+  expm_f64(s, n, AT, t, op->E.as<double>(), ews, nullptr, nullptr, info_dev);
+  if (precision == DME_MIXED) {
+    op->mix = mixed_op_new();
+    mixed_op_build(s, n, op->E.as<double>(), *op->mix);
   }
-  DME_HIP(hipStreamSynchronize(s));
+  if (keep_nodes) {
+    std::vector<double> nodes, weights;
+    gauss_legendre(K, t, nodes, weights);
+    op->nodes.resize(K);
+    for (int q = 0; q < K; ++q) {
+      ews.reset();
+      op->nodes[q].ensure((size_t)n * n * sizeof(double));
+      expm_f64(s, n, AT, nodes[q], op->nodes[q].as<double>(), ews, nullptr, nullptr, info_dev);
+    }
+  }
+  DME_HIP(hipEventRecord(b, s));
+  DME_HIP(hipEventSynchronize(b));
+  float ms = 0.f;
+  DME_HIP(hipEventElapsedTime(&ms, a, b));
+  op->build_ms = ms;
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  return op;
+}
+
+size_t Solver::workspace_bytes(int64_t n, int64_t m, int64_t max_rank, int64_t kmax, int precision) {
+  size_t wsb = compress_workspace(n, kmax);
+  wsb += gemm_f64_workspace(max_rank, std::max<int64_t>(m, 1), n) + 4096;
+  wsb += gemm_f64_workspace(n, max_rank, n) + 4096;
+  if (precision == DME_MIXED) wsb += gemm_mixed_workspace(n, max_rank) + 4096;
+  wsb += (size_t)max_rank * (max_rank + 64) * sizeof(double) + 4096;  // riccati scratch
+  return wsb;
+}
+
+void Solver::sizes_for(int64_t n, int64_t p, const dme_opts& o, int64_t* max_rank_out,
+                       int64_t* kmax_out) {
+  const int K = o.quad_nodes > 0 ? o.quad_nodes : 7;
+  const int64_t mr = (o.max_rank > 0) ? std::min<int64_t>(o.max_rank, n) : std::min<int64_t>(n, 512);
+  const int64_t Kp = (int64_t)K * p;
+  *max_rank_out = mr;
+  *kmax_out = std::max({mr + p, mr + Kp, 3 * mr, Kp});
+}
+
+size_t Solver::state_bytes(int64_t n, int64_t m, int64_t p, bool has_S, const dme_opts& o) {
+  int64_t mr = 0, km = 0;
+  sizes_for(n, p, o, &mr, &km);
+  const int K = o.quad_nodes > 0 ? o.quad_nodes : 7;
+  const int64_t Kp = (int64_t)K * p;
+  size_t b = 0;
+  auto add = [&](size_t x) { b += (x + 255) & ~size_t(255); };
+  add((size_t)n * p * 8);                                     // C^T
+  add((size_t)n * std::max<int64_t>(m, 1) * 8);                // B
+  add((size_t)std::max<int64_t>(m, 1) * std::max<int64_t>(m, 1) * 8);
+  if (has_S) add((size_t)n * n * 8 + (size_t)n * mr * 8);
+  add(2 * ((size_t)n * mr * 8 + (size_t)mr * mr * 8));          // L, D ping-pong
+  add((size_t)n * km * 8 + (size_t)km * km * 8);                // W, Dhat
+  add((size_t)mr * std::max<int64_t>(m, 1) * 8);                // W_B
+  add(2 * ((size_t)n * Kp * 8 + (size_t)Kp * Kp * 8));          // quadrature factors (h and h/2)
+  add(workspace_bytes(n, m, mr, km, o.precision));
+  return b + 64;
 }
 
 void Solver::build_quadrature(double t) {
@@ -301,17 +369,27 @@ void Solver::build_quadrature(double t) {
   std::vector<double> nodes, weights;
   gauss_legendre(K, t, nodes, weights);
   const int64_t kq = (int64_t)K * p;
-  DevBuf Ek((size_t)n * n * sizeof(double));
-  Arena ews;
-  ews.reserve(expm_workspace(n));
+  const OperatorSet& op = *ops.at(t);
   // columns [e^{s_k A^T} C^T]_k directly into W, weights into Dhat
   double* Wd = W.as<double>();
-  for (int q = 0; q < K; ++q) {
-    ews.reset();
-    expm_f64(s, n, AT.as<double>(), nodes[q], Ek.as<double>(), ews, nullptr, nullptr, flag_dev() + 1);
-    ews.reset();
-    gemm_f64(s, 'N', 'N', n, p, n, 1.0, Ek.as<double>(), n, CT.as<double>(), n, 0.0,
-             Wd + (int64_t)q * p * n, n, &ews);
+  if ((int)op.nodes.size() == K) {
+    for (int q = 0; q < K; ++q) {
+      ws.reset();
+      gemm_f64(s, 'N', 'N', n, p, n, 1.0, op.nodes[q].as<double>(), n, CT.as<double>(), n, 0.0,
+               Wd + (int64_t)q * p * n, n, &ws);
+    }
+  } else {
+    DME_REQUIRE(AT.p != nullptr, DME_EINTERNAL, "quadrature factor needs the operator or its nodes");
+    DevBuf Ek((size_t)n * n * sizeof(double));
+    Arena ews;
+    ews.reserve(expm_workspace(n));
+    for (int q = 0; q < K; ++q) {
+      ews.reset();
+      expm_f64(s, n, AT.as<double>(), nodes[q], Ek.as<double>(), ews, nullptr, nullptr, flag_dev() + 1);
+      ews.reset();
+      gemm_f64(s, 'N', 'N', n, p, n, 1.0, Ek.as<double>(), n, CT.as<double>(), n, 0.0,
+               Wd + (int64_t)q * p * n, n, &ews);
+    }
   }
   double* Dh = Dhat.as<double>();
   fill_f64(s, Dh, kq, kq, kq, 0.0);
@@ -332,11 +410,11 @@ void Solver::apply_E(double t, const double* X, int64_t rr, double* Y, int64_t l
   ws.reset();
   hipEvent_t ev = mark_begin();
   if (opts.precision == DME_MIXED) {
-    gemm_mixed(s, *Emix.at(t), X, n, rr, Y, ldy, ws);
+    gemm_mixed(s, *ops.at(t)->mix, X, n, rr, Y, ldy, ws);
     // algorithmic work of Y = E X: 2 n^2 r flops; the FP32 operator read once
     mark_end(0, ev, 2.0 * n * n * rr, 4.0 * (double)n * n + 16.0 * n * rr);
   } else {
-    gemm_f64(s, 'N', 'N', n, rr, n, 1.0, E.at(t).as<double>(), n, X, n, 0.0, Y, ldy, &ws);
+    gemm_f64(s, 'N', 'N', n, rr, n, 1.0, ops.at(t)->E.as<double>(), n, X, n, 0.0, Y, ldy, &ws);
     // algorithmic work of Y = E X: 2 n^2 r flops; E read once, X read, Y written
     mark_end(0, ev, 2.0 * n * n * rr, 8.0 * ((double)n * n + 2.0 * n * rr));
   }
@@ -371,10 +449,10 @@ void Solver::apply_T2(double t) {
   compress_into(k);
 }
 
-void Solver::apply_T12(double t) {
+void Solver::apply_T12(double t, bool ext_product) {
   const QuadFactor& f = Q.at(t);
   double* Wd = W.as<double>();
-  if (r > 0) apply_E(t, Lc(), r, Wd, n);
+  if (r > 0 && !ext_product) apply_E(t, Lc(), r, Wd, n);
   if (f.r > 0) copy_f64(s, f.L.as<double>(), n, Wd + r * n, n, n, f.r);
   const int64_t k = r + f.r;
   if (k == 0) return;
@@ -411,19 +489,22 @@ void Solver::apply_T4(double t) {
   compress_into(k);
 }
 
+void Solver::run_stage(size_t i, bool ext_product) {
+  const Stage& st = seq.at(i);
+  const double t = st.frac * opts.h;
+  switch (st.sub) {
+    case Sub::T1: apply_T1(t); break;
+    case Sub::T2: apply_T2(t); break;
+    case Sub::T12: apply_T12(t, ext_product); break;
+    case Sub::T3: apply_T3(t); break;
+    case Sub::T4: apply_T4(t); break;
+  }
+}
+
 void Solver::advance(int64_t nsteps) {
   for (int64_t it = 0; it < nsteps; ++it) {
-    for (const Stage& st : seq) {
-      const double t = st.frac * opts.h;
-      switch (st.sub) {
-        case Sub::T1: apply_T1(t); break;
-        case Sub::T2: apply_T2(t); break;
-        case Sub::T12: apply_T12(t); break;
-        case Sub::T3: apply_T3(t); break;
-        case Sub::T4: apply_T4(t); break;
-      }
-    }
-    ++step;
+    for (size_t i = 0; i < seq.size(); ++i) run_stage(i);
+    end_step();
   }
   flush_timings();
   check_flags("step");

@@ -7,16 +7,22 @@
 //   2. bisect_kernel    : every eigenvalue by Sturm-count bisection, one
 //                         thread per eigenvalue index (embarrassingly parallel).
 //   3. select_kernel    : threshold, |lambda|-descending order of the kept set
-//                         and the clusters (relative gap < 1e-3) that need
-//                         mutual orthogonalisation.
+//                         and the clusters of kept eigenvalues whose gaps are
+//                         below 1e-3 ||T|| (the absolute criterion of LAPACK's
+//                         inverse iteration).
 //   4. invit_kernel     : inverse iteration with a partially pivoted
-//                         tridiagonal LU, one workgroup per cluster, modified
-//                         Gram-Schmidt inside the cluster.
-//   5. backtr_kernel    : V = H_0 ... H_{k-3} Z, one workgroup per column.
+//                         tridiagonal LU, one workgroup per kept eigenvalue,
+//                         all independent.
+//   5. orth_kernel      : one workgroup per cluster orthonormalises the
+//                         cluster's vectors (right-looking modified Gram-Schmidt,
+//                         two passes).
+//   6. backtr_kernel    : V = H_0 ... H_{k-3} Z, one workgroup per column.
 //
-// The tridiagonal eigenvectors are accurate to O(u ||M|| / gap); with the
-// relative cluster criterion the error this leaves in sum_i lam_i v_i v_i^T is
-// O(1e3 u ||M||), far below the truncation tolerances used by the method.
+// An inverse-iteration vector is off its eigenvector by O(u ||M|| / gap) in
+// the directions of nearby eigenvectors; orthonormalising a cluster mixes its
+// vectors by that much, which changes sum_i lam_i v_i v_i^T by O(u ||M||) per
+// pair (the mixing times the eigenvalue difference), so the kept part is
+// reproduced to roundoff and the vectors are orthonormal to roundoff.
 #include "common.h"
 
 namespace dme {
@@ -25,8 +31,9 @@ namespace {
 constexpr int kTriT = 1024;
 constexpr int kRowLanes = 256;
 constexpr int kColGroups = kTriT / kRowLanes;
-constexpr double kOrtol = 1e-3;  // relative gap below which eigenvectors are orthogonalised
+constexpr double kOrtol = 1e-3;  // gaps below kOrtol ||T|| join a cluster
 constexpr int kInvitIters = 3;
+constexpr int kInvitLdsMaxK = 2048;  // inverse-iteration arrays in LDS up to this k
 
 __device__ inline double block_sum_1024(double v, double* red) {
   // red: kTriT doubles of LDS; returns the total to every thread
@@ -39,6 +46,114 @@ __device__ inline double block_sum_1024(double v, double* red) {
   for (int w = 0; w < nw; ++w) tot += red[w];
   __syncthreads();
   return tot;
+}
+
+// Householder tridiagonalisation for k <= kTriMaxK, same outputs as
+// tridiag_kernel.  Wave w owns the columns l = r0 + w, r0 + w + 16, ... of the
+// trailing block and lane i its rows r0 + i, r0 + i + 64, ..., so the products
+// with the trailing block read whole column segments (coalesced) with many
+// independent loads per lane; v, w and the product p live in LDS.
+constexpr int kTriMaxK = 512;
+constexpr int kTriRows = kTriMaxK / 64;  // row blocks per lane
+
+__global__ __launch_bounds__(kTriT) void tridiag_small_kernel(double* A, int64_t lda, int k, double* d,
+                                                              double* e, double* tau) {
+  extern __shared__ double sm[];
+  double* sv = sm;             // v (rows r0 .. k-1; sv[r0] = 1)
+  double* sw = sm + k;         // w
+  double* sp = sm + 2 * k;     // p
+  double* pp = sm + 3 * k;     // [16][k] per-wave partial products
+  __shared__ double red[kTriT / 64];
+  const int t = threadIdx.x;
+  const int lane = t & 63, wv = t >> 6;
+  constexpr int NW = kTriT / 64;
+  for (int j = 0; j + 2 < k; ++j) {
+    const int r0 = j + 1;
+    const double alpha = A[r0 + (int64_t)j * lda];
+    double part = 0.0;
+    for (int i = j + 2 + t; i < k; i += kTriT) {
+      const double a = A[i + (int64_t)j * lda];
+      part += a * a;
+    }
+    const double sig2 = block_sum_1024(part, red);
+    if (sig2 == 0.0) {
+      if (t == 0) { tau[j] = 0.0; e[j] = alpha; d[j] = A[j + (int64_t)j * lda]; }
+      __syncthreads();
+      continue;
+    }
+    const double beta = -copysign(sqrt(alpha * alpha + sig2), alpha);
+    const double tj = (beta - alpha) / beta;
+    const double scale = 1.0 / (alpha - beta);
+    for (int i = r0 + t; i < k; i += kTriT) {
+      double vi = 1.0;
+      if (i > r0) {
+        vi = A[i + (int64_t)j * lda] * scale;
+        A[i + (int64_t)j * lda] = vi;
+      }
+      sv[i] = vi;
+    }
+    if (t == 0) {
+      tau[j] = tj;
+      e[j] = beta;
+      d[j] = A[j + (int64_t)j * lda];
+      A[r0 + (int64_t)j * lda] = beta;
+    }
+    __syncthreads();
+    // p = tau * A22 v: per-wave column sums, then across waves
+    {
+      double acc[kTriRows];
+#pragma unroll
+      for (int q = 0; q < kTriRows; ++q) acc[q] = 0.0;
+      for (int l = r0 + wv; l < k; l += NW) {
+        const double vl = sv[l];
+        const double* col = A + (int64_t)l * lda;
+#pragma unroll
+        for (int q = 0; q < kTriRows; ++q) {
+          const int i = r0 + lane + 64 * q;
+          if (i < k) acc[q] += col[i] * vl;
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < kTriRows; ++q) {
+        const int i = r0 + lane + 64 * q;
+        if (i < k) pp[wv * k + i] = acc[q];
+      }
+    }
+    __syncthreads();
+    part = 0.0;
+    for (int i = r0 + t; i < k; i += kTriT) {
+      double sacc = 0.0;
+      for (int g = 0; g < NW; ++g) sacc += pp[g * k + i];
+      const double pi = tj * sacc;
+      sp[i] = pi;
+      part += pi * sv[i];
+    }
+    // K = tau/2 * p^T v ; w = p - K v
+    const double pv = block_sum_1024(part, red);
+    const double Kc = 0.5 * tj * pv;
+    for (int i = r0 + t; i < k; i += kTriT) sw[i] = sp[i] - Kc * sv[i];
+    __syncthreads();
+    // A22 -= v w^T + w v^T
+    for (int l = r0 + wv; l < k; l += NW) {
+      const double vl = sv[l], wl = sw[l];
+      double* col = A + (int64_t)l * lda;
+#pragma unroll
+      for (int q = 0; q < kTriRows; ++q) {
+        const int i = r0 + lane + 64 * q;
+        if (i < k) col[i] -= sv[i] * wl + sw[i] * vl;
+      }
+    }
+    __syncthreads();
+  }
+  if (t == 0) {
+    if (k >= 2) {
+      d[k - 2] = A[(k - 2) + (int64_t)(k - 2) * lda];
+      e[k - 2] = A[(k - 1) + (int64_t)(k - 2) * lda];
+      tau[k - 2] = 0.0;
+    }
+    d[k - 1] = A[(k - 1) + (int64_t)(k - 1) * lda];
+    tau[k - 1] = 0.0;
+  }
 }
 
 // Householder tridiagonalisation of A (k x k, ld lda, full symmetric storage,
@@ -192,39 +307,49 @@ __global__ void tri_prep_kernel(const double* d, const double* e, int k, double*
   }
 }
 
-// Eigenvalue i (ascending) by bisection on the Sturm count.
-__global__ void bisect_kernel(const double* d, const double* e2, int k, const double* bounds,
-                              double* lam) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+// Eigenvalue i (ascending) by multisection on the Sturm count: wave i
+// evaluates the count at 63 interior points of its interval and keeps the
+// sub-interval where the count passes i, so each round shrinks the interval
+// 64-fold.  Stops at the width the reduction determines the eigenvalue to.
+__global__ __launch_bounds__(64) void bisect_kernel(const double* d, const double* e2, int k,
+                                                    const double* bounds, double* lam) {
+  const int i = blockIdx.x;
+  const int lane = threadIdx.x;
   if (i >= k) return;
   double lo = bounds[0], hi = bounds[1];
   const double pivmin = bounds[2];
-  // eigenvalues are determined only to about u * ||T|| by the reduction, so
-  // bisection stops at that absolute width
   const double atol = DBL_EPSILON * bounds[3] + 2.0 * DBL_MIN;
-  for (int it = 0; it < 200; ++it) {
-    const double mid = 0.5 * (lo + hi);
-    if (!(mid > lo && mid < hi)) break;  // interval cannot shrink further
+  for (int it = 0; it < 64; ++it) {
     if (hi - lo <= 2.0 * DBL_EPSILON * fmax(fabs(lo), fabs(hi)) + atol) break;
-    if (sturm_count(d, e2, k, mid, pivmin) > i) hi = mid;
-    else lo = mid;
+    const double h = (hi - lo) / 64.0;
+    const double x = (lane < 63) ? lo + h * (double)(lane + 1) : hi;
+    const bool above = (lane < 63) ? (sturm_count(d, e2, k, x, pivmin) > i) : true;
+    const uint64_t mask = __ballot(above);
+    const int first = __ffsll((unsigned long long)mask) - 1;  // lane 63 is always set
+    const double nlo = (first == 0) ? lo : lo + h * (double)first;
+    const double nhi = (first == 63) ? hi : lo + h * (double)(first + 1);
+    if (!(nhi - nlo < hi - lo)) break;  // no progress in floating point
+    lo = nlo;
+    hi = nhi;
   }
-  lam[i] = 0.5 * (lo + hi);
+  if (lane == 0) lam[i] = 0.5 * (lo + hi);
 }
 
 // One thread: threshold, ordering by |lambda| descending (negatives first on
 // ties), clusters of the kept set.  Outputs:
 //   order[c]  : ascending index of the c-th kept eigenvalue
 //   lam_out   : kept eigenvalues (|lambda| desc), then the rest
-//   clusters  : (start, len) runs in ascending order over kept eigenvalues;
+//   clusters  : (start, len) runs in ascending order over kept eigenvalues
+//               with consecutive gaps <= kOrtol ||T||;
 //               cl_count[0] = number of clusters
 //   keep[0]   : kept count (capped at max_keep, flag |= 2 when capped)
-__global__ void select_kernel(const double* lam, int k, double tol, int64_t max_keep, int* order,
-                              int* pos_of, double* lam_out, int* clusters, int* cl_count,
-                              int64_t* keep, int* flag) {
+__global__ void select_kernel(const double* lam, int k, double tol, int64_t max_keep,
+                              const double* bounds, int* order, int* pos_of, double* lam_out,
+                              int* clusters, int* cl_count, int64_t* keep, int* flag) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  // eigenvalues are known to about u ||T||; a zero matrix has no nonzero ones
   double amax = 0.0;
-  if (k > 0) amax = fmax(fabs(lam[0]), fabs(lam[k - 1]));
+  if (k > 0 && bounds[3] > 0.0) amax = fmax(fabs(lam[0]), fabs(lam[k - 1]));
   const double thr = tol * amax;
   int lo = 0, hi = k - 1, c = 0;
   int kept = 0;
@@ -262,8 +387,7 @@ __global__ void select_kernel(const double* lam, int k, double tol, int64_t max_
     int start = q, len = 1;
     while (q + len < k && pos_of[q + len] >= 0) {
       const double a = lam[q + len - 1], b = lam[q + len];
-      const double scale = fmax(fabs(a), fabs(b));
-      if (b - a < kOrtol * scale) ++len;
+      if (b - a <= kOrtol * bounds[3]) ++len;
       else break;
     }
     clusters[2 * ncl] = start;
@@ -282,21 +406,24 @@ __device__ inline double start_entry(int idx, int i) {
   return ((double)(h & 0xFFFFFF) / (double)0x1000000) * 2.0 - 1.0;
 }
 
-// Inverse iteration, one workgroup per cluster of kept eigenvalues.  The
-// tridiagonal LU and the two triangular solves are sequential (thread 0); the
-// normalisation and the Gram-Schmidt against the cluster's earlier vectors run
-// on the whole block.  Z is stored transposed: Zt[c + i * ldz] is entry i of
-// output column c.
+// Inverse iteration for kept eigenvalue number `blockIdx.x` (ascending index
+// idx, output column pos_of[idx]); the tridiagonal LU and the solves are
+// sequential (thread 0), the rescaling and normalisation use the block.
+// Eigenvalues inside one cluster get shifts nudged apart by a few ulps of
+// ||T|| and distinct start vectors, so their iterates differ.  Z is column-
+// major: Z[i + c * ldz] is entry i of output column c.
 __global__ void invit_kernel(const double* d, const double* e, int k, const double* lam,
-                             const int* clusters, const int* cl_count, const int* pos_of,
-                             const double* bounds, double* work, double* Zt, int64_t ldz) {
-  const int cl = blockIdx.x;
-  if (cl >= cl_count[0]) return;
-  const int start = clusters[2 * cl], len = clusters[2 * cl + 1];
+                             const int* order, const int64_t* keep, const double* bounds,
+                             double* work, double* Z, int64_t ldz, int use_lds) {
+  const int c = blockIdx.x;
+  if (c >= keep[0]) return;
+  const int idx = order[c];
+  extern __shared__ double ism[];
   __shared__ double red[256 / 64];
   __shared__ double sscale;
-  // per-cluster sequential scratch: 5 arrays of length k
-  double* u0 = work + (int64_t)cl * 6 * k;
+  // the sequential LU and solves touch these arrays element by element:
+  // keep them in LDS when they fit
+  double* u0 = use_lds ? ism : work + (int64_t)c * 6 * k;
   double* u1 = u0 + k;
   double* u2 = u1 + k;
   double* lm = u2 + k;
@@ -305,109 +432,128 @@ __global__ void invit_kernel(const double* d, const double* e, int k, const doub
   const double nrmT = bounds[3];
   const double eps = DBL_EPSILON;
   const double small = eps * fmax(nrmT, DBL_MIN);
-  for (int q = 0; q < len; ++q) {
-    const int idx = start + q;
-    const int col = pos_of[idx];
-    double lamq = lam[idx];
-    // nudge apart equal eigenvalues inside a cluster so the solves differ
-    if (q > 0 && lamq <= lam[idx - 1]) lamq = lam[idx - 1] + eps * fmax(fabs(lam[idx - 1]), nrmT);
-    if (threadIdx.x == 0) {
-      // LU with partial pivoting of T - lamq I: rows i, i+1 may swap.
-      // After elimination row i holds u0[i] (diag), u1[i], u2[i] (super-diags).
-      double a = d[0] - lamq;                 // current diagonal
-      double b = (k > 1) ? e[0] : 0.0;        // current first super-diagonal
-      for (int i = 0; i + 1 < k; ++i) {
-        const double sub = e[i];              // entry (i+1, i)
-        const double dn = d[i + 1] - lamq;    // (i+1, i+1)
-        const double sn = (i + 2 < k) ? e[i + 1] : 0.0;  // (i+1, i+2)
-        if (fabs(a) >= fabs(sub)) {
-          sw[i] = 0;
-          const double piv = (a == 0.0) ? small : a;
-          const double mlt = sub / piv;
-          u0[i] = piv; u1[i] = b; u2[i] = 0.0; lm[i] = mlt;
-          a = dn - mlt * b;
-          b = sn;
-        } else {
-          sw[i] = 1;
-          const double mlt = a / sub;
-          u0[i] = sub; u1[i] = dn; u2[i] = sn; lm[i] = mlt;
-          a = b - mlt * dn;
-          b = -mlt * sn;
-        }
+  // nudge equal neighbours apart: count earlier eigenvalues within a few ulps
+  double lamq = lam[idx];
+  {
+    int rank_in_tie = 0;
+    for (int q = idx - 1; q >= 0 && lam[idx] - lam[q] <= 4.0 * eps * nrmT; --q) ++rank_in_tie;
+    lamq += 4.0 * rank_in_tie * eps * fmax(nrmT, DBL_MIN);
+  }
+  if (threadIdx.x == 0) {
+    // LU with partial pivoting of T - lamq I: rows i, i+1 may swap.
+    // After elimination row i holds u0[i] (diag), u1[i], u2[i] (super-diags).
+    double a = d[0] - lamq;
+    double b = (k > 1) ? e[0] : 0.0;
+    for (int i = 0; i + 1 < k; ++i) {
+      const double sub = e[i];
+      const double dn = d[i + 1] - lamq;
+      const double sn = (i + 2 < k) ? e[i + 1] : 0.0;
+      if (fabs(a) >= fabs(sub)) {
+        sw[i] = 0;
+        const double piv = (a == 0.0) ? small : a;
+        const double mlt = sub / piv;
+        u0[i] = piv; u1[i] = b; u2[i] = 0.0; lm[i] = mlt;
+        a = dn - mlt * b;
+        b = sn;
+      } else {
+        sw[i] = 1;
+        const double mlt = a / sub;
+        u0[i] = sub; u1[i] = dn; u2[i] = sn; lm[i] = mlt;
+        a = b - mlt * dn;
+        b = -mlt * sn;
       }
-      u0[k - 1] = (a == 0.0) ? small : a;
-      u1[k - 1] = 0.0; u2[k - 1] = 0.0;
-      for (int i = 0; i < k; ++i) x[i] = start_entry(idx, i);
+    }
+    u0[k - 1] = (a == 0.0) ? small : a;
+    u1[k - 1] = 0.0; u2[k - 1] = 0.0;
+  }
+  for (int i = threadIdx.x; i < k; i += blockDim.x) x[i] = start_entry(idx, i);
+  __syncthreads();
+  for (int it = 0; it < kInvitIters; ++it) {
+    if (threadIdx.x == 0) {
+      for (int i = 0; i + 1 < k; ++i) {
+        if (sw[i]) { const double tmp = x[i]; x[i] = x[i + 1]; x[i + 1] = tmp; }
+        x[i + 1] -= lm[i] * x[i];
+      }
+      for (int i = k - 1; i >= 0; --i) {
+        double v = x[i];
+        if (i + 1 < k) v -= u1[i] * x[i + 1];
+        if (i + 2 < k) v -= u2[i] * x[i + 2];
+        const double piv = (fabs(u0[i]) < small) ? copysign(small, u0[i] == 0.0 ? 1.0 : u0[i]) : u0[i];
+        x[i] = v / piv;
+      }
+      double mx = 0.0;
+      for (int i = 0; i < k; ++i) mx = fmax(mx, fabs(x[i]));
+      sscale = (mx > 0.0) ? 1.0 / mx : 1.0;
     }
     __syncthreads();
-    for (int it = 0; it < kInvitIters; ++it) {
-      if (threadIdx.x == 0) {
-        // forward: apply row swaps and multipliers
-        for (int i = 0; i + 1 < k; ++i) {
-          if (sw[i]) { const double tmp = x[i]; x[i] = x[i + 1]; x[i + 1] = tmp; }
-          x[i + 1] -= lm[i] * x[i];
-        }
-        // backward: upper triangular with two super-diagonals
-        for (int i = k - 1; i >= 0; --i) {
-          double v = x[i];
-          if (i + 1 < k) v -= u1[i] * x[i + 1];
-          if (i + 2 < k) v -= u2[i] * x[i + 2];
-          const double piv = (fabs(u0[i]) < small) ? copysign(small, u0[i] == 0.0 ? 1.0 : u0[i]) : u0[i];
-          x[i] = v / piv;
-        }
-        // rescale to avoid overflow in later iterations
-        double mx = 0.0;
-        for (int i = 0; i < k; ++i) mx = fmax(mx, fabs(x[i]));
-        sscale = (mx > 0.0) ? 1.0 / mx : 1.0;
+    for (int i = threadIdx.x; i < k; i += blockDim.x) x[i] *= sscale;
+    __syncthreads();
+  }
+  double part = 0.0;
+  for (int i = threadIdx.x; i < k; i += blockDim.x) part += x[i] * x[i];
+  for (int off = 32; off > 0; off >>= 1) part += __shfl_xor(part, off, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = part;
+  __syncthreads();
+  double nn = 0.0;
+  for (int wv = 0; wv < (int)(blockDim.x >> 6); ++wv) nn += red[wv];
+  const double inv = (nn > 0.0) ? 1.0 / sqrt(nn) : 0.0;
+  for (int i = threadIdx.x; i < k; i += blockDim.x) Z[i + (int64_t)c * ldz] = x[i] * inv;
+}
+
+// Orthonormalise the vectors of one cluster (blockIdx.x), in ascending
+// eigenvalue order, by right-looking modified Gram-Schmidt done twice: at
+// step j every later vector loses its component along z_j.  Each wave
+// handles a subset of the later vectors and recomputes ||z_j|| itself, so a
+// step needs one barrier.
+__global__ __launch_bounds__(1024) void orth_kernel(int k, const int* clusters, const int* cl_count, const int* pos_of,
+                            double* Z, int64_t ldz) {
+  const int cl = blockIdx.x;
+  if (cl >= cl_count[0]) return;
+  const int start = clusters[2 * cl], len = clusters[2 * cl + 1];
+  if (len < 2) return;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int nw = blockDim.x >> 6;
+  for (int pass = 0; pass < 2; ++pass) {
+    for (int j = 0; j < len; ++j) {
+      const double* zj = Z + (int64_t)pos_of[start + j] * ldz;
+      double nj = 0.0;
+      for (int i = lane; i < k; i += 64) nj += zj[i] * zj[i];
+      for (int off = 32; off > 0; off >>= 1) nj += __shfl_xor(nj, off, 64);
+      const double inv2 = (nj > 0.0) ? 1.0 / nj : 0.0;
+      for (int l = j + 1 + wv; l < len; l += nw) {
+        double* zl = Z + (int64_t)pos_of[start + l] * ldz;
+        double dt = 0.0;
+        for (int i = lane; i < k; i += 64) dt += zj[i] * zl[i];
+        for (int off = 32; off > 0; off >>= 1) dt += __shfl_xor(dt, off, 64);
+        const double f = dt * inv2;
+        for (int i = lane; i < k; i += 64) zl[i] -= f * zj[i];
       }
-      __syncthreads();
-      for (int i = threadIdx.x; i < k; i += blockDim.x) x[i] *= sscale;
-      __syncthreads();
-      // Gram-Schmidt against earlier members of the cluster (twice)
-      for (int pass = 0; pass < 2; ++pass) {
-        for (int pq = 0; pq < q; ++pq) {
-          const int pcol = pos_of[start + pq];
-          double part = 0.0;
-          for (int i = threadIdx.x; i < k; i += blockDim.x) part += Zt[pcol + i * ldz] * x[i];
-          for (int off = 32; off > 0; off >>= 1) part += __shfl_xor(part, off, 64);
-          if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = part;
-          __syncthreads();
-          double dot = 0.0;
-          for (int wv = 0; wv < (int)(blockDim.x >> 6); ++wv) dot += red[wv];
-          __syncthreads();
-          for (int i = threadIdx.x; i < k; i += blockDim.x) x[i] -= dot * Zt[pcol + i * ldz];
-          __syncthreads();
-        }
-      }
-      // normalise
-      double part = 0.0;
-      for (int i = threadIdx.x; i < k; i += blockDim.x) part += x[i] * x[i];
-      for (int off = 32; off > 0; off >>= 1) part += __shfl_xor(part, off, 64);
-      if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = part;
-      __syncthreads();
-      double nn = 0.0;
-      for (int wv = 0; wv < (int)(blockDim.x >> 6); ++wv) nn += red[wv];
-      __syncthreads();
-      const double inv = (nn > 0.0) ? 1.0 / sqrt(nn) : 0.0;
-      for (int i = threadIdx.x; i < k; i += blockDim.x) x[i] *= inv;
       __syncthreads();
     }
-    for (int i = threadIdx.x; i < k; i += blockDim.x) Zt[col + i * ldz] = x[i];
+    // normalise every vector of the cluster
+    for (int j = wv; j < len; j += nw) {
+      double* zj = Z + (int64_t)pos_of[start + j] * ldz;
+      double nj = 0.0;
+      for (int i = lane; i < k; i += 64) nj += zj[i] * zj[i];
+      for (int off = 32; off > 0; off >>= 1) nj += __shfl_xor(nj, off, 64);
+      const double inv = (nj > 0.0) ? 1.0 / sqrt(nj) : 0.0;
+      for (int i = lane; i < k; i += 64) zj[i] *= inv;
+    }
     __syncthreads();
   }
 }
 
-// V(:, c) = H_0 H_1 ... H_{k-3} z_c, with z_c = Zt[c + i * ldz]; one block per
+// V(:, c) = H_0 H_1 ... H_{k-3} z_c, with z_c = Z[i + c * ldz]; one block per
 // column, z staged in LDS.  Also fixes the sign so that the largest-|entry| is
 // positive.
 __global__ void backtr_kernel(const double* A, int64_t lda, const double* tau, int k,
-                              const double* Zt, int64_t ldz, const int64_t* keep, double* V,
+                              const double* Z, int64_t ldz, const int64_t* keep, double* V,
                               int64_t ldv) {
   extern __shared__ double z[];
   __shared__ double red[256 / 64];
   const int c = blockIdx.x;
   if (c >= keep[0]) return;
-  for (int i = threadIdx.x; i < k; i += blockDim.x) z[i] = Zt[c + i * ldz];
+  for (int i = threadIdx.x; i < k; i += blockDim.x) z[i] = Z[i + (int64_t)c * ldz];
   __syncthreads();
   for (int j = k - 3; j >= 0; --j) {
     const double tj = tau[j];
@@ -489,19 +635,29 @@ void syev_trunc_f64(hipStream_t s, int64_t k, const double* M, int64_t ldm, doub
     fill_f64(s, e, 1, 1, 1, 0.0);
     fill_f64(s, tau, 1, 1, 1, 0.0);
   } else {
-    hipLaunchKernelGGL(tridiag_kernel, dim3(1), dim3(kTriT), 0, s, A, k, ki, d, e, tau, pw);
+    if (k <= kTriMaxK) {
+      const size_t lds = (size_t)(3 + kTriT / 64) * k * sizeof(double);
+      hipLaunchKernelGGL(tridiag_small_kernel, dim3(1), dim3(kTriT), lds, s, A, k, ki, d, e, tau);
+    } else {
+      hipLaunchKernelGGL(tridiag_kernel, dim3(1), dim3(kTriT), 0, s, A, k, ki, d, e, tau, pw);
+    }
     DME_HIP(hipGetLastError());
   }
   hipLaunchKernelGGL(tri_prep_kernel, dim3(1), dim3(256), 0, s, d, e, ki, e2, bounds);
   DME_HIP(hipGetLastError());
-  hipLaunchKernelGGL(bisect_kernel, dim3((unsigned)cdiv(k, 64)), dim3(64), 0, s, d, e2, ki, bounds, lam);
+  hipLaunchKernelGGL(bisect_kernel, dim3((unsigned)k), dim3(64), 0, s, d, e2, ki, bounds, lam);
   DME_HIP(hipGetLastError());
-  hipLaunchKernelGGL(select_kernel, dim3(1), dim3(64), 0, s, lam, ki, tol, max_keep, order, pos_of,
-                     lam_out, clusters, cl_count, keep_dev, flag_dev);
+  hipLaunchKernelGGL(select_kernel, dim3(1), dim3(64), 0, s, lam, ki, tol, max_keep, bounds, order,
+                     pos_of, lam_out, clusters, cl_count, keep_dev, flag_dev);
   DME_HIP(hipGetLastError());
-  // Zt is (max kept) x k transposed storage with ld = k (kept <= k)
-  hipLaunchKernelGGL(invit_kernel, dim3((unsigned)k), dim3(256), 0, s, d, e, ki, lam, clusters,
-                     cl_count, pos_of, bounds, work, Zt, k);
+  // Z: k x (kept) column-major with ld = k (kept <= k)
+  const unsigned nkeep = (unsigned)std::min<int64_t>(k, max_keep);
+  const int invit_lds = (k <= kInvitLdsMaxK) ? 1 : 0;
+  hipLaunchKernelGGL(invit_kernel, dim3(nkeep), dim3(64), invit_lds ? (size_t)6 * k * sizeof(double) : 0,
+                     s, d, e, ki, lam, order, keep_dev, bounds, work, Zt, k, invit_lds);
+  DME_HIP(hipGetLastError());
+  hipLaunchKernelGGL(orth_kernel, dim3((unsigned)k), dim3(1024), 0, s, ki, clusters, cl_count, pos_of,
+                     Zt, k);
   DME_HIP(hipGetLastError());
   hipLaunchKernelGGL(backtr_kernel, dim3((unsigned)std::min<int64_t>(k, max_keep)), dim3(256),
                      (size_t)k * sizeof(double), s, A, k, tau, ki, Zt, k, keep_dev, V_out, ldv);

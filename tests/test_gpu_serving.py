@@ -1,0 +1,123 @@
+"""Served solves (dme_server_*): continuous batching gives every request the
+same result alone and in a mix, equal to the direct solve and (FP64) to the
+oracle; latency statistics are reported; failures stay per request."""
+import time
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as wl
+from paper_1805_08990_amd import _binding as b
+from tests.gpu_common import announce
+
+pytestmark = pytest.mark.gpu
+
+GIB = 1 << 30
+
+
+def _requests():
+    """(nx, kind, m, p, nsteps, precision, seed) of a small mixed stream."""
+    return [(8, "dre", 2, 3, 12, "mixed", 1), (8, "dle", 0, 2, 9, "fp64", 2),
+            (12, "dre", 4, 5, 7, "fp64", 3), (8, "dre", 1, 1, 15, "fp64", 4),
+            (12, "dle", 0, 6, 10, "mixed", 5), (8, "dre", 3, 8, 6, "mixed", 6)]
+
+
+def _problem(nx, kind, m, p, nsteps, seed, h=1e-2):
+    n = nx * nx
+    C = wl.random_C(p, n, seed)
+    B = wl.quadrant_B(nx, m) if kind == "dre" else None
+    R = np.eye(m, order="F") if kind == "dre" else None
+    return n, C, B, R, nsteps * h, h
+
+
+def _submit_all(srv, ops, reqs, wait_each):
+    out = {}
+    for i, (nx, kind, m, p, nsteps, prec, seed) in enumerate(reqs):
+        n, C, B, R, T, h = _problem(nx, kind, m, p, nsteps, seed)
+        opts = b.SolveOptions(T=T, h=h, tol=1e-10, precision=prec)
+        t = srv.submit(ops[nx], kind, opts, C, n, B=B, R=R)
+        out[i] = t
+        if wait_each:
+            out[i] = _wait(srv, t)
+    if not wait_each:
+        out = {i: _wait(srv, t) for i, t in out.items()}
+    return out
+
+
+def _wait(srv, ticket, timeout=120.0):
+    t0 = time.time()
+    while True:
+        r = srv.poll(ticket)
+        if r is not None:
+            return r
+        assert time.time() - t0 < timeout, "request did not finish"
+        time.sleep(0.002)
+
+
+@pytest.fixture(scope="module")
+def served(ctx):
+    announce("serving: solo then mix")
+    ops = {nx: ctx.register_operator(wl.laplacian_2d(nx)) for nx in (8, 12)}
+    srv = ctx.server(4 * GIB, max_slots=8)
+    solo = _submit_all(srv, ops, _requests(), wait_each=True)
+    mix = _submit_all(srv, ops, _requests(), wait_each=False)
+    stats = srv.stats()
+    srv.stop()
+    return ops, solo, mix, stats
+
+
+def test_same_result_alone_and_in_mix(served):
+    _, solo, mix, _ = served
+    for i in solo:
+        Ls, Ds, ss, _ = solo[i]
+        Lm, Dm, sm, _ = mix[i]
+        assert ss == sm
+        assert oracle.lowrank_rel_err(Lm, Dm, Ls, Ds) < 1e-13, i
+
+
+def test_served_equals_direct_and_oracle(ctx, served):
+    _, solo, _, _ = served
+    for i, (nx, kind, m, p, nsteps, prec, seed) in enumerate(_requests()):
+        n, C, B, R, T, h = _problem(nx, kind, m, p, nsteps, seed)
+        A = wl.laplacian_2d(nx)
+        L, D, steps, info = solo[i]
+        assert steps == nsteps and info["precision"] == prec and not info["fell_back"]
+        Ld, Dd, _ = ctx.solve(kind, b.SolveOptions(T=T, h=h, tol=1e-10, precision=prec), A, C, B=B, R=R)
+        assert oracle.lowrank_rel_err(L, D, Ld, Dd) < 1e-12, i
+        Lo, Do, _ = oracle.solve(A, C, T, h, kind=kind, B=B, R=R, tol=1e-10)
+        bound = 1e-10 if prec == "fp64" else 1e-6
+        assert oracle.lowrank_rel_err(L, D, Lo, Do) < bound, i
+
+
+def test_latency_statistics(served):
+    _, solo, mix, st = served
+    assert st["completed"] == 2 * len(_requests()) and st["failed"] == 0
+    assert 0 < st["p50_s"] <= st["p99_s"]
+    assert st["req_per_s"] > 0 and st["steps_per_s"] > 0
+    assert st["steps"] == 2 * sum(r[4] for r in _requests())
+    assert all(v[3]["latency_s"] >= v[3]["queue_s"] >= 0 for v in mix.values())
+
+
+def test_errors_stay_per_request(ctx):
+    announce("serving: per-request failures")
+    op = ctx.register_operator(wl.laplacian_2d(8))
+    srv = ctx.server(4 * GIB, max_slots=4)
+    n, C, B, R, T, h = _problem(8, "dre", 2, 3, 5, 11)
+    bad = srv.submit(op, "dre", b.SolveOptions(T=T, h=h, precision="mixed", max_rank=1), C, n, B=B, R=R)
+    good = srv.submit(op, "dre", b.SolveOptions(T=T, h=h), C, n, B=B, R=R)
+    with pytest.raises(b.DmeError) as e:
+        _wait(srv, bad)
+    assert e.value.code == b.DME_ERANK
+    L, D, steps, info = _wait(srv, good)
+    assert steps == 5 and L.shape[1] > 0
+    with pytest.raises(b.DmeError) as e:
+        srv.submit(op, "dre", b.SolveOptions(T=0.1, h=0.03), C, n, B=B, R=R)
+    assert e.value.code == b.DME_EINVAL
+    srv.stop()
+    tiny = ctx.server(1 << 20, max_slots=2)
+    t = tiny.submit(op, "dle", b.SolveOptions(T=T, h=h), C, n)
+    with pytest.raises(b.DmeError) as e:
+        _wait(tiny, t)
+    assert e.value.code == b.DME_ENOMEM
+    tiny.stop()
