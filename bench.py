@@ -1,27 +1,28 @@
-"""Benchmark: DRE Strang steps/s at n = 16384 on one MI355X, FP64 and mixed.
+"""Benchmark: DRE Strang steps/s at n = 16384 on one MI355X, FP64 and mixed
+precision, plus served latency (p50/p99) of a continuous-batching request mix.
 
-Workload (the paper's heat-equation Riccati setting, Sec. 5.1, at the size
-named by the headline metric): A = 5-point Dirichlet Laplacian on a 128 x 128
-grid (n = 16384) scaled by 1/dx^2; B = the four quadrant indicators (n x 4);
+Workload (the heat-equation Riccati setting of the paper's Sec. 5.1 at the size
+of the headline metric): A = 5-point Dirichlet Laplacian on a 128 x 128 grid
+(n = 16384) scaled by 1/dx^2; B = the four quadrant indicators (n x 4);
 R = I_4; C = 8 x n with i.i.d. N(0,1)/sqrt(n) entries (numpy default_rng(0));
-P0 = 0; h = 1e-3 (T = 0.1, N = 100); two-term Strang splitting
-T12(h/2) T3(h) T12(h/2) with a 7-node Gauss-Legendre quadrature factor;
-compression tolerance 1e-10.
+P0 = 0; h = 1e-3; two-term Strang splitting T12(h/2) T3(h) T12(h/2) with a
+7-node Gauss-Legendre quadrature factor; compression tolerance 1e-10.
 
 A "step" is one Strang time step of the whole hot path (two e^{(h/2)A^T} L
-products, two compressions, one Riccati update) with all operands resident in
-HBM.  Setup (operator and quadrature factor) is done once before the timed
-region and reported separately.  --warmup W steps run untimed, then exactly
+products, two compressions, one Riccati update) with every operand resident
+in HBM.  Setup (operator and quadrature factor) runs once before the timed
+region and is reported separately.  --warmup W steps run untimed, then exactly
 --steps K are timed between two device synchronisations.
 
-Printed: one JSON line with the throughput of the (default) precision, the
-roofline position of the dominant kernel (the step product e^{tA^T} L,
-FP64 MFMA-bound) from HIP events recorded by the library on its own stream,
-and the CPU oracle timed on a bounded sample of the same workload.
+Printed: one JSON line.  `value` is the mixed-precision steps/s (FP64 beside
+it), `roofline` is the step product's main kernel timed with HIP events on the
+library's stream inside the timed region, `cpu_baseline` the CPU oracle on a
+bounded sample of the same workload, `serving` the request-mix statistics.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -34,20 +35,32 @@ if ROOT not in sys.path:
 PEAK_FP64_TFLOPS = 78.6      # MI355X dense FP64 matrix
 PEAK_BF16_TFLOPS = 2500.0    # MI355X dense BF16 matrix
 PEAK_HBM_GBS = 8000.0        # MI355X HBM3E
+GIB = 1 << 30
+
+KERNEL_SOURCES = {
+    "gemm_mixed_kernel": "paper_1805_08990_amd/csrc/gemm_mixed.hip",
+    "gemm_f64_skinny_kernel": "paper_1805_08990_amd/csrc/gemm_f64.hip",
+}
 
 
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=90)
-    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--steps", type=int, default=40)
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--nx", type=int, default=128, help="grid side (n = nx^2)")
-    ap.add_argument("--precision", choices=["fp64", "mixed", "both"], default="fp64")
+    ap.add_argument("--precision", choices=["fp64", "mixed", "both"], default="both")
     ap.add_argument("--cpu-seconds", type=float, default=20.0,
                     help="budget for the CPU oracle sample (0 disables it)")
-    ap.add_argument("--no-profile", action="store_true",
-                    help="skip the per-launch event timing of the step product")
+    ap.add_argument("--serve-requests", type=int, default=48,
+                    help="requests in the served mix (0 disables the serving leg)")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run one device copy of known size (counter calibration)")
     return ap.parse_args()
+
+
+def log(msg):
+    print(f"[bench] {msg}", flush=True)
 
 
 def workload(nx):
@@ -55,54 +68,78 @@ def workload(nx):
     return wl.config_dre_quadrant(nx=nx, seed=0, p=8, m=4, T=0.1, h=1e-3)
 
 
-def run_gpu(prob, precision, steps, warmup, profile=True):
+def run_gpu(ctx, prob, precision, steps, warmup):
     import torch
     from paper_1805_08990_amd import _binding as b
 
-    ctx = b.Context(0)
     opts = b.SolveOptions(T=prob.T, h=prob.h, tol=prob.tol, scheme="strang", split="F12",
                           precision=precision, quad_nodes=prob.quad_nodes)
+    log(f"{precision}: setup (operator e^(h/2 A^T), {prob.quad_nodes} node exponentials)")
     t0 = time.perf_counter()
     sv = ctx.solver("dre", opts, prob.A, prob.C, B=prob.B, R=prob.R)
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
     setup = sv.setup_info()
-    print(f"[bench] {precision}: setup {setup_s:.2f} s (expm {setup['expm_ms']:.0f} ms, "
-          f"quadrature {setup['quad_ms']:.0f} ms, rank L_I {setup['rank_quad']})", flush=True)
+    log(f"{precision}: setup {setup_s:.2f} s (expm {setup['expm_ms']:.0f} ms, quadrature "
+        f"{setup['quad_ms']:.0f} ms, rank L_I {setup['rank_quad']})")
     if warmup:
         sv.step(warmup)
     torch.cuda.synchronize()
-    if profile:
-        sv.profile(True)
+    sv.profile(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     sv.step(steps)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     st, tot, rank = sv.state()
-    prof = {ph: sv.profile_get(ph) for ph in ("step_gemm", "compress", "riccati")} if profile else {}
-    print(f"[bench] {precision}: {steps} steps in {elapsed:.3f} s, rank {rank}", flush=True)
+    prof = {ph: sv.profile_get(ph) for ph in ("step_gemm", "step_kernel", "compress", "riccati")}
+    log(f"{precision}: {steps} steps in {elapsed:.3f} s ({steps / elapsed:.1f} steps/s), rank {rank}")
+    L, D, _ = sv.result()
     sv.close()
-    ctx.close()
-    return {"elapsed_s": elapsed, "setup_s": setup_s, "setup": setup, "rank": rank, "prof": prof}
+    return {"elapsed_s": elapsed, "setup_s": setup_s, "setup": setup, "rank": rank, "prof": prof,
+            "L": L, "D": D}
+
+
+def kernel_source_hash(kernel):
+    path = os.path.join(ROOT, KERNEL_SOURCES[kernel])
+    with open(path, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed counter summary, if
+    it was taken on the current source of the kernel (else None)."""
+    path = os.path.join(ROOT, "profiles", f"{kernel}_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    if rec.get("source_sha256_16") != kernel_source_hash(kernel):
+        return None
+    return rec.get("bytes_per_launch")
 
 
 def roofline_from(prof, precision):
-    g = prof.get("step_gemm")
+    g = prof.get("step_kernel")
     if not g or g["count"] == 0 or g["ms"] <= 0:
         return None
-    avg_ms = g["ms"] / g["count"]
+    avg_s = g["ms"] / g["count"] * 1e-3
     if precision == "fp64":
-        achieved = g["flops"] / g["count"] / (avg_ms * 1e-3) / 1e12
-        return {"bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK_FP64_TFLOPS,
-                "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP64_TFLOPS, 4), "traffic": None,
-                "kernel": "gemm_f64 (e^{tA^T} L)", "avg_launch_ms": round(avg_ms, 4),
-                "launches": g["count"]}
-    achieved = g["bytes"] / g["count"] / (avg_ms * 1e-3) / 1e9
-    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
-            "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": None,
-            "kernel": "gemm split-bf16 (e^{tA^T} L)", "avg_launch_ms": round(avg_ms, 4),
-            "launches": g["count"]}
+        kernel = "gemm_f64_skinny_kernel"
+        achieved = g["flops"] / g["count"] / avg_s / 1e12
+        out = {"bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK_FP64_TFLOPS,
+               "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP64_TFLOPS, 4)}
+    else:
+        # the FP32 operator is streamed once per launch: HBM-bound form
+        kernel = "gemm_mixed_kernel"
+        achieved = g["bytes"] / g["count"] / avg_s / 1e9
+        out = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+               "frac": round(achieved / PEAK_HBM_GBS, 4)}
+    out["traffic"] = measured_traffic(kernel)
+    out.update({"kernel": kernel, "avg_launch_ms": round(avg_s * 1e3, 4), "launches": g["count"],
+                "algorithmic_per_launch": {"flops": g["flops"] / g["count"],
+                                           "bytes": g["bytes"] / g["count"]}})
+    return out
 
 
 def cpu_baseline(prob, budget_s):
@@ -139,22 +176,108 @@ def cpu_baseline(prob, budget_s):
             "elapsed_s": round(el, 2)}
 
 
+def serve_mix(ctx, count, seed=7):
+    """Served request mix: grid sides in {32, 48, 64, 96, 128}, DLE or DRE,
+    m in 1..4, p in 1..8, N in 50..200 steps of h = 1e-3, mixed precision.
+    Capacity is measured first with a burst of count/2 requests, then `count`
+    requests arrive as a Poisson stream at 0.7 x capacity."""
+    import numpy as np
+    import workloads as wl
+    from paper_1805_08990_amd import _binding as b
+
+    sides = wl.SERVE_GRID_SIDES
+    h = 1e-3
+    srv = ctx.server(160 * GIB, max_slots=16)
+    ops = {}
+    t0 = time.perf_counter()
+    for nx in sides:
+        ops[nx] = ctx.register_operator(wl.laplacian_2d(nx))
+        for t in (0.5 * h, h):  # DRE Strang half step, DLE full step
+            srv.warm(ops[nx], t, "mixed", 7)
+        log(f"serving: operator nx={nx} warm ({time.perf_counter() - t0:.1f} s)")
+    warm_s = time.perf_counter() - t0
+
+    def submit(req):
+        p = wl.request_problem(req)
+        opts = b.SolveOptions(T=p.T, h=h, tol=p.tol, scheme="strang", split="F12", precision="mixed")
+        return srv.submit(ops[req.nx], p.kind, opts, p.C, p.n, B=p.B, R=p.R)
+
+    def drain(tickets):
+        res = {}
+        while len(res) < len(tickets):
+            for i, tk in tickets.items():
+                if i not in res:
+                    r = srv.poll(tk)
+                    if r is not None:
+                        res[i] = r
+            time.sleep(0.001)
+        return res
+
+    # capacity: a burst
+    burst = wl.request_stream(max(1, count // 2), rate_per_s=1e9, base_seed=5000, stream_seed=seed)
+    t0 = time.perf_counter()
+    tickets = {r.index: submit(r) for r in burst}
+    drain(tickets)
+    cap = len(burst) / (time.perf_counter() - t0)
+    log(f"serving: capacity {cap:.2f} requests/s from a burst of {len(burst)}")
+
+    # Poisson arrivals at 0.7 x capacity
+    rate = 0.7 * cap
+    stream = wl.request_stream(count, rate_per_s=rate, base_seed=1000, stream_seed=seed)
+    t0 = time.perf_counter()
+    tickets = {}
+    for r in stream:
+        wait = r.arrival_s - (time.perf_counter() - t0)
+        if wait > 0:
+            time.sleep(wait)
+        tickets[r.index] = submit(r)
+    res = drain(tickets)
+    span = time.perf_counter() - t0
+    st = srv.stats()
+    srv.stop()
+    lat = np.array([res[r.index][3]["latency_s"] for r in stream])
+    queue = np.array([res[r.index][3]["queue_s"] for r in stream])
+    fell = sum(1 for v in res.values() if v[3]["fell_back"])
+    steps = sum(r.nsteps for r in stream)
+    log(f"serving: {count} requests at {rate:.2f}/s, p50 {np.percentile(lat, 50):.3f} s, "
+        f"p99 {np.percentile(lat, 99):.3f} s")
+    return {"requests": count, "arrival_rate_per_s": round(rate, 3), "capacity_req_per_s": round(cap, 3),
+            "p50_s": round(float(np.percentile(lat, 50)), 4), "p99_s": round(float(np.percentile(lat, 99)), 4),
+            "mean_latency_s": round(float(lat.mean()), 4),
+            "queue_p50_s": round(float(np.percentile(queue, 50)), 4),
+            "req_per_s": round(count / span, 3), "steps_per_s": round(steps / span, 1),
+            "failed": st["failed"], "fallbacks": fell, "cold_builds": st["cold_builds"],
+            "warm_operators_s": round(warm_s, 1), "max_slots": 16, "hbm_budget_gib": 160,
+            "peak_ledger_gib": round(st["peak_bytes"] / GIB, 2)}
+
+
 def main():
     args = parse()
-    if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
-              "(the path would shard E row-wise across GPUs, see the design notes)", file=sys.stderr)
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print(f"bench.py runs on one GPU; --gpus {args.gpus} is not supported (the design notes "
+              "describe how the path would shard across GPUs)", file=sys.stderr)
         sys.exit(2)
+    import torch
+    import oracle
+    from paper_1805_08990_amd import _binding as b
+
     prob = workload(args.nx)
+    ctx = b.Context(0)
+    if args.calibrate_copy:
+        # one plain device copy of 1 GiB, for the HBM counter calibration
+        x = torch.ones(GIB // 8, dtype=torch.float64, device="cuda")
+        y = torch.empty_like(x)
+        torch.cuda.synchronize()
+        y.copy_(x)
+        torch.cuda.synchronize()
+        del x, y
     precisions = ["fp64", "mixed"] if args.precision == "both" else [args.precision]
-    results = {}
-    for prec in precisions:
-        results[prec] = run_gpu(prob, prec, args.steps, args.warmup, profile=not args.no_profile)
-    main_prec = precisions[-1]
+    results = {p: run_gpu(ctx, prob, p, args.steps, args.warmup) for p in precisions}
+    main_prec = "mixed" if "mixed" in results else "fp64"
     res = results[main_prec]
     value = args.steps / res["elapsed_s"]
     line = {
-        "metric": "DRE Strang steps/s at n=16384 (two-term splitting, quadrature linear part)",
+        "metric": "DRE Strang steps/s at n=16384, FP64 vs mixed; p50/p99 served latency",
         "value": round(value, 4),
         "unit": "steps/s",
         "n_gpus": 1,
@@ -164,21 +287,33 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if main_prec == "fp64" else "bf16-split x3 + f32 acc + f64",
+        "dtype": "f64" if main_prec == "fp64" else "bf16x3-split/f32-acc products, f64 elsewhere",
         "data": "synthetic",
         "config": {"workload": f"dre_strang_f12f3_quadrant_n{prob.n}", "n": prob.n, "m": 4, "p": 8,
-                   "h": prob.h, "T": prob.T, "tol": prob.tol, "quad_nodes": prob.quad_nodes,
+                   "h": prob.h, "tol": prob.tol, "quad_nodes": prob.quad_nodes,
                    "precision": main_prec, "rank_end": res["rank"],
                    "setup_s": round(res["setup_s"], 3)},
         "roofline": roofline_from(res["prof"], main_prec),
     }
     for prec, r in results.items():
         line[f"{prec}_steps_per_s"] = round(args.steps / r["elapsed_s"], 4)
-        line[f"{prec}_phases_ms"] = {k: round(v["ms"], 3) for k, v in r["prof"].items()}
+        line[f"{prec}_phase_ms_per_step"] = {k: round(v["ms"] / args.steps, 4)
+                                             for k, v in r["prof"].items()}
+        if prec != main_prec:
+            line[f"roofline_{prec}"] = roofline_from(r["prof"], prec)
+    if "fp64" in results and "mixed" in results:
+        rf, rm = results["fp64"], results["mixed"]
+        line["mixed_vs_fp64_rel_err"] = float(oracle.lowrank_rel_err(rm["L"], rm["D"], rf["L"], rf["D"]))
+    if args.serve_requests > 0:
+        try:
+            line["serving"] = serve_mix(ctx, args.serve_requests)
+        except Exception as e:  # the steps/s line is still reported
+            line["serving"] = {"error": str(e)}
     if args.cpu_seconds > 0:
         line["cpu_baseline"] = cpu_baseline(prob, args.cpu_seconds)
     else:
         line["cpu_baseline"] = None
+    ctx.close()
     print(json.dumps(line), flush=True)
 
 

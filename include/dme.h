@@ -97,8 +97,9 @@ typedef struct {
 } dme_opts;
 
 /* ------------------------------------------------------------- context */
-/* Create a context on HIP device `device`.  `stream` is a hipStream_t to
- * enqueue on, or NULL for a library-owned stream. */
+/* Create a context on HIP device `device`.  `stream` is the hipStream_t the
+ * context enqueues on (NULL: the null stream); it stays owned by the caller
+ * and must outlive the context. */
 int dme_create(dme_ctx **ctx, int device, void *stream);
 void dme_destroy(dme_ctx *ctx);
 const char *dme_strerror(int code);
@@ -135,6 +136,9 @@ int dme_solver_result(dme_solver *sv, dme_result **out);
 #define DME_PHASE_COMPRESS 1
 #define DME_PHASE_RICCATI 2
 #define DME_PHASE_S 3
+/* the main kernel of each step product alone (skinny FP64 or split-BF16),
+ * with the algorithmic work of that launch                                 */
+#define DME_PHASE_STEP_KERNEL 4
 int dme_solver_profile(dme_solver *sv, int enable);
 int dme_solver_profile_get(dme_solver *sv, int phase, int64_t *count, double *ms, double *flops,
                            double *bytes);

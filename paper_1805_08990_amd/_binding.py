@@ -94,7 +94,7 @@ _lib_solver_profile = _sig("dme_solver_profile", _int, [_p, _int])
 _lib_solver_profile_get = _sig("dme_solver_profile_get", _int,
                                [_p, _int, ctypes.POINTER(_i64), ctypes.POINTER(_dbl),
                                 ctypes.POINTER(_dbl), ctypes.POINTER(_dbl)])
-PHASES = {"step_gemm": 0, "compress": 1, "riccati": 2, "S": 3}
+PHASES = {"step_gemm": 0, "compress": 1, "riccati": 2, "S": 3, "step_kernel": 4}
 _lib_result_info = _sig("dme_result_info", _int,
                         [_p, ctypes.POINTER(_i64), ctypes.POINTER(_i64), ctypes.POINTER(_i64)])
 _lib_result_copy = _sig("dme_result_copy", _int, [_p, _p, _p])

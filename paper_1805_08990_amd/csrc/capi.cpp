@@ -29,6 +29,11 @@ void DevBuf::release() {
   bytes = 0;
 }
 
+KernelTimer*& kernel_timer() {
+  thread_local KernelTimer* t = nullptr;
+  return t;
+}
+
 dme_result* result_from_solver(Solver& sv) {
   auto res = std::make_unique<dme_result>();
   res->n = sv.n;
@@ -137,12 +142,9 @@ int dme_create(dme_ctx** ctx, int device, void* stream) {
     DME_HIP(hipSetDevice(device));
     auto c = std::make_unique<dme_ctx>();
     c->device = device;
-    if (stream) {
-      c->stream = static_cast<hipStream_t>(stream);
-    } else {
-      DME_HIP(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
-      c->own_stream = true;
-    }
+    // NULL is the null (default) stream, which is what PyTorch's current
+    // stream usually is: the library then orders with the caller's work
+    c->stream = static_cast<hipStream_t>(stream);
     c->flags.ensure(64);
     *ctx = c.release();
   });
@@ -227,7 +229,7 @@ int dme_solver_profile(dme_solver* sv, int enable) {
 int dme_solver_profile_get(dme_solver* sv, int phase, int64_t* count, double* ms, double* flops,
                            double* bytes) {
   return guarded([&] {
-    DME_REQUIRE(sv != nullptr && phase >= 0 && phase < 4, DME_EINVAL, "bad solver or phase");
+    DME_REQUIRE(sv != nullptr && phase >= 0 && phase < 5, DME_EINVAL, "bad solver or phase");
     DME_HIP(hipSetDevice(sv->sv.device));
     sv->sv.flush_timings();
     const dme::PhaseAcc& a = sv->sv.phase[phase];

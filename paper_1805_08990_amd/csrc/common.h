@@ -74,6 +74,18 @@ struct Arena {
   }
 };
 
+// Optional hook around the main kernel of the step product (the skinny FP64
+// kernel or the split-BF16 kernel): a caller that wants that one kernel's
+// device time installs it for the current host thread; the launcher calls
+// before() and after() on the launch stream with the product's shape
+// (Y = E X, E m x k, X k x ncols) and the bytes per entry of E.
+struct KernelTimer {
+  virtual ~KernelTimer() = default;
+  virtual void before(hipStream_t s) = 0;
+  virtual void after(hipStream_t s, int64_t m, int64_t ncols, int64_t k, int e_bytes) = 0;
+};
+KernelTimer*& kernel_timer();
+
 // ---------------------------------------------------------------------------
 // Kernel launchers (each in its own .hip file)
 // ---------------------------------------------------------------------------

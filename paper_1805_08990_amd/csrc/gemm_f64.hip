@@ -343,6 +343,8 @@ void gemm_f64_skinny(hipStream_t s, int M, int N, int K, double alpha, const dou
   const int ns = skinny_nsplit(M, K);
   const int kchunk = (int)(cdiv(cdiv(K, ns), kSkBK) * kSkBK);
   const int tn = (int)cdiv(N, 16);
+  KernelTimer* kt = kernel_timer();
+  if (kt) kt->before(s);
   switch (tn) {
 #define DME_SKINNY_CASE(T) \
   case T: launch_skinny<T>(s, M, N, K, ns, kchunk, A, lda, B, ldb, partial); break;
@@ -354,6 +356,7 @@ void gemm_f64_skinny(hipStream_t s, int M, int N, int K, double alpha, const dou
     default: fail(DME_EINTERNAL, "skinny gemm: bad tile count");
   }
   DME_HIP(hipGetLastError());
+  if (kt) kt->after(s, M, N, K, (int)sizeof(double));
   const int64_t total = (int64_t)M * N;
   const int blocks = (int)std::min<int64_t>(cdiv(total, 256), 8192);
   hipLaunchKernelGGL(skinny_reduce_kernel, dim3(blocks), dim3(256), 0, s, M, N, ns, alpha, partial,

@@ -344,6 +344,8 @@ void gemm_mixed(hipStream_t s, const MixedOp& op, const double* X, int64_t ldx, 
                        dim3(256), 0, s, X + c0 * ldx, ldx, n, rc, op.lde, rpad, Xs);
     DME_HIP(hipGetLastError());
     const float* Et = op.Et.as<float>();
+    KernelTimer* kt = kernel_timer();
+    if (kt) kt->before(s);
     switch (tn) {
 #define DME_MIXED_CASE(T) \
   case T: launch_mixed<T>(s, n, op.lde, rpad, ns, kchunk, Et, Xs, rc, partial); break;
@@ -355,6 +357,7 @@ void gemm_mixed(hipStream_t s, const MixedOp& op, const double* X, int64_t ldx, 
       default: fail(DME_EINTERNAL, "mixed gemm: bad tile count");
     }
     DME_HIP(hipGetLastError());
+    if (kt) kt->after(s, n, rc, n, (int)sizeof(float));
     hipLaunchKernelGGL(mixed_reduce_kernel, dim3((unsigned)std::min<int64_t>(cdiv(n * rc, 256), 8192)),
                        dim3(256), 0, s, partial, n, rc, ns, Y + c0 * ldy, ldy);
     DME_HIP(hipGetLastError());

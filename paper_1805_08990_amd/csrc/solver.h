@@ -114,7 +114,7 @@ struct Solver {
   int64_t rank_quad = 0;
 
   bool profiling = false;
-  PhaseAcc phase[4];
+  PhaseAcc phase[5];
   std::vector<PendingTiming> pending;
   std::vector<hipEvent_t> event_pool;
   hipEvent_t mark_begin();

@@ -406,8 +406,28 @@ void Solver::build_quadrature(double t) {
   check_flags("quadrature factor");
 }
 
+namespace {
+// Times the main kernel of each step product into phase DME_PHASE_STEP_KERNEL
+// with the method's algorithmic work of that launch: 2 m k ncols flops; E
+// read once plus X read and Y written in FP64.
+struct StepKernelTimer : KernelTimer {
+  Solver* sv = nullptr;
+  hipEvent_t a = nullptr;
+  void before(hipStream_t) override { a = sv->mark_begin(); }
+  void after(hipStream_t, int64_t m, int64_t ncols, int64_t k, int e_bytes) override {
+    sv->mark_end(DME_PHASE_STEP_KERNEL, a, 2.0 * m * k * ncols,
+                 (double)e_bytes * m * k + 8.0 * ((double)k * ncols + (double)m * ncols));
+    a = nullptr;
+  }
+};
+}  // namespace
+
 void Solver::apply_E(double t, const double* X, int64_t rr, double* Y, int64_t ldy) {
   ws.reset();
+  StepKernelTimer kt;
+  kt.sv = this;
+  KernelTimer* prev = kernel_timer();
+  if (profiling) kernel_timer() = &kt;
   hipEvent_t ev = mark_begin();
   if (opts.precision == DME_MIXED) {
     gemm_mixed(s, *ops.at(t)->mix, X, n, rr, Y, ldy, ws);
@@ -418,6 +438,7 @@ void Solver::apply_E(double t, const double* X, int64_t rr, double* Y, int64_t l
     // algorithmic work of Y = E X: 2 n^2 r flops; E read once, X read, Y written
     mark_end(0, ev, 2.0 * n * n * rr, 8.0 * ((double)n * n + 2.0 * n * rr));
   }
+  kernel_timer() = prev;
 }
 
 void Solver::compress_into(int64_t k) {

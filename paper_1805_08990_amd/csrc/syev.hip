@@ -48,6 +48,147 @@ __device__ inline double block_sum_1024(double v, double* red) {
   return tot;
 }
 
+// Householder tridiagonalisation with the whole matrix in registers, for
+// k <= 32 RB: the 1024 threads form a 32 x 32 grid and thread (a, b) holds the
+// RB x RB block of rows a RB .. and columns b RB ..  A step broadcasts column j
+// through LDS, wave 0 forms the reflector, the product p = tau A22 v is summed
+// across the 32 column owners of a row block with lane shuffles (they share a
+// wave), and the rank-2 update touches registers only.  The reflector vectors
+// are written to A(j+2:, j) at the end, as in tridiag_kernel.
+template <int RBR, int RBC, int NT>
+__global__ __launch_bounds__(NT) void tridiag_reg_kernel(double* A, int64_t lda, int k, double* d,
+                                                           double* e, double* tau) {
+  constexpr int G = 32;         // column blocks (one half-wave per row block)
+  constexpr int KM = G * RBC;   // largest k
+  static_assert((NT / G) * RBR == KM, "row and column blocks must cover the same k");
+  __shared__ double col[KM];    // column j, then v
+  __shared__ double sp[KM];     // p, then w
+  __shared__ double coef[4];    // beta, tau, scale, K
+  const int t = threadIdx.x;
+  const int a = t / G, b = t % G;  // a: row block, b: column block (b runs along the wave)
+  const int lane = t & 63;
+  double blk[RBR][RBC];
+#pragma unroll
+  for (int ii = 0; ii < RBR; ++ii)
+#pragma unroll
+    for (int jj = 0; jj < RBC; ++jj) {
+      const int i = a * RBR + ii, l = b * RBC + jj;
+      blk[ii][jj] = (i < k && l < k) ? A[i + (int64_t)l * lda] : 0.0;
+    }
+  for (int j = 0; j + 2 < k; ++j) {
+    const int r0 = j + 1;
+    // broadcast column j
+    if (b == j / RBC) {
+#pragma unroll
+      for (int jj = 0; jj < RBC; ++jj)
+        if (jj == j % RBC) {
+#pragma unroll
+          for (int ii = 0; ii < RBR; ++ii) col[a * RBR + ii] = blk[ii][jj];
+        }
+    }
+    __syncthreads();
+    if (t < 64) {
+      double s2 = 0.0;
+      for (int i = j + 2 + lane; i < k; i += 64) s2 += col[i] * col[i];
+      for (int off = 32; off > 0; off >>= 1) s2 += __shfl_xor(s2, off, 64);
+      if (lane == 0) {
+        const double alpha = col[r0];
+        if (s2 == 0.0) {
+          coef[0] = alpha; coef[1] = 0.0; coef[2] = 0.0;
+        } else {
+          const double beta = -copysign(sqrt(alpha * alpha + s2), alpha);
+          coef[0] = beta;
+          coef[1] = (beta - alpha) / beta;
+          coef[2] = 1.0 / (alpha - beta);
+        }
+        d[j] = col[j];
+        e[j] = coef[0];
+        tau[j] = coef[1];
+      }
+    }
+    __syncthreads();
+    const double tj = coef[1], sc = coef[2];
+    if (tj == 0.0) continue;  // uniform: nothing to annihilate
+    // v (in place of col): v(r0) = 1, v(i) = sc col(i) below, 0 above
+    for (int i = t; i < KM; i += NT) {
+      double v = 0.0;
+      if (i == r0) v = 1.0;
+      else if (i > r0 && i < k) v = sc * col[i];
+      col[i] = v;  // each entry written by its own thread after every read above
+    }
+    __syncthreads();
+    // p = tau A22 v: row-block partial over this thread's columns, summed
+    // across the 32 threads of the row block (one half of a wave)
+#pragma unroll
+    for (int ii = 0; ii < RBR; ++ii) {
+      double acc = 0.0;
+#pragma unroll
+      for (int jj = 0; jj < RBC; ++jj) acc += blk[ii][jj] * col[b * RBC + jj];
+      for (int off = 16; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+      const int i = a * RBR + ii;
+      if (b == 0) sp[i] = (i >= r0 && i < k) ? tj * acc : 0.0;
+    }
+    __syncthreads();
+    if (t < 64) {
+      double pv = 0.0;
+      for (int i = r0 + lane; i < k; i += 64) pv += sp[i] * col[i];
+      for (int off = 32; off > 0; off >>= 1) pv += __shfl_xor(pv, off, 64);
+      if (lane == 0) coef[3] = 0.5 * tj * pv;
+    }
+    __syncthreads();
+    const double Kc = coef[3];
+    // rank-2 update of the trailing block: A22 -= v w^T + w v^T, w = p - K v
+    // (v, w of this thread's columns in registers, of its rows read per row)
+    double vl[RBC], wl[RBC];
+#pragma unroll
+    for (int q = 0; q < RBC; ++q) {
+      const int l = b * RBC + q;
+      vl[q] = col[l];
+      wl[q] = sp[l] - Kc * col[l];
+    }
+#pragma unroll
+    for (int ii = 0; ii < RBR; ++ii) {
+      const int i = a * RBR + ii;
+      const double vi = col[i];
+      const double wi = sp[i] - Kc * vi;
+#pragma unroll
+      for (int jj = 0; jj < RBC; ++jj) blk[ii][jj] -= vi * wl[jj] + wi * vl[jj];
+    }
+    // keep the reflector in column j (rows >= j + 2) and beta at (r0, j)
+    if (b == j / RBC) {
+#pragma unroll
+      for (int jj = 0; jj < RBC; ++jj)
+        if (jj == j % RBC) {
+#pragma unroll
+          for (int ii = 0; ii < RBR; ++ii) {
+            const int i = a * RBR + ii;
+            if (i == r0) blk[ii][jj] = coef[0];
+            else if (i > r0) blk[ii][jj] = col[i];
+          }
+        }
+    }
+    __syncthreads();
+  }
+  // write back; d, e of the last 2 x 2 block
+#pragma unroll
+  for (int ii = 0; ii < RBR; ++ii)
+#pragma unroll
+    for (int jj = 0; jj < RBC; ++jj) {
+      const int i = a * RBR + ii, l = b * RBC + jj;
+      if (i < k && l < k) A[i + (int64_t)l * lda] = blk[ii][jj];
+    }
+  __syncthreads();
+  if (t == 0) {
+    if (k >= 2) {
+      d[k - 2] = A[(k - 2) + (int64_t)(k - 2) * lda];
+      e[k - 2] = A[(k - 1) + (int64_t)(k - 2) * lda];
+      tau[k - 2] = 0.0;
+    }
+    d[k - 1] = A[(k - 1) + (int64_t)(k - 1) * lda];
+    tau[k - 1] = 0.0;
+  }
+}
+
 // Householder tridiagonalisation for k <= kTriMaxK, same outputs as
 // tridiag_kernel.  Wave w owns the columns l = r0 + w, r0 + w + 16, ... of the
 // trailing block and lane i its rows r0 + i, r0 + i + 64, ..., so the products
@@ -504,24 +645,39 @@ __global__ void invit_kernel(const double* d, const double* e, int k, const doub
 // eigenvalue order, by right-looking modified Gram-Schmidt done twice: at
 // step j every later vector loses its component along z_j.  Each wave
 // handles a subset of the later vectors and recomputes ||z_j|| itself, so a
-// step needs one barrier.
-__global__ __launch_bounds__(1024) void orth_kernel(int k, const int* clusters, const int* cl_count, const int* pos_of,
-                            double* Z, int64_t ldz) {
+// step needs one barrier.  The cluster is staged in LDS when it fits
+// (lds_doubles entries of dynamic shared memory).
+__global__ __launch_bounds__(1024) void orth_kernel(int k, const int* clusters, const int* cl_count,
+                                                    const int* pos_of, double* Z, int64_t ldz,
+                                                    int lds_doubles) {
+  extern __shared__ double zs[];
   const int cl = blockIdx.x;
   if (cl >= cl_count[0]) return;
   const int start = clusters[2 * cl], len = clusters[2 * cl + 1];
   if (len < 2) return;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int nw = blockDim.x >> 6;
+  const bool staged = (int64_t)len * k <= (int64_t)lds_doubles;
+  // vector q of the cluster: zs[q * k + i] when staged, else Z column pos_of[start + q]
+  auto vec = [&](int q) -> double* {
+    return staged ? zs + (int64_t)q * k : Z + (int64_t)pos_of[start + q] * ldz;
+  };
+  if (staged) {
+    for (int q = wv; q < len; q += nw) {
+      const double* src = Z + (int64_t)pos_of[start + q] * ldz;
+      for (int i = lane; i < k; i += 64) zs[(int64_t)q * k + i] = src[i];
+    }
+    __syncthreads();
+  }
   for (int pass = 0; pass < 2; ++pass) {
     for (int j = 0; j < len; ++j) {
-      const double* zj = Z + (int64_t)pos_of[start + j] * ldz;
+      const double* zj = vec(j);
       double nj = 0.0;
       for (int i = lane; i < k; i += 64) nj += zj[i] * zj[i];
       for (int off = 32; off > 0; off >>= 1) nj += __shfl_xor(nj, off, 64);
       const double inv2 = (nj > 0.0) ? 1.0 / nj : 0.0;
       for (int l = j + 1 + wv; l < len; l += nw) {
-        double* zl = Z + (int64_t)pos_of[start + l] * ldz;
+        double* zl = vec(l);
         double dt = 0.0;
         for (int i = lane; i < k; i += 64) dt += zj[i] * zl[i];
         for (int off = 32; off > 0; off >>= 1) dt += __shfl_xor(dt, off, 64);
@@ -532,7 +688,7 @@ __global__ __launch_bounds__(1024) void orth_kernel(int k, const int* clusters, 
     }
     // normalise every vector of the cluster
     for (int j = wv; j < len; j += nw) {
-      double* zj = Z + (int64_t)pos_of[start + j] * ldz;
+      double* zj = vec(j);
       double nj = 0.0;
       for (int i = lane; i < k; i += 64) nj += zj[i] * zj[i];
       for (int off = 32; off > 0; off >>= 1) nj += __shfl_xor(nj, off, 64);
@@ -540,6 +696,12 @@ __global__ __launch_bounds__(1024) void orth_kernel(int k, const int* clusters, 
       for (int i = lane; i < k; i += 64) zj[i] *= inv;
     }
     __syncthreads();
+  }
+  if (staged) {
+    for (int q = wv; q < len; q += nw) {
+      double* dst = Z + (int64_t)pos_of[start + q] * ldz;
+      for (int i = lane; i < k; i += 64) dst[i] = zs[(int64_t)q * k + i];
+    }
   }
 }
 
@@ -635,7 +797,13 @@ void syev_trunc_f64(hipStream_t s, int64_t k, const double* M, int64_t ldm, doub
     fill_f64(s, e, 1, 1, 1, 0.0);
     fill_f64(s, tau, 1, 1, 1, 0.0);
   } else {
-    if (k <= kTriMaxK) {
+    if (k <= 128) {
+      hipLaunchKernelGGL((tridiag_reg_kernel<4, 4, 1024>), dim3(1), dim3(1024), 0, s, A, k, ki, d, e, tau);
+    } else if (k <= 160) {
+      hipLaunchKernelGGL((tridiag_reg_kernel<5, 5, 1024>), dim3(1), dim3(1024), 0, s, A, k, ki, d, e, tau);
+    } else if (k <= 192) {
+      hipLaunchKernelGGL((tridiag_reg_kernel<12, 6, 512>), dim3(1), dim3(512), 0, s, A, k, ki, d, e, tau);
+    } else if (k <= kTriMaxK) {
       const size_t lds = (size_t)(3 + kTriT / 64) * k * sizeof(double);
       hipLaunchKernelGGL(tridiag_small_kernel, dim3(1), dim3(kTriT), lds, s, A, k, ki, d, e, tau);
     } else {
@@ -656,8 +824,10 @@ void syev_trunc_f64(hipStream_t s, int64_t k, const double* M, int64_t ldm, doub
   hipLaunchKernelGGL(invit_kernel, dim3(nkeep), dim3(64), invit_lds ? (size_t)6 * k * sizeof(double) : 0,
                      s, d, e, ki, lam, order, keep_dev, bounds, work, Zt, k, invit_lds);
   DME_HIP(hipGetLastError());
-  hipLaunchKernelGGL(orth_kernel, dim3((unsigned)k), dim3(1024), 0, s, ki, clusters, cl_count, pos_of,
-                     Zt, k);
+  // cluster staging in LDS: up to 144 KiB, never more than the whole k x k set
+  const int64_t orth_lds = std::min<int64_t>(k * k, (144 * 1024) / (int64_t)sizeof(double));
+  hipLaunchKernelGGL(orth_kernel, dim3((unsigned)k), dim3(1024), (size_t)orth_lds * sizeof(double), s,
+                     ki, clusters, cl_count, pos_of, Zt, k, (int)orth_lds);
   DME_HIP(hipGetLastError());
   hipLaunchKernelGGL(backtr_kernel, dim3((unsigned)std::min<int64_t>(k, max_keep)), dim3(256),
                      (size_t)k * sizeof(double), s, A, k, tau, ki, Zt, k, keep_dev, V_out, ldv);

@@ -64,7 +64,8 @@ def _sym_with_spectrum(k, lam, seed):
     return (Q * lam) @ Q.T
 
 
-@pytest.mark.parametrize("case", ["random", "graded", "clusters", "psd_lowrank", "k2", "k1", "k300"])
+@pytest.mark.parametrize("case", ["random", "graded", "clusters", "psd_lowrank", "k2", "k1", "k150",
+                                  "k180", "k300", "k600"])
 def test_syev(ctx, case):
     announce("syev", case)
     rng = np.random.default_rng(5)
@@ -87,9 +88,18 @@ def test_syev(ctx, case):
     elif case == "k1":
         k = 1
         M = np.array([[-4.0]])
-    else:
+    elif case == "k150":  # register-resident reduction sizes
+        k = 150
+        M = _sym_with_spectrum(k, np.exp(-0.15 * np.arange(k)) * np.where(np.arange(k) % 7 == 3, -1, 1), 6)
+    elif case == "k180":
+        k = 180
+        F = rng.standard_normal((k, 120)); M = F @ np.diag(10.0 ** -np.linspace(0, 9, 120)) @ F.T
+    elif case == "k300":  # LDS-staged reduction
         k = 300
         M = _sym_with_spectrum(k, np.exp(-0.1 * np.arange(k)), 4)
+    else:  # global-memory reduction
+        k = 600
+        X = rng.standard_normal((k, k)); M = 0.5 * (X + X.T)
     tol = 1e-12
     lam, V, kk = ctx.syev(M, tol=tol)
     lam, V = to_np(lam), to_np(V)
