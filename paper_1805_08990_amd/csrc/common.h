@@ -87,6 +87,70 @@ struct KernelTimer {
 KernelTimer*& kernel_timer();
 
 // ---------------------------------------------------------------------------
+// Wave reductions on the DPP / permlane paths (register-to-register lane
+// moves, no LDS round trip).  Every lane of a group ends with the group's sum,
+// bitwise the same in every lane (each step adds a pair in both orders, and
+// addition commutes).  Groups: 8 lanes (xor 1, 2, then the 8-lane mirror),
+// 16 (the 16-lane mirror), 32 (swap of adjacent 16-lane rows) and the whole
+// wave (swap of the two 32-lane halves).
+// ---------------------------------------------------------------------------
+template <int CTRL>
+__device__ inline double dpp_mov_f64(double v) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  const uint64_t b = (uint64_t)__double_as_longlong(v);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)b, CTRL, 0xF, 0xF, false);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(b >> 32), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+#else
+  return v;
+#endif
+}
+constexpr int kDppXor1 = 0xB1;        // quad_perm [1, 0, 3, 2]
+constexpr int kDppXor2 = 0x4E;        // quad_perm [2, 3, 0, 1]
+constexpr int kDppHalfMirror = 0x141; // lane i <-> 7 - i within 8
+constexpr int kDppMirror = 0x140;     // lane i <-> 15 - i within 16
+
+// v + (v of the lane 16 (S = 16) or 32 (S = 32) away), by a permlane swap
+template <int S>
+__device__ inline double swap_sum_f64(double v) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  const uint64_t b = (uint64_t)__double_as_longlong(v);
+  const uint32_t l = (uint32_t)b, h = (uint32_t)(b >> 32);
+  uint32_t l0, l1, h0, h1;
+  if constexpr (S == 16) {
+    const auto lo = __builtin_amdgcn_permlane16_swap(l, l, false, false);
+    const auto hi = __builtin_amdgcn_permlane16_swap(h, h, false, false);
+    l0 = lo[0]; l1 = lo[1]; h0 = hi[0]; h1 = hi[1];
+  } else {
+    const auto lo = __builtin_amdgcn_permlane32_swap(l, l, false, false);
+    const auto hi = __builtin_amdgcn_permlane32_swap(h, h, false, false);
+    l0 = lo[0]; l1 = lo[1]; h0 = hi[0]; h1 = hi[1];
+  }
+  const double a = __longlong_as_double((long long)(((uint64_t)h0 << 32) | l0));
+  const double c = __longlong_as_double((long long)(((uint64_t)h1 << 32) | l1));
+  return a + c;
+#else
+  return v;
+#endif
+}
+// sum over aligned groups of 8 lanes
+__device__ inline double group8_sum_f64(double v) {
+  v += dpp_mov_f64<kDppXor1>(v);
+  v += dpp_mov_f64<kDppXor2>(v);
+  v += dpp_mov_f64<kDppHalfMirror>(v);
+  return v;
+}
+// sum over aligned groups of 16 lanes
+__device__ inline double group16_sum_f64(double v) {
+  v = group8_sum_f64(v);
+  return v + dpp_mov_f64<kDppMirror>(v);
+}
+// sum over aligned halves of the wave (32 lanes)
+__device__ inline double half_wave_sum_f64(double v) { return swap_sum_f64<16>(group16_sum_f64(v)); }
+// sum over the whole wave
+__device__ inline double wave_sum_f64(double v) { return swap_sum_f64<32>(half_wave_sum_f64(v)); }
+
+// ---------------------------------------------------------------------------
 // Kernel launchers (each in its own .hip file)
 // ---------------------------------------------------------------------------
 

@@ -4,15 +4,16 @@
 // E (n x n, the operator e^{tA^T}) is kept as FP32; every FP32 value is the
 // exact sum of three BF16 pieces x = x1 + x2 + x3 (each piece takes the next
 // 8 significant bits).  X (n x r, FP64) is rounded to FP32 and split the same
-// way.  The product keeps the six piece products whose order is at most
+// way (directly from FP64).  The product keeps the six piece products whose order is at most
 // 2^-16 of the leading one,
 //
 //     E X ~ E1 X1 + (E1 X2 + E2 X1) + (E1 X3 + E2 X2 + E3 X1),
 //
 // so the result carries the FP32 representation error of E and X (relative
 // 2^-24 per entry) and the dropped terms (E2 X3, E3 X2, E3 X3: below 2^-24
-// relative).  All six products accumulate in one FP32 accumulator per K
-// chunk with v_mfma_f32_16x16x32_bf16; the chunks are summed in FP64 in a
+// relative).  For each 32-wide K step the six products are summed by
+// v_mfma_f32_16x16x32_bf16 into a fresh FP32 accumulator, and the step sums
+// are added in FP64; the chunks of the split K range are summed in FP64 in a
 // fixed order, so results are deterministic.
 //
 // Layout:
@@ -21,16 +22,17 @@
 //          are one 32-byte load.
 //   Xs     BF16, three planes, column-major with ld = lde and rpad = 16 TN
 //          columns, zero padded.
-//   partial FP32, [split][col][row].
+//   partial FP64, [split][col][row].
 //
-// Work decomposition: a 512-thread workgroup (8 wave64s) owns 256 rows of Y
-// and every column (TN 16-column tiles); wave w owns rows w*32 .. w*32+31.
+// Work decomposition: a 512-thread workgroup (8 wave64s, 4 row groups x 2
+// column halves) owns 128 rows of Y and every column (TN 16-column tiles).
 // The K range is split into nsplit chunks; workgroup b takes chunk b % nsplit,
-// so with nsplit a multiple of 8 every chunk is handled by one XCD and the
-// chunk's slice of Xs (lde/nsplit x rpad x 3 pieces) stays in that XCD's L2.
-// The Xs tile of a K step is staged once in LDS (double-buffered) and read by
-// all 8 waves; E fragments go straight from HBM to registers (every E entry
-// is read once) and are split into pieces in registers.
+// so every chunk is handled by the same one or two XCDs and the chunk's slice
+// of Xs (lde/nsplit x rpad x 3 pieces) stays in their L2.  The Xs tile of a K
+// step is staged once in LDS (double-buffered) and read by all 8 waves; E
+// fragments go straight from HBM to registers (the two waves of a row group
+// read the same rows, the second from cache) and are split into pieces in
+// registers.
 #include "solver.h"
 
 namespace dme {
@@ -49,7 +51,7 @@ typedef unsigned short u16;
 constexpr int kMT = 512;       // threads per workgroup
 constexpr int kMWaves = kMT / 64;
 constexpr int kMRowsWave = 32;  // two 16-row MFMA tiles per wave
-constexpr int kMRows = kMWaves * kMRowsWave;  // 256 rows per workgroup
+constexpr int kMRows = 4 * kMRowsWave;  // 128 rows per workgroup (4 row groups)
 constexpr int kMBK = 32;        // K per step (one MFMA K)
 constexpr int kMLdsK = kMBK + 8;  // padded k extent of an LDS column (bf16)
 
@@ -68,6 +70,16 @@ __device__ __forceinline__ void split3(float x, u16& a, u16& b, u16& c) {
   b = bf16_rne(r1);
   const float r2 = r1 - bf16_to_f32(b);
   c = bf16_rne(r2);
+}
+
+// Three-piece split of an FP64 value (each piece rounds what the earlier
+// ones left; the residual is below 2^-24 of |x|).
+__device__ __forceinline__ void split3_d(double x, u16& a, u16& b, u16& c) {
+  a = bf16_rne((float)x);
+  const double r1 = x - (double)bf16_to_f32(a);
+  b = bf16_rne((float)r1);
+  const double r2 = r1 - (double)bf16_to_f32(b);
+  c = bf16_rne((float)r2);
 }
 
 union Frag {
@@ -104,9 +116,9 @@ __global__ void mixed_split_x_kernel(const double* __restrict__ X, int64_t ldx, 
   for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
        idx += (int64_t)gridDim.x * blockDim.x) {
     const int64_t k = idx % lde, c = idx / lde;
-    const float x = (k < n && c < r) ? (float)X[k + c * ldx] : 0.0f;
+    const double x = (k < n && c < r) ? X[k + c * ldx] : 0.0;
     u16 a, b, d;
-    split3(x, a, b, d);
+    split3_d(x, a, b, d);
     Xs[idx] = a;
     Xs[plane + idx] = b;
     Xs[2 * plane + idx] = d;
@@ -115,12 +127,20 @@ __global__ void mixed_split_x_kernel(const double* __restrict__ X, int64_t ldx, 
 
 // KS = MFMA K-steps (of 32) per main-loop iteration: 2 when the double-
 // buffered X tile fits in LDS (TN <= 8), else 1.
+//
+// Wave layout: 8 waves = 4 row groups x 2 column halves.  Wave (g, hc) owns
+// rows g*32 .. g*32+31 of the workgroup's 128 (two 16-row MFMA tiles) and the
+// column tiles [hc*TW, min(TN, (hc+1)*TW)).  For every 32-wide K step the six
+// piece products of a tile are summed by the MFMA into a fresh FP32
+// accumulator (the five small ones first) and that step's sum is added to an
+// FP64 accumulator: FP32 rounding then acts on one step's partial only.
 template <int TN, int KS>
 __global__ __launch_bounds__(kMT) void gemm_mixed_kernel(int n, int lde, int rpad, int nsplit,
                                                          int kchunk, const float* __restrict__ Et,
                                                          const u16* __restrict__ Xs, int r,
-                                                         float* __restrict__ partial) {
+                                                         double* __restrict__ partial) {
   constexpr int NC = TN * 16;             // columns covered
+  constexpr int TW = (TN + 1) / 2;        // column tiles per wave
   constexpr int BK = kMBK * KS;           // K per iteration
   constexpr int QPC = BK / 8;             // 16-byte chunks per column of the tile
   constexpr int CHUNKS = 3 * NC * QPC;    // 16-byte chunks of one Xs tile
@@ -130,6 +150,8 @@ __global__ __launch_bounds__(kMT) void gemm_mixed_kernel(int n, int lde, int rpa
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
+  const int rg = wave & 3, hc = wave >> 2;
+  const int jbeg = hc * TW;
   const int split = blockIdx.x % nsplit;
   const int rb = blockIdx.x / nsplit;
   const int kbeg = split * kchunk;
@@ -138,15 +160,17 @@ __global__ __launch_bounds__(kMT) void gemm_mixed_kernel(int n, int lde, int rpa
   const int kg = lane >> 4;  // k group: k = 8 kg .. 8 kg + 7 of a 32-wide step
   const int64_t plane = (int64_t)lde * rpad;
 
-  f32x4 acc[2][TN];
+  double acc[2][TW][4];
 #pragma unroll
   for (int t = 0; t < 2; ++t)
 #pragma unroll
-    for (int j = 0; j < TN; ++j) acc[t][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int j = 0; j < TW; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) acc[t][j][v] = 0.0;
 
   int rows[2];
 #pragma unroll
-  for (int t = 0; t < 2; ++t) rows[t] = rb * kMRows + wave * kMRowsWave + t * 16 + row_l;
+  for (int t = 0; t < 2; ++t) rows[t] = rb * kMRows + rg * kMRowsWave + t * 16 + row_l;
 
   // E fragments of an iteration: [substep][tile][8 consecutive k]
   float ecur[KS][2][8];
@@ -218,20 +242,24 @@ __global__ __launch_bounds__(kMT) void gemm_mixed_kernel(int n, int lde, int rpa
         for (int q = 0; q < 8; ++q)
           split3(ecur[ks][t][q], ef[t][0].h[q], ef[t][1].h[q], ef[t][2].h[q]);
 #pragma unroll
-      for (int j = 0; j < TN; ++j) {
-        Frag xf[3];
+      for (int jj = 0; jj < TW; ++jj) {
+        const int j = jbeg + jj;
+        if (j < TN) {
+          Frag xf[3];
 #pragma unroll
-        for (int pc = 0; pc < 3; ++pc) xf[pc].q = sX[buf][pc][j * 16 + row_l][ks * 4 + kg];
+          for (int pc = 0; pc < 3; ++pc) xf[pc].q = sX[buf][pc][j * 16 + row_l][ks * 4 + kg];
 #pragma unroll
-        for (int t = 0; t < 2; ++t) {
-          f32x4 a = acc[t][j];
-          a = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ef[t][2].v, xf[0].v, a, 0, 0, 0);
-          a = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ef[t][1].v, xf[1].v, a, 0, 0, 0);
-          a = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ef[t][0].v, xf[2].v, a, 0, 0, 0);
-          a = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ef[t][1].v, xf[0].v, a, 0, 0, 0);
-          a = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ef[t][0].v, xf[1].v, a, 0, 0, 0);
-          a = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ef[t][0].v, xf[0].v, a, 0, 0, 0);
-          acc[t][j] = a;
+          for (int t = 0; t < 2; ++t) {
+            f32x4 a = f32x4{0.f, 0.f, 0.f, 0.f};
+            a = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ef[t][2].v, xf[0].v, a, 0, 0, 0);
+            a = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ef[t][1].v, xf[1].v, a, 0, 0, 0);
+            a = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ef[t][0].v, xf[2].v, a, 0, 0, 0);
+            a = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ef[t][1].v, xf[0].v, a, 0, 0, 0);
+            a = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ef[t][0].v, xf[1].v, a, 0, 0, 0);
+            a = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ef[t][0].v, xf[0].v, a, 0, 0, 0);
+#pragma unroll
+            for (int v = 0; v < 4; ++v) acc[t][jj][v] += (double)a[v];
+          }
         }
       }
     }
@@ -251,28 +279,28 @@ __global__ __launch_bounds__(kMT) void gemm_mixed_kernel(int n, int lde, int rpa
   // lane holds rows 4 kg .. 4 kg + 3 of column row_l of each 16 x 16 tile
 #pragma unroll
   for (int t = 0; t < 2; ++t) {
-    const int row0 = rb * kMRows + wave * kMRowsWave + t * 16 + kg * 4;
+    const int row0 = rb * kMRows + rg * kMRowsWave + t * 16 + kg * 4;
 #pragma unroll
-    for (int j = 0; j < TN; ++j) {
-      const int col = j * 16 + row_l;
-      if (col < r) {
-        float* dst = partial + ((int64_t)split * r + col) * n;
+    for (int jj = 0; jj < TW; ++jj) {
+      const int col = (jbeg + jj) * 16 + row_l;
+      if (jbeg + jj < TN && col < r) {
+        double* dst = partial + ((int64_t)split * r + col) * n;
 #pragma unroll
         for (int v = 0; v < 4; ++v)
-          if (row0 + v < n) dst[row0 + v] = acc[t][j][v];
+          if (row0 + v < n) dst[row0 + v] = acc[t][jj][v];
       }
     }
   }
 }
 
 // Y(i, j) = sum over splits of partial, in FP64 and split order.
-__global__ void mixed_reduce_kernel(const float* __restrict__ partial, int64_t n, int64_t r,
+__global__ void mixed_reduce_kernel(const double* __restrict__ partial, int64_t n, int64_t r,
                                     int nsplit, double* __restrict__ Y, int64_t ldy) {
   const int64_t total = n * r;
   for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
        idx += (int64_t)gridDim.x * blockDim.x) {
     double s = 0.0;
-    for (int z = 0; z < nsplit; ++z) s += (double)partial[(int64_t)z * total + idx];
+    for (int z = 0; z < nsplit; ++z) s += partial[(int64_t)z * total + idx];
     const int64_t i = idx % n, j = idx / n;
     Y[i + j * ldy] = s;
   }
@@ -289,7 +317,7 @@ int64_t lde_for(int64_t n) { return cdiv(n, kMKGran) * kMKGran; }
 int nsplit_for(int64_t n) {
   const int64_t lde = lde_for(n);
   const int64_t rowblocks = cdiv(n, kMRows);
-  int64_t ns = 8;
+  int64_t ns = 4;
   while (rowblocks * ns < 512 && lde / (ns * 2) >= kMinChunk) ns *= 2;
   while (ns > 1 && lde / ns < kMKGran) ns /= 2;
   return (int)ns;
@@ -297,7 +325,7 @@ int nsplit_for(int64_t n) {
 
 template <int TN>
 void launch_mixed(hipStream_t s, int64_t n, int64_t lde, int64_t rpad, int nsplit, int kchunk,
-                  const float* Et, const u16* Xs, int64_t r, float* partial) {
+                  const float* Et, const u16* Xs, int64_t r, double* partial) {
   const int64_t rowblocks = cdiv(n, kMRows);
   constexpr int KS = (TN <= 8) ? 2 : 1;
   hipLaunchKernelGGL((gemm_mixed_kernel<TN, KS>), dim3((unsigned)(rowblocks * nsplit)), dim3(kMT), 0,
@@ -321,7 +349,8 @@ size_t gemm_mixed_workspace(int64_t n, int64_t r) {
   const int64_t lde = lde_for(n);
   const int64_t rpad = cdiv(std::min<int64_t>(r, 16 * kMaxTN), 16) * 16;
   const int ns = nsplit_for(n);
-  return (size_t)3 * lde * rpad * sizeof(u16) + 256 + (size_t)ns * n * std::min<int64_t>(r, 16 * kMaxTN) * sizeof(float) + 256;
+  return (size_t)3 * lde * rpad * sizeof(u16) + 256 +
+         (size_t)ns * n * std::min<int64_t>(r, 16 * kMaxTN) * sizeof(double) + 256;
 }
 
 // Y (n x r, ld ldy, FP64) = E X with X (n x r, ld ldx, FP64).
@@ -339,7 +368,7 @@ void gemm_mixed(hipStream_t s, const MixedOp& op, const double* X, int64_t ldx, 
     const int64_t rpad = 16 * tn;
     ws.used = mark;
     u16* Xs = ws.get<u16>((size_t)3 * op.lde * rpad);
-    float* partial = ws.get<float>((size_t)ns * n * rc);
+    double* partial = ws.get<double>((size_t)ns * n * rc);
     hipLaunchKernelGGL(mixed_split_x_kernel, dim3((unsigned)std::min<int64_t>(cdiv(op.lde * rpad, 256), 8192)),
                        dim3(256), 0, s, X + c0 * ldx, ldx, n, rc, op.lde, rpad, Xs);
     DME_HIP(hipGetLastError());

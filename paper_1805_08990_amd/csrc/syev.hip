@@ -2,21 +2,24 @@
 // the column compression, with truncation: only eigenpairs with
 // |lambda| > tol * max|lambda| are formed, ordered by |lambda| descending.
 //
-//   1. tridiag_kernel   : Householder reduction to tridiagonal form
-//                         (one workgroup, 256 row lanes x 4 column groups).
-//   2. bisect_kernel    : every eigenvalue by Sturm-count bisection, one
-//                         thread per eigenvalue index (embarrassingly parallel).
+//   1. tridiagonalisation: Householder reduction to tridiagonal form in one
+//                         workgroup: tridiag_rows_kernel holds the matrix in
+//                         registers by rows (k <= 192), tridiag_small_kernel
+//                         keeps the vectors in LDS (k <= 512), tridiag_kernel
+//                         works from global memory (larger k).
+//   2. bisect_kernel    : every eigenvalue by Sturm-count multisection, one
+//                         wave per eigenvalue index (all independent).
 //   3. select_kernel    : threshold, |lambda|-descending order of the kept set
 //                         and the clusters of kept eigenvalues whose gaps are
 //                         below 1e-3 ||T|| (the absolute criterion of LAPACK's
-//                         inverse iteration).
+//                         inverse iteration), one workgroup with prefix sums.
 //   4. invit_kernel     : inverse iteration with a partially pivoted
-//                         tridiagonal LU, one workgroup per kept eigenvalue,
-//                         all independent.
+//                         tridiagonal LU, one wave per kept eigenvalue, all
+//                         independent.
 //   5. orth_kernel      : one workgroup per cluster orthonormalises the
 //                         cluster's vectors (right-looking modified Gram-Schmidt,
 //                         two passes).
-//   6. backtr_kernel    : V = H_0 ... H_{k-3} Z, one workgroup per column.
+//   6. backtr_kernel    : V = H_0 ... H_{k-3} Z, one wave per column.
 //
 // An inverse-iteration vector is off its eigenvector by O(u ||M|| / gap) in
 // the directions of nearby eigenvectors; orthonormalising a cluster mixes its
@@ -34,11 +37,12 @@ constexpr int kColGroups = kTriT / kRowLanes;
 constexpr double kOrtol = 1e-3;  // gaps below kOrtol ||T|| join a cluster
 constexpr int kInvitIters = 3;
 constexpr int kInvitLdsMaxK = 2048;  // inverse-iteration arrays in LDS up to this k
+constexpr int kInvitArrays = 8;      // k-long arrays per inverse iteration
 
 __device__ inline double block_sum_1024(double v, double* red) {
   // red: kTriT doubles of LDS; returns the total to every thread
   const int t = threadIdx.x;
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  v = wave_sum_f64(v);
   if ((t & 63) == 0) red[t >> 6] = v;
   __syncthreads();
   double tot = 0.0;
@@ -48,143 +52,138 @@ __device__ inline double block_sum_1024(double v, double* red) {
   return tot;
 }
 
-// Householder tridiagonalisation with the whole matrix in registers, for
-// k <= 32 RB: the 1024 threads form a 32 x 32 grid and thread (a, b) holds the
-// RB x RB block of rows a RB .. and columns b RB ..  A step broadcasts column j
-// through LDS, wave 0 forms the reflector, the product p = tau A22 v is summed
-// across the 32 column owners of a row block with lane shuffles (they share a
-// wave), and the rank-2 update touches registers only.  The reflector vectors
-// are written to A(j+2:, j) at the end, as in tridiag_kernel.
-template <int RBR, int RBC, int NT>
-__global__ __launch_bounds__(NT) void tridiag_reg_kernel(double* A, int64_t lda, int k, double* d,
-                                                           double* e, double* tau) {
-  constexpr int G = 32;         // column blocks (one half-wave per row block)
-  constexpr int KM = G * RBC;   // largest k
-  static_assert((NT / G) * RBR == KM, "row and column blocks must cover the same k");
-  __shared__ double col[KM];    // column j, then v
-  __shared__ double sp[KM];     // p, then w
-  __shared__ double coef[4];    // beta, tau, scale, K
+// Householder tridiagonalisation with the whole matrix in registers, by rows:
+// 4 adjacent lanes own row i (i = t / 4), lane q of them the columns
+// 32 c + 4 m + q (chunk c < NCH, m < 8), so column block c spans whole
+// 32-column stretches and a wave can skip the blocks (and rows) that lie
+// before the trailing part.  Because A is symmetric, column j is row j: its
+// four owners publish it to LDS, and every wave forms the reflector from it
+// redundantly.  A step then takes three barriers: v into LDS; p = tau A v
+// (row sums over the 4 lanes by DPP) and the per-wave parts of p^T v; the
+// rank-2 update A -= v w^T + w v^T, w = p - (tau/2)(p^T v) v, with row j + 1
+// published for the next step.  The reflector of step j goes to A(j+2:, j)
+// and d, e, tau as in tridiag_kernel.
+template <int NCH>
+__global__ __launch_bounds__(128 * NCH) void tridiag_rows_kernel(double* A, int64_t lda, int k,
+                                                                 double* d, double* e, double* tau) {
+  constexpr int KM = 32 * NCH;  // largest k
+  constexpr int NT = 4 * KM;
+  constexpr int NW = NT / 64;
+  __shared__ double xrow[2][KM];  // row j of step j in xrow[j & 1]
+  __shared__ double vb[KM];
+  __shared__ double pb[KM];
+  __shared__ double wpart[NW];
   const int t = threadIdx.x;
-  const int a = t / G, b = t % G;  // a: row block, b: column block (b runs along the wave)
-  const int lane = t & 63;
-  double blk[RBR][RBC];
+  const int i = t >> 2, q = t & 3;
+  const int lane = t & 63, wv = t >> 6;
+  const int wrow_last = wv * 16 + 15;  // last row of this wave
+  double a[NCH][8];
 #pragma unroll
-  for (int ii = 0; ii < RBR; ++ii)
+  for (int c = 0; c < NCH; ++c)
 #pragma unroll
-    for (int jj = 0; jj < RBC; ++jj) {
-      const int i = a * RBR + ii, l = b * RBC + jj;
-      blk[ii][jj] = (i < k && l < k) ? A[i + (int64_t)l * lda] : 0.0;
+    for (int m = 0; m < 8; ++m) {
+      const int l = 32 * c + 4 * m + q;
+      a[c][m] = (i < k && l < k) ? A[i + (int64_t)l * lda] : 0.0;
     }
+  if (i == 0) {
+#pragma unroll
+    for (int c = 0; c < NCH; ++c)
+#pragma unroll
+      for (int m = 0; m < 8; ++m) xrow[0][32 * c + 4 * m + q] = a[c][m];
+  }
+  __syncthreads();
   for (int j = 0; j + 2 < k; ++j) {
     const int r0 = j + 1;
-    // broadcast column j
-    if (b == j / RBC) {
+    const double* x = xrow[j & 1];
+    // reflector from row j (= column j), formed by every wave
+    double s2 = 0.0;
 #pragma unroll
-      for (int jj = 0; jj < RBC; ++jj)
-        if (jj == j % RBC) {
-#pragma unroll
-          for (int ii = 0; ii < RBR; ++ii) col[a * RBR + ii] = blk[ii][jj];
-        }
+    for (int mm = 0; mm < KM / 64 + 1; ++mm) {
+      const int l = lane + 64 * mm;
+      if (l < KM && l >= j + 2 && l < k) s2 += x[l] * x[l];
     }
-    __syncthreads();
-    if (t < 64) {
-      double s2 = 0.0;
-      for (int i = j + 2 + lane; i < k; i += 64) s2 += col[i] * col[i];
-      for (int off = 32; off > 0; off >>= 1) s2 += __shfl_xor(s2, off, 64);
-      if (lane == 0) {
-        const double alpha = col[r0];
-        if (s2 == 0.0) {
-          coef[0] = alpha; coef[1] = 0.0; coef[2] = 0.0;
-        } else {
-          const double beta = -copysign(sqrt(alpha * alpha + s2), alpha);
-          coef[0] = beta;
-          coef[1] = (beta - alpha) / beta;
-          coef[2] = 1.0 / (alpha - beta);
-        }
-        d[j] = col[j];
-        e[j] = coef[0];
-        tau[j] = coef[1];
+    s2 = wave_sum_f64(s2);
+    const double alpha = x[r0];
+    double beta = alpha, tj = 0.0, sc = 0.0;
+    if (s2 != 0.0) {
+      beta = -copysign(sqrt(alpha * alpha + s2), alpha);
+      tj = (beta - alpha) / beta;
+      sc = 1.0 / (alpha - beta);
+    }
+    if (t == 0) {
+      d[j] = x[j];
+      e[j] = beta;
+      tau[j] = tj;
+    }
+    if (tj != 0.0) {  // uniform across the workgroup
+      if (q == 0 && i < KM) {
+        const double vi = (i == r0) ? 1.0 : ((i > r0 && i < k) ? sc * x[i] : 0.0);
+        vb[i] = vi;
+        if (i > r0 && i < k) A[i + (int64_t)j * lda] = vi;
       }
-    }
-    __syncthreads();
-    const double tj = coef[1], sc = coef[2];
-    if (tj == 0.0) continue;  // uniform: nothing to annihilate
-    // v (in place of col): v(r0) = 1, v(i) = sc col(i) below, 0 above
-    for (int i = t; i < KM; i += NT) {
-      double v = 0.0;
-      if (i == r0) v = 1.0;
-      else if (i > r0 && i < k) v = sc * col[i];
-      col[i] = v;  // each entry written by its own thread after every read above
-    }
-    __syncthreads();
-    // p = tau A22 v: row-block partial over this thread's columns, summed
-    // across the 32 threads of the row block (one half of a wave)
+      __syncthreads();
+      const bool live = wrow_last >= r0;  // wave-uniform
+      double pi = 0.0;
+      if (live) {
+        double s = 0.0;
 #pragma unroll
-    for (int ii = 0; ii < RBR; ++ii) {
-      double acc = 0.0;
+        for (int c = 0; c < NCH; ++c) {
+          if (32 * c + 31 < r0) continue;  // uniform: v is zero there
 #pragma unroll
-      for (int jj = 0; jj < RBC; ++jj) acc += blk[ii][jj] * col[b * RBC + jj];
-      for (int off = 16; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
-      const int i = a * RBR + ii;
-      if (b == 0) sp[i] = (i >= r0 && i < k) ? tj * acc : 0.0;
-    }
-    __syncthreads();
-    if (t < 64) {
-      double pv = 0.0;
-      for (int i = r0 + lane; i < k; i += 64) pv += sp[i] * col[i];
-      for (int off = 32; off > 0; off >>= 1) pv += __shfl_xor(pv, off, 64);
-      if (lane == 0) coef[3] = 0.5 * tj * pv;
-    }
-    __syncthreads();
-    const double Kc = coef[3];
-    // rank-2 update of the trailing block: A22 -= v w^T + w v^T, w = p - K v
-    // (v, w of this thread's columns in registers, of its rows read per row)
-    double vl[RBC], wl[RBC];
+          for (int m = 0; m < 8; ++m) s += a[c][m] * vb[32 * c + 4 * m + q];
+        }
+        s += dpp_mov_f64<kDppXor1>(s);
+        s += dpp_mov_f64<kDppXor2>(s);
+        pi = (i >= r0 && i < k) ? tj * s : 0.0;
+      }
+      if (q == 0) pb[i] = pi;  // zero on rows before the trailing part
+      double pv = (q == 0 && live) ? pi * vb[i] : 0.0;
+      pv = wave_sum_f64(pv);
+      if (lane == 0) wpart[wv] = pv;
+      __syncthreads();
+      double pvt = 0.0;
 #pragma unroll
-    for (int q = 0; q < RBC; ++q) {
-      const int l = b * RBC + q;
-      vl[q] = col[l];
-      wl[q] = sp[l] - Kc * col[l];
-    }
+      for (int w = 0; w < NW; ++w) pvt += wpart[w];
+      const double Kc = 0.5 * tj * pvt;
+      if (live) {
+        const double vi = vb[i];
+        const double wi = pb[i] - Kc * vi;
 #pragma unroll
-    for (int ii = 0; ii < RBR; ++ii) {
-      const int i = a * RBR + ii;
-      const double vi = col[i];
-      const double wi = sp[i] - Kc * vi;
+        for (int c = 0; c < NCH; ++c) {
+          if (32 * c + 31 < r0) continue;
 #pragma unroll
-      for (int jj = 0; jj < RBC; ++jj) blk[ii][jj] -= vi * wl[jj] + wi * vl[jj];
-    }
-    // keep the reflector in column j (rows >= j + 2) and beta at (r0, j)
-    if (b == j / RBC) {
-#pragma unroll
-      for (int jj = 0; jj < RBC; ++jj)
-        if (jj == j % RBC) {
-#pragma unroll
-          for (int ii = 0; ii < RBR; ++ii) {
-            const int i = a * RBR + ii;
-            if (i == r0) blk[ii][jj] = coef[0];
-            else if (i > r0) blk[ii][jj] = col[i];
+          for (int m = 0; m < 8; ++m) {
+            const int l = 32 * c + 4 * m + q;
+            const double vl = vb[l];
+            const double wl = pb[l] - Kc * vl;
+            a[c][m] -= vi * wl + wi * vl;
           }
         }
+      }
+    }
+    // publish row j + 1 (updated, or unchanged when the reflector is trivial)
+    if (i == j + 1) {
+#pragma unroll
+      for (int c = 0; c < NCH; ++c)
+#pragma unroll
+        for (int m = 0; m < 8; ++m) xrow[(j + 1) & 1][32 * c + 4 * m + q] = a[c][m];
     }
     __syncthreads();
   }
-  // write back; d, e of the last 2 x 2 block
+  // the last 2 x 2 block: row k - 2 is published; row k - 1 goes to vb
+  if (i == k - 1) {
 #pragma unroll
-  for (int ii = 0; ii < RBR; ++ii)
+    for (int c = 0; c < NCH; ++c)
 #pragma unroll
-    for (int jj = 0; jj < RBC; ++jj) {
-      const int i = a * RBR + ii, l = b * RBC + jj;
-      if (i < k && l < k) A[i + (int64_t)l * lda] = blk[ii][jj];
-    }
+      for (int m = 0; m < 8; ++m) vb[32 * c + 4 * m + q] = a[c][m];
+  }
   __syncthreads();
   if (t == 0) {
-    if (k >= 2) {
-      d[k - 2] = A[(k - 2) + (int64_t)(k - 2) * lda];
-      e[k - 2] = A[(k - 1) + (int64_t)(k - 2) * lda];
-      tau[k - 2] = 0.0;
-    }
-    d[k - 1] = A[(k - 1) + (int64_t)(k - 1) * lda];
+    const double* x = xrow[(k - 2) & 1];
+    d[k - 2] = x[k - 2];
+    e[k - 2] = x[k - 1];
+    tau[k - 2] = 0.0;
+    d[k - 1] = vb[k - 1];
     tau[k - 1] = 0.0;
   }
 }
@@ -476,68 +475,107 @@ __global__ __launch_bounds__(64) void bisect_kernel(const double* d, const doubl
   if (lane == 0) lam[i] = 0.5 * (lo + hi);
 }
 
-// One thread: threshold, ordering by |lambda| descending (negatives first on
-// ties), clusters of the kept set.  Outputs:
-//   order[c]  : ascending index of the c-th kept eigenvalue
-//   lam_out   : kept eigenvalues (|lambda| desc), then the rest
+// Selection, by one block of kSelT threads.  Outputs:
+//   order[c]  : ascending index of the c-th kept eigenvalue, kept ones ordered
+//               by |lambda| descending, ties by ascending index (so negatives
+//               come first)
+//   pos_of[i] : output column of eigenvalue i, -1 when not kept
+//   lam_out   : kept eigenvalues (in that order), then the rest ascending
 //   clusters  : (start, len) runs in ascending order over kept eigenvalues
 //               with consecutive gaps <= kOrtol ||T||;
 //               cl_count[0] = number of clusters
 //   keep[0]   : kept count (capped at max_keep, flag |= 2 when capped)
-__global__ void select_kernel(const double* lam, int k, double tol, int64_t max_keep,
-                              const double* bounds, int* order, int* pos_of, double* lam_out,
-                              int* clusters, int* cl_count, int64_t* keep, int* flag) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+// The counts that place the unkept eigenvalues and the clusters come from
+// block-wide prefix sums over contiguous chunks of the index range.
+constexpr int kSelT = 1024;
+
+__device__ inline int block_scan_incl(int v, int* sh) {
+  // inclusive prefix sum of v over the block (Hillis-Steele in LDS)
+  const int t = threadIdx.x;
+  sh[t] = v;
+  __syncthreads();
+  for (int off = 1; off < kSelT; off <<= 1) {
+    const int add = (t >= off) ? sh[t - off] : 0;
+    __syncthreads();
+    sh[t] += add;
+    __syncthreads();
+  }
+  const int r = sh[t];
+  __syncthreads();
+  return r;
+}
+
+__global__ __launch_bounds__(kSelT) void select_kernel(const double* lam, int k, double tol,
+                                                       int64_t max_keep, const double* bounds,
+                                                       int* order, int* pos_of, double* lam_out,
+                                                       int* clusters, int* cl_count, int64_t* keep,
+                                                       int* flag) {
+  __shared__ int sh[kSelT];
+  const int t = threadIdx.x;
   // eigenvalues are known to about u ||T||; a zero matrix has no nonzero ones
+  const double nrmT = bounds[3];
   double amax = 0.0;
-  if (k > 0 && bounds[3] > 0.0) amax = fmax(fabs(lam[0]), fabs(lam[k - 1]));
+  if (k > 0 && nrmT > 0.0) amax = fmax(fabs(lam[0]), fabs(lam[k - 1]));
   const double thr = tol * amax;
-  int lo = 0, hi = k - 1, c = 0;
-  int kept = 0;
-  // merge from both ends of the ascending list
-  while (lo <= hi) {
-    const double al = fabs(lam[lo]), ah = fabs(lam[hi]);
-    int take;
-    if (al >= ah) take = lo++;
-    else take = hi--;
-    const double a = fabs(lam[take]);
-    if (amax > 0.0 && a > thr) {
-      order[c] = take;
-      ++c;
+  const bool any = amax > 0.0;
+  // contiguous chunk of indices of this thread
+  const int per = (k + kSelT - 1) / kSelT;
+  const int i0 = min(k, t * per), i1 = min(k, i0 + per);
+  int cnt = 0;
+  for (int i = i0; i < i1; ++i) cnt += (any && fabs(lam[i]) > thr) ? 1 : 0;
+  const int nkept = block_scan_incl(cnt, sh);
+  __shared__ int tot_kept;
+  if (t == kSelT - 1) tot_kept = nkept;
+  __syncthreads();
+  const int kept = tot_kept;
+  const int cap = (int)min<int64_t>(kept, max_keep);
+  if (t == 0 && kept > max_keep) atomicOr(flag, 2);
+  // rank of every kept eigenvalue (every |lambda_j| >= |lambda_i| is kept too)
+  for (int i = i0; i < i1; ++i) {
+    int pos = -1;
+    const double a = fabs(lam[i]);
+    if (any && a > thr) {
+      int rk = 0;
+      for (int j = 0; j < k; ++j) {
+        const double b = fabs(lam[j]);
+        rk += (b > a || (b == a && j < i)) ? 1 : 0;
+      }
+      if (rk < cap) {
+        pos = rk;
+        order[rk] = i;
+        lam_out[rk] = lam[i];
+      }
     }
-    pos_of[take] = -1;
+    pos_of[i] = pos;
   }
-  kept = c;
-  int64_t cap = kept;
-  if (cap > max_keep) {
-    cap = max_keep;
-    atomicOr(flag, 2);
+  __syncthreads();  // pos_of (global) visible to the block
+  // the unkept ones, ascending, after the kept ones
+  int un = 0;
+  for (int i = i0; i < i1; ++i) un += (pos_of[i] < 0) ? 1 : 0;
+  int o = cap + block_scan_incl(un, sh) - un;
+  for (int i = i0; i < i1; ++i)
+    if (pos_of[i] < 0) lam_out[o++] = lam[i];
+  // clusters: a run starts at a kept eigenvalue whose lower neighbour is not
+  // kept or lies more than kOrtol ||T|| below
+  auto starts = [&](int i) {
+    return pos_of[i] >= 0 && (i == 0 || pos_of[i - 1] < 0 || lam[i] - lam[i - 1] > kOrtol * nrmT);
+  };
+  int ns = 0;
+  for (int i = i0; i < i1; ++i) ns += starts(i) ? 1 : 0;
+  const int incl = block_scan_incl(ns, sh);
+  int id = incl - ns;
+  for (int i = i0; i < i1; ++i) {
+    if (!starts(i)) continue;
+    int len = 1;
+    while (i + len < k && pos_of[i + len] >= 0 && !starts(i + len)) ++len;
+    clusters[2 * id] = i;
+    clusters[2 * id + 1] = len;
+    ++id;
   }
-  for (int q = 0; q < k; ++q) pos_of[q] = -1;
-  for (int q = 0; q < cap; ++q) pos_of[order[q]] = q;
-  // lam_out: kept first (in order), then the remaining ones in ascending order
-  int o = 0;
-  for (int q = 0; q < cap; ++q) lam_out[o++] = lam[order[q]];
-  for (int q = 0; q < k; ++q)
-    if (pos_of[q] < 0) lam_out[o++] = lam[q];
-  // clusters among kept eigenvalues, scanning in ascending order
-  int ncl = 0;
-  int q = 0;
-  while (q < k) {
-    if (pos_of[q] < 0) { ++q; continue; }
-    int start = q, len = 1;
-    while (q + len < k && pos_of[q + len] >= 0) {
-      const double a = lam[q + len - 1], b = lam[q + len];
-      if (b - a <= kOrtol * bounds[3]) ++len;
-      else break;
-    }
-    clusters[2 * ncl] = start;
-    clusters[2 * ncl + 1] = len;
-    ++ncl;
-    q = start + len;
+  if (t == kSelT - 1) {
+    cl_count[0] = incl;
+    keep[0] = cap;
   }
-  cl_count[0] = ncl;
-  keep[0] = cap;
 }
 
 // Deterministic start vector in (-1, 1).
@@ -548,28 +586,34 @@ __device__ inline double start_entry(int idx, int i) {
 }
 
 // Inverse iteration for kept eigenvalue number `blockIdx.x` (ascending index
-// idx, output column pos_of[idx]); the tridiagonal LU and the solves are
-// sequential (thread 0), the rescaling and normalisation use the block.
-// Eigenvalues inside one cluster get shifts nudged apart by a few ulps of
-// ||T|| and distinct start vectors, so their iterates differ.  Z is column-
-// major: Z[i + c * ldz] is entry i of output column c.
-__global__ void invit_kernel(const double* d, const double* e, int k, const double* lam,
-                             const int* order, const int64_t* keep, const double* bounds,
-                             double* work, double* Z, int64_t ldz, int use_lds) {
+// idx, output column pos_of[idx]), one wave per eigenvalue.  The tridiagonal
+// LU with partial pivoting and the solves are sequential (lane 0); their
+// recurrences carry their state in registers and read only the arrays that do
+// not depend on it, and the pivots are stored as reciprocals, so the critical
+// path is a few floating-point operations per row.  Eigenvalues inside one
+// cluster get shifts nudged apart by a few ulps of ||T|| and distinct start
+// vectors, so their iterates differ.  Z is column-major: Z[i + c * ldz] is
+// entry i of output column c.
+__global__ __launch_bounds__(64) void invit_kernel(const double* d, const double* e, int k,
+                                                   const double* lam, const int* order,
+                                                   const int64_t* keep, const double* bounds,
+                                                   double* work, double* Z, int64_t ldz,
+                                                   int use_lds) {
   const int c = blockIdx.x;
   if (c >= keep[0]) return;
   const int idx = order[c];
+  const int lane = threadIdx.x;
   extern __shared__ double ism[];
-  __shared__ double red[256 / 64];
   __shared__ double sscale;
-  // the sequential LU and solves touch these arrays element by element:
-  // keep them in LDS when they fit
-  double* u0 = use_lds ? ism : work + (int64_t)c * 6 * k;
-  double* u1 = u0 + k;
-  double* u2 = u1 + k;
-  double* lm = u2 + k;
-  double* x = lm + k;
-  int* sw = reinterpret_cast<int*>(x + k);
+  // keep the arrays in LDS when they fit
+  double* dd = use_lds ? ism : work + (int64_t)c * kInvitArrays * k;
+  double* ee = dd + k;   // e (0 past the end)
+  double* u1 = ee + k;   // first super-diagonal of U
+  double* u2 = u1 + k;   // second super-diagonal of U
+  double* lm = u2 + k;   // multipliers
+  double* rp = lm + k;   // 1 / pivots
+  double* x = rp + k;    // iterate
+  double* swd = x + k;   // row swap flags (0 or 1)
   const double nrmT = bounds[3];
   const double eps = DBL_EPSILON;
   const double small = eps * fmax(nrmT, DBL_MIN);
@@ -580,65 +624,82 @@ __global__ void invit_kernel(const double* d, const double* e, int k, const doub
     for (int q = idx - 1; q >= 0 && lam[idx] - lam[q] <= 4.0 * eps * nrmT; --q) ++rank_in_tie;
     lamq += 4.0 * rank_in_tie * eps * fmax(nrmT, DBL_MIN);
   }
-  if (threadIdx.x == 0) {
-    // LU with partial pivoting of T - lamq I: rows i, i+1 may swap.
-    // After elimination row i holds u0[i] (diag), u1[i], u2[i] (super-diags).
-    double a = d[0] - lamq;
-    double b = (k > 1) ? e[0] : 0.0;
-    for (int i = 0; i + 1 < k; ++i) {
-      const double sub = e[i];
-      const double dn = d[i + 1] - lamq;
-      const double sn = (i + 2 < k) ? e[i + 1] : 0.0;
-      if (fabs(a) >= fabs(sub)) {
-        sw[i] = 0;
-        const double piv = (a == 0.0) ? small : a;
-        const double mlt = sub / piv;
-        u0[i] = piv; u1[i] = b; u2[i] = 0.0; lm[i] = mlt;
-        a = dn - mlt * b;
-        b = sn;
-      } else {
-        sw[i] = 1;
-        const double mlt = a / sub;
-        u0[i] = sub; u1[i] = dn; u2[i] = sn; lm[i] = mlt;
-        a = b - mlt * dn;
-        b = -mlt * sn;
-      }
-    }
-    u0[k - 1] = (a == 0.0) ? small : a;
-    u1[k - 1] = 0.0; u2[k - 1] = 0.0;
+  for (int i = lane; i < k; i += 64) {
+    dd[i] = d[i] - lamq;
+    ee[i] = (i + 1 < k) ? e[i] : 0.0;
+    x[i] = start_entry(idx, i);
   }
-  for (int i = threadIdx.x; i < k; i += blockDim.x) x[i] = start_entry(idx, i);
+  __syncthreads();
+  if (lane == 0) {
+    // LU with partial pivoting of T - lamq I: rows i, i+1 may swap.  After
+    // elimination row i holds the pivot, u1[i], u2[i].
+    double a = dd[0];
+    double b = (k > 1) ? ee[0] : 0.0;
+    for (int i = 0; i + 1 < k; ++i) {
+      const double sub = ee[i];
+      const double dn = dd[i + 1];
+      const double sn = ee[i + 1];
+      double piv, mlt, na, nb, w1, w2, sw;
+      if (fabs(a) >= fabs(sub)) {
+        piv = (a == 0.0) ? small : a;
+        mlt = sub / piv;
+        w1 = b; w2 = 0.0; sw = 0.0;
+        na = dn - mlt * b;
+        nb = sn;
+      } else {
+        piv = sub;
+        mlt = a / sub;
+        w1 = dn; w2 = sn; sw = 1.0;
+        na = b - mlt * dn;
+        nb = -mlt * sn;
+      }
+      const double pv = (fabs(piv) < small) ? copysign(small, piv) : piv;
+      rp[i] = 1.0 / pv;
+      u1[i] = w1; u2[i] = w2; lm[i] = mlt; swd[i] = sw;
+      a = na;
+      b = nb;
+    }
+    {
+      const double piv = (a == 0.0) ? small : a;
+      const double pv = (fabs(piv) < small) ? copysign(small, piv) : piv;
+      rp[k - 1] = 1.0 / pv;
+      u1[k - 1] = 0.0; u2[k - 1] = 0.0;
+    }
+  }
   __syncthreads();
   for (int it = 0; it < kInvitIters; ++it) {
-    if (threadIdx.x == 0) {
+    if (lane == 0) {
+      // forward: apply the row swaps and multipliers; (xa, xb) = rows i, i+1
+      double xa = x[0];
       for (int i = 0; i + 1 < k; ++i) {
-        if (sw[i]) { const double tmp = x[i]; x[i] = x[i + 1]; x[i + 1] = tmp; }
-        x[i + 1] -= lm[i] * x[i];
+        double xb = x[i + 1];
+        if (swd[i] != 0.0) { const double tmp = xa; xa = xb; xb = tmp; }
+        xb -= lm[i] * xa;
+        x[i] = xa;
+        xa = xb;
       }
+      x[k - 1] = xa;
+      // backward: (x1, x2) = solved rows i + 1, i + 2
+      double x1 = 0.0, x2 = 0.0, mx = 0.0;
       for (int i = k - 1; i >= 0; --i) {
-        double v = x[i];
-        if (i + 1 < k) v -= u1[i] * x[i + 1];
-        if (i + 2 < k) v -= u2[i] * x[i + 2];
-        const double piv = (fabs(u0[i]) < small) ? copysign(small, u0[i] == 0.0 ? 1.0 : u0[i]) : u0[i];
-        x[i] = v / piv;
+        const double v = (x[i] - u1[i] * x1 - u2[i] * x2) * rp[i];
+        x[i] = v;
+        mx = fmax(mx, fabs(v));
+        x2 = x1;
+        x1 = v;
       }
-      double mx = 0.0;
-      for (int i = 0; i < k; ++i) mx = fmax(mx, fabs(x[i]));
       sscale = (mx > 0.0) ? 1.0 / mx : 1.0;
     }
     __syncthreads();
-    for (int i = threadIdx.x; i < k; i += blockDim.x) x[i] *= sscale;
+    const double sc = sscale;
+    for (int i = lane; i < k; i += 64) x[i] *= sc;
     __syncthreads();
   }
   double part = 0.0;
-  for (int i = threadIdx.x; i < k; i += blockDim.x) part += x[i] * x[i];
-  for (int off = 32; off > 0; off >>= 1) part += __shfl_xor(part, off, 64);
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = part;
-  __syncthreads();
-  double nn = 0.0;
-  for (int wv = 0; wv < (int)(blockDim.x >> 6); ++wv) nn += red[wv];
-  const double inv = (nn > 0.0) ? 1.0 / sqrt(nn) : 0.0;
-  for (int i = threadIdx.x; i < k; i += blockDim.x) Z[i + (int64_t)c * ldz] = x[i] * inv;
+  for (int i = lane; i < k; i += 64) part += x[i] * x[i];
+  part = wave_sum_f64(part);
+  const double inv = (part > 0.0) ? 1.0 / sqrt(part) : 0.0;
+  for (int i = lane; i < k; i += 64) Z[i + (int64_t)c * ldz] = x[i] * inv;
 }
 
 // Orthonormalise the vectors of one cluster (blockIdx.x), in ascending
@@ -674,13 +735,13 @@ __global__ __launch_bounds__(1024) void orth_kernel(int k, const int* clusters, 
       const double* zj = vec(j);
       double nj = 0.0;
       for (int i = lane; i < k; i += 64) nj += zj[i] * zj[i];
-      for (int off = 32; off > 0; off >>= 1) nj += __shfl_xor(nj, off, 64);
+      nj = wave_sum_f64(nj);
       const double inv2 = (nj > 0.0) ? 1.0 / nj : 0.0;
       for (int l = j + 1 + wv; l < len; l += nw) {
         double* zl = vec(l);
         double dt = 0.0;
         for (int i = lane; i < k; i += 64) dt += zj[i] * zl[i];
-        for (int off = 32; off > 0; off >>= 1) dt += __shfl_xor(dt, off, 64);
+        dt = wave_sum_f64(dt);
         const double f = dt * inv2;
         for (int i = lane; i < k; i += 64) zl[i] -= f * zj[i];
       }
@@ -691,7 +752,7 @@ __global__ __launch_bounds__(1024) void orth_kernel(int k, const int* clusters, 
       double* zj = vec(j);
       double nj = 0.0;
       for (int i = lane; i < k; i += 64) nj += zj[i] * zj[i];
-      for (int off = 32; off > 0; off >>= 1) nj += __shfl_xor(nj, off, 64);
+      nj = wave_sum_f64(nj);
       const double inv = (nj > 0.0) ? 1.0 / sqrt(nj) : 0.0;
       for (int i = lane; i < k; i += 64) zj[i] *= inv;
     }
@@ -705,52 +766,50 @@ __global__ __launch_bounds__(1024) void orth_kernel(int k, const int* clusters, 
   }
 }
 
-// V(:, c) = H_0 H_1 ... H_{k-3} z_c, with z_c = Z[i + c * ldz]; one block per
-// column, z staged in LDS.  Also fixes the sign so that the largest-|entry| is
-// positive.
-__global__ void backtr_kernel(const double* A, int64_t lda, const double* tau, int k,
-                              const double* Z, int64_t ldz, const int64_t* keep, double* V,
-                              int64_t ldv) {
-  extern __shared__ double z[];
-  __shared__ double red[256 / 64];
-  const int c = blockIdx.x;
-  if (c >= keep[0]) return;
-  for (int i = threadIdx.x; i < k; i += blockDim.x) z[i] = Z[i + (int64_t)c * ldz];
-  __syncthreads();
+// V(:, c) = H_0 H_1 ... H_{k-3} z_c, with z_c = Z[i + c * ldz]; one wave per
+// column (kBtCols columns per block), z in LDS, so the reflectors are applied
+// with wave reductions only.  Also fixes the sign so that the largest |entry|
+// is positive (the first one on ties).
+constexpr int kBtCols = 4;
+constexpr int kBtLdsMaxK = 4096;  // z of the block's columns in LDS up to this k
+
+__global__ __launch_bounds__(64 * kBtCols) void backtr_kernel(const double* A, int64_t lda,
+                                                              const double* tau, int k,
+                                                              const double* Z, int64_t ldz,
+                                                              const int64_t* keep, double* V,
+                                                              int64_t ldv, int use_lds) {
+  extern __shared__ double zsh[];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int c = blockIdx.x * kBtCols + wv;
+  if (c >= keep[0]) return;  // whole wave
+  // z in LDS, or in place in the output column when k is large
+  double* z = use_lds ? zsh + (int64_t)wv * k : V + (int64_t)c * ldv;
+  for (int i = lane; i < k; i += 64) z[i] = Z[i + (int64_t)c * ldz];
   for (int j = k - 3; j >= 0; --j) {
     const double tj = tau[j];
     if (tj == 0.0) continue;
     const int r0 = j + 1;
+    const double* vj = A + (int64_t)j * lda;
     double part = 0.0;
-    for (int i = r0 + threadIdx.x; i < k; i += blockDim.x) {
-      const double vi = (i == r0) ? 1.0 : A[i + (int64_t)j * lda];
-      part += vi * z[i];
-    }
-    for (int off = 32; off > 0; off >>= 1) part += __shfl_xor(part, off, 64);
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = part;
-    __syncthreads();
-    double s = 0.0;
-    for (int wv = 0; wv < (int)(blockDim.x >> 6); ++wv) s += red[wv];
-    __syncthreads();
-    s *= tj;
-    for (int i = r0 + threadIdx.x; i < k; i += blockDim.x) {
-      const double vi = (i == r0) ? 1.0 : A[i + (int64_t)j * lda];
-      z[i] -= s * vi;
-    }
-    __syncthreads();
+    for (int i = r0 + lane; i < k; i += 64) part += ((i == r0) ? 1.0 : vj[i]) * z[i];
+    part = wave_sum_f64(part);
+    const double s = tj * part;
+    for (int i = r0 + lane; i < k; i += 64) z[i] -= s * ((i == r0) ? 1.0 : vj[i]);
   }
   // sign convention: largest |entry| positive (first one on ties)
-  if (threadIdx.x == 0) {
-    double best = -1.0, sgn = 1.0;
-    for (int i = 0; i < k; ++i) {
-      const double a = fabs(z[i]);
-      if (a > best) { best = a; sgn = (z[i] < 0.0) ? -1.0 : 1.0; }
-    }
-    red[0] = sgn;
+  double best = -1.0;
+  int bi = k;
+  for (int i = lane; i < k; i += 64) {
+    const double a = fabs(z[i]);
+    if (a > best) { best = a; bi = i; }
   }
-  __syncthreads();
-  const double sgn = red[0];
-  for (int i = threadIdx.x; i < k; i += blockDim.x) V[i + (int64_t)c * ldv] = sgn * z[i];
+  for (int off = 32; off > 0; off >>= 1) {
+    const double ob = __shfl_xor(best, off, 64);
+    const int oi = __shfl_xor(bi, off, 64);
+    if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
+  }
+  const double sgn = (bi < k && z[bi] < 0.0) ? -1.0 : 1.0;
+  for (int i = lane; i < k; i += 64) V[i + (int64_t)c * ldv] = sgn * z[i];
 }
 
 }  // namespace
@@ -761,7 +820,7 @@ size_t syev_workspace(int64_t k) {
   b += 8 * ((size_t)k * sizeof(double) + 256);    // d, e, tau, p, w, e2, lam, bounds
   b += 4 * ((size_t)k * sizeof(int) + 256);       // order, pos_of, clusters(2k), count
   b += (size_t)k * 2 * sizeof(int) + 256;
-  b += (size_t)k * 6 * k * sizeof(double) + 256;  // invit scratch (per cluster)
+  b += (size_t)k * kInvitArrays * k * sizeof(double) + 256;  // inverse-iteration arrays
   b += (size_t)k * k * sizeof(double) + 256;      // Zt
   return b;
 }
@@ -787,7 +846,7 @@ void syev_trunc_f64(hipStream_t s, int64_t k, const double* M, int64_t ldm, doub
   int* pos_of = ws.get<int>(k);
   int* clusters = ws.get<int>(2 * k);
   int* cl_count = ws.get<int>(4);
-  double* work = ws.get<double>((size_t)k * 6 * k);
+  double* work = ws.get<double>((size_t)k * kInvitArrays * k);
   double* Zt = ws.get<double>((size_t)k * k);
 
   copy_f64(s, M, ldm, A, k, k, k);
@@ -798,11 +857,11 @@ void syev_trunc_f64(hipStream_t s, int64_t k, const double* M, int64_t ldm, doub
     fill_f64(s, tau, 1, 1, 1, 0.0);
   } else {
     if (k <= 128) {
-      hipLaunchKernelGGL((tridiag_reg_kernel<4, 4, 1024>), dim3(1), dim3(1024), 0, s, A, k, ki, d, e, tau);
+      hipLaunchKernelGGL((tridiag_rows_kernel<4>), dim3(1), dim3(512), 0, s, A, k, ki, d, e, tau);
     } else if (k <= 160) {
-      hipLaunchKernelGGL((tridiag_reg_kernel<5, 5, 1024>), dim3(1), dim3(1024), 0, s, A, k, ki, d, e, tau);
+      hipLaunchKernelGGL((tridiag_rows_kernel<5>), dim3(1), dim3(640), 0, s, A, k, ki, d, e, tau);
     } else if (k <= 192) {
-      hipLaunchKernelGGL((tridiag_reg_kernel<12, 6, 512>), dim3(1), dim3(512), 0, s, A, k, ki, d, e, tau);
+      hipLaunchKernelGGL((tridiag_rows_kernel<6>), dim3(1), dim3(768), 0, s, A, k, ki, d, e, tau);
     } else if (k <= kTriMaxK) {
       const size_t lds = (size_t)(3 + kTriT / 64) * k * sizeof(double);
       hipLaunchKernelGGL(tridiag_small_kernel, dim3(1), dim3(kTriT), lds, s, A, k, ki, d, e, tau);
@@ -815,13 +874,14 @@ void syev_trunc_f64(hipStream_t s, int64_t k, const double* M, int64_t ldm, doub
   DME_HIP(hipGetLastError());
   hipLaunchKernelGGL(bisect_kernel, dim3((unsigned)k), dim3(64), 0, s, d, e2, ki, bounds, lam);
   DME_HIP(hipGetLastError());
-  hipLaunchKernelGGL(select_kernel, dim3(1), dim3(64), 0, s, lam, ki, tol, max_keep, bounds, order,
+  hipLaunchKernelGGL(select_kernel, dim3(1), dim3(kSelT), 0, s, lam, ki, tol, max_keep, bounds, order,
                      pos_of, lam_out, clusters, cl_count, keep_dev, flag_dev);
   DME_HIP(hipGetLastError());
   // Z: k x (kept) column-major with ld = k (kept <= k)
   const unsigned nkeep = (unsigned)std::min<int64_t>(k, max_keep);
   const int invit_lds = (k <= kInvitLdsMaxK) ? 1 : 0;
-  hipLaunchKernelGGL(invit_kernel, dim3(nkeep), dim3(64), invit_lds ? (size_t)6 * k * sizeof(double) : 0,
+  hipLaunchKernelGGL(invit_kernel, dim3(nkeep), dim3(64),
+                     invit_lds ? (size_t)kInvitArrays * k * sizeof(double) : 0,
                      s, d, e, ki, lam, order, keep_dev, bounds, work, Zt, k, invit_lds);
   DME_HIP(hipGetLastError());
   // cluster staging in LDS: up to 144 KiB, never more than the whole k x k set
@@ -829,8 +889,10 @@ void syev_trunc_f64(hipStream_t s, int64_t k, const double* M, int64_t ldm, doub
   hipLaunchKernelGGL(orth_kernel, dim3((unsigned)k), dim3(1024), (size_t)orth_lds * sizeof(double), s,
                      ki, clusters, cl_count, pos_of, Zt, k, (int)orth_lds);
   DME_HIP(hipGetLastError());
-  hipLaunchKernelGGL(backtr_kernel, dim3((unsigned)std::min<int64_t>(k, max_keep)), dim3(256),
-                     (size_t)k * sizeof(double), s, A, k, tau, ki, Zt, k, keep_dev, V_out, ldv);
+  const int bt_lds = (k <= kBtLdsMaxK) ? 1 : 0;
+  hipLaunchKernelGGL(backtr_kernel, dim3((unsigned)cdiv(std::min<int64_t>(k, max_keep), kBtCols)),
+                     dim3(64 * kBtCols), bt_lds ? (size_t)kBtCols * k * sizeof(double) : 0, s, A, k,
+                     tau, ki, Zt, k, keep_dev, V_out, ldv, bt_lds);
   DME_HIP(hipGetLastError());
 }
 

@@ -143,13 +143,24 @@ def _compress_case(name):
     elif name == "tall_multi_panel":
         n, k = 4097, 97
         W = rng.standard_normal((n, k)) / np.sqrt(n); Dh = np.diag(np.exp(-0.2 * np.arange(k)))
+    elif name == "tree_ragged":  # tree QR: last block 476 rows, last panel 6 columns
+        n, k = 1500, 70
+        W = rng.standard_normal((n, k)) * (10.0 ** -np.linspace(0, 6, k)); Dh = np.eye(k)
+    elif name == "tree_two_levels":  # product-like columns, rank-deficient
+        n, k = 2048, 200
+        W = rng.standard_normal((n, 150)) @ rng.standard_normal((150, k)) / np.sqrt(n)
+        F = rng.standard_normal((k, k)); Dh = F @ F.T / k
+    elif name == "tree_full_size":  # n of the headline workload: three tree levels
+        n, k = 16384, 180
+        W = rng.standard_normal((n, k)) / np.sqrt(n) * np.exp(-0.05 * np.arange(k)); Dh = np.eye(k)
     else:
         raise KeyError(name)
     return W, Dh
 
 
 @pytest.mark.parametrize("name", ["random", "rankdef", "wide", "zero", "identity", "graded",
-                                  "tall_multi_panel"])
+                                  "tall_multi_panel", "tree_ragged", "tree_two_levels",
+                                  "tree_full_size"])
 def test_compress_matches_oracle(ctx, name):
     announce("compress", name)
     W, Dh = _compress_case(name)
@@ -189,7 +200,9 @@ def test_gemm_mixed(ctx, n, r):
     got = to_np(ctx.gemm_mixed(E, X))
     ref = E @ X
     scale = np.abs(E) @ np.abs(X)
-    assert np.all(np.abs(got - ref) <= 1e-5 * scale + 1e-300)
+    # FP32 representation of E and X plus the dropped piece products: a few
+    # units of 2^-24 of |E||X| per entry (FP64 accumulation across K steps)
+    assert np.all(np.abs(got - ref) <= 4e-7 * scale + 1e-300)
     assert rel_fro(got, ref) < 1e-6
 
 
@@ -202,4 +215,4 @@ def test_gemm_mixed_heat_operator(ctx):
     rng = np.random.default_rng(3)
     X, _ = np.linalg.qr(rng.standard_normal((A.shape[0], 40)))
     got = to_np(ctx.gemm_mixed(E, X))
-    assert rel_fro(got, E @ X) < 2e-7
+    assert rel_fro(got, E @ X) < 1e-7
