@@ -48,12 +48,13 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef unsigned short u16;
 
-constexpr int kMT = 512;       // threads per workgroup
-constexpr int kMWaves = kMT / 64;
+constexpr int kMT = 256;        // threads per workgroup (4 waves)
 constexpr int kMRowsWave = 32;  // two 16-row MFMA tiles per wave
-constexpr int kMRows = 4 * kMRowsWave;  // 128 rows per workgroup (4 row groups)
+constexpr int kMRows = (kMT / 64) * kMRowsWave;  // 128 rows per workgroup
 constexpr int kMBK = 32;        // K per step (one MFMA K)
-constexpr int kMLdsK = kMBK + 8;  // padded k extent of an LDS column (bf16)
+constexpr int kMPD = 4;         // E register stages (steps loaded ahead)
+constexpr int kMFl = 4;         // steps per FP32 accumulation span (128 K)
+static_assert(kMFl % kMPD == 0, "the E ring must cycle within an accumulation span");
 
 // FP32 -> BF16 bits with round-to-nearest-even (finite inputs).
 __device__ __forceinline__ u16 bf16_rne(float x) {
@@ -82,10 +83,12 @@ __device__ __forceinline__ void split3_d(double x, u16& a, u16& b, u16& c) {
   c = bf16_rne((float)r2);
 }
 
+typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+
 union Frag {
   bf16x8 v;
   u16 h[8];
-  uint4 q;
+  u32x4 q;
 };
 
 // E (FP64, column-major, ld n) -> Et (FP32 row-major, ld lde), zero padding in
@@ -125,169 +128,163 @@ __global__ void mixed_split_x_kernel(const double* __restrict__ X, int64_t ldx, 
   }
 }
 
-// KS = MFMA K-steps (of 32) per main-loop iteration: 2 when the double-
-// buffered X tile fits in LDS (TN <= 8), else 1.
-//
-// Wave layout: 8 waves = 4 row groups x 2 column halves.  Wave (g, hc) owns
-// rows g*32 .. g*32+31 of the workgroup's 128 (two 16-row MFMA tiles) and the
-// column tiles [hc*TW, min(TN, (hc+1)*TW)).  For every 32-wide K step the six
-// piece products of a tile are summed by the MFMA into a fresh FP32
-// accumulator (the five small ones first) and that step's sum is added to an
-// FP64 accumulator: FP32 rounding then acts on one step's partial only.
-template <int TN, int KS>
+// One workgroup = 4 waves = 128 rows of Y and every column (TN 16-column
+// tiles); wave w owns rows 32 w .. 32 w + 31 (two 16-row MFMA tiles).  The K
+// range is split into nsplit chunks; workgroup b takes chunk b % nsplit.  Per
+// 32-wide K step the Xs tile (three pieces) is staged in LDS (double-buffered,
+// one barrier per step) and shared by the four waves; every wave reads its E
+// fragments straight from HBM into a ring of kMPD register stages (loads
+// issued kMPD steps ahead, addresses clamped so no load sits behind a
+// branch), splits them into BF16 pieces in registers and runs the six piece
+// products of its 2 x TN tiles.  The products accumulate in FP32 over kMFl
+// steps (128 K) and are then added to FP64 accumulators.
+template <int TN>
 __global__ __launch_bounds__(kMT) void gemm_mixed_kernel(int n, int lde, int rpad, int nsplit,
                                                          int kchunk, const float* __restrict__ Et,
                                                          const u16* __restrict__ Xs, int r,
                                                          double* __restrict__ partial) {
-  constexpr int NC = TN * 16;             // columns covered
-  constexpr int TW = (TN + 1) / 2;        // column tiles per wave
-  constexpr int BK = kMBK * KS;           // K per iteration
-  constexpr int QPC = BK / 8;             // 16-byte chunks per column of the tile
-  constexpr int CHUNKS = 3 * NC * QPC;    // 16-byte chunks of one Xs tile
+  constexpr int NC = TN * 16;          // columns covered
+  constexpr int QPC = kMBK / 8;        // 16-byte chunks per column of a step's tile
+  constexpr int CHUNKS = 3 * NC * QPC; // 16-byte chunks of one Xs tile
   constexpr int CPT = (CHUNKS + kMT - 1) / kMT;
-  __shared__ uint4 sX[2][3][NC][QPC + 1];
+  __shared__ u32x4 sX[2][3][NC][QPC + 1];
+  __shared__ u32x4 sSink;  // target of the stores of threads past the tile (no branch)
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
-  const int rg = wave & 3, hc = wave >> 2;
-  const int jbeg = hc * TW;
   const int split = blockIdx.x % nsplit;
   const int rb = blockIdx.x / nsplit;
   const int kbeg = split * kchunk;
   const int kend = min(lde, kbeg + kchunk);
+  const int nsteps = (kend - kbeg) / kMBK;  // a multiple of kMFl
   const int row_l = lane & 15;
-  const int kg = lane >> 4;  // k group: k = 8 kg .. 8 kg + 7 of a 32-wide step
+  const int kg = lane >> 4;  // k group: k = 8 kg .. 8 kg + 7 of a step
   const int64_t plane = (int64_t)lde * rpad;
 
-  double acc[2][TW][4];
+  double acc[2][TN][4];
+  f32x4 fa[2][TN];
 #pragma unroll
   for (int t = 0; t < 2; ++t)
 #pragma unroll
-    for (int j = 0; j < TW; ++j)
+    for (int j = 0; j < TN; ++j) {
 #pragma unroll
       for (int v = 0; v < 4; ++v) acc[t][j][v] = 0.0;
+      fa[t][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    }
 
-  int rows[2];
+  // E rows of this lane (clamped: rows past n compute values nobody stores)
+  const float* erow[2];
 #pragma unroll
-  for (int t = 0; t < 2; ++t) rows[t] = rb * kMRows + rg * kMRowsWave + t * 16 + row_l;
-
-  // E fragments of an iteration: [substep][tile][8 consecutive k]
-  float ecur[KS][2][8];
-  auto load_e = [&](int k0, float (&dst)[KS][2][8]) {
+  for (int t = 0; t < 2; ++t) {
+    const int row = min(rb * kMRows + wave * kMRowsWave + t * 16 + row_l, n - 1);
+    erow[t] = Et + (int64_t)row * lde + kg * 8;
+  }
+  float4 ering[kMPD][2][2];
+  auto load_e = [&](int step, float4 (&dst)[2][2]) {
+    const int k0 = kbeg + min(step, nsteps - 1) * kMBK;  // clamped: the tail re-reads the last step
 #pragma unroll
-    for (int ks = 0; ks < KS; ++ks)
-#pragma unroll
-      for (int t = 0; t < 2; ++t) {
-        if (rows[t] < n) {
-          const float4* src =
-              reinterpret_cast<const float4*>(Et + (int64_t)rows[t] * lde + k0 + ks * kMBK + kg * 8);
-          const float4 a = src[0], b = src[1];
-          dst[ks][t][0] = a.x; dst[ks][t][1] = a.y; dst[ks][t][2] = a.z; dst[ks][t][3] = a.w;
-          dst[ks][t][4] = b.x; dst[ks][t][5] = b.y; dst[ks][t][6] = b.z; dst[ks][t][7] = b.w;
-        } else {
-#pragma unroll
-          for (int q = 0; q < 8; ++q) dst[ks][t][q] = 0.f;
-        }
-      }
-  };
-
-  uint4 stage[CPT];
-  auto load_x = [&](int k0) {
-#pragma unroll
-    for (int c = 0; c < CPT; ++c) {
-      const int idx = tid + c * kMT;
-      if (idx < CHUNKS) {
-        const int q = idx % QPC;
-        const int col = (idx / QPC) % NC;
-        const int pc = (idx / QPC) / NC;
-        stage[c] = *reinterpret_cast<const uint4*>(Xs + pc * plane + (int64_t)col * lde + k0 + q * 8);
-      }
+    for (int t = 0; t < 2; ++t) {
+      const float4* src = reinterpret_cast<const float4*>(erow[t] + k0);
+      dst[t][0] = src[0];
+      dst[t][1] = src[1];
     }
   };
-  auto store_x = [&](int buf) {
-#pragma unroll
-    for (int c = 0; c < CPT; ++c) {
-      const int idx = tid + c * kMT;
-      if (idx < CHUNKS) {
-        const int q = idx % QPC;
-        const int col = (idx / QPC) % NC;
-        const int pc = (idx / QPC) / NC;
-        sX[buf][pc][col][q] = stage[c];
-      }
-    }
-  };
+  // the next Xs tile passes through registers (u32x4: promotable to VGPRs)
+  u32x4 stage[CPT];
+#define DME_LOAD_X(step)                                                                         \
+  do {                                                                                           \
+    const int k0_ = kbeg + min((step), nsteps - 1) * kMBK;                                       \
+    _Pragma("unroll") for (int c = 0; c < CPT; ++c) {                                            \
+      const int idx = min(tid + c * kMT, CHUNKS - 1);                                            \
+      const int q = idx % QPC, col = (idx / QPC) % NC, pc = (idx / QPC) / NC;                    \
+      stage[c] = *reinterpret_cast<const u32x4*>(Xs + pc * plane + (int64_t)col * lde + k0_ + q * 8); \
+    }                                                                                            \
+  } while (0)
+#define DME_STORE_X(buf)                                                                         \
+  do {                                                                                           \
+    _Pragma("unroll") for (int c = 0; c < CPT; ++c) {                                            \
+      const int idx = tid + c * kMT;                                                             \
+      const int ic = min(idx, CHUNKS - 1);                                                       \
+      const int q = ic % QPC, col = (ic / QPC) % NC, pc = (ic / QPC) / NC;                       \
+      u32x4* dst = (idx < CHUNKS) ? &sX[(buf)][pc][col][q] : &sSink;                             \
+      *dst = stage[c];                                                                           \
+    }                                                                                            \
+  } while (0)
 
-  if (kbeg < kend) {
-    load_x(kbeg);
-    store_x(0);
-    load_e(kbeg, ecur);
+  if (nsteps > 0) {
+    DME_LOAD_X(0);
+#pragma unroll
+    for (int u = 0; u < kMPD; ++u) load_e(u, ering[u]);
+    DME_STORE_X(0);
   }
   __syncthreads();
-  int buf = 0;
-  for (int k0 = kbeg; k0 < kend; k0 += BK) {
-    const bool more = (k0 + BK) < kend;
-    float enext[KS][2][8];
-    if (more) {
-      load_x(k0 + BK);
-      load_e(k0 + BK, enext);
-    }
+  for (int s0 = 0; s0 < nsteps; s0 += kMFl) {
 #pragma unroll
-    for (int ks = 0; ks < KS; ++ks) {
-      // split this substep's E fragments into three BF16 pieces
+    for (int u = 0; u < kMFl; ++u) {
+      const int s = s0 + u;
+      const int slot = u % kMPD;  // kMFl is a multiple of kMPD
+      const int buf = u & 1;      // s0 is even
+      // the next Xs tile is loaded before the E refill, so that waiting for it
+      // (before the LDS store below) leaves the E loads in flight
+      DME_LOAD_X(s + 1);
+      // split this step's E fragments into three BF16 pieces, then refill the slot
       Frag ef[2][3];
 #pragma unroll
-      for (int t = 0; t < 2; ++t)
+      for (int t = 0; t < 2; ++t) {
+        const float ev[8] = {ering[slot][t][0].x, ering[slot][t][0].y, ering[slot][t][0].z,
+                             ering[slot][t][0].w, ering[slot][t][1].x, ering[slot][t][1].y,
+                             ering[slot][t][1].z, ering[slot][t][1].w};
 #pragma unroll
-        for (int q = 0; q < 8; ++q)
-          split3(ecur[ks][t][q], ef[t][0].h[q], ef[t][1].h[q], ef[t][2].h[q]);
+        for (int q = 0; q < 8; ++q) split3(ev[q], ef[t][0].h[q], ef[t][1].h[q], ef[t][2].h[q]);
+      }
+      load_e(s + kMPD, ering[slot]);
 #pragma unroll
-      for (int jj = 0; jj < TW; ++jj) {
-        const int j = jbeg + jj;
-        if (j < TN) {
-          Frag xf[3];
+      for (int j = 0; j < TN; ++j) {
+        Frag xf[3];
 #pragma unroll
-          for (int pc = 0; pc < 3; ++pc) xf[pc].q = sX[buf][pc][j * 16 + row_l][ks * 4 + kg];
+        for (int pc = 0; pc < 3; ++pc) xf[pc].q = sX[buf][pc][j * 16 + row_l][kg];
 #pragma unroll
-          for (int t = 0; t < 2; ++t) {
-            f32x4 a = f32x4{0.f, 0.f, 0.f, 0.f};
-            a = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ef[t][2].v, xf[0].v, a, 0, 0, 0);
-            a = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ef[t][1].v, xf[1].v, a, 0, 0, 0);
-            a = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ef[t][0].v, xf[2].v, a, 0, 0, 0);
-            a = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ef[t][1].v, xf[0].v, a, 0, 0, 0);
-            a = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ef[t][0].v, xf[1].v, a, 0, 0, 0);
-            a = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ef[t][0].v, xf[0].v, a, 0, 0, 0);
-#pragma unroll
-            for (int v = 0; v < 4; ++v) acc[t][jj][v] += (double)a[v];
-          }
+        for (int t = 0; t < 2; ++t) {
+          f32x4 a = fa[t][j];
+          a = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ef[t][2].v, xf[0].v, a, 0, 0, 0);
+          a = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ef[t][1].v, xf[1].v, a, 0, 0, 0);
+          a = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ef[t][0].v, xf[2].v, a, 0, 0, 0);
+          a = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ef[t][1].v, xf[0].v, a, 0, 0, 0);
+          a = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ef[t][0].v, xf[1].v, a, 0, 0, 0);
+          a = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ef[t][0].v, xf[0].v, a, 0, 0, 0);
+          fa[t][j] = a;
         }
       }
-    }
-    if (more) {
-      store_x(buf ^ 1);
-#pragma unroll
-      for (int ks = 0; ks < KS; ++ks)
+      if (u == kMFl - 1) {
 #pragma unroll
         for (int t = 0; t < 2; ++t)
 #pragma unroll
-          for (int q = 0; q < 8; ++q) ecur[ks][t][q] = enext[ks][t][q];
+          for (int j = 0; j < TN; ++j) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) acc[t][j][v] += (double)fa[t][j][v];
+            fa[t][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+          }
+      }
+      DME_STORE_X(buf ^ 1);
+      __syncthreads();
     }
-    __syncthreads();
-    buf ^= 1;
   }
 
+#undef DME_LOAD_X
+#undef DME_STORE_X
   // lane holds rows 4 kg .. 4 kg + 3 of column row_l of each 16 x 16 tile
 #pragma unroll
   for (int t = 0; t < 2; ++t) {
-    const int row0 = rb * kMRows + rg * kMRowsWave + t * 16 + kg * 4;
+    const int row0 = rb * kMRows + wave * kMRowsWave + t * 16 + kg * 4;
 #pragma unroll
-    for (int jj = 0; jj < TW; ++jj) {
-      const int col = (jbeg + jj) * 16 + row_l;
-      if (jbeg + jj < TN && col < r) {
+    for (int j = 0; j < TN; ++j) {
+      const int col = j * 16 + row_l;
+      if (col < r) {
         double* dst = partial + ((int64_t)split * r + col) * n;
 #pragma unroll
         for (int v = 0; v < 4; ++v)
-          if (row0 + v < n) dst[row0 + v] = acc[t][jj][v];
+          if (row0 + v < n) dst[row0 + v] = acc[t][j][v];
       }
     }
   }
@@ -306,20 +303,20 @@ __global__ void mixed_reduce_kernel(const double* __restrict__ partial, int64_t 
   }
 }
 
-constexpr int kMaxTN = 16;
-constexpr int kMinChunk = 256;
+constexpr int kMaxTN = 8;
+constexpr int kMinChunk = 1024;
 
-// K granularity: two MFMA K-steps, so every main-loop iteration is full
-constexpr int kMKGran = 2 * kMBK;
+// K granularity: one FP32 accumulation span, so every span is full
+constexpr int kMKGran = kMFl * kMBK;
 
 int64_t lde_for(int64_t n) { return cdiv(n, kMKGran) * kMKGran; }
 
+// K chunks: enough workgroups to cover every CU, chunks of at least kMinChunk
 int nsplit_for(int64_t n) {
   const int64_t lde = lde_for(n);
   const int64_t rowblocks = cdiv(n, kMRows);
-  int64_t ns = 4;
-  while (rowblocks * ns < 512 && lde / (ns * 2) >= kMinChunk) ns *= 2;
-  while (ns > 1 && lde / ns < kMKGran) ns /= 2;
+  int64_t ns = 1;
+  while (rowblocks * ns < 256 && lde / (ns * 2) >= kMinChunk) ns *= 2;
   return (int)ns;
 }
 
@@ -327,9 +324,8 @@ template <int TN>
 void launch_mixed(hipStream_t s, int64_t n, int64_t lde, int64_t rpad, int nsplit, int kchunk,
                   const float* Et, const u16* Xs, int64_t r, double* partial) {
   const int64_t rowblocks = cdiv(n, kMRows);
-  constexpr int KS = (TN <= 8) ? 2 : 1;
-  hipLaunchKernelGGL((gemm_mixed_kernel<TN, KS>), dim3((unsigned)(rowblocks * nsplit)), dim3(kMT), 0,
-                     s, (int)n, (int)lde, (int)rpad, nsplit, kchunk, Et, Xs, (int)r, partial);
+  hipLaunchKernelGGL((gemm_mixed_kernel<TN>), dim3((unsigned)(rowblocks * nsplit)), dim3(kMT), 0, s,
+                     (int)n, (int)lde, (int)rpad, nsplit, kchunk, Et, Xs, (int)r, partial);
 }
 
 }  // namespace
@@ -380,8 +376,6 @@ void gemm_mixed(hipStream_t s, const MixedOp& op, const double* X, int64_t ldx, 
   case T: launch_mixed<T>(s, n, op.lde, rpad, ns, kchunk, Et, Xs, rc, partial); break;
       DME_MIXED_CASE(1) DME_MIXED_CASE(2) DME_MIXED_CASE(3) DME_MIXED_CASE(4)
       DME_MIXED_CASE(5) DME_MIXED_CASE(6) DME_MIXED_CASE(7) DME_MIXED_CASE(8)
-      DME_MIXED_CASE(9) DME_MIXED_CASE(10) DME_MIXED_CASE(11) DME_MIXED_CASE(12)
-      DME_MIXED_CASE(13) DME_MIXED_CASE(14) DME_MIXED_CASE(15) DME_MIXED_CASE(16)
 #undef DME_MIXED_CASE
       default: fail(DME_EINTERNAL, "mixed gemm: bad tile count");
     }

@@ -38,6 +38,7 @@ constexpr double kOrtol = 1e-3;  // gaps below kOrtol ||T|| join a cluster
 constexpr int kInvitIters = 3;
 constexpr int kInvitLdsMaxK = 2048;  // inverse-iteration arrays in LDS up to this k
 constexpr int kInvitArrays = 8;      // k-long arrays per inverse iteration
+constexpr int kBisLdsMaxK = 4096;    // bisection reads d, e^2 from LDS up to this k
 
 __device__ inline double block_sum_1024(double v, double* red) {
   // red: kTriT doubles of LDS; returns the total to every thread
@@ -54,15 +55,15 @@ __device__ inline double block_sum_1024(double v, double* red) {
 
 // Householder tridiagonalisation with the whole matrix in registers, by rows:
 // 4 adjacent lanes own row i (i = t / 4), lane q of them the columns
-// 32 c + 4 m + q (chunk c < NCH, m < 8), so column block c spans whole
-// 32-column stretches and a wave can skip the blocks (and rows) that lie
-// before the trailing part.  Because A is symmetric, column j is row j: its
-// four owners publish it to LDS, and every wave forms the reflector from it
-// redundantly.  A step then takes three barriers: v into LDS; p = tau A v
-// (row sums over the 4 lanes by DPP) and the per-wave parts of p^T v; the
-// rank-2 update A -= v w^T + w v^T, w = p - (tau/2)(p^T v) v, with row j + 1
-// published for the next step.  The reflector of step j goes to A(j+2:, j)
-// and d, e, tau as in tridiag_kernel.
+// 32 c + 8 q + m (chunk c < NCH, m < 8), so a chunk spans a whole 32-column
+// stretch (a wave skips the chunks, and rows, that lie before the trailing
+// part) and a lane's columns of a chunk are contiguous in LDS.  Because A is
+// symmetric, column j is row j: its four owners publish it to LDS, and every
+// wave forms the reflector from it redundantly.  A step then takes three
+// barriers: v into LDS; p = tau A v (row sums over the 4 lanes by DPP) and the
+// per-wave parts of p^T v; the rank-2 update A -= v w^T + w v^T,
+// w = p - (tau/2)(p^T v) v, with row j + 1 published for the next step.  The
+// reflector of step j goes to A(j+2:, j) and d, e, tau as in tridiag_kernel.
 template <int NCH>
 __global__ __launch_bounds__(128 * NCH) void tridiag_rows_kernel(double* A, int64_t lda, int k,
                                                                  double* d, double* e, double* tau) {
@@ -82,14 +83,15 @@ __global__ __launch_bounds__(128 * NCH) void tridiag_rows_kernel(double* A, int6
   for (int c = 0; c < NCH; ++c)
 #pragma unroll
     for (int m = 0; m < 8; ++m) {
-      const int l = 32 * c + 4 * m + q;
-      a[c][m] = (i < k && l < k) ? A[i + (int64_t)l * lda] : 0.0;
+      const int l = 32 * c + 8 * q + m;
+      const double v = A[min(i, k - 1) + (int64_t)min(l, k - 1) * lda];  // unconditional load
+      a[c][m] = (i < k && l < k) ? v : 0.0;
     }
   if (i == 0) {
 #pragma unroll
     for (int c = 0; c < NCH; ++c)
 #pragma unroll
-      for (int m = 0; m < 8; ++m) xrow[0][32 * c + 4 * m + q] = a[c][m];
+      for (int m = 0; m < 8; ++m) xrow[0][32 * c + 8 * q + m] = a[c][m];
   }
   __syncthreads();
   for (int j = 0; j + 2 < k; ++j) {
@@ -125,13 +127,14 @@ __global__ __launch_bounds__(128 * NCH) void tridiag_rows_kernel(double* A, int6
       const bool live = wrow_last >= r0;  // wave-uniform
       double pi = 0.0;
       if (live) {
-        double s = 0.0;
+        double sp[4] = {0.0, 0.0, 0.0, 0.0};  // independent chains
 #pragma unroll
         for (int c = 0; c < NCH; ++c) {
           if (32 * c + 31 < r0) continue;  // uniform: v is zero there
 #pragma unroll
-          for (int m = 0; m < 8; ++m) s += a[c][m] * vb[32 * c + 4 * m + q];
+          for (int m = 0; m < 8; ++m) sp[m & 3] += a[c][m] * vb[32 * c + 8 * q + m];
         }
+        double s = (sp[0] + sp[1]) + (sp[2] + sp[3]);
         s += dpp_mov_f64<kDppXor1>(s);
         s += dpp_mov_f64<kDppXor2>(s);
         pi = (i >= r0 && i < k) ? tj * s : 0.0;
@@ -153,7 +156,7 @@ __global__ __launch_bounds__(128 * NCH) void tridiag_rows_kernel(double* A, int6
           if (32 * c + 31 < r0) continue;
 #pragma unroll
           for (int m = 0; m < 8; ++m) {
-            const int l = 32 * c + 4 * m + q;
+            const int l = 32 * c + 8 * q + m;
             const double vl = vb[l];
             const double wl = pb[l] - Kc * vl;
             a[c][m] -= vi * wl + wi * vl;
@@ -166,7 +169,7 @@ __global__ __launch_bounds__(128 * NCH) void tridiag_rows_kernel(double* A, int6
 #pragma unroll
       for (int c = 0; c < NCH; ++c)
 #pragma unroll
-        for (int m = 0; m < 8; ++m) xrow[(j + 1) & 1][32 * c + 4 * m + q] = a[c][m];
+        for (int m = 0; m < 8; ++m) xrow[(j + 1) & 1][32 * c + 8 * q + m] = a[c][m];
     }
     __syncthreads();
   }
@@ -175,7 +178,7 @@ __global__ __launch_bounds__(128 * NCH) void tridiag_rows_kernel(double* A, int6
 #pragma unroll
     for (int c = 0; c < NCH; ++c)
 #pragma unroll
-      for (int m = 0; m < 8; ++m) vb[32 * c + 4 * m + q] = a[c][m];
+      for (int m = 0; m < 8; ++m) vb[32 * c + 8 * q + m] = a[c][m];
   }
   __syncthreads();
   if (t == 0) {
@@ -395,20 +398,6 @@ __global__ __launch_bounds__(kTriT) void tridiag_kernel(double* A, int64_t lda, 
   (void)scal;
 }
 
-// Number of eigenvalues of the tridiagonal (d, e) strictly below x.
-__device__ inline int sturm_count(const double* d, const double* e2, int k, double x, double pivmin) {
-  int cnt = 0;
-  double q = d[0] - x;
-  if (fabs(q) < pivmin) q = -pivmin;
-  cnt += (q < 0.0);
-  for (int i = 1; i < k; ++i) {
-    q = d[i] - x - e2[i - 1] / q;
-    if (fabs(q) < pivmin) q = -pivmin;
-    cnt += (q < 0.0);
-  }
-  return cnt;
-}
-
 // bounds[0..1] = Gershgorin interval, bounds[2] = pivmin, bounds[3] = ||T||_inf;
 // e2 = e^2.
 __global__ void tri_prep_kernel(const double* d, const double* e, int k, double* e2, double* bounds) {
@@ -447,27 +436,83 @@ __global__ void tri_prep_kernel(const double* d, const double* e, int k, double*
   }
 }
 
+// Sturm counts (eigenvalues of the tridiagonal (d, e) strictly below x) at
+// two shifts x1 < x2 at once (two independent recurrences interleaved, so
+// each hides the other's latency).  1/q comes from the
+// hardware reciprocal refined by one Newton step; the count only needs the
+// signs of q, which such a perturbation (a relative change of a few ulps of
+// the pivots, i.e. of d) leaves as correct as the exact division.
+__device__ inline double rcp_f64(double q) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  double r = __builtin_amdgcn_rcp(q);
+  const double e = fma(-q, r, 1.0);
+  return fma(r, e, r);
+#else
+  return 1.0 / q;
+#endif
+}
+
+__device__ inline void sturm_count2(const double* d, const double* e2, int k, double x1, double x2,
+                                    double pivmin, int& c1, int& c2) {
+  double q1 = d[0] - x1, q2 = d[0] - x2;
+  if (fabs(q1) < pivmin) q1 = -pivmin;
+  if (fabs(q2) < pivmin) q2 = -pivmin;
+  int n1 = (q1 < 0.0), n2 = (q2 < 0.0);
+  for (int i = 1; i < k; ++i) {
+    const double di = d[i], ei = e2[i - 1];
+    q1 = (di - x1) - ei * rcp_f64(q1);
+    q2 = (di - x2) - ei * rcp_f64(q2);
+    if (fabs(q1) < pivmin) q1 = -pivmin;
+    if (fabs(q2) < pivmin) q2 = -pivmin;
+    n1 += (q1 < 0.0);
+    n2 += (q2 < 0.0);
+  }
+  c1 = n1;
+  c2 = n2;
+}
+
 // Eigenvalue i (ascending) by multisection on the Sturm count: wave i
-// evaluates the count at 63 interior points of its interval and keeps the
-// sub-interval where the count passes i, so each round shrinks the interval
-// 64-fold.  Stops at the width the reduction determines the eigenvalue to.
+// evaluates the count at 127 interior points of its interval (two per lane)
+// and keeps the sub-interval where the count passes i, so each round shrinks
+// the interval 128-fold.  Stops at the width the reduction determines the
+// eigenvalue to.  d and e2 are staged in LDS when LDS.
+// (LDS is a template parameter so that every access has a known address
+// space: a pointer that may be either becomes a slow generic access.)
+template <bool LDS>
 __global__ __launch_bounds__(64) void bisect_kernel(const double* d, const double* e2, int k,
                                                     const double* bounds, double* lam) {
+  extern __shared__ double bsh[];
   const int i = blockIdx.x;
   const int lane = threadIdx.x;
   if (i >= k) return;
+  const double* dd = d;
+  const double* ee = e2;
+  if constexpr (LDS) {
+    for (int q = lane; q < k; q += 64) {
+      bsh[q] = d[q];
+      bsh[k + q] = (q + 1 < k) ? e2[q] : 0.0;
+    }
+    __syncthreads();
+    dd = bsh;
+    ee = bsh + k;
+  }
   double lo = bounds[0], hi = bounds[1];
   const double pivmin = bounds[2];
   const double atol = DBL_EPSILON * bounds[3] + 2.0 * DBL_MIN;
   for (int it = 0; it < 64; ++it) {
     if (hi - lo <= 2.0 * DBL_EPSILON * fmax(fabs(lo), fabs(hi)) + atol) break;
-    const double h = (hi - lo) / 64.0;
-    const double x = (lane < 63) ? lo + h * (double)(lane + 1) : hi;
-    const bool above = (lane < 63) ? (sturm_count(d, e2, k, x, pivmin) > i) : true;
-    const uint64_t mask = __ballot(above);
-    const int first = __ffsll((unsigned long long)mask) - 1;  // lane 63 is always set
-    const double nlo = (first == 0) ? lo : lo + h * (double)first;
-    const double nhi = (first == 63) ? hi : lo + h * (double)(first + 1);
+    const double h = (hi - lo) / 128.0;
+    // points p = 1 .. 128 at lo + h p (p = 128 is hi): lane takes p = lane + 1, lane + 65
+    const double x1 = lo + h * (double)(lane + 1);
+    const double x2 = (lane < 63) ? lo + h * (double)(lane + 65) : hi;
+    int c1, c2;
+    sturm_count2(dd, ee, k, x1, x2, pivmin, c1, c2);
+    const uint64_t m1 = __ballot(c1 > i);
+    const uint64_t m2 = __ballot(lane == 63 || c2 > i);  // hi is always above
+    const int f = (m1 != 0) ? __ffsll((unsigned long long)m1) - 1
+                            : 64 + __ffsll((unsigned long long)m2) - 1;  // first point above, 0-based
+    const double nlo = (f == 0) ? lo : lo + h * (double)f;
+    const double nhi = (f == 127) ? hi : lo + h * (double)(f + 1);
     if (!(nhi - nlo < hi - lo)) break;  // no progress in floating point
     lo = nlo;
     hi = nhi;
@@ -594,19 +639,22 @@ __device__ inline double start_entry(int idx, int i) {
 // cluster get shifts nudged apart by a few ulps of ||T|| and distinct start
 // vectors, so their iterates differ.  Z is column-major: Z[i + c * ldz] is
 // entry i of output column c.
+template <bool LDS>
 __global__ __launch_bounds__(64) void invit_kernel(const double* d, const double* e, int k,
                                                    const double* lam, const int* order,
                                                    const int64_t* keep, const double* bounds,
-                                                   double* work, double* Z, int64_t ldz,
-                                                   int use_lds) {
+                                                   double* work, double* Z, int64_t ldz) {
   const int c = blockIdx.x;
   if (c >= keep[0]) return;
   const int idx = order[c];
   const int lane = threadIdx.x;
   extern __shared__ double ism[];
   __shared__ double sscale;
-  // keep the arrays in LDS when they fit
-  double* dd = use_lds ? ism : work + (int64_t)c * kInvitArrays * k;
+  // keep the arrays in LDS when they fit (a compile-time choice, so that
+  // every access has a known address space)
+  double* dd;
+  if constexpr (LDS) dd = ism;
+  else dd = work + (int64_t)c * kInvitArrays * k;
   double* ee = dd + k;   // e (0 past the end)
   double* u1 = ee + k;   // first super-diagonal of U
   double* u2 = u1 + k;   // second super-diagonal of U
@@ -633,12 +681,17 @@ __global__ __launch_bounds__(64) void invit_kernel(const double* d, const double
   if (lane == 0) {
     // LU with partial pivoting of T - lamq I: rows i, i+1 may swap.  After
     // elimination row i holds the pivot, u1[i], u2[i].
+    // (each loop loads the next row's operands before it works on this one)
     double a = dd[0];
     double b = (k > 1) ? ee[0] : 0.0;
+    double sub_n = ee[0], dn_n = (k > 1) ? dd[1] : 0.0, sn_n = (k > 1) ? ee[1] : 0.0;
     for (int i = 0; i + 1 < k; ++i) {
-      const double sub = ee[i];
-      const double dn = dd[i + 1];
-      const double sn = ee[i + 1];
+      const double sub = sub_n, dn = dn_n, sn = sn_n;
+      if (i + 2 < k) {
+        sub_n = ee[i + 1];
+        dn_n = dd[i + 2];
+        sn_n = ee[i + 2];
+      }
       double piv, mlt, na, nb, w1, w2, sw;
       if (fabs(a) >= fabs(sub)) {
         piv = (a == 0.0) ? small : a;
@@ -671,18 +724,33 @@ __global__ __launch_bounds__(64) void invit_kernel(const double* d, const double
     if (lane == 0) {
       // forward: apply the row swaps and multipliers; (xa, xb) = rows i, i+1
       double xa = x[0];
+      double xb_n = (k > 1) ? x[1] : 0.0, sw_n = swd[0], lm_n = lm[0];
       for (int i = 0; i + 1 < k; ++i) {
-        double xb = x[i + 1];
-        if (swd[i] != 0.0) { const double tmp = xa; xa = xb; xb = tmp; }
-        xb -= lm[i] * xa;
+        double xb = xb_n;
+        const double swv = sw_n, lmv = lm_n;
+        if (i + 2 < k) {
+          xb_n = x[i + 2];
+          sw_n = swd[i + 1];
+          lm_n = lm[i + 1];
+        }
+        if (swv != 0.0) { const double tmp = xa; xa = xb; xb = tmp; }
+        xb -= lmv * xa;
         x[i] = xa;
         xa = xb;
       }
       x[k - 1] = xa;
       // backward: (x1, x2) = solved rows i + 1, i + 2
       double x1 = 0.0, x2 = 0.0, mx = 0.0;
+      double xi_n = x[k - 1], a1_n = u1[k - 1], a2_n = u2[k - 1], r_n = rp[k - 1];
       for (int i = k - 1; i >= 0; --i) {
-        const double v = (x[i] - u1[i] * x1 - u2[i] * x2) * rp[i];
+        const double xi = xi_n, a1 = a1_n, a2 = a2_n, ri = r_n;
+        if (i > 0) {
+          xi_n = x[i - 1];
+          a1_n = u1[i - 1];
+          a2_n = u2[i - 1];
+          r_n = rp[i - 1];
+        }
+        const double v = (xi - a1 * x1 - a2 * x2) * ri;
         x[i] = v;
         mx = fmax(mx, fabs(v));
         x2 = x1;
@@ -704,26 +772,26 @@ __global__ __launch_bounds__(64) void invit_kernel(const double* d, const double
 
 // Orthonormalise the vectors of one cluster (blockIdx.x), in ascending
 // eigenvalue order, by right-looking modified Gram-Schmidt done twice: at
-// step j every later vector loses its component along z_j.  Each wave
-// handles a subset of the later vectors and recomputes ||z_j|| itself, so a
-// step needs one barrier.  The cluster is staged in LDS when it fits
-// (lds_doubles entries of dynamic shared memory).
-__global__ __launch_bounds__(1024) void orth_kernel(int k, const int* clusters, const int* cl_count,
-                                                    const int* pos_of, double* Z, int64_t ldz,
-                                                    int lds_doubles) {
-  extern __shared__ double zs[];
-  const int cl = blockIdx.x;
-  if (cl >= cl_count[0]) return;
-  const int start = clusters[2 * cl], len = clusters[2 * cl + 1];
-  if (len < 2) return;
+// step j every later vector loses its component along z_j.  The later vectors
+// are spread over the 32 half-waves of the block (a half-wave sums its dot
+// products with lane moves only), the half-wave that updates z_{j+1} also
+// forms its new squared norm for the next step, so a step needs one barrier.
+// The cluster is staged in LDS when it fits (lds_doubles entries of dynamic
+// shared memory); the two cases are separate instantiations so that every
+// access has a known address space.
+template <bool STAGED>
+__device__ void orth_cluster(int k, int start, int len, const int* pos_of, double* Z, int64_t ldz,
+                             double* zs, double* nrm) {
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int nw = blockDim.x >> 6;
-  const bool staged = (int64_t)len * k <= (int64_t)lds_doubles;
+  const int hw = 2 * wv + (lane >> 5), hl = lane & 31;  // half-wave index, lane in it
+  const int nhw = 2 * nw;
   // vector q of the cluster: zs[q * k + i] when staged, else Z column pos_of[start + q]
   auto vec = [&](int q) -> double* {
-    return staged ? zs + (int64_t)q * k : Z + (int64_t)pos_of[start + q] * ldz;
+    if constexpr (STAGED) return zs + (int64_t)q * k;
+    else return Z + (int64_t)pos_of[start + q] * ldz;
   };
-  if (staged) {
+  if constexpr (STAGED) {
     for (int q = wv; q < len; q += nw) {
       const double* src = Z + (int64_t)pos_of[start + q] * ldz;
       for (int i = lane; i < k; i += 64) zs[(int64_t)q * k + i] = src[i];
@@ -731,19 +799,34 @@ __global__ __launch_bounds__(1024) void orth_kernel(int k, const int* clusters, 
     __syncthreads();
   }
   for (int pass = 0; pass < 2; ++pass) {
+    if (wv == 0) {
+      const double* z0 = vec(0);
+      double n0 = 0.0;
+      for (int i = lane; i < k; i += 64) n0 += z0[i] * z0[i];
+      n0 = wave_sum_f64(n0);
+      if (lane == 0) nrm[0] = n0;
+    }
+    __syncthreads();
     for (int j = 0; j < len; ++j) {
       const double* zj = vec(j);
-      double nj = 0.0;
-      for (int i = lane; i < k; i += 64) nj += zj[i] * zj[i];
-      nj = wave_sum_f64(nj);
+      const double nj = nrm[j & 1];
       const double inv2 = (nj > 0.0) ? 1.0 / nj : 0.0;
-      for (int l = j + 1 + wv; l < len; l += nw) {
+      for (int l = j + 1 + hw; l < len; l += nhw) {
         double* zl = vec(l);
         double dt = 0.0;
-        for (int i = lane; i < k; i += 64) dt += zj[i] * zl[i];
-        dt = wave_sum_f64(dt);
+        for (int i = hl; i < k; i += 32) dt += zj[i] * zl[i];
+        dt = half_wave_sum_f64(dt);
         const double f = dt * inv2;
-        for (int i = lane; i < k; i += 64) zl[i] -= f * zj[i];
+        double nn = 0.0;
+        for (int i = hl; i < k; i += 32) {
+          const double v = zl[i] - f * zj[i];
+          zl[i] = v;
+          nn += v * v;
+        }
+        if (l == j + 1) {
+          nn = half_wave_sum_f64(nn);
+          if (hl == 0) nrm[(j + 1) & 1] = nn;
+        }
       }
       __syncthreads();
     }
@@ -758,7 +841,7 @@ __global__ __launch_bounds__(1024) void orth_kernel(int k, const int* clusters, 
     }
     __syncthreads();
   }
-  if (staged) {
+  if constexpr (STAGED) {
     for (int q = wv; q < len; q += nw) {
       double* dst = Z + (int64_t)pos_of[start + q] * ldz;
       for (int i = lane; i < k; i += 64) dst[i] = zs[(int64_t)q * k + i];
@@ -766,36 +849,84 @@ __global__ __launch_bounds__(1024) void orth_kernel(int k, const int* clusters, 
   }
 }
 
-// V(:, c) = H_0 H_1 ... H_{k-3} z_c, with z_c = Z[i + c * ldz]; one wave per
-// column (kBtCols columns per block), z in LDS, so the reflectors are applied
-// with wave reductions only.  Also fixes the sign so that the largest |entry|
-// is positive (the first one on ties).
-constexpr int kBtCols = 4;
-constexpr int kBtLdsMaxK = 4096;  // z of the block's columns in LDS up to this k
+__global__ __launch_bounds__(1024) void orth_kernel(int k, const int* clusters, const int* cl_count,
+                                                    const int* pos_of, double* Z, int64_t ldz,
+                                                    int lds_doubles) {
+  extern __shared__ double zs[];
+  __shared__ double nrm[2];  // squared norm of the pivot of step j in nrm[j & 1]
+  const int cl = blockIdx.x;
+  if (cl >= cl_count[0]) return;
+  const int start = clusters[2 * cl], len = clusters[2 * cl + 1];
+  if (len < 2) return;
+  if ((int64_t)len * k <= (int64_t)lds_doubles) orth_cluster<true>(k, start, len, pos_of, Z, ldz, zs, nrm);
+  else orth_cluster<false>(k, start, len, pos_of, Z, ldz, zs, nrm);
+}
 
+// V(:, c) = H_0 H_1 ... H_{k-3} z_c, with z_c = Z[i + c * ldz]; one wave per
+// column (kBtCols columns per block).  With LDS the block stages each
+// chunk of kBtChunk reflectors (with the implicit unit entry) and z in LDS,
+// so the reflectors are read from HBM once per block and every wave applies
+// them with wave reductions only; otherwise z stays in its output column and
+// the reflectors are read from A.  Also fixes the sign so that the largest
+// |entry| is positive (the first one on ties).
+constexpr int kBtCols = 4;
+constexpr int kBtChunk = 16;
+constexpr int kBtLdsMaxK = 960;  // LDS staging up to this k (20 k doubles)
+
+template <bool LDS>
 __global__ __launch_bounds__(64 * kBtCols) void backtr_kernel(const double* A, int64_t lda,
                                                               const double* tau, int k,
                                                               const double* Z, int64_t ldz,
                                                               const int64_t* keep, double* V,
-                                                              int64_t ldv, int use_lds) {
-  extern __shared__ double zsh[];
+                                                              int64_t ldv) {
+  constexpr bool use_lds = LDS;
+  extern __shared__ double bsh[];  // z of the block's columns, then a chunk of reflectors
+  __shared__ double tch[kBtChunk];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int c = blockIdx.x * kBtCols + wv;
-  if (c >= keep[0]) return;  // whole wave
-  // z in LDS, or in place in the output column when k is large
-  double* z = use_lds ? zsh + (int64_t)wv * k : V + (int64_t)c * ldv;
-  for (int i = lane; i < k; i += 64) z[i] = Z[i + (int64_t)c * ldz];
-  for (int j = k - 3; j >= 0; --j) {
-    const double tj = tau[j];
-    if (tj == 0.0) continue;
-    const int r0 = j + 1;
-    const double* vj = A + (int64_t)j * lda;
-    double part = 0.0;
-    for (int i = r0 + lane; i < k; i += 64) part += ((i == r0) ? 1.0 : vj[i]) * z[i];
-    part = wave_sum_f64(part);
-    const double s = tj * part;
-    for (int i = r0 + lane; i < k; i += 64) z[i] -= s * ((i == r0) ? 1.0 : vj[i]);
+  const bool active = c < keep[0];  // wave-uniform; no early return (barriers below)
+  double* z;
+  if constexpr (LDS) z = bsh + (int64_t)wv * k;
+  else z = V + (int64_t)c * ldv;
+  double* vch = bsh + (int64_t)kBtCols * k;
+  if (active)
+    for (int i = lane; i < k; i += 64) z[i] = Z[i + (int64_t)c * ldz];
+  for (int jhi = k - 3; jhi >= 0; jhi -= kBtChunk) {
+    const int jlo = max(0, jhi - kBtChunk + 1);
+    if (use_lds) {
+      __syncthreads();  // the previous chunk is consumed
+      const int nj = jhi - jlo + 1;
+      for (int idx = threadIdx.x; idx < nj * k; idx += blockDim.x) {
+        const int jj = idx / k, i = idx % k;
+        const int j = jlo + jj;
+        const double v = A[i + (int64_t)j * lda];  // unconditional load, masked below
+        vch[idx] = (i == j + 1) ? 1.0 : ((i > j + 1) ? v : 0.0);
+      }
+      if ((int)threadIdx.x < nj) tch[threadIdx.x] = tau[jlo + threadIdx.x];
+      __syncthreads();
+    }
+    if (!active) continue;
+    for (int j = jhi; j >= jlo; --j) {
+      const double tj = use_lds ? tch[j - jlo] : tau[j];
+      if (tj == 0.0) continue;
+      const int r0 = j + 1;
+      double part = 0.0;
+      if (use_lds) {
+        const double* vj = vch + (int64_t)(j - jlo) * k;
+        for (int i = r0 + lane; i < k; i += 64) part += vj[i] * z[i];
+        part = wave_sum_f64(part);
+        const double s = tj * part;
+        for (int i = r0 + lane; i < k; i += 64) z[i] -= s * vj[i];
+      } else {
+        const double* vj = A + (int64_t)j * lda;
+        for (int i = r0 + lane; i < k; i += 64) part += ((i == r0) ? 1.0 : vj[i]) * z[i];
+        part = wave_sum_f64(part);
+        const double s = tj * part;
+        for (int i = r0 + lane; i < k; i += 64) z[i] -= s * ((i == r0) ? 1.0 : vj[i]);
+      }
+    }
   }
+  if (!active) return;
   // sign convention: largest |entry| positive (first one on ties)
   double best = -1.0;
   int bi = k;
@@ -872,27 +1003,37 @@ void syev_trunc_f64(hipStream_t s, int64_t k, const double* M, int64_t ldm, doub
   }
   hipLaunchKernelGGL(tri_prep_kernel, dim3(1), dim3(256), 0, s, d, e, ki, e2, bounds);
   DME_HIP(hipGetLastError());
-  hipLaunchKernelGGL(bisect_kernel, dim3((unsigned)k), dim3(64), 0, s, d, e2, ki, bounds, lam);
+  if (k <= kBisLdsMaxK)
+    hipLaunchKernelGGL(bisect_kernel<true>, dim3((unsigned)k), dim3(64), (size_t)2 * k * sizeof(double), s, d,
+                       e2, ki, bounds, lam);
+  else
+    hipLaunchKernelGGL(bisect_kernel<false>, dim3((unsigned)k), dim3(64), 0, s, d, e2, ki, bounds, lam);
   DME_HIP(hipGetLastError());
   hipLaunchKernelGGL(select_kernel, dim3(1), dim3(kSelT), 0, s, lam, ki, tol, max_keep, bounds, order,
                      pos_of, lam_out, clusters, cl_count, keep_dev, flag_dev);
   DME_HIP(hipGetLastError());
   // Z: k x (kept) column-major with ld = k (kept <= k)
   const unsigned nkeep = (unsigned)std::min<int64_t>(k, max_keep);
-  const int invit_lds = (k <= kInvitLdsMaxK) ? 1 : 0;
-  hipLaunchKernelGGL(invit_kernel, dim3(nkeep), dim3(64),
-                     invit_lds ? (size_t)kInvitArrays * k * sizeof(double) : 0,
-                     s, d, e, ki, lam, order, keep_dev, bounds, work, Zt, k, invit_lds);
+  if (k <= kInvitLdsMaxK)
+    hipLaunchKernelGGL(invit_kernel<true>, dim3(nkeep), dim3(64), (size_t)kInvitArrays * k * sizeof(double),
+                       s, d, e, ki, lam, order, keep_dev, bounds, work, Zt, k);
+  else
+    hipLaunchKernelGGL(invit_kernel<false>, dim3(nkeep), dim3(64), 0, s, d, e, ki, lam, order, keep_dev,
+                       bounds, work, Zt, k);
   DME_HIP(hipGetLastError());
   // cluster staging in LDS: up to 144 KiB, never more than the whole k x k set
   const int64_t orth_lds = std::min<int64_t>(k * k, (144 * 1024) / (int64_t)sizeof(double));
   hipLaunchKernelGGL(orth_kernel, dim3((unsigned)k), dim3(1024), (size_t)orth_lds * sizeof(double), s,
                      ki, clusters, cl_count, pos_of, Zt, k, (int)orth_lds);
   DME_HIP(hipGetLastError());
-  const int bt_lds = (k <= kBtLdsMaxK) ? 1 : 0;
-  hipLaunchKernelGGL(backtr_kernel, dim3((unsigned)cdiv(std::min<int64_t>(k, max_keep), kBtCols)),
-                     dim3(64 * kBtCols), bt_lds ? (size_t)kBtCols * k * sizeof(double) : 0, s, A, k,
-                     tau, ki, Zt, k, keep_dev, V_out, ldv, bt_lds);
+  const dim3 bt_grid((unsigned)cdiv(std::min<int64_t>(k, max_keep), kBtCols));
+  if (k <= kBtLdsMaxK)
+    hipLaunchKernelGGL(backtr_kernel<true>, bt_grid, dim3(64 * kBtCols),
+                       (size_t)(kBtCols + kBtChunk) * k * sizeof(double), s, A, k, tau, ki, Zt, k, keep_dev,
+                       V_out, ldv);
+  else
+    hipLaunchKernelGGL(backtr_kernel<false>, bt_grid, dim3(64 * kBtCols), 0, s, A, k, tau, ki, Zt, k,
+                       keep_dev, V_out, ldv);
   DME_HIP(hipGetLastError());
 }
 

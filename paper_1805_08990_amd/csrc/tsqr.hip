@@ -26,6 +26,8 @@
 // kept unscaled until the end, so no thread rewrites what another still reads.
 #include "tsqr.h"
 
+#include <type_traits>
+
 namespace dme {
 namespace {
 
@@ -36,21 +38,23 @@ constexpr int kTHead = kTB;               // head rows of a leaf (LDS)
 constexpr int kTPer = 32;                 // body rows per thread (registers)
 constexpr int kTLeaf = kTHead + kTG * kTPer;  // 288 rows per leaf
 constexpr int kTHq = kTHead / kTG;        // head rows per row group
-constexpr int kTAq = kTLeaf / kTG;        // rows per thread in the apply kernel (36)
 
 // Rows of every level of a panel (kernel argument by value).
 struct LevelRows {
   int64_t M[kTsqrMaxLevels];
 };
 
-// Level-l row s -> row of level 0, or -1 for a padding row (a leaf with fewer
+// Level-L row s -> row of level 0, or -1 for a padding row (a leaf with fewer
 // than 32 rows stacks zero rows that exist on no lower level).
-__device__ inline int64_t phys_row(int64_t s, int level, const LevelRows& lr) {
-  for (int l = level; l > 0; --l) {
+template <int L>
+__device__ inline int64_t phys_row(int64_t s, const LevelRows& lr) {
+  bool pad = false;
+#pragma unroll
+  for (int l = L; l > 0; --l) {
     s = (s >> 5) * kTLeaf + (s & (kTB - 1));
-    if (s >= lr.M[l - 1]) return -1;
+    pad = pad || (s >= lr.M[l - 1]);
   }
-  return s;
+  return pad ? -1 : s;
 }
 
 // r_mode: 0 = R stays in place (single leaf of level 0); 1 = R_g stacked into
@@ -60,7 +64,7 @@ __global__ __launch_bounds__(kTT) void tsqr_leaf_kernel(double* mat, int64_t ld,
                                                         double* Tout, double* Rdst, int64_t ld_r,
                                                         int r_mode) {
   __shared__ double H[kTHead][kTB + 1];  // head rows
-  __shared__ double xb[2][kTPer][kTG];   // body rows of the step's column, [r][g]
+  __shared__ double xb[2][kTG][kTPer + 2];  // body rows of the step's column, [g][r] (padded: no bank conflicts)
   __shared__ double tot[kTB];            // the step's column sums
   __shared__ double Zs[kTB][kTB + 1];    // Zs[c][j] = v_c^T v_j for c < j
   __shared__ double coef[3][kTB];        // beta, tau, scale of each reflector
@@ -71,20 +75,27 @@ __global__ __launch_bounds__(kTT) void tsqr_leaf_kernel(double* mat, int64_t ld,
   const int nv = min(rows, pb);
   double* base = mat + rbeg;
   const bool cin = c < pb;
+  // loads are unconditional (clamped to an entry of the block) and masked
+  // afterwards, so they are all in flight together
+  const int64_t cc0 = (int64_t)min(c, pb - 1) * ld;
 #pragma unroll
   for (int q = 0; q < kTHq; ++q) {
     const int i = g + kTG * q;
-    H[i][c] = (i < rows && cin) ? base[i + (int64_t)c * ld] : 0.0;
+    const bool ok = i < rows && cin;
+    const double v = base[min(i, rows - 1) + cc0];
+    H[i][c] = ok ? v : 0.0;
   }
   double vals[kTPer];
 #pragma unroll
   for (int r = 0; r < kTPer; ++r) {
     const int i = kTHead + g + kTG * r;
-    vals[r] = (i < rows && cin) ? base[i + (int64_t)c * ld] : 0.0;
+    const bool ok = i < rows && cin;
+    const double v = base[min(i, rows - 1) + cc0];
+    vals[r] = ok ? v : 0.0;
   }
   if (c == 0) {
 #pragma unroll
-    for (int r = 0; r < kTPer; ++r) xb[0][r][g] = vals[r];
+    for (int r = 0; r < kTPer; ++r) xb[0][g][r] = vals[r];
   }
   if (t < kTB) {
     coef[0][t] = 0.0;
@@ -96,14 +107,18 @@ __global__ __launch_bounds__(kTT) void tsqr_leaf_kernel(double* mat, int64_t ld,
   for (int j = 0; j < nv; ++j) {
     const int bf = j & 1;
     // partial sum over this thread's rows i > j of x_j(i) a_c(i)
-    double part = 0.0;
+    double xv[kTPer];  // body rows of column j, kept for the update below
 #pragma unroll
-    for (int r = 0; r < kTPer; ++r) part += xb[bf][r][g] * vals[r];
+    for (int r = 0; r < kTPer; ++r) xv[r] = xb[bf][g][r];
+    double pp[4] = {0.0, 0.0, 0.0, 0.0};  // independent chains
+#pragma unroll
+    for (int r = 0; r < kTPer; ++r) pp[r & 3] += xv[r] * vals[r];
 #pragma unroll
     for (int q = 0; q < kTHq; ++q) {
       const int i = g + kTG * q;
-      if (i > j) part += H[i][j] * H[i][c];
+      if (i > j) pp[q] += H[i][j] * H[i][c];
     }
+    double part = (pp[0] + pp[1]) + (pp[2] + pp[3]);
     const double ahead = H[j][c];  // read before row j is updated below
     part = group8_sum_f64(part);
     if (g == 0) tot[c] = part;
@@ -131,7 +146,7 @@ __global__ __launch_bounds__(kTT) void tsqr_leaf_kernel(double* mat, int64_t ld,
       const double wv = tau * (ahead + sc * tc);
       const double f = wv * sc;
 #pragma unroll
-      for (int r = 0; r < kTPer; ++r) vals[r] -= f * xb[bf][r][g];
+      for (int r = 0; r < kTPer; ++r) vals[r] -= f * xv[r];
 #pragma unroll
       for (int q = 0; q < kTHq; ++q) {
         const int i = g + kTG * q;
@@ -141,7 +156,7 @@ __global__ __launch_bounds__(kTT) void tsqr_leaf_kernel(double* mat, int64_t ld,
     }
     if (c == j + 1) {
 #pragma unroll
-      for (int r = 0; r < kTPer; ++r) xb[bf ^ 1][r][g] = vals[r];
+      for (int r = 0; r < kTPer; ++r) xb[bf ^ 1][g][r] = vals[r];
     }
     __syncthreads();
   }
@@ -186,24 +201,21 @@ __global__ __launch_bounds__(kTT) void tsqr_leaf_kernel(double* mat, int64_t ld,
   }
   // T (upper triangular): T(j, j) = tau_j, T(0:j, j) = -tau_j T(0:j, 0:j) Zs(0:j, j);
   // lane cc forms row cc, which depends on its own earlier entries only
+  // (branch-free: entries outside the triangle are zero)
   if (t < kTB) {
     const int cc = t;
     double Trow[kTB];
 #pragma unroll
     for (int j = 0; j < kTB; ++j) {
-      double v = 0.0;
-      if (j < nv && j >= cc) {
-        if (j == cc) {
-          v = coef[1][j];
-        } else {
-          double s = 0.0;
+      double s0 = 0.0, s1 = 0.0;
 #pragma unroll
-          for (int c2 = 0; c2 < j; ++c2)
-            if (c2 >= cc) s += Trow[c2] * Zs[c2][j];
-          v = -coef[1][j] * s;
-        }
+      for (int c2 = 0; c2 < j; ++c2) {  // Trow[c2] is zero for c2 < cc
+        if (c2 & 1) s1 += Trow[c2] * Zs[c2][j];
+        else s0 += Trow[c2] * Zs[c2][j];
       }
-      Trow[j] = v;
+      const double tj = coef[1][j];
+      const double v = (j == cc) ? tj : -tj * (s0 + s1);
+      Trow[j] = (j < nv && j >= cc) ? v : 0.0;
     }
     double* To = Tout + (int64_t)blockIdx.x * kTB * kTB;
 #pragma unroll
@@ -212,30 +224,59 @@ __global__ __launch_bounds__(kTT) void tsqr_leaf_kernel(double* mat, int64_t ld,
 }
 
 // C <- (I - V T' V^T) C for every leaf of one level, T' = T^T (trans: applies
-// Q^T) or T.  Block (g, ct) handles leaf g and columns [32 ct, 32 ct + 32);
-// thread (c, q8) holds the leaf rows q8 + 8 m.  V of leaf g: level matrix rows
+// Q^T) or T, on FP64 MFMA.  Block (g, ct) handles leaf g (288 rows) and the
+// columns [32 ct, 32 ct + 32).  The leaf's V (with its implicit unit
+// diagonal) is staged in LDS and the block's C entries are loaded into
+// registers, all loads issued together.  Wave w takes the 16 x 16 tile
+// (w / 2, w % 2) of Y = V^T C (72 MFMAs over the leaf's rows), the block forms
+// Z = T' Y in LDS, and wave w then updates rows [144 (w / 2), 144 (w / 2) + 144)
+// of column tile w % 2 with 72 more MFMAs.  The C entries a lane feeds to the
+// first product are exactly the ones its result lanes hold in the second, so
+// C is read once and written once.  V of leaf g: level matrix rows
 // [288 g, 288 g + rows), unit diagonal implicit, zero above; C rows are this
-// level's rows mapped to rows of level 0.
+// level's rows mapped to rows of level 0 (padding rows read as zero and are
+// not written).
+typedef double v4d __attribute__((ext_vector_type(4)));
+constexpr int kTSteps = kTLeaf / 4;  // 72 K-steps of the MFMA over a leaf
+constexpr int kTVld = (kTLeaf * kTB) / kTT;  // V entries staged per thread (36)
+
+template <int LEVEL>
 __global__ __launch_bounds__(kTT) void tsqr_apply_kernel(const double* V, int64_t ldv, int64_t M,
                                                          int pb, const double* Tin, int trans,
-                                                         int level, LevelRows lr, double* C,
-                                                         int64_t ldc, int64_t ncols) {
+                                                         LevelRows lr, double* C, int64_t ldc,
+                                                         int64_t ncols) {
   __shared__ double Vs[kTLeaf][kTB + 1];
   __shared__ double Ys[kTB][kTB + 1];
   __shared__ double Zs[kTB][kTB + 1];
   __shared__ double Ts[kTB][kTB + 1];
   const int t = threadIdx.x;
-  const int c = t >> 3, g = t & (kTG - 1);
+  const int lane = t & 63, w = t >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const int at = w >> 1, ct = w & 1;
   const int64_t rbeg = (int64_t)blockIdx.x * kTLeaf;
   const int rows = (int)min<int64_t>(kTLeaf, M - rbeg);
   const int nv = min(rows, pb);
-  const int64_t col = (int64_t)blockIdx.y * kTB + c;
+  const int64_t col = (int64_t)blockIdx.y * kTB + ct * 16 + li;
   const bool cok = col < ncols;
-  for (int idx = t; idx < kTLeaf * kTB; idx += kTT) {
+  // rows of C (n < 2^31), -1 for none
+  auto crow = [&](int s) -> int {
+    const int i = 4 * s + lk;
+    return (i < rows && cok) ? (int)phys_row<LEVEL>(rbeg + i, lr) : -1;
+  };
+  // every load is unconditional (clamped) and masked afterwards, so all are in flight together
+  double vst[kTVld];
+#pragma unroll
+  for (int m = 0; m < kTVld; ++m) {
+    const int idx = t + kTT * m;
     const int i = idx % kTLeaf, a = idx / kTLeaf;
-    double v = 0.0;
-    if (i < rows && a < nv) v = (i > a) ? V[rbeg + i + (int64_t)a * ldv] : (i == a ? 1.0 : 0.0);
-    Vs[i][a] = v;
+    vst[m] = V[rbeg + min(i, rows - 1) + (int64_t)min(a, pb - 1) * ldv];
+  }
+  double cr[kTSteps];
+#pragma unroll
+  for (int s = 0; s < kTSteps; ++s) {
+    const int pr = crow(s);
+    const double cv = C[(pr >= 0) ? (int64_t)pr + col * ldc : 0];
+    cr[s] = (pr >= 0) ? cv : 0.0;
   }
   {
     const double* Tg = Tin + (int64_t)blockIdx.x * kTB * kTB;
@@ -246,59 +287,83 @@ __global__ __launch_bounds__(kTT) void tsqr_apply_kernel(const double* V, int64_
       else Ts[a][b] = v;
     }
   }
-  // rows of C this thread holds (-1: none); V is zero on padding rows
-  double cr[kTAq];
-  int64_t pr[kTAq];
 #pragma unroll
-  for (int m = 0; m < kTAq; ++m) {
-    const int i = g + kTG * m;
-    pr[m] = (i < rows && cok) ? phys_row(rbeg + i, level, lr) : -1;
-    cr[m] = (pr[m] >= 0) ? C[pr[m] + col * ldc] : 0.0;
+  for (int m = 0; m < kTVld; ++m) {
+    const int idx = t + kTT * m;
+    const int i = idx % kTLeaf, a = idx / kTLeaf;
+    const double y = (i > a) ? vst[m] : (i == a ? 1.0 : 0.0);
+    Vs[i][a] = (i < rows && a < nv) ? y : 0.0;
   }
   __syncthreads();
-  // Y = V^T C: partial over this thread's rows, then summed over the 8 lanes
-  // of the column
-  double y[kTB];
+  // phase 1: Y tile (at, ct) = sum over the leaf rows of V(:, at*16 + .)^T C(:, ct*16 + .)
+  // (operands read from LDS 8 steps at a time, ahead of their MFMAs)
+  v4d acc = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-  for (int a = 0; a < kTB; ++a) y[a] = 0.0;
+  for (int s0 = 0; s0 < kTSteps; s0 += 8) {
+    double va[8];
 #pragma unroll
-  for (int m = 0; m < kTAq; ++m) {
-    const int i = g + kTG * m;
+    for (int u = 0; u < 8; ++u) va[u] = Vs[4 * (s0 + u) + lk][at * 16 + li];
 #pragma unroll
-    for (int a = 0; a < kTB; ++a) y[a] += Vs[i][a] * cr[m];
+    for (int u = 0; u < 8; ++u) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(va[u], cr[s0 + u], acc, 0, 0, 0);
   }
 #pragma unroll
-  for (int a = 0; a < kTB; ++a) y[a] = group8_sum_f64(y[a]);
-#pragma unroll
-  for (int m = 0; m < kTB / kTG; ++m) {
-    const int a = g + kTG * m;
-    Ys[a][c] = y[a];
-  }
+  for (int v = 0; v < 4; ++v) Ys[at * 16 + 4 * v + lk][ct * 16 + li] = acc[v];
   __syncthreads();
-  // Z = T' Y (rows g + 8 m of column c)
+  // Z = T' Y: thread (zr, zc) forms rows zr, zr + 8, zr + 16, zr + 24 of column zc
+  {
+    const int zc = t & 31, zr = t >> 5;
 #pragma unroll
-  for (int m = 0; m < kTB / kTG; ++m) {
-    const int a = g + kTG * m;
-    double s = 0.0;
-#pragma unroll
-    for (int b = 0; b < kTB; ++b) s += Ts[a][b] * Ys[b][c];
-    Zs[a][c] = s;
-  }
-  __syncthreads();
-  double z[kTB];
-#pragma unroll
-  for (int a = 0; a < kTB; ++a) z[a] = Zs[a][c];
-  if (!cok) return;
-#pragma unroll
-  for (int m = 0; m < kTAq; ++m) {
-    const int i = g + kTG * m;
-    if (pr[m] >= 0) {
+    for (int m = 0; m < 4; ++m) {
+      const int a = zr + 8 * m;
       double s = 0.0;
 #pragma unroll
-      for (int a = 0; a < kTB; ++a) s += Vs[i][a] * z[a];
-      C[pr[m] + col * ldc] = cr[m] - s;
+      for (int b = 0; b < kTB; ++b) s += Ts[a][b] * Ys[b][zc];
+      Zs[a][zc] = s;
     }
   }
+  __syncthreads();
+  double zb[kTB / 4];
+#pragma unroll
+  for (int q = 0; q < kTB / 4; ++q) zb[q] = Zs[4 * q + lk][ct * 16 + li];
+  // phase 3: rows of tiles rt = at * 9 .. at * 9 + 8 of column tile ct
+  auto update = [&](auto base_tag) {
+    constexpr int R0 = decltype(base_tag)::value;
+#pragma unroll
+    for (int r = 0; r < 9; ++r) {
+      const int rt = R0 + r;
+      double va[kTB / 4];
+#pragma unroll
+      for (int q = 0; q < kTB / 4; ++q) va[q] = Vs[rt * 16 + li][4 * q + lk];
+      v4d p = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int q = 0; q < kTB / 4; ++q) p = __builtin_amdgcn_mfma_f64_16x16x4f64(va[q], zb[q], p, 0, 0, 0);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int s = 4 * rt + v;
+        const int pr = crow(s);
+        if (pr >= 0) C[(int64_t)pr + col * ldc] = cr[s] - p[v];
+      }
+    }
+  };
+  if (at == 0) update(std::integral_constant<int, 0>{});
+  else update(std::integral_constant<int, 9>{});
+}
+
+void launch_apply(hipStream_t s, const TsqrLevel& L, int level, int pb, int trans, const LevelRows& lr,
+                  double* C, int64_t ldc, int64_t ncols) {
+  dim3 grid((unsigned)L.G, (unsigned)cdiv(ncols, kTB));
+  switch (level) {
+#define DME_TSQR_APPLY(LV)                                                                       \
+  case LV:                                                                                        \
+    hipLaunchKernelGGL(tsqr_apply_kernel<LV>, grid, dim3(kTT), 0, s, L.mat, L.ld, L.M, pb, L.T, \
+                       trans, lr, C, ldc, ncols);                                                 \
+    break;
+    DME_TSQR_APPLY(0) DME_TSQR_APPLY(1) DME_TSQR_APPLY(2) DME_TSQR_APPLY(3)
+    DME_TSQR_APPLY(4) DME_TSQR_APPLY(5) DME_TSQR_APPLY(6) DME_TSQR_APPLY(7)
+#undef DME_TSQR_APPLY
+    default: fail(DME_EINTERNAL, "tsqr: bad level");
+  }
+  DME_HIP(hipGetLastError());
 }
 
 LevelRows level_rows(const TsqrPanel& P) {
@@ -331,6 +396,7 @@ size_t tsqr_workspace(int64_t n, int64_t k) {
 }
 
 void tsqr_factor(hipStream_t s, int64_t n, int64_t k, double* W, TsqrState& st, Arena& ws) {
+  DME_REQUIRE(n < (int64_t(1) << 31), DME_EINVAL, "tsqr: n too large");
   const int64_t ld = n;
   const int64_t kr = std::min(n, k);
   st.n = n;
@@ -376,13 +442,7 @@ void tsqr_factor(hipStream_t s, int64_t n, int64_t k, double* W, TsqrState& st, 
     if (rest > 0) {
       double* C = W + c0 + (c0 + pb) * ld;
       const LevelRows lr = level_rows(P);
-      for (int l = 0; l < P.nlev; ++l) {
-        const TsqrLevel& L = P.lev[l];
-        dim3 grid((unsigned)L.G, (unsigned)cdiv(rest, kTB));
-        hipLaunchKernelGGL(tsqr_apply_kernel, grid, dim3(kTT), 0, s, L.mat, L.ld, L.M, pb, L.T, 1, l,
-                           lr, C, ld, rest);
-        DME_HIP(hipGetLastError());
-      }
+      for (int l = 0; l < P.nlev; ++l) launch_apply(s, P.lev[l], l, pb, 1, lr, C, ld, rest);
     }
     st.panels.push_back(P);
   }
@@ -395,13 +455,7 @@ void tsqr_apply_q(hipStream_t s, const TsqrState& st, double* X, int64_t ldx, in
     const TsqrPanel& P = st.panels[p];
     double* C = X + P.c0;
     const LevelRows lr = level_rows(P);
-    for (int l = P.nlev - 1; l >= 0; --l) {
-      const TsqrLevel& L = P.lev[l];
-      dim3 grid((unsigned)L.G, (unsigned)cdiv(ncols, kTB));
-      hipLaunchKernelGGL(tsqr_apply_kernel, grid, dim3(kTT), 0, s, L.mat, L.ld, L.M, P.pb, L.T, 0, l,
-                         lr, C, ldx, ncols);
-      DME_HIP(hipGetLastError());
-    }
+    for (int l = P.nlev - 1; l >= 0; --l) launch_apply(s, P.lev[l], l, P.pb, 0, lr, C, ldx, ncols);
   }
 }
 

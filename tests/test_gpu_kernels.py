@@ -208,11 +208,13 @@ def test_gemm_mixed(ctx, n, r):
 
 def test_gemm_mixed_heat_operator(ctx):
     """On the heat semigroup of the 2-D Laplacian (the operator the mixed mode
-    applies) the relative error of E L stays near FP32 resolution."""
+    applies) the relative error of E L stays near FP32 resolution: the FP32
+    representation of E and X (2^-24 per entry) plus FP32 accumulation over
+    128-term spans."""
     announce("gemm_mixed heat")
     A = wl.laplacian_2d(24)
     E = oracle.expm(5e-4 * A.T)
     rng = np.random.default_rng(3)
     X, _ = np.linalg.qr(rng.standard_normal((A.shape[0], 40)))
     got = to_np(ctx.gemm_mixed(E, X))
-    assert rel_fro(got, E @ X) < 1e-7
+    assert rel_fro(got, E @ X) < 2e-7
