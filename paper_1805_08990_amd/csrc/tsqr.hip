@@ -26,6 +26,7 @@
 // kept unscaled until the end, so no thread rewrites what another still reads.
 #include "tsqr.h"
 
+#include <memory>
 #include <type_traits>
 
 namespace dme {
@@ -395,6 +396,49 @@ size_t tsqr_workspace(int64_t n, int64_t k) {
   return b + 4096;
 }
 
+namespace {
+
+// A second stream and a ring of events per host thread and device, for the
+// look-ahead of the panel factorisation (default priority, created on first
+// use; they are not destroyed, since a thread's end may come after the
+// runtime's).
+struct AuxStream {
+  int device = -1;
+  hipStream_t s2 = nullptr;
+  std::vector<hipEvent_t> ev;
+  size_t next = 0;
+  // A recorded event is only waited on by calls enqueued right after its
+  // record, so a ring much longer than the waits in flight can be reused.
+  hipEvent_t record(hipStream_t st) {
+    hipEvent_t e = ev[next];
+    next = (next + 1) % ev.size();
+    DME_HIP(hipEventRecord(e, st));
+    return e;
+  }
+};
+
+AuxStream& aux_stream() {
+  static thread_local std::vector<std::unique_ptr<AuxStream>> per_device;
+  int dev = 0;
+  DME_HIP(hipGetDevice(&dev));
+  for (auto& a : per_device)
+    if (a->device == dev) return *a;
+  auto a = std::make_unique<AuxStream>();
+  a->device = dev;
+  DME_HIP(hipStreamCreateWithFlags(&a->s2, hipStreamNonBlocking));
+  a->ev.resize(64);
+  for (hipEvent_t& e : a->ev) DME_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  per_device.push_back(std::move(a));
+  return *per_device.back();
+}
+
+}  // namespace
+
+// Panels are factored on s.  Q^T of panel p reaches the next panel's columns
+// on s (they are what panel p + 1 factors next) and the columns beyond on a
+// second stream, which waits for each tree level's factor and runs behind
+// the factorisation of the following panels; s waits for that stream before
+// it touches those columns (and before returning).
 void tsqr_factor(hipStream_t s, int64_t n, int64_t k, double* W, TsqrState& st, Arena& ws) {
   DME_REQUIRE(n < (int64_t(1) << 31), DME_EINVAL, "tsqr: n too large");
   const int64_t ld = n;
@@ -404,6 +448,11 @@ void tsqr_factor(hipStream_t s, int64_t n, int64_t k, double* W, TsqrState& st, 
   st.ld = ld;
   st.W = W;
   st.panels.clear();
+  AuxStream& ax = aux_stream();
+  bool aux_used = false;
+  hipEvent_t rest_done = nullptr;  // the second stream finished the previous panel's share
+  // the second stream starts after everything s has queued so far (W is ready)
+  DME_HIP(hipStreamWaitEvent(ax.s2, ax.record(s), 0));
   for (int64_t c0 = 0; c0 < kr; c0 += kTB) {
     TsqrPanel P;
     P.c0 = c0;
@@ -412,6 +461,7 @@ void tsqr_factor(hipStream_t s, int64_t n, int64_t k, double* W, TsqrState& st, 
     int64_t M = n - c0;
     double* mat = W + c0 + c0 * ld;  // level 0 is the panel itself, in W
     int64_t mld = ld;
+    hipEvent_t lev_done[kTsqrMaxLevels] = {};
     for (int l = 0; l < kTsqrMaxLevels; ++l) {
       TsqrLevel& L = P.lev[l];
       L.M = M;
@@ -425,6 +475,7 @@ void tsqr_factor(hipStream_t s, int64_t n, int64_t k, double* W, TsqrState& st, 
         hipLaunchKernelGGL(tsqr_leaf_kernel, dim3(1), dim3(kTT), 0, s, mat, mld, M, pb, L.T,
                            W + c0 + c0 * ld, ld, l > 0 ? 2 : 0);
         DME_HIP(hipGetLastError());
+        lev_done[l] = ax.record(s);
         break;
       }
       if (l + 1 == kTsqrMaxLevels) fail(DME_EINVAL, "tsqr: matrix too tall for the reduction tree");
@@ -433,19 +484,35 @@ void tsqr_factor(hipStream_t s, int64_t n, int64_t k, double* W, TsqrState& st, 
       hipLaunchKernelGGL(tsqr_leaf_kernel, dim3((unsigned)L.G), dim3(kTT), 0, s, mat, mld, M, pb, L.T,
                          next, Mn, 1);
       DME_HIP(hipGetLastError());
+      lev_done[l] = ax.record(s);
       M = Mn;
       mat = next;
       mld = Mn;
     }
-    // Q^T on the trailing columns, level by level
+    const LevelRows lr = level_rows(P);
     const int64_t rest = k - c0 - pb;
-    if (rest > 0) {
-      double* C = W + c0 + (c0 + pb) * ld;
-      const LevelRows lr = level_rows(P);
-      for (int l = 0; l < P.nlev; ++l) launch_apply(s, P.lev[l], l, pb, 1, lr, C, ld, rest);
+    const int64_t near = std::min<int64_t>(rest, kTB);  // the next panel's columns
+    const int64_t far = rest - near;
+    // Q^T on the columns beyond the next panel: second stream, level by level
+    if (far > 0) {
+      double* C = W + c0 + (c0 + pb + near) * ld;
+      for (int l = 0; l < P.nlev; ++l) {
+        DME_HIP(hipStreamWaitEvent(ax.s2, lev_done[l], 0));
+        launch_apply(ax.s2, P.lev[l], l, pb, 1, lr, C, ld, far);
+      }
+      aux_used = true;
     }
+    // Q^T on the next panel's columns, on s, after the previous panels' share
+    // of the second stream (it updated these columns too)
+    if (near > 0) {
+      if (rest_done) DME_HIP(hipStreamWaitEvent(s, rest_done, 0));
+      double* C = W + c0 + (c0 + pb) * ld;
+      for (int l = 0; l < P.nlev; ++l) launch_apply(s, P.lev[l], l, pb, 1, lr, C, ld, near);
+    }
+    if (far > 0) rest_done = ax.record(ax.s2);
     st.panels.push_back(P);
   }
+  if (aux_used) DME_HIP(hipStreamWaitEvent(s, ax.record(ax.s2), 0));
 }
 
 // X (n x ncols, ld ldx) <- Q X.
