@@ -73,6 +73,24 @@ __device__ __forceinline__ void split3(float x, u16& a, u16& b, u16& c) {
   c = bf16_rne(r2);
 }
 
+// Three-piece split of two FP32 values at once, packed two BF16 per word
+// (low half: x0's piece).  The first piece rounds to nearest even, the
+// remainder r = x - x1 is exact and has at most 16 significant bits; the
+// second piece truncates r to 8 significant bits and the third is the exact
+// rest (at most 8 significant bits, so it is a BF16 value as it stands).
+// |x2| <= 2^-8 |x|, |x3| < 2^-15 |x|; x = x1 + x2 + x3 exactly.
+__device__ __forceinline__ void split3x2(float x0, float x1, uint32_t& a, uint32_t& b, uint32_t& c) {
+  const uint32_t u0 = __float_as_uint(x0), u1 = __float_as_uint(x1);
+  const uint32_t a0 = (u0 + 0x7FFFu + ((u0 >> 16) & 1u)) & 0xFFFF0000u;
+  const uint32_t a1 = (u1 + 0x7FFFu + ((u1 >> 16) & 1u)) & 0xFFFF0000u;
+  const float r0 = x0 - __uint_as_float(a0), r1 = x1 - __uint_as_float(a1);
+  const uint32_t b0 = __float_as_uint(r0) & 0xFFFF0000u, b1 = __float_as_uint(r1) & 0xFFFF0000u;
+  const float q0 = r0 - __uint_as_float(b0), q1 = r1 - __uint_as_float(b1);
+  a = (a0 >> 16) | a1;
+  b = (b0 >> 16) | b1;
+  c = (__float_as_uint(q0) >> 16) | (__float_as_uint(q1) & 0xFFFF0000u);
+}
+
 // Three-piece split of an FP64 value (each piece rounds what the earlier
 // ones left; the residual is below 2^-24 of |x|).
 __device__ __forceinline__ void split3_d(double x, u16& a, u16& b, u16& c) {
@@ -190,33 +208,40 @@ __global__ __launch_bounds__(kMT) void gemm_mixed_kernel(int n, int lde, int rpa
       dst[t][1] = src[1];
     }
   };
-  // the next Xs tile passes through registers (u32x4: promotable to VGPRs)
-  u32x4 stage[CPT];
-#define DME_LOAD_X(step)                                                                         \
+  // Xs tiles pass through a ring of register stages (u32x4: promotable to
+  // VGPRs), loaded as far ahead as the E fragments
+  u32x4 xring[kMPD][CPT];
+#define DME_LOAD_X(step, dst)                                                                    \
   do {                                                                                           \
     const int k0_ = kbeg + min((step), nsteps - 1) * kMBK;                                       \
     _Pragma("unroll") for (int c = 0; c < CPT; ++c) {                                            \
       const int idx = min(tid + c * kMT, CHUNKS - 1);                                            \
       const int q = idx % QPC, col = (idx / QPC) % NC, pc = (idx / QPC) / NC;                    \
-      stage[c] = *reinterpret_cast<const u32x4*>(Xs + pc * plane + (int64_t)col * lde + k0_ + q * 8); \
+      (dst)[c] = *reinterpret_cast<const u32x4*>(Xs + pc * plane + (int64_t)col * lde + k0_ + q * 8); \
     }                                                                                            \
   } while (0)
-#define DME_STORE_X(buf)                                                                         \
+#define DME_STORE_X(buf, src)                                                                    \
   do {                                                                                           \
     _Pragma("unroll") for (int c = 0; c < CPT; ++c) {                                            \
       const int idx = tid + c * kMT;                                                             \
       const int ic = min(idx, CHUNKS - 1);                                                       \
       const int q = ic % QPC, col = (ic / QPC) % NC, pc = (ic / QPC) / NC;                       \
       u32x4* dst = (idx < CHUNKS) ? &sX[(buf)][pc][col][q] : &sSink;                             \
-      *dst = stage[c];                                                                           \
+      *dst = (src)[c];                                                                           \
     }                                                                                            \
   } while (0)
 
+  // Loads are issued in the order X(s), E(s) (prologue) and E(s + kMPD),
+  // X(s + 1 + kMPD) (step s); waiting for the tile or fragments a step needs
+  // then leaves the loads of the next kMPD - 1 steps in flight.
   if (nsteps > 0) {
-    DME_LOAD_X(0);
 #pragma unroll
-    for (int u = 0; u < kMPD; ++u) load_e(u, ering[u]);
-    DME_STORE_X(0);
+    for (int u = 0; u < kMPD; ++u) {
+      DME_LOAD_X(u, xring[u]);
+      load_e(u, ering[u]);
+    }
+    DME_STORE_X(0, xring[0]);
+    DME_LOAD_X(kMPD, xring[0]);
   }
   __syncthreads();
   for (int s0 = 0; s0 < nsteps; s0 += kMFl) {
@@ -225,18 +250,18 @@ __global__ __launch_bounds__(kMT) void gemm_mixed_kernel(int n, int lde, int rpa
       const int s = s0 + u;
       const int slot = u % kMPD;  // kMFl is a multiple of kMPD
       const int buf = u & 1;      // s0 is even
-      // the next Xs tile is loaded before the E refill, so that waiting for it
-      // (before the LDS store below) leaves the E loads in flight
-      DME_LOAD_X(s + 1);
       // split this step's E fragments into three BF16 pieces, then refill the slot
       Frag ef[2][3];
 #pragma unroll
       for (int t = 0; t < 2; ++t) {
-        const float ev[8] = {ering[slot][t][0].x, ering[slot][t][0].y, ering[slot][t][0].z,
-                             ering[slot][t][0].w, ering[slot][t][1].x, ering[slot][t][1].y,
-                             ering[slot][t][1].z, ering[slot][t][1].w};
+        const float4 lo = ering[slot][t][0], hi = ering[slot][t][1];
+        uint32_t w[3][4];
+        split3x2(lo.x, lo.y, w[0][0], w[1][0], w[2][0]);
+        split3x2(lo.z, lo.w, w[0][1], w[1][1], w[2][1]);
+        split3x2(hi.x, hi.y, w[0][2], w[1][2], w[2][2]);
+        split3x2(hi.z, hi.w, w[0][3], w[1][3], w[2][3]);
 #pragma unroll
-        for (int q = 0; q < 8; ++q) split3(ev[q], ef[t][0].h[q], ef[t][1].h[q], ef[t][2].h[q]);
+        for (int pc = 0; pc < 3; ++pc) ef[t][pc].q = u32x4{w[pc][0], w[pc][1], w[pc][2], w[pc][3]};
       }
       load_e(s + kMPD, ering[slot]);
 #pragma unroll
@@ -266,7 +291,10 @@ __global__ __launch_bounds__(kMT) void gemm_mixed_kernel(int n, int lde, int rpa
             fa[t][j] = f32x4{0.f, 0.f, 0.f, 0.f};
           }
       }
-      DME_STORE_X(buf ^ 1);
+      // the next step's tile goes to LDS, and its ring stage takes the tile
+      // kMPD steps later
+      DME_STORE_X(buf ^ 1, xring[(u + 1) % kMPD]);
+      DME_LOAD_X(s + 1 + kMPD, xring[(u + 1) % kMPD]);
       __syncthreads();
     }
   }
