@@ -38,7 +38,6 @@ constexpr double kOrtol = 1e-3;  // gaps below kOrtol ||T|| join a cluster
 constexpr int kInvitIters = 3;
 constexpr int kInvitLdsMaxK = 2048;  // inverse-iteration arrays in LDS up to this k
 constexpr int kInvitArrays = 8;      // k-long arrays per inverse iteration
-constexpr int kInvitCh = 16;         // rows whose operands are loaded at once
 constexpr int kBisLdsMaxK = 4096;    // bisection reads d, e^2 from LDS up to this k
 
 __device__ inline double block_sum_1024(double v, double* red) {
@@ -681,44 +680,37 @@ __global__ __launch_bounds__(64) void invit_kernel(const double* d, const double
   __syncthreads();
   if (lane == 0) {
     // LU with partial pivoting of T - lamq I: rows i, i+1 may swap.  After
-    // elimination row i holds the pivot, u1[i], u2[i].  The loops below read
-    // their operands kInvitCh rows at a time (clamped indices, no branches
-    // around the loads) and then run the recurrence on registers.
+    // elimination row i holds the pivot, u1[i], u2[i].
+    // (each loop loads the next row's operands before it works on this one)
     double a = dd[0];
     double b = (k > 1) ? ee[0] : 0.0;
-    for (int i0 = 0; i0 + 1 < k; i0 += kInvitCh) {
-      double cs[kInvitCh], cd[kInvitCh], cn[kInvitCh];
-#pragma unroll
-      for (int u = 0; u < kInvitCh; ++u) {
-        cs[u] = ee[min(i0 + u, k - 1)];
-        cd[u] = dd[min(i0 + u + 1, k - 1)];
-        cn[u] = ee[min(i0 + u + 1, k - 1)];
+    double sub_n = ee[0], dn_n = (k > 1) ? dd[1] : 0.0, sn_n = (k > 1) ? ee[1] : 0.0;
+    for (int i = 0; i + 1 < k; ++i) {
+      const double sub = sub_n, dn = dn_n, sn = sn_n;
+      if (i + 2 < k) {
+        sub_n = ee[i + 1];
+        dn_n = dd[i + 2];
+        sn_n = ee[i + 2];
       }
-#pragma unroll
-      for (int u = 0; u < kInvitCh; ++u) {
-        const int i = i0 + u;
-        if (i + 1 >= k) break;
-        const double sub = cs[u], dn = cd[u], sn = cn[u];
-        double piv, mlt, na, nb, w1, w2, sw;
-        if (fabs(a) >= fabs(sub)) {
-          piv = (a == 0.0) ? small : a;
-          mlt = sub / piv;
-          w1 = b; w2 = 0.0; sw = 0.0;
-          na = dn - mlt * b;
-          nb = sn;
-        } else {
-          piv = sub;
-          mlt = a / sub;
-          w1 = dn; w2 = sn; sw = 1.0;
-          na = b - mlt * dn;
-          nb = -mlt * sn;
-        }
-        const double pv = (fabs(piv) < small) ? copysign(small, piv) : piv;
-        rp[i] = 1.0 / pv;
-        u1[i] = w1; u2[i] = w2; lm[i] = mlt; swd[i] = sw;
-        a = na;
-        b = nb;
+      double piv, mlt, na, nb, w1, w2, sw;
+      if (fabs(a) >= fabs(sub)) {
+        piv = (a == 0.0) ? small : a;
+        mlt = sub / piv;
+        w1 = b; w2 = 0.0; sw = 0.0;
+        na = dn - mlt * b;
+        nb = sn;
+      } else {
+        piv = sub;
+        mlt = a / sub;
+        w1 = dn; w2 = sn; sw = 1.0;
+        na = b - mlt * dn;
+        nb = -mlt * sn;
       }
+      const double pv = (fabs(piv) < small) ? copysign(small, piv) : piv;
+      rp[i] = 1.0 / pv;
+      u1[i] = w1; u2[i] = w2; lm[i] = mlt; swd[i] = sw;
+      a = na;
+      b = nb;
     }
     {
       const double piv = (a == 0.0) ? small : a;
@@ -732,48 +724,37 @@ __global__ __launch_bounds__(64) void invit_kernel(const double* d, const double
     if (lane == 0) {
       // forward: apply the row swaps and multipliers; (xa, xb) = rows i, i+1
       double xa = x[0];
-      for (int i0 = 0; i0 + 1 < k; i0 += kInvitCh) {
-        double cx[kInvitCh], cw[kInvitCh], cl[kInvitCh];
-#pragma unroll
-        for (int u = 0; u < kInvitCh; ++u) {
-          cx[u] = x[min(i0 + u + 1, k - 1)];
-          cw[u] = swd[min(i0 + u, k - 1)];
-          cl[u] = lm[min(i0 + u, k - 1)];
+      double xb_n = (k > 1) ? x[1] : 0.0, sw_n = swd[0], lm_n = lm[0];
+      for (int i = 0; i + 1 < k; ++i) {
+        double xb = xb_n;
+        const double swv = sw_n, lmv = lm_n;
+        if (i + 2 < k) {
+          xb_n = x[i + 2];
+          sw_n = swd[i + 1];
+          lm_n = lm[i + 1];
         }
-#pragma unroll
-        for (int u = 0; u < kInvitCh; ++u) {
-          const int i = i0 + u;
-          if (i + 1 >= k) break;
-          double xb = cx[u];
-          if (cw[u] != 0.0) { const double tmp = xa; xa = xb; xb = tmp; }
-          xb -= cl[u] * xa;
-          x[i] = xa;
-          xa = xb;
-        }
+        if (swv != 0.0) { const double tmp = xa; xa = xb; xb = tmp; }
+        xb -= lmv * xa;
+        x[i] = xa;
+        xa = xb;
       }
       x[k - 1] = xa;
       // backward: (x1, x2) = solved rows i + 1, i + 2
       double x1 = 0.0, x2 = 0.0, mx = 0.0;
-      for (int i1 = k - 1; i1 >= 0; i1 -= kInvitCh) {
-        double cx[kInvitCh], c1[kInvitCh], c2[kInvitCh], cr[kInvitCh];
-#pragma unroll
-        for (int u = 0; u < kInvitCh; ++u) {
-          const int i = max(i1 - u, 0);
-          cx[u] = x[i];
-          c1[u] = u1[i];
-          c2[u] = u2[i];
-          cr[u] = rp[i];
+      double xi_n = x[k - 1], a1_n = u1[k - 1], a2_n = u2[k - 1], r_n = rp[k - 1];
+      for (int i = k - 1; i >= 0; --i) {
+        const double xi = xi_n, a1 = a1_n, a2 = a2_n, ri = r_n;
+        if (i > 0) {
+          xi_n = x[i - 1];
+          a1_n = u1[i - 1];
+          a2_n = u2[i - 1];
+          r_n = rp[i - 1];
         }
-#pragma unroll
-        for (int u = 0; u < kInvitCh; ++u) {
-          const int i = i1 - u;
-          if (i < 0) break;
-          const double v = (cx[u] - c1[u] * x1 - c2[u] * x2) * cr[u];
-          x[i] = v;
-          mx = fmax(mx, fabs(v));
-          x2 = x1;
-          x1 = v;
-        }
+        const double v = (xi - a1 * x1 - a2 * x2) * ri;
+        x[i] = v;
+        mx = fmax(mx, fabs(v));
+        x2 = x1;
+        x1 = v;
       }
       sscale = (mx > 0.0) ? 1.0 / mx : 1.0;
     }

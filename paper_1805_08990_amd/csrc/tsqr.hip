@@ -15,15 +15,15 @@
 // (s / 32) * 288 + s % 32 of level l - 1 (the head rows of each leaf), which
 // maps every level back to rows of W.
 //
-// Leaf factorisation (256 threads = 32 columns x 8 row groups): the first 32
-// rows of the leaf (where the diagonal of every reflector lies) stay in LDS,
-// the other 256 rows in registers, thread (c, g) holding rows 32 + g + 8 r of
-// column c.  Column step j makes one reduction: thread (c, g) sums
-// x_j(i) a_c(i) over its rows i > j, which for c = j is sigma^2 of the
-// reflector, for c > j the product that updates column c and for c < j the
-// entry v_c^T v_j of the Gram matrix that builds T (the columns c < j are
-// final, so their threads would be idle otherwise).  The column of step j is
-// kept unscaled until the end, so no thread rewrites what another still reads.
+// Leaf factorisation (256 threads = 32 columns x 8 row groups): thread
+// (c, g) holds rows g + 8 m (m < 36) of column c in registers.  Column step j
+// needs one broadcast, the pivot column x_j (LDS, written by its owners at the
+// end of step j - 1 together with its alpha and sigma^2), and one reduction
+// within each column's 8 lanes: the sum over rows i > j of x_j(i) a_c(i),
+// which for c > j is the product that updates column c and for c < j the
+// entry v_c^T v_j of the Gram matrix that builds T.  So a step has a single
+// barrier.  The pivot column is kept unscaled until the end, so no thread
+// rewrites what another still reads.
 #include "tsqr.h"
 
 #include <memory>
@@ -39,6 +39,7 @@ constexpr int kTHead = kTB;               // head rows of a leaf (LDS)
 constexpr int kTPer = 32;                 // body rows per thread (registers)
 constexpr int kTLeaf = kTHead + kTG * kTPer;  // 288 rows per leaf
 constexpr int kTHq = kTHead / kTG;        // head rows per row group
+constexpr int kTRows = kTLeaf / kTG;      // rows per thread (36)
 
 // Rows of every level of a panel (kernel argument by value).
 struct LevelRows {
@@ -64,11 +65,11 @@ __device__ inline int64_t phys_row(int64_t s, const LevelRows& lr) {
 __global__ __launch_bounds__(kTT) void tsqr_leaf_kernel(double* mat, int64_t ld, int64_t M, int pb,
                                                         double* Tout, double* Rdst, int64_t ld_r,
                                                         int r_mode) {
-  __shared__ double H[kTHead][kTB + 1];  // head rows
-  __shared__ double xb[2][kTG][kTPer + 2];  // body rows of the step's column, [g][r] (padded: no bank conflicts)
-  __shared__ double tot[kTB];            // the step's column sums
-  __shared__ double Zs[kTB][kTB + 1];    // Zs[c][j] = v_c^T v_j for c < j
-  __shared__ double coef[3][kTB];        // beta, tau, scale of each reflector
+  __shared__ double xb[2][kTG][kTRows + 2];  // pivot column, [g][m] (padded: no bank conflicts)
+  __shared__ double piv[2][2];               // alpha and sigma^2 of the pivot column
+  __shared__ double Zs[kTB][kTB + 1];        // Zs[c][j] = v_c^T v_j for c < j
+  __shared__ double Ts[kTB][kTB + 1];        // T, one column per step
+  __shared__ double coef[kTB];               // tau of each reflector
   const int t = threadIdx.x;
   const int c = t >> 3, g = t & (kTG - 1);
   const int64_t rbeg = (int64_t)blockIdx.x * kTLeaf;
@@ -79,167 +80,166 @@ __global__ __launch_bounds__(kTT) void tsqr_leaf_kernel(double* mat, int64_t ld,
   // loads are unconditional (clamped to an entry of the block) and masked
   // afterwards, so they are all in flight together
   const int64_t cc0 = (int64_t)min(c, pb - 1) * ld;
+  double a[kTRows];
 #pragma unroll
-  for (int q = 0; q < kTHq; ++q) {
-    const int i = g + kTG * q;
-    const bool ok = i < rows && cin;
+  for (int m = 0; m < kTRows; ++m) {
+    const int i = g + kTG * m;
     const double v = base[min(i, rows - 1) + cc0];
-    H[i][c] = ok ? v : 0.0;
+    a[m] = (i < rows && cin) ? v : 0.0;
   }
-  double vals[kTPer];
+  // pivot data of column p from its owners (all 8 lanes of the column)
+  auto publish = [&](int p, int buf) {
+    double s2 = 0.0, al = 0.0;
 #pragma unroll
-  for (int r = 0; r < kTPer; ++r) {
-    const int i = kTHead + g + kTG * r;
-    const bool ok = i < rows && cin;
-    const double v = base[min(i, rows - 1) + cc0];
-    vals[r] = ok ? v : 0.0;
-  }
-  if (c == 0) {
-#pragma unroll
-    for (int r = 0; r < kTPer; ++r) xb[0][g][r] = vals[r];
-  }
-  if (t < kTB) {
-    coef[0][t] = 0.0;
-    coef[1][t] = 0.0;
-    coef[2][t] = 0.0;
-  }
+    for (int m = 0; m < kTRows; ++m) {
+      const int i = g + kTG * m;
+      xb[buf][g][m] = a[m];
+      if (m < kTHq) {
+        s2 += (i > p) ? a[m] * a[m] : 0.0;
+        al += (i == p) ? a[m] : 0.0;
+      } else {
+        s2 += a[m] * a[m];
+      }
+    }
+    s2 = group8_sum_f64(s2);
+    al = group8_sum_f64(al);
+    if (g == 0) {
+      piv[buf][0] = al;
+      piv[buf][1] = s2;
+    }
+  };
+  if (c == 0) publish(0, 0);
   __syncthreads();
 
+  // Column jj of T (upper triangular, Q = I - V T V^T): T(jj, jj) = tau_jj and
+  // T(c, jj) = -tau_jj sum_{c <= c2 < jj} T(c, c2) Zs(c2, jj), from the columns
+  // before it; thread (c, g) sums over c2 = g (mod 8).  Formed one step after
+  // Zs(:, jj), beside the next column step.
+  double* To = Tout + (int64_t)blockIdx.x * kTB * kTB;
+  auto t_column = [&](int jj) {
+    double s = 0.0;
+#pragma unroll
+    for (int q = 0; q < kTB / kTG; ++q) {
+      const int c2 = g + kTG * q;
+      s += (c2 >= c && c2 < jj) ? Ts[c][c2] * Zs[c2][jj] : 0.0;
+    }
+    s = group8_sum_f64(s);
+    const double tj = coef[jj];
+    const double v = (c == jj) ? tj : ((c < jj) ? -tj * s : 0.0);
+    if (g == 0) {
+      Ts[c][jj] = v;
+      To[c + jj * kTB] = v;
+    }
+  };
+
+  double my_sc = 0.0, my_beta = 0.0;  // this column's reflector, once it has been the pivot
   for (int j = 0; j < nv; ++j) {
     const int bf = j & 1;
-    // partial sum over this thread's rows i > j of x_j(i) a_c(i)
-    double xv[kTPer];  // body rows of column j, kept for the update below
+    if (j > 0) t_column(j - 1);
+    double xv[kTRows];
 #pragma unroll
-    for (int r = 0; r < kTPer; ++r) xv[r] = xb[bf][g][r];
-    double pp[4] = {0.0, 0.0, 0.0, 0.0};  // independent chains
-#pragma unroll
-    for (int r = 0; r < kTPer; ++r) pp[r & 3] += xv[r] * vals[r];
-#pragma unroll
-    for (int q = 0; q < kTHq; ++q) {
-      const int i = g + kTG * q;
-      if (i > j) pp[q] += H[i][j] * H[i][c];
-    }
-    double part = (pp[0] + pp[1]) + (pp[2] + pp[3]);
-    const double ahead = H[j][c];  // read before row j is updated below
-    part = group8_sum_f64(part);
-    if (g == 0) tot[c] = part;
-    __syncthreads();
-    // reflector j (every thread forms the same values)
-    const double alpha = H[j][j];
-    const double s2 = tot[j];
+    for (int m = 0; m < kTRows; ++m) xv[m] = xb[bf][g][m];
+    const double alpha = piv[bf][0], s2 = piv[bf][1];
+    // reflector j (every thread forms the same values; independent of the
+    // products below, so its latency overlaps them)
     double beta = alpha, tau = 0.0, sc = 0.0;
     if (s2 != 0.0) {
       beta = -copysign(sqrt(alpha * alpha + s2), alpha);
       tau = (beta - alpha) / beta;
       sc = 1.0 / (alpha - beta);
     }
-    const double tc = tot[c];
+    // sum over rows i > j of x_j(i) a_c(i), and a_c(j)
+    double pp[4] = {0.0, 0.0, 0.0, 0.0};  // independent chains
+    double ah = 0.0;
+#pragma unroll
+    for (int m = 0; m < kTHq; ++m) {
+      const int i = g + kTG * m;
+      xv[m] = (i > j) ? xv[m] : 0.0;
+      ah += (i == j) ? a[m] : 0.0;
+    }
+#pragma unroll
+    for (int m = 0; m < kTRows; ++m) pp[m & 3] += xv[m] * a[m];
+    double tc = (pp[0] + pp[1]) + (pp[2] + pp[3]);
+    tc = group8_sum_f64(tc);
+    const double ahead = group8_sum_f64(ah);
     if (c < j) {
-      if (g == 0) Zs[c][j] = coef[2][c] * (ahead + sc * tc);
+      if (g == 0) Zs[c][j] = my_sc * (ahead + sc * tc);
     } else if (c == j) {
-      if (g == 0) {
-        coef[0][j] = beta;
-        coef[1][j] = tau;
-        coef[2][j] = sc;
-      }
-    } else if (tau != 0.0) {
+      my_sc = sc;
+      my_beta = beta;
+      if (g == 0) coef[j] = tau;
+    } else {
       // a_c -= tau v (v^T a_c), v = [1; sc x_j(i > j)]
       const double wv = tau * (ahead + sc * tc);
       const double f = wv * sc;
 #pragma unroll
-      for (int r = 0; r < kTPer; ++r) vals[r] -= f * xv[r];
-#pragma unroll
-      for (int q = 0; q < kTHq; ++q) {
-        const int i = g + kTG * q;
-        if (i > j) H[i][c] -= f * H[i][j];
-        else if (i == j) H[j][c] = ahead - wv;
+      for (int m = 0; m < kTRows; ++m) {
+        const int i = g + kTG * m;
+        const double u = a[m] - f * xv[m];
+        a[m] = (m < kTHq && i == j) ? ahead - wv : u;
       }
-    }
-    if (c == j + 1) {
-#pragma unroll
-      for (int r = 0; r < kTPer; ++r) xb[bf ^ 1][g][r] = vals[r];
+      if (c == j + 1 && j + 1 < nv) publish(j + 1, bf ^ 1);
     }
     __syncthreads();
   }
 
   // reflectors scaled in place, R in the upper part of the head rows
   if (c < nv) {
-    const double scc = coef[2][c];
 #pragma unroll
-    for (int r = 0; r < kTPer; ++r) vals[r] *= scc;
-#pragma unroll
-    for (int q = 0; q < kTHq; ++q) {
-      const int i = g + kTG * q;
-      if (i > c) H[i][c] *= scc;
-      else if (i == c) H[c][c] = coef[0][c];
+    for (int m = 0; m < kTRows; ++m) {
+      const int i = g + kTG * m;
+      if (m >= kTHq || i > c) a[m] *= my_sc;
+      else if (i == c) a[m] = my_beta;
     }
   }
-  __syncthreads();
   if (cin) {
 #pragma unroll
-    for (int q = 0; q < kTHq; ++q) {
-      const int i = g + kTG * q;
-      if (i < rows) base[i + (int64_t)c * ld] = H[i][c];
-    }
-#pragma unroll
-    for (int r = 0; r < kTPer; ++r) {
-      const int i = kTHead + g + kTG * r;
-      if (i < rows) base[i + (int64_t)c * ld] = vals[r];
+    for (int m = 0; m < kTRows; ++m) {
+      const int i = g + kTG * m;
+      if (i < rows) base[i + (int64_t)c * ld] = a[m];
     }
     if (r_mode == 1) {
 #pragma unroll
-      for (int q = 0; q < kTHq; ++q) {
-        const int i = g + kTG * q;
-        Rdst[(int64_t)blockIdx.x * kTB + i + (int64_t)c * ld_r] = (i <= c && i < rows) ? H[i][c] : 0.0;
+      for (int m = 0; m < kTHq; ++m) {
+        const int i = g + kTG * m;
+        Rdst[(int64_t)blockIdx.x * kTB + i + (int64_t)c * ld_r] = (i <= c && i < rows) ? a[m] : 0.0;
       }
     } else if (r_mode == 2) {
 #pragma unroll
-      for (int q = 0; q < kTHq; ++q) {
-        const int i = g + kTG * q;
-        if (i <= c && i < rows) Rdst[i + (int64_t)c * ld_r] = H[i][c];
+      for (int m = 0; m < kTHq; ++m) {
+        const int i = g + kTG * m;
+        if (i <= c && i < rows) Rdst[i + (int64_t)c * ld_r] = a[m];
       }
     }
   }
-  // T (upper triangular): T(j, j) = tau_j, T(0:j, j) = -tau_j T(0:j, 0:j) Zs(0:j, j);
-  // lane cc forms row cc, which depends on its own earlier entries only
-  // (branch-free: entries outside the triangle are zero)
-  if (t < kTB) {
-    const int cc = t;
-    double Trow[kTB];
+  // the last column of T, and zero columns past the reflectors
+  t_column(nv - 1);
 #pragma unroll
-    for (int j = 0; j < kTB; ++j) {
-      double s0 = 0.0, s1 = 0.0;
-#pragma unroll
-      for (int c2 = 0; c2 < j; ++c2) {  // Trow[c2] is zero for c2 < cc
-        if (c2 & 1) s1 += Trow[c2] * Zs[c2][j];
-        else s0 += Trow[c2] * Zs[c2][j];
-      }
-      const double tj = coef[1][j];
-      const double v = (j == cc) ? tj : -tj * (s0 + s1);
-      Trow[j] = (j < nv && j >= cc) ? v : 0.0;
-    }
-    double* To = Tout + (int64_t)blockIdx.x * kTB * kTB;
-#pragma unroll
-    for (int j = 0; j < kTB; ++j) To[cc + j * kTB] = Trow[j];
+  for (int q = 0; q < kTB / kTG; ++q) {
+    const int jj = g + kTG * q;
+    if (jj >= nv) To[c + jj * kTB] = 0.0;
   }
 }
 
 // C <- (I - V T' V^T) C for every leaf of one level, T' = T^T (trans: applies
-// Q^T) or T, on FP64 MFMA.  Block (g, ct) handles leaf g (288 rows) and the
-// columns [32 ct, 32 ct + 32).  The leaf's V (with its implicit unit
-// diagonal) is staged in LDS and the block's C entries are loaded into
-// registers, all loads issued together.  Wave w takes the 16 x 16 tile
-// (w / 2, w % 2) of Y = V^T C (72 MFMAs over the leaf's rows), the block forms
-// Z = T' Y in LDS, and wave w then updates rows [144 (w / 2), 144 (w / 2) + 144)
-// of column tile w % 2 with 72 more MFMAs.  The C entries a lane feeds to the
-// first product are exactly the ones its result lanes hold in the second, so
-// C is read once and written once.  V of leaf g: level matrix rows
-// [288 g, 288 g + rows), unit diagonal implicit, zero above; C rows are this
-// level's rows mapped to rows of level 0 (padding rows read as zero and are
-// not written).
+// Q^T) or T, on FP64 MFMA.  Block (g, y) handles leaf g (288 rows) and the
+// columns [32 y, 32 y + 32); wave w = 2 h + e takes the row half h (144 rows)
+// and the column half e (16 columns).  Each lane loads the 36 C entries it
+// feeds to the first product, and its result lanes of the last product hold
+// exactly those entries, so C is read once and written once:
+//   Y_h = V_h^T C_h  (two 16 x 16 tiles per wave, 72 MFMAs over its rows),
+//   Z = T' (Y_0 + Y_1)  (one 16 x 16 tile per wave, 8 MFMAs),
+//   C_h -= V_h Z  (nine 16-row tiles per wave, 72 MFMAs).
+// V of leaf g: level matrix rows [288 g, 288 g + rows), unit diagonal
+// implicit, zero above; it is staged in LDS.  C rows are this level's rows
+// mapped to rows of level 0: each aligned run of 32 rows of a level is a run
+// of 32 rows of level 0, so a block needs 9 base rows.  A run's padding rows
+// (a leaf of the level below with fewer than 32 rows) are a suffix of it;
+// they read as zero and are not written.  Blocks with no padding rows and a
+// full column tile take loads and stores without masks.
 typedef double v4d __attribute__((ext_vector_type(4)));
-constexpr int kTSteps = kTLeaf / 4;  // 72 K-steps of the MFMA over a leaf
-constexpr int kTVld = (kTLeaf * kTB) / kTT;  // V entries staged per thread (36)
+constexpr int kTRuns = kTLeaf / kTB;        // 32-row runs per leaf (9)
+constexpr int kTHalfSteps = kTLeaf / 8;     // K-steps of 4 rows per row half (36)
 
 template <int LEVEL>
 __global__ __launch_bounds__(kTT) void tsqr_apply_kernel(const double* V, int64_t ldv, int64_t M,
@@ -247,41 +247,69 @@ __global__ __launch_bounds__(kTT) void tsqr_apply_kernel(const double* V, int64_
                                                          LevelRows lr, double* C, int64_t ldc,
                                                          int64_t ncols) {
   __shared__ double Vs[kTLeaf][kTB + 1];
-  __shared__ double Ys[kTB][kTB + 1];
+  __shared__ double Yp[2][kTB][kTB + 1];  // Y of each row half
   __shared__ double Zs[kTB][kTB + 1];
   __shared__ double Ts[kTB][kTB + 1];
   const int t = threadIdx.x;
   const int lane = t & 63, w = t >> 6;
   const int li = lane & 15, lk = lane >> 4;
-  const int at = w >> 1, ct = w & 1;
+  const int h = w >> 1, e = w & 1;
   const int64_t rbeg = (int64_t)blockIdx.x * kTLeaf;
   const int rows = (int)min<int64_t>(kTLeaf, M - rbeg);
   const int nv = min(rows, pb);
-  const int64_t col = (int64_t)blockIdx.y * kTB + ct * 16 + li;
+  const int64_t col = (int64_t)blockIdx.y * kTB + e * 16 + li;
   const bool cok = col < ncols;
-  // rows of C (n < 2^31), -1 for none
-  auto crow = [&](int s) -> int {
-    const int i = 4 * s + lk;
-    return (i < rows && cok) ? (int)phys_row<LEVEL>(rbeg + i, lr) : -1;
+  // level-0 base row of each 32-row run (uniform over the block)
+  int64_t rb[kTRuns];
+  bool full = rows == kTLeaf && (int64_t)blockIdx.y * kTB + kTB <= ncols;
+#pragma unroll
+  for (int q = 0; q < kTRuns; ++q) {
+    rb[q] = phys_row<LEVEL>(rbeg + kTB * q, lr);
+    full = full && phys_row<LEVEL>(rbeg + kTB * q + kTB - 1, lr) >= 0;
+  }
+  const double* Ccol = C + col * ldc;
+  // row of level 0 for leaf row i (masked path), -1 for none
+  auto crow = [&](int i) -> int64_t {
+    return (i < rows && cok) ? phys_row<LEVEL>(rbeg + i, lr) : -1;
   };
-  // every load is unconditional (clamped) and masked afterwards, so all are in flight together
-  double vst[kTVld];
+  // V staged through registers: thread (a, r0) loads rows r0 + 8 m of column a
+  const int va = t >> 3, vr = t & 7;
+  double vst[kTRows];
+  if (full && pb == kTB) {
+    const double* vp = V + rbeg + vr + (int64_t)va * ldv;
 #pragma unroll
-  for (int m = 0; m < kTVld; ++m) {
-    const int idx = t + kTT * m;
-    const int i = idx % kTLeaf, a = idx / kTLeaf;
-    vst[m] = V[rbeg + min(i, rows - 1) + (int64_t)min(a, pb - 1) * ldv];
-  }
-  double cr[kTSteps];
+    for (int m = 0; m < kTRows; ++m) vst[m] = vp[kTG * m];
+  } else {
+    const double* vp = V + rbeg + (int64_t)min(va, pb - 1) * ldv;
 #pragma unroll
-  for (int s = 0; s < kTSteps; ++s) {
-    const int pr = crow(s);
-    const double cv = C[(pr >= 0) ? (int64_t)pr + col * ldc : 0];
-    cr[s] = (pr >= 0) ? cv : 0.0;
+    for (int m = 0; m < kTRows; ++m) vst[m] = vp[min(vr + kTG * m, rows - 1)];
   }
+  // C entries of this lane: rows 4 s + lk of the leaf, s = 36 h + u
+  double cr[kTHalfSteps];
+  auto load_c = [&](auto h_tag) {
+    constexpr int H = decltype(h_tag)::value;
+    if (full) {
+#pragma unroll
+      for (int u = 0; u < kTHalfSteps; ++u) {
+        const int s = kTHalfSteps * H + u;
+        cr[u] = Ccol[rb[s >> 3] + 4 * (s & 7) + lk];
+      }
+    } else {
+#pragma unroll
+      for (int u = 0; u < kTHalfSteps; ++u) {
+        const int64_t pr = crow(4 * (kTHalfSteps * H + u) + lk);
+        const double v = Ccol[pr >= 0 ? pr : 0 - col * ldc];
+        cr[u] = (pr >= 0) ? v : 0.0;
+      }
+    }
+  };
+  if (h == 0) load_c(std::integral_constant<int, 0>{});
+  else load_c(std::integral_constant<int, 1>{});
   {
     const double* Tg = Tin + (int64_t)blockIdx.x * kTB * kTB;
-    for (int idx = t; idx < kTB * kTB; idx += kTT) {
+#pragma unroll
+    for (int m = 0; m < kTB * kTB / kTT; ++m) {
+      const int idx = t + kTT * m;
       const int a = idx % kTB, b = idx / kTB;  // T(a, b)
       const double v = Tg[a + b * kTB];
       if (trans) Ts[b][a] = v;
@@ -289,65 +317,70 @@ __global__ __launch_bounds__(kTT) void tsqr_apply_kernel(const double* V, int64_
     }
   }
 #pragma unroll
-  for (int m = 0; m < kTVld; ++m) {
-    const int idx = t + kTT * m;
-    const int i = idx % kTLeaf, a = idx / kTLeaf;
-    const double y = (i > a) ? vst[m] : (i == a ? 1.0 : 0.0);
-    Vs[i][a] = (i < rows && a < nv) ? y : 0.0;
+  for (int m = 0; m < kTRows; ++m) {
+    const int i = vr + kTG * m;
+    const double y = (i > va) ? vst[m] : (i == va ? 1.0 : 0.0);
+    Vs[i][va] = (i < rows && va < nv) ? y : 0.0;
   }
   __syncthreads();
-  // phase 1: Y tile (at, ct) = sum over the leaf rows of V(:, at*16 + .)^T C(:, ct*16 + .)
-  // (operands read from LDS 8 steps at a time, ahead of their MFMAs)
-  v4d acc = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-  for (int s0 = 0; s0 < kTSteps; s0 += 8) {
-    double va[8];
-#pragma unroll
-    for (int u = 0; u < 8; ++u) va[u] = Vs[4 * (s0 + u) + lk][at * 16 + li];
-#pragma unroll
-    for (int u = 0; u < 8; ++u) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(va[u], cr[s0 + u], acc, 0, 0, 0);
-  }
-#pragma unroll
-  for (int v = 0; v < 4; ++v) Ys[at * 16 + 4 * v + lk][ct * 16 + li] = acc[v];
-  __syncthreads();
-  // Z = T' Y: thread (zr, zc) forms rows zr, zr + 8, zr + 16, zr + 24 of column zc
+  // Y_h tiles (reflectors 0-15 and 16-31) x (columns of half e)
   {
-    const int zc = t & 31, zr = t >> 5;
+    v4d y0 = {0.0, 0.0, 0.0, 0.0}, y1 = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-    for (int m = 0; m < 4; ++m) {
-      const int a = zr + 8 * m;
-      double s = 0.0;
-#pragma unroll
-      for (int b = 0; b < kTB; ++b) s += Ts[a][b] * Ys[b][zc];
-      Zs[a][zc] = s;
+    for (int u = 0; u < kTHalfSteps; ++u) {
+      const int i = 4 * (kTHalfSteps * h + u) + lk;
+      y0 = __builtin_amdgcn_mfma_f64_16x16x4f64(Vs[i][li], cr[u], y0, 0, 0, 0);
+      y1 = __builtin_amdgcn_mfma_f64_16x16x4f64(Vs[i][16 + li], cr[u], y1, 0, 0, 0);
     }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      Yp[h][4 * v + lk][e * 16 + li] = y0[v];
+      Yp[h][16 + 4 * v + lk][e * 16 + li] = y1[v];
+    }
+  }
+  __syncthreads();
+  // Z tile (w / 2, w % 2) = T' Y
+  {
+    const int zt = w >> 1, zc = w & 1;
+    v4d z = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int q = 0; q < kTB / 4; ++q) {
+      const int k = 4 * q + lk;
+      const double y = Yp[0][k][zc * 16 + li] + Yp[1][k][zc * 16 + li];
+      z = __builtin_amdgcn_mfma_f64_16x16x4f64(Ts[zt * 16 + li][k], y, z, 0, 0, 0);
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) Zs[zt * 16 + 4 * v + lk][zc * 16 + li] = z[v];
   }
   __syncthreads();
   double zb[kTB / 4];
 #pragma unroll
-  for (int q = 0; q < kTB / 4; ++q) zb[q] = Zs[4 * q + lk][ct * 16 + li];
-  // phase 3: rows of tiles rt = at * 9 .. at * 9 + 8 of column tile ct
-  auto update = [&](auto base_tag) {
-    constexpr int R0 = decltype(base_tag)::value;
+  for (int q = 0; q < kTB / 4; ++q) zb[q] = Zs[4 * q + lk][e * 16 + li];
+  // C rows of tiles 9 h .. 9 h + 8, columns of half e
+  auto update = [&](auto h_tag) {
+    constexpr int H = decltype(h_tag)::value;
 #pragma unroll
-    for (int r = 0; r < 9; ++r) {
-      const int rt = R0 + r;
-      double va[kTB / 4];
-#pragma unroll
-      for (int q = 0; q < kTB / 4; ++q) va[q] = Vs[rt * 16 + li][4 * q + lk];
+    for (int r = 0; r < kTRuns; ++r) {
+      const int rt = kTRuns * H + r;
       v4d p = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-      for (int q = 0; q < kTB / 4; ++q) p = __builtin_amdgcn_mfma_f64_16x16x4f64(va[q], zb[q], p, 0, 0, 0);
+      for (int q = 0; q < kTB / 4; ++q)
+        p = __builtin_amdgcn_mfma_f64_16x16x4f64(Vs[rt * 16 + li][4 * q + lk], zb[q], p, 0, 0, 0);
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int s = 4 * rt + v;
-        const int pr = crow(s);
-        if (pr >= 0) C[(int64_t)pr + col * ldc] = cr[s] - p[v];
+        const int u = 4 * r + v;  // s = 4 rt + v = 36 H + u
+        const int s = kTHalfSteps * H + u;
+        if (full) {
+          C[rb[s >> 3] + 4 * (s & 7) + lk + col * ldc] = cr[u] - p[v];
+        } else {
+          const int64_t pr = crow(4 * s + lk);
+          if (pr >= 0) C[pr + col * ldc] = cr[u] - p[v];
+        }
       }
     }
   };
-  if (at == 0) update(std::integral_constant<int, 0>{});
-  else update(std::integral_constant<int, 9>{});
+  if (h == 0) update(std::integral_constant<int, 0>{});
+  else update(std::integral_constant<int, 1>{});
 }
 
 void launch_apply(hipStream_t s, const TsqrLevel& L, int level, int pb, int trans, const LevelRows& lr,
