@@ -15,11 +15,11 @@
 // (s / 32) * 288 + s % 32 of level l - 1 (the head rows of each leaf), which
 // maps every level back to rows of W.
 //
-// Leaf factorisation (256 threads = 32 columns x 8 row groups): thread
-// (c, g) holds rows g + 8 m (m < 36) of column c in registers.  Column step j
+// Leaf factorisation (512 threads = 32 columns x 16 row groups): thread
+// (c, g) holds rows g + 16 m (m < 18) of column c in registers.  Column step j
 // needs one broadcast, the pivot column x_j (LDS, written by its owners at the
 // end of step j - 1 together with its alpha and sigma^2), and one reduction
-// within each column's 8 lanes: the sum over rows i > j of x_j(i) a_c(i),
+// within each column's 16 lanes: the sum over rows i > j of x_j(i) a_c(i),
 // which for c > j is the product that updates column c and for c < j the
 // entry v_c^T v_j of the Gram matrix that builds T.  So a step has a single
 // barrier.  The pivot column is kept unscaled until the end, so no thread
@@ -33,13 +33,14 @@ namespace dme {
 namespace {
 
 constexpr int kTB = 32;                   // panel width
-constexpr int kTT = 256;                  // threads: 32 columns x 8 row groups
-constexpr int kTG = kTT / kTB;            // row groups
-constexpr int kTHead = kTB;               // head rows of a leaf (LDS)
-constexpr int kTPer = 32;                 // body rows per thread (registers)
-constexpr int kTLeaf = kTHead + kTG * kTPer;  // 288 rows per leaf
-constexpr int kTHq = kTHead / kTG;        // head rows per row group
-constexpr int kTRows = kTLeaf / kTG;      // rows per thread (36)
+constexpr int kTLeaf = 288;               // rows per leaf (9 runs of 32)
+constexpr int kTT = 256;                  // block-reflector threads: 32 columns x 8 row groups
+constexpr int kTG = kTT / kTB;            // their row groups
+constexpr int kTRows = kTLeaf / kTG;      // rows each stages (36)
+constexpr int kLT = 512;                  // leaf threads: 32 columns x 16 row groups
+constexpr int kLG = kLT / kTB;            // leaf row groups
+constexpr int kLRows = kTLeaf / kLG;      // rows per leaf thread (18)
+constexpr int kLHq = kTB / kLG;           // of them in the top 32 rows (2)
 
 // Rows of every level of a panel (kernel argument by value).
 struct LevelRows {
@@ -62,16 +63,15 @@ __device__ inline int64_t phys_row(int64_t s, const LevelRows& lr) {
 // r_mode: 0 = R stays in place (single leaf of level 0); 1 = R_g stacked into
 // Rdst rows 32 g .. 32 g + 31 (zeros below the diagonal); 2 = R's upper
 // triangle written to Rdst (the panel's top rows in W).
-__global__ __launch_bounds__(kTT) void tsqr_leaf_kernel(double* mat, int64_t ld, int64_t M, int pb,
+__global__ __launch_bounds__(kLT) void tsqr_leaf_kernel(double* mat, int64_t ld, int64_t M, int pb,
                                                         double* Tout, double* Rdst, int64_t ld_r,
                                                         int r_mode) {
-  __shared__ double xb[2][kTG][kTRows + 2];  // pivot column, [g][m] (padded: no bank conflicts)
+  __shared__ double xb[2][kLG][kLRows];  // pivot column, [g][m]: 144-byte rows, 16-byte reads conflict-free
   __shared__ double piv[2][2];               // alpha and sigma^2 of the pivot column
-  __shared__ double Zs[kTB][kTB + 1];        // Zs[c][j] = v_c^T v_j for c < j
-  __shared__ double Ts[kTB][kTB + 1];        // T, one column per step
+  __shared__ double Zs[kTB][kTB + 1];        // Zs[c][j] = v_c^T v_j for c < j, zero elsewhere
   __shared__ double coef[kTB];               // tau of each reflector
   const int t = threadIdx.x;
-  const int c = t >> 3, g = t & (kTG - 1);
+  const int c = t / kLG, g = t % kLG;
   const int64_t rbeg = (int64_t)blockIdx.x * kTLeaf;
   const int rows = (int)min<int64_t>(kTLeaf, M - rbeg);
   const int nv = min(rows, pb);
@@ -80,29 +80,31 @@ __global__ __launch_bounds__(kTT) void tsqr_leaf_kernel(double* mat, int64_t ld,
   // loads are unconditional (clamped to an entry of the block) and masked
   // afterwards, so they are all in flight together
   const int64_t cc0 = (int64_t)min(c, pb - 1) * ld;
-  double a[kTRows];
+  double a[kLRows];
 #pragma unroll
-  for (int m = 0; m < kTRows; ++m) {
-    const int i = g + kTG * m;
+  for (int m = 0; m < kLRows; ++m) {
+    const int i = g + kLG * m;
     const double v = base[min(i, rows - 1) + cc0];
     a[m] = (i < rows && cin) ? v : 0.0;
   }
-  // pivot data of column p from its owners (all 8 lanes of the column)
+  for (int idx = t; idx < kTB * (kTB + 1); idx += kLT) (&Zs[0][0])[idx] = 0.0;
+  // pivot data of column p from its owners (all 16 lanes of the column)
   auto publish = [&](int p, int buf) {
-    double s2 = 0.0, al = 0.0;
+    double sq[2] = {0.0, 0.0};  // independent chains
+    double al = 0.0;
 #pragma unroll
-    for (int m = 0; m < kTRows; ++m) {
-      const int i = g + kTG * m;
+    for (int m = 0; m < kLRows; ++m) {
+      const int i = g + kLG * m;
       xb[buf][g][m] = a[m];
-      if (m < kTHq) {
-        s2 += (i > p) ? a[m] * a[m] : 0.0;
+      if (m < kLHq) {
+        sq[m & 1] += (i > p) ? a[m] * a[m] : 0.0;
         al += (i == p) ? a[m] : 0.0;
       } else {
-        s2 += a[m] * a[m];
+        sq[m & 1] += a[m] * a[m];
       }
     }
-    s2 = group8_sum_f64(s2);
-    al = group8_sum_f64(al);
+    const double s2 = group16_sum_f64(sq[0] + sq[1]);
+    al = group16_sum_f64(al);
     if (g == 0) {
       piv[buf][0] = al;
       piv[buf][1] = s2;
@@ -113,32 +115,34 @@ __global__ __launch_bounds__(kTT) void tsqr_leaf_kernel(double* mat, int64_t ld,
 
   // Column jj of T (upper triangular, Q = I - V T V^T): T(jj, jj) = tau_jj and
   // T(c, jj) = -tau_jj sum_{c <= c2 < jj} T(c, c2) Zs(c2, jj), from the columns
-  // before it; thread (c, g) sums over c2 = g (mod 8).  Formed one step after
-  // Zs(:, jj), beside the next column step.
+  // before it.  Thread (c, g) sums over c2 = g + 16 q and keeps T(c, c2) for
+  // those c2 in registers.  Formed one step after Zs(:, jj), beside the next
+  // column step.  (The reads are unconditional; Zs is zero outside c2 < jj.)
   double* To = Tout + (int64_t)blockIdx.x * kTB * kTB;
+  double trow[kTB / kLG] = {0.0, 0.0};
   auto t_column = [&](int jj) {
     double s = 0.0;
 #pragma unroll
-    for (int q = 0; q < kTB / kTG; ++q) {
-      const int c2 = g + kTG * q;
-      s += (c2 >= c && c2 < jj) ? Ts[c][c2] * Zs[c2][jj] : 0.0;
+    for (int q = 0; q < kTB / kLG; ++q) {
+      const int c2 = g + kLG * q;
+      const double z = Zs[c2][jj];
+      s += ((c2 >= c) ? trow[q] : 0.0) * z;
     }
-    s = group8_sum_f64(s);
+    s = group16_sum_f64(s);
     const double tj = coef[jj];
     const double v = (c == jj) ? tj : ((c < jj) ? -tj * s : 0.0);
-    if (g == 0) {
-      Ts[c][jj] = v;
-      To[c + jj * kTB] = v;
-    }
+#pragma unroll
+    for (int q = 0; q < kTB / kLG; ++q) trow[q] = (jj == g + kLG * q) ? v : trow[q];
+    if (g == 0) To[c + jj * kTB] = v;
   };
 
   double my_sc = 0.0, my_beta = 0.0;  // this column's reflector, once it has been the pivot
   for (int j = 0; j < nv; ++j) {
     const int bf = j & 1;
     if (j > 0) t_column(j - 1);
-    double xv[kTRows];
+    double xv[kLRows];
 #pragma unroll
-    for (int m = 0; m < kTRows; ++m) xv[m] = xb[bf][g][m];
+    for (int m = 0; m < kLRows; ++m) xv[m] = xb[bf][g][m];
     const double alpha = piv[bf][0], s2 = piv[bf][1];
     // reflector j (every thread forms the same values; independent of the
     // products below, so its latency overlaps them)
@@ -149,19 +153,18 @@ __global__ __launch_bounds__(kTT) void tsqr_leaf_kernel(double* mat, int64_t ld,
       sc = 1.0 / (alpha - beta);
     }
     // sum over rows i > j of x_j(i) a_c(i), and a_c(j)
-    double pp[4] = {0.0, 0.0, 0.0, 0.0};  // independent chains
+    double pp[2] = {0.0, 0.0};  // independent chains
     double ah = 0.0;
 #pragma unroll
-    for (int m = 0; m < kTHq; ++m) {
-      const int i = g + kTG * m;
+    for (int m = 0; m < kLHq; ++m) {
+      const int i = g + kLG * m;
       xv[m] = (i > j) ? xv[m] : 0.0;
       ah += (i == j) ? a[m] : 0.0;
     }
 #pragma unroll
-    for (int m = 0; m < kTRows; ++m) pp[m & 3] += xv[m] * a[m];
-    double tc = (pp[0] + pp[1]) + (pp[2] + pp[3]);
-    tc = group8_sum_f64(tc);
-    const double ahead = group8_sum_f64(ah);
+    for (int m = 0; m < kLRows; ++m) pp[m & 1] += xv[m] * a[m];
+    const double tc = group16_sum_f64(pp[0] + pp[1]);
+    const double ahead = group16_sum_f64(ah);
     if (c < j) {
       if (g == 0) Zs[c][j] = my_sc * (ahead + sc * tc);
     } else if (c == j) {
@@ -173,10 +176,10 @@ __global__ __launch_bounds__(kTT) void tsqr_leaf_kernel(double* mat, int64_t ld,
       const double wv = tau * (ahead + sc * tc);
       const double f = wv * sc;
 #pragma unroll
-      for (int m = 0; m < kTRows; ++m) {
-        const int i = g + kTG * m;
+      for (int m = 0; m < kLRows; ++m) {
+        const int i = g + kLG * m;
         const double u = a[m] - f * xv[m];
-        a[m] = (m < kTHq && i == j) ? ahead - wv : u;
+        a[m] = (m < kLHq && i == j) ? ahead - wv : u;
       }
       if (c == j + 1 && j + 1 < nv) publish(j + 1, bf ^ 1);
     }
@@ -186,28 +189,28 @@ __global__ __launch_bounds__(kTT) void tsqr_leaf_kernel(double* mat, int64_t ld,
   // reflectors scaled in place, R in the upper part of the head rows
   if (c < nv) {
 #pragma unroll
-    for (int m = 0; m < kTRows; ++m) {
-      const int i = g + kTG * m;
-      if (m >= kTHq || i > c) a[m] *= my_sc;
+    for (int m = 0; m < kLRows; ++m) {
+      const int i = g + kLG * m;
+      if (m >= kLHq || i > c) a[m] *= my_sc;
       else if (i == c) a[m] = my_beta;
     }
   }
   if (cin) {
 #pragma unroll
-    for (int m = 0; m < kTRows; ++m) {
-      const int i = g + kTG * m;
+    for (int m = 0; m < kLRows; ++m) {
+      const int i = g + kLG * m;
       if (i < rows) base[i + (int64_t)c * ld] = a[m];
     }
     if (r_mode == 1) {
 #pragma unroll
-      for (int m = 0; m < kTHq; ++m) {
-        const int i = g + kTG * m;
+      for (int m = 0; m < kLHq; ++m) {
+        const int i = g + kLG * m;
         Rdst[(int64_t)blockIdx.x * kTB + i + (int64_t)c * ld_r] = (i <= c && i < rows) ? a[m] : 0.0;
       }
     } else if (r_mode == 2) {
 #pragma unroll
-      for (int m = 0; m < kTHq; ++m) {
-        const int i = g + kTG * m;
+      for (int m = 0; m < kLHq; ++m) {
+        const int i = g + kLG * m;
         if (i <= c && i < rows) Rdst[i + (int64_t)c * ld_r] = a[m];
       }
     }
@@ -215,8 +218,8 @@ __global__ __launch_bounds__(kTT) void tsqr_leaf_kernel(double* mat, int64_t ld,
   // the last column of T, and zero columns past the reflectors
   t_column(nv - 1);
 #pragma unroll
-  for (int q = 0; q < kTB / kTG; ++q) {
-    const int jj = g + kTG * q;
+  for (int q = 0; q < kTB / kLG; ++q) {
+    const int jj = g + kLG * q;
     if (jj >= nv) To[c + jj * kTB] = 0.0;
   }
 }
@@ -505,7 +508,7 @@ void tsqr_factor(hipStream_t s, int64_t n, int64_t k, double* W, TsqrState& st, 
       P.nlev = l + 1;
       if (L.G == 1) {
         // top: R into W rows [c0, c0 + pb) (a single leaf of level 0 holds it in place)
-        hipLaunchKernelGGL(tsqr_leaf_kernel, dim3(1), dim3(kTT), 0, s, mat, mld, M, pb, L.T,
+        hipLaunchKernelGGL(tsqr_leaf_kernel, dim3(1), dim3(kLT), 0, s, mat, mld, M, pb, L.T,
                            W + c0 + c0 * ld, ld, l > 0 ? 2 : 0);
         DME_HIP(hipGetLastError());
         lev_done[l] = ax.record(s);
@@ -514,7 +517,7 @@ void tsqr_factor(hipStream_t s, int64_t n, int64_t k, double* W, TsqrState& st, 
       if (l + 1 == kTsqrMaxLevels) fail(DME_EINVAL, "tsqr: matrix too tall for the reduction tree");
       const int64_t Mn = (int64_t)L.G * kTB;
       double* next = ws.get<double>((size_t)Mn * pb);
-      hipLaunchKernelGGL(tsqr_leaf_kernel, dim3((unsigned)L.G), dim3(kTT), 0, s, mat, mld, M, pb, L.T,
+      hipLaunchKernelGGL(tsqr_leaf_kernel, dim3((unsigned)L.G), dim3(kLT), 0, s, mat, mld, M, pb, L.T,
                          next, Mn, 1);
       DME_HIP(hipGetLastError());
       lev_done[l] = ax.record(s);
