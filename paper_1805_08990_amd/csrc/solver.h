@@ -154,6 +154,8 @@ struct Solver {
   void apply_T3(double t);
   void apply_T4(double t);
   void compress_into(int64_t k);  // W (n x k), Dhat (k x k) -> new (L, D)
+  // W[:, 0:rY] = e^{tA} L and the quadrature factor f (orthonormal L_I) -> new (L, D)
+  void compress_lead_into(int64_t rY, const QuadFactor& f);
   void apply_E(double t, const double* X, int64_t r, double* Y, int64_t ldy);
   void build_quadrature(double t);
 };

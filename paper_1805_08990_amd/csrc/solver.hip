@@ -454,6 +454,22 @@ void Solver::compress_into(int64_t k) {
   r = rn;
 }
 
+void Solver::compress_lead_into(int64_t rY, const QuadFactor& f) {
+  ws.reset();
+  hipEvent_t ev = mark_begin();
+  const int64_t k = rY + f.r;
+  const int64_t rn = compress_f64_lead(s, n, rY, W.as<double>(), f.L.as<double>(), n, f.r,
+                                       Dhat.as<double>(), opts.tol, max_rank, Ln(), n, Dn(), 0,
+                                       rank_dev(), flag_dev(), ws);
+  // projections 8 n q r, Householder QR 2 n r^2 - 2/3 r^3, Q application 4 n r r',
+  // U terms 4 n q r', small eigenproblem ~ 10 k^3
+  const double kk = (double)k, ry = (double)rY, qq = (double)f.r, rr = (double)rn;
+  mark_end(1, ev, 8.0 * n * qq * ry + 2.0 * n * ry * ry + 4.0 * n * ry * rr + 4.0 * n * qq * rr + 10.0 * kk * kk * kk,
+           8.0 * (2.0 * n * kk + 2.0 * n * rr));
+  cur ^= 1;
+  r = rn;
+}
+
 void Solver::apply_T1(double t) {
   if (r == 0) return;
   apply_E(t, Lc(), r, Ln(), n);
@@ -474,10 +490,16 @@ void Solver::apply_T12(double t, bool ext_product) {
   const QuadFactor& f = Q.at(t);
   double* Wd = W.as<double>();
   if (r > 0 && !ext_product) apply_E(t, Lc(), r, Wd, n);
-  if (f.r > 0) copy_f64(s, f.L.as<double>(), n, Wd + r * n, n, n, f.r);
   const int64_t k = r + f.r;
   if (k == 0) return;
   blkdiag2_f64(s, Dc(), r, r, f.D.as<double>(), f.r, f.r, 1.0, Dhat.as<double>(), k);
+  if (r > 0 && f.r > 0 && n >= k) {
+    // L_I has orthonormal columns (it is a compression output): it takes no
+    // Householder panels of its own
+    compress_lead_into(r, f);
+    return;
+  }
+  if (f.r > 0) copy_f64(s, f.L.as<double>(), n, Wd + r * n, n, n, f.r);
   compress_into(k);
 }
 
