@@ -24,6 +24,7 @@ from __future__ import annotations
 import argparse
 import hashlib
 import json
+import math
 import os
 import sys
 import time
@@ -56,6 +57,9 @@ def parse():
                     help="requests in the served mix (0 disables the serving leg)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run one device copy of known size (counter calibration)")
+    ap.add_argument("--product-only", type=int, default=0, metavar="R",
+                    help="run only the split-BF16 step product E X (n x n times n x R, random "
+                         "E and X, 3 launches) for hardware counters, and exit")
     return ap.parse_args()
 
 
@@ -273,7 +277,6 @@ def main():
     import torch
     from paper_1805_08990_amd import _binding as b
 
-    prob = workload(args.nx)
     ctx = b.Context(0)
     if args.calibrate_copy:
         # one plain device copy of 1 GiB, for the HBM counter calibration
@@ -283,6 +286,19 @@ def main():
         y.copy_(x)
         torch.cuda.synchronize()
         del x, y
+    if args.product_only > 0:
+        # the step product alone, at the workload's n, with no operator set-up
+        # (its LU issues ~10^5 small launches, which counter collection does not bear)
+        n, r = args.nx * args.nx, args.product_only
+        g = torch.Generator(device="cuda").manual_seed(0)
+        E = torch.randn((n, n), dtype=torch.float64, device="cuda", generator=g) / math.sqrt(n)
+        X = torch.randn((n, r), dtype=torch.float64, device="cuda", generator=g)
+        for _ in range(3):
+            ctx.gemm_mixed(E, X)
+            torch.cuda.synchronize()
+        print(json.dumps({"product_only": {"n": n, "r": r, "launches": 3}}), flush=True)
+        return
+    prob = workload(args.nx)
     precisions = ["fp64", "mixed"] if args.precision == "both" else [args.precision]
     results = {p: run_gpu(ctx, prob, p, args.steps, args.warmup) for p in precisions}
     main_prec = "mixed" if "mixed" in results else "fp64"

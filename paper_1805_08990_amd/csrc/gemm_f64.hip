@@ -371,12 +371,15 @@ struct Plan {
 constexpr int kBK = 16;
 constexpr int kTargetBlocks = 1024;  // ~4 workgroups per CU on 256 CUs
 constexpr int kMinKChunk = 256;
+constexpr int64_t kMinTiles = 256;      // one tile per CU
 
 Plan plan_for(int64_t M, int64_t N, int64_t K) {
   Plan p;
-  if (M >= 128 && N >= 128) { p.bm = 128; p.bn = 128; }
-  else if (M >= 128)        { p.bm = 128; p.bn = 64; }
-  else                      { p.bm = 64;  p.bn = 64; }
+  // the largest tile that still gives every CU a tile (small products are
+  // latency-bound: more, smaller tiles finish sooner)
+  if (M >= 128 && N >= 128 && cdiv(M, 128) * cdiv(N, 128) >= kMinTiles) { p.bm = 128; p.bn = 128; }
+  else if (M >= 128 && cdiv(M, 128) * cdiv(N, 64) >= kMinTiles)         { p.bm = 128; p.bn = 64; }
+  else                                                                   { p.bm = 64;  p.bn = 64; }
   const int64_t tiles = cdiv(M, p.bm) * cdiv(N, p.bn);
   int64_t nsplit = 1;
   if (tiles < kTargetBlocks && K >= 2 * kMinKChunk) {
