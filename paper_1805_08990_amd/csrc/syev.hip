@@ -13,9 +13,10 @@
 //                         and the clusters of kept eigenvalues whose gaps are
 //                         below 1e-3 ||T|| (the absolute criterion of LAPACK's
 //                         inverse iteration), one workgroup with prefix sums.
-//   4. invit_kernel     : inverse iteration with a partially pivoted
-//                         tridiagonal LU, one wave per kept eigenvalue, all
-//                         independent.
+//   4. twist_kernel     : eigenvector from a twisted factorisation, one
+//                         wave per kept eigenvalue, all independent;
+//      invit_kernel     : inverse iteration with a partially pivoted
+//                         tridiagonal LU for tied eigenvalues (and k > 512).
 //   5. orth_kernel      : one workgroup per cluster orthonormalises the
 //                         cluster's vectors (right-looking modified Gram-Schmidt,
 //                         two passes).
@@ -643,13 +644,15 @@ template <bool LDS>
 __global__ __launch_bounds__(64) void invit_kernel(const double* d, const double* e, int k,
                                                    const double* lam, const int* order,
                                                    const int64_t* keep, const double* bounds,
-                                                   double* work, double* Z, int64_t ldz) {
+                                                   double* work, double* Z, int64_t ldz,
+                                                   int ties_only) {
   const int c = blockIdx.x;
   if (c >= keep[0]) return;
   const int idx = order[c];
   const int lane = threadIdx.x;
   extern __shared__ double ism[];
   __shared__ double sscale;
+  if (ties_only && !(idx > 0 && lam[idx] - lam[idx - 1] <= 4.0 * DBL_EPSILON * bounds[3])) return;
   // keep the arrays in LDS when they fit (a compile-time choice, so that
   // every access has a known address space)
   double* dd;
@@ -768,6 +771,160 @@ __global__ __launch_bounds__(64) void invit_kernel(const double* d, const double
   part = wave_sum_f64(part);
   const double inv = (part > 0.0) ? 1.0 / sqrt(part) : 0.0;
   for (int i = lane; i < k; i += 64) Z[i + (int64_t)c * ldz] = x[i] * inv;
+}
+
+// Eigenvector of T for kept eigenvalue number `blockIdx.x` from a twisted
+// factorisation (Fernando 1997; Parlett & Dhillon 1997), one wave per
+// eigenvalue.  With the shift lam:
+//   dp_0 = d_0 - lam,          dp_i = (d_i - lam) - e_{i-1}^2 / dp_{i-1}
+//   dm_{k-1} = d_{k-1} - lam,  dm_i = (d_i - lam) - e_i^2 / dm_{i+1}
+//   gamma_i = dp_i + dm_i - (d_i - lam)
+// (T - lam I = N_r diag(..., gamma_r, ...) N_r^T twisted at r), and with
+// r = argmin |gamma_i|: z_r = 1, z_i = -e_i z_{i+1} / dp_i below the twist,
+// z_i = -e_{i-1} z_{i-1} / dm_i above it.  Two sweeps down and up instead of
+// a factorisation and repeated solves.  Row i of every k-vector sits in lane
+// i mod 64, slot i / 64 of the wave; the sweeps read the current row's values
+// with lane reads (no LDS), and store results by selecting the owning lane.
+// Pivots below eps ||T|| in magnitude are replaced by +-eps ||T||, as in the
+// LU of the inverse iteration.  Tied eigenvalues (within 4 ulps of ||T|| of
+// the previous one) are left to the inverse iteration, whose distinct start
+// vectors separate them.
+__device__ inline double lane_read_f64(double v, int l) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
+  return __hiloint2double(hi, lo);
+}
+
+template <int NS>
+__global__ __launch_bounds__(64) void twist_kernel(const double* __restrict__ d, const double* __restrict__ e,
+                                                   int k, const double* __restrict__ lam,
+                                                   const int* __restrict__ order,
+                                                   const int64_t* __restrict__ keep,
+                                                   const double* __restrict__ bounds, double* Z,
+                                                   int64_t ldz) {
+  const int c = blockIdx.x;
+  if (c >= keep[0]) return;
+  const int idx = order[c];
+  const double nrmT = bounds[3];
+  const double small = DBL_EPSILON * fmax(nrmT, DBL_MIN);
+  if (idx > 0 && lam[idx] - lam[idx - 1] <= 4.0 * DBL_EPSILON * nrmT) return;  // a tie
+  const double lamq = lam[idx];
+  const int lane = threadIdx.x;
+  double dn[NS], en[NS], rdp[NS], rdm[NS], gam[NS], z[NS];
+#pragma unroll
+  for (int m = 0; m < NS; ++m) {
+    const int i = 64 * m + lane;
+    dn[m] = (i < k) ? d[i] - lamq : 0.0;
+    en[m] = (i + 1 < k) ? e[i] : 0.0;
+    rdp[m] = rdm[m] = gam[m] = z[m] = 0.0;
+  }
+  auto guard = [&](double p) { return (fabs(p) < small) ? copysign(small, p) : p; };
+  // forward sweep: dp (kept as 1 / dp), up the rows
+  {
+    double ep = 0.0, rprev = 0.0;
+#pragma unroll
+    for (int m = 0; m < NS; ++m) {
+      for (int j = 0; j < 64; ++j) {
+        const int i = 64 * m + j;
+        if (i >= k) break;
+        const double di = lane_read_f64(dn[m], j);
+        const double p = guard(di - ep * ep * rprev);
+        const double rp = 1.0 / p;
+        rdp[m] = (lane == j) ? rp : rdp[m];
+        gam[m] = (lane == j) ? p - di : gam[m];  // dp_i - (d_i - lam); dm_i is added below
+        ep = lane_read_f64(en[m], j);
+        rprev = rp;
+      }
+    }
+  }
+  // backward sweep: dm (kept as 1 / dm), down the rows
+  {
+    double rprev = 0.0;
+#pragma unroll
+    for (int m = NS - 1; m >= 0; --m) {
+      for (int j = 63; j >= 0; --j) {
+        const int i = 64 * m + j;
+        if (i >= k) continue;
+        const double di = lane_read_f64(dn[m], j);
+        const double ei = lane_read_f64(en[m], j);  // coupling of rows i and i + 1 (0 for the last)
+        const double p = guard(di - ei * ei * rprev);
+        const double rp = 1.0 / p;
+        rdm[m] = (lane == j) ? rp : rdm[m];
+        gam[m] = (lane == j) ? gam[m] + p : gam[m];
+        rprev = rp;
+      }
+    }
+  }
+  // twist r = argmin |gamma_i| (lowest i among equals)
+  double best = DBL_MAX;
+  int bi = 0x7fffffff;
+#pragma unroll
+  for (int m = 0; m < NS; ++m) {
+    const int i = 64 * m + lane;
+    const double g = fabs(gam[m]);
+    if (i < k && (g < best || (g == best && i < bi))) { best = g; bi = i; }
+  }
+  for (int off = 32; off >= 1; off >>= 1) {
+    const double ob = __shfl_xor(best, off, 64);
+    const int oi = __shfl_xor(bi, off, 64);
+    if (ob < best || (ob == best && oi < bi)) { best = ob; bi = oi; }
+  }
+  const int r = bi;
+  // z_r = 1 and the two sweeps out of the twist; a running rescale keeps the
+  // entries in range (|z| grows at most where the pivots are tiny)
+  const int rm = r >> 6, rl = r & 63;
+#pragma unroll
+  for (int m = 0; m < NS; ++m) z[m] = (m == rm && lane == rl) ? 1.0 : 0.0;
+  {
+    double zc = 1.0;  // z_{i+1}
+#pragma unroll
+    for (int m = NS - 1; m >= 0; --m) {
+      for (int j = 63; j >= 0; --j) {
+        const int i = 64 * m + j;
+        if (i >= r) continue;
+        const double ei = lane_read_f64(en[m], j);
+        const double ri = lane_read_f64(rdp[m], j);
+        zc = -ei * zc * ri;
+        z[m] = (lane == j) ? zc : z[m];
+        if (fabs(zc) > 1e150) {  // uniform
+#pragma unroll
+          for (int q = 0; q < NS; ++q) z[q] *= 1e-150;
+          zc *= 1e-150;
+        }
+      }
+    }
+  }
+  {
+    double zc = 1.0;  // z_{i-1}
+    double ep = (r < 64 * NS) ? lane_read_f64(en[rm], rl) : 0.0;  // e_r
+#pragma unroll
+    for (int m = 0; m < NS; ++m) {
+      for (int j = 0; j < 64; ++j) {
+        const int i = 64 * m + j;
+        if (i <= r) continue;
+        if (i >= k) break;
+        const double ri = lane_read_f64(rdm[m], j);
+        zc = -ep * zc * ri;
+        z[m] = (lane == j) ? zc : z[m];
+        ep = lane_read_f64(en[m], j);
+        if (fabs(zc) > 1e150) {  // uniform
+#pragma unroll
+          for (int q = 0; q < NS; ++q) z[q] *= 1e-150;
+          zc *= 1e-150;
+        }
+      }
+    }
+  }
+  double part = 0.0;
+#pragma unroll
+  for (int m = 0; m < NS; ++m) part += z[m] * z[m];
+  part = wave_sum_f64(part);
+  const double inv = (part > 0.0) ? 1.0 / sqrt(part) : 0.0;
+#pragma unroll
+  for (int m = 0; m < NS; ++m) {
+    const int i = 64 * m + lane;
+    if (i < k) Z[i + (int64_t)c * ldz] = z[m] * inv;
+  }
 }
 
 // Orthonormalise the vectors of one cluster (blockIdx.x), in ascending
@@ -1014,12 +1171,26 @@ void syev_trunc_f64(hipStream_t s, int64_t k, const double* M, int64_t ldm, doub
   DME_HIP(hipGetLastError());
   // Z: k x (kept) column-major with ld = k (kept <= k)
   const unsigned nkeep = (unsigned)std::min<int64_t>(k, max_keep);
+  // twisted factorisations for k <= 512, inverse iteration for ties (and larger k)
+  int ties_only = 1;
+  switch (cdiv(k, 64)) {
+#define DME_TWIST(NS)                                                                             \
+  case NS:                                                                                        \
+    hipLaunchKernelGGL(twist_kernel<NS>, dim3(nkeep), dim3(64), 0, s, d, e, ki, lam, order, keep_dev, \
+                       bounds, Zt, k);                                                            \
+    break;
+    DME_TWIST(1) DME_TWIST(2) DME_TWIST(3) DME_TWIST(4) DME_TWIST(5) DME_TWIST(6) DME_TWIST(7)
+    DME_TWIST(8)
+#undef DME_TWIST
+    default: ties_only = 0;
+  }
+  DME_HIP(hipGetLastError());
   if (k <= kInvitLdsMaxK)
     hipLaunchKernelGGL(invit_kernel<true>, dim3(nkeep), dim3(64), (size_t)kInvitArrays * k * sizeof(double),
-                       s, d, e, ki, lam, order, keep_dev, bounds, work, Zt, k);
+                       s, d, e, ki, lam, order, keep_dev, bounds, work, Zt, k, ties_only);
   else
     hipLaunchKernelGGL(invit_kernel<false>, dim3(nkeep), dim3(64), 0, s, d, e, ki, lam, order, keep_dev,
-                       bounds, work, Zt, k);
+                       bounds, work, Zt, k, ties_only);
   DME_HIP(hipGetLastError());
   // cluster staging in LDS: up to 144 KiB, never more than the whole k x k set
   const int64_t orth_lds = std::min<int64_t>(k * k, (144 * 1024) / (int64_t)sizeof(double));
