@@ -197,6 +197,26 @@ struct LuWork;
 void lu_solve_f64(hipStream_t s, int64_t n, double* P, double* Q, Arena& ws, int* info_dev);
 size_t lu_solve_workspace(int64_t n);
 
+// A second stream and a ring of events per host thread and device, for work
+// that runs beside the caller's stream (default priority, created on first
+// use; they are not destroyed, since a thread's end may come after the
+// runtime's).  Defined in tsqr.hip.
+struct AuxStream {
+  int device = -1;
+  hipStream_t s2 = nullptr;
+  std::vector<hipEvent_t> ev;
+  size_t next = 0;
+  // A recorded event is only waited on by calls enqueued right after its
+  // record, so a ring much longer than the waits in flight can be reused.
+  hipEvent_t record(hipStream_t st) {
+    hipEvent_t e = ev[next];
+    next = (next + 1) % ev.size();
+    DME_HIP(hipEventRecord(e, st));
+    return e;
+  }
+};
+AuxStream& aux_stream();
+
 // Householder QR + eigen compression (compress.hip)
 size_t compress_workspace(int64_t n, int64_t k);
 // W (n x k, ld n) is destroyed.  Dhat k x k (ld k).  Output L (n x r, ld ldl), Dout (r x r, ld ldd).

@@ -17,10 +17,14 @@
 //                         wave per kept eigenvalue, all independent;
 //      invit_kernel     : inverse iteration with a partially pivoted
 //                         tridiagonal LU for tied eigenvalues (and k > 512).
-//   5. orth_kernel      : one workgroup per cluster orthonormalises the
-//                         cluster's vectors (right-looking modified Gram-Schmidt,
+//   5. polar steps      : clusters whose vectors are nearly orthonormal get
+//                         two Newton-Schulz steps Z <- Z (3I - Z^T Z) / 2 by
+//                         GEMMs (restricted to each cluster's block);
+//      orth_kernel      : one workgroup per remaining cluster orthonormalises
+//                         its vectors (right-looking modified Gram-Schmidt,
 //                         two passes).
-//   6. backtr_kernel    : V = H_0 ... H_{k-3} Z, one wave per column.
+//   6. backtr_kernel    : Q = H_0 ... H_{k-3} formed one wave per column, on a
+//                         second stream beside steps 2-5; then V = Q Z (GEMM).
 //
 // An inverse-iteration vector is off its eigenvector by O(u ||M|| / gap) in
 // the directions of nearby eigenvectors; orthonormalising a cluster mixes its
@@ -453,12 +457,13 @@ __device__ inline double rcp_f64(double q) {
 #endif
 }
 
-__device__ inline void sturm_count2(const double* d, const double* e2, int k, double x1, double x2,
-                                    double pivmin, int& c1, int& c2) {
+__device__ inline void sturm_count2(const double* __restrict__ d, const double* __restrict__ e2, int k,
+                                    double x1, double x2, double pivmin, int& c1, int& c2) {
   double q1 = d[0] - x1, q2 = d[0] - x2;
   if (fabs(q1) < pivmin) q1 = -pivmin;
   if (fabs(q2) < pivmin) q2 = -pivmin;
   int n1 = (q1 < 0.0), n2 = (q2 < 0.0);
+#pragma unroll 4
   for (int i = 1; i < k; ++i) {
     const double di = d[i], ei = e2[i - 1];
     q1 = (di - x1) - ei * rcp_f64(q1);
@@ -476,12 +481,15 @@ __device__ inline void sturm_count2(const double* d, const double* e2, int k, do
 // evaluates the count at 127 interior points of its interval (two per lane)
 // and keeps the sub-interval where the count passes i, so each round shrinks
 // the interval 128-fold.  Stops at the width the reduction determines the
-// eigenvalue to.  d and e2 are staged in LDS when LDS.
+// eigenvalue to.  d and e2 are staged in LDS when LDS; otherwise the loop
+// reads them with scalar loads (the same entry for every lane), which costs
+// the wave far less than an LDS read per row.
 // (LDS is a template parameter so that every access has a known address
 // space: a pointer that may be either becomes a slow generic access.)
 template <bool LDS>
-__global__ __launch_bounds__(64) void bisect_kernel(const double* d, const double* e2, int k,
-                                                    const double* bounds, double* lam) {
+__global__ __launch_bounds__(64) void bisect_kernel(const double* __restrict__ d,
+                                                    const double* __restrict__ e2, int k,
+                                                    const double* __restrict__ bounds, double* lam) {
   extern __shared__ double bsh[];
   const int i = blockIdx.x;
   const int lane = threadIdx.x;
@@ -536,19 +544,21 @@ __global__ __launch_bounds__(64) void bisect_kernel(const double* d, const doubl
 constexpr int kSelT = 1024;
 
 __device__ inline int block_scan_incl(int v, int* sh) {
-  // inclusive prefix sum of v over the block (Hillis-Steele in LDS)
-  const int t = threadIdx.x;
-  sh[t] = v;
-  __syncthreads();
-  for (int off = 1; off < kSelT; off <<= 1) {
-    const int add = (t >= off) ? sh[t - off] : 0;
-    __syncthreads();
-    sh[t] += add;
-    __syncthreads();
+  // inclusive prefix sum of v over the block: within each wave by lane
+  // shifts, then over the wave totals (two barriers)
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  int x = v;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const int y = __shfl_up(x, off, 64);
+    if (lane >= off) x += y;
   }
-  const int r = sh[t];
+  if (lane == 63) sh[w] = x;
   __syncthreads();
-  return r;
+  int before = 0;
+  for (int q = 0; q < w; ++q) before += sh[q];
+  __syncthreads();  // sh is reused by the next scan
+  return x + before;
 }
 
 __global__ __launch_bounds__(kSelT) void select_kernel(const double* lam, int k, double tol,
@@ -606,20 +616,24 @@ __global__ __launch_bounds__(kSelT) void select_kernel(const double* lam, int k,
   auto starts = [&](int i) {
     return pos_of[i] >= 0 && (i == 0 || pos_of[i - 1] < 0 || lam[i] - lam[i - 1] > kOrtol * nrmT);
   };
+  // ... and ends at a kept eigenvalue whose upper neighbour starts a run or
+  // is not kept; a run's id is the number of starts up to it, minus one
+  auto ends = [&](int i) { return pos_of[i] >= 0 && (i + 1 == k || pos_of[i + 1] < 0 || starts(i + 1)); };
   int ns = 0;
   for (int i = i0; i < i1; ++i) ns += starts(i) ? 1 : 0;
   const int incl = block_scan_incl(ns, sh);
-  int id = incl - ns;
+  int id = incl - ns;  // runs started before this chunk
   for (int i = i0; i < i1; ++i) {
-    if (!starts(i)) continue;
-    int len = 1;
-    while (i + len < k && pos_of[i + len] >= 0 && !starts(i + len)) ++len;
-    clusters[2 * id] = i;
-    clusters[2 * id + 1] = len;
-    ++id;
+    if (starts(i)) clusters[2 * id++] = i;
+    if (ends(i)) clusters[2 * (id - 1) + 1] = i;  // the end index for now
   }
+  __shared__ int tot_runs;
+  if (t == kSelT - 1) tot_runs = incl;
+  __syncthreads();  // every run's start and end are written, and the run count is known
+  const int runs = tot_runs;
+  for (int q = t; q < runs; q += kSelT) clusters[2 * q + 1] = clusters[2 * q + 1] - clusters[2 * q] + 1;
   if (t == kSelT - 1) {
-    cl_count[0] = incl;
+    cl_count[0] = runs;
     keep[0] = cap;
   }
 }
@@ -647,7 +661,11 @@ __global__ __launch_bounds__(64) void invit_kernel(const double* d, const double
                                                    double* work, double* Z, int64_t ldz,
                                                    int ties_only) {
   const int c = blockIdx.x;
-  if (c >= keep[0]) return;
+  if (c >= keep[0]) {  // unused column: zero (the polar step multiplies it by 0)
+    if (!ties_only)
+      for (int i = threadIdx.x; i < k; i += 64) Z[i + (int64_t)c * ldz] = 0.0;
+    return;
+  }
   const int idx = order[c];
   const int lane = threadIdx.x;
   extern __shared__ double ism[];
@@ -796,50 +814,63 @@ __device__ inline double lane_read_f64(double v, int l) {
 }
 
 template <int NS>
-__global__ __launch_bounds__(64) void twist_kernel(const double* __restrict__ d, const double* __restrict__ e,
-                                                   int k, const double* __restrict__ lam,
-                                                   const int* __restrict__ order,
-                                                   const int64_t* __restrict__ keep,
-                                                   const double* __restrict__ bounds, double* Z,
-                                                   int64_t ldz) {
+__global__ __launch_bounds__(128) void twist_kernel(const double* __restrict__ d, const double* __restrict__ e,
+                                                    int k, const double* __restrict__ lam,
+                                                    const int* __restrict__ order,
+                                                    const int64_t* __restrict__ keep,
+                                                    const double* __restrict__ bounds, double* Z,
+                                                    int64_t ldz) {
+  // wave 0 runs the forward sweep and then z below the twist, wave 1 the
+  // backward sweep and then z above it; gamma and the norm meet in LDS
+  __shared__ double gsh[64 * NS];  // dp_i - (d_i - lam), from wave 0
+  __shared__ double dsh[64 * NS];  // dm_i, from wave 1
+  __shared__ double part2[2];
+  __shared__ int rsh;
   const int c = blockIdx.x;
-  if (c >= keep[0]) return;
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  if (c >= keep[0]) {  // unused column: zero (the polar step multiplies it by 0)
+    for (int i = threadIdx.x; i < k; i += 128) Z[i + (int64_t)c * ldz] = 0.0;
+    return;
+  }
   const int idx = order[c];
   const double nrmT = bounds[3];
   const double small = DBL_EPSILON * fmax(nrmT, DBL_MIN);
   if (idx > 0 && lam[idx] - lam[idx - 1] <= 4.0 * DBL_EPSILON * nrmT) return;  // a tie
   const double lamq = lam[idx];
-  const int lane = threadIdx.x;
-  double dn[NS], en[NS], rdp[NS], rdm[NS], gam[NS], z[NS];
+  double dn[NS], en[NS], rp[NS], z[NS];
 #pragma unroll
   for (int m = 0; m < NS; ++m) {
     const int i = 64 * m + lane;
     dn[m] = (i < k) ? d[i] - lamq : 0.0;
     en[m] = (i + 1 < k) ? e[i] : 0.0;
-    rdp[m] = rdm[m] = gam[m] = z[m] = 0.0;
+    rp[m] = z[m] = 0.0;
   }
   auto guard = [&](double p) { return (fabs(p) < small) ? copysign(small, p) : p; };
-  // forward sweep: dp (kept as 1 / dp), up the rows
-  {
+  if (w == 0) {
+    // forward: dp (kept as 1 / dp); gamma part dp_i - (d_i - lam) into LDS
     double ep = 0.0, rprev = 0.0;
 #pragma unroll
     for (int m = 0; m < NS; ++m) {
+      double gm = 0.0;
       for (int j = 0; j < 64; ++j) {
         const int i = 64 * m + j;
         if (i >= k) break;
         const double di = lane_read_f64(dn[m], j);
         const double p = guard(di - ep * ep * rprev);
-        const double rp = 1.0 / p;
-        rdp[m] = (lane == j) ? rp : rdp[m];
-        gam[m] = (lane == j) ? p - di : gam[m];  // dp_i - (d_i - lam); dm_i is added below
+        const double r = rcp_f64(p);
+        rp[m] = (lane == j) ? r : rp[m];
+        gm = (lane == j) ? p - di : gm;
         ep = lane_read_f64(en[m], j);
-        rprev = rp;
+        rprev = r;
       }
+      gsh[64 * m + lane] = gm;
     }
-  }
-  // backward sweep: dm (kept as 1 / dm), down the rows
-  {
+  } else {
+    // backward: dm (kept as 1 / dm)
     double rprev = 0.0;
+    double dmv[NS];
+#pragma unroll
+    for (int m = 0; m < NS; ++m) dmv[m] = 0.0;
 #pragma unroll
     for (int m = NS - 1; m >= 0; --m) {
       for (int j = 63; j >= 0; --j) {
@@ -848,34 +879,42 @@ __global__ __launch_bounds__(64) void twist_kernel(const double* __restrict__ d,
         const double di = lane_read_f64(dn[m], j);
         const double ei = lane_read_f64(en[m], j);  // coupling of rows i and i + 1 (0 for the last)
         const double p = guard(di - ei * ei * rprev);
-        const double rp = 1.0 / p;
-        rdm[m] = (lane == j) ? rp : rdm[m];
-        gam[m] = (lane == j) ? gam[m] + p : gam[m];
-        rprev = rp;
+        const double r = rcp_f64(p);
+        rp[m] = (lane == j) ? r : rp[m];
+        dmv[m] = (lane == j) ? p : dmv[m];
+        rprev = r;
       }
     }
-  }
-  // twist r = argmin |gamma_i| (lowest i among equals)
-  double best = DBL_MAX;
-  int bi = 0x7fffffff;
 #pragma unroll
-  for (int m = 0; m < NS; ++m) {
-    const int i = 64 * m + lane;
-    const double g = fabs(gam[m]);
-    if (i < k && (g < best || (g == best && i < bi))) { best = g; bi = i; }
+    for (int m = 0; m < NS; ++m) dsh[64 * m + lane] = dmv[m];
   }
-  for (int off = 32; off >= 1; off >>= 1) {
-    const double ob = __shfl_xor(best, off, 64);
-    const int oi = __shfl_xor(bi, off, 64);
-    if (ob < best || (ob == best && oi < bi)) { best = ob; bi = oi; }
+  __syncthreads();  // both parts of gamma are in LDS
+  // twist r = argmin |gamma_i| (lowest i among equals), by wave 1
+  if (w == 1) {
+    double best = DBL_MAX;
+    int bi = 0x7fffffff;
+#pragma unroll
+    for (int m = 0; m < NS; ++m) {
+      const int i = 64 * m + lane;
+      const double g = fabs(gsh[i] + dsh[i]);
+      if (i < k && (g < best || (g == best && i < bi))) { best = g; bi = i; }
+    }
+    for (int off = 32; off >= 1; off >>= 1) {
+      const double ob = __shfl_xor(best, off, 64);
+      const int oi = __shfl_xor(bi, off, 64);
+      if (ob < best || (ob == best && oi < bi)) { best = ob; bi = oi; }
+    }
+    if (lane == 0) rsh = bi;
   }
-  const int r = bi;
-  // z_r = 1 and the two sweeps out of the twist; a running rescale keeps the
-  // entries in range (|z| grows at most where the pivots are tiny)
+  __syncthreads();
+  const int r = rsh;
   const int rm = r >> 6, rl = r & 63;
+  // z_r = 1 (wave 0 holds it); z below the twist by wave 0 (1 / dp), above by
+  // wave 1 (1 / dm); a running rescale keeps the entries in range
+  double scale_pow = 0.0;  // number of 1e-150 rescales of this wave's part
+  if (w == 0) {
 #pragma unroll
-  for (int m = 0; m < NS; ++m) z[m] = (m == rm && lane == rl) ? 1.0 : 0.0;
-  {
+    for (int m = 0; m < NS; ++m) z[m] = (m == rm && lane == rl) ? 1.0 : 0.0;
     double zc = 1.0;  // z_{i+1}
 #pragma unroll
     for (int m = NS - 1; m >= 0; --m) {
@@ -883,27 +922,30 @@ __global__ __launch_bounds__(64) void twist_kernel(const double* __restrict__ d,
         const int i = 64 * m + j;
         if (i >= r) continue;
         const double ei = lane_read_f64(en[m], j);
-        const double ri = lane_read_f64(rdp[m], j);
+        const double ri = lane_read_f64(rp[m], j);
         zc = -ei * zc * ri;
         z[m] = (lane == j) ? zc : z[m];
         if (fabs(zc) > 1e150) {  // uniform
 #pragma unroll
           for (int q = 0; q < NS; ++q) z[q] *= 1e-150;
           zc *= 1e-150;
+          scale_pow += 1.0;
         }
       }
     }
-  }
-  {
+  } else {
     double zc = 1.0;  // z_{i-1}
-    double ep = (r < 64 * NS) ? lane_read_f64(en[rm], rl) : 0.0;  // e_r
+    double ep = lane_read_f64(en[0], 0);
+#pragma unroll
+    for (int m = 0; m < NS; ++m)
+      if (m == rm) ep = lane_read_f64(en[m], rl);  // e_r
 #pragma unroll
     for (int m = 0; m < NS; ++m) {
       for (int j = 0; j < 64; ++j) {
         const int i = 64 * m + j;
         if (i <= r) continue;
         if (i >= k) break;
-        const double ri = lane_read_f64(rdm[m], j);
+        const double ri = lane_read_f64(rp[m], j);
         zc = -ep * zc * ri;
         z[m] = (lane == j) ? zc : z[m];
         ep = lane_read_f64(en[m], j);
@@ -911,19 +953,89 @@ __global__ __launch_bounds__(64) void twist_kernel(const double* __restrict__ d,
 #pragma unroll
           for (int q = 0; q < NS; ++q) z[q] *= 1e-150;
           zc *= 1e-150;
+          scale_pow += 1.0;
         }
       }
     }
   }
-  double part = 0.0;
+  // the two parts share z_r = 1; a part that was rescaled is scaled back
+  // relative to the other before the norm
+  __shared__ double spow[2];
+  if (lane == 0) spow[w] = scale_pow;
+  __syncthreads();
+  const double mine = spow[w], other = spow[1 - w];
+  const double rel = (mine >= other) ? 1.0 : pow(1e-150, other - mine);
 #pragma unroll
-  for (int m = 0; m < NS; ++m) part += z[m] * z[m];
-  part = wave_sum_f64(part);
-  const double inv = (part > 0.0) ? 1.0 / sqrt(part) : 0.0;
+  for (int m = 0; m < NS; ++m) z[m] *= rel;
+  double sq = 0.0;
+#pragma unroll
+  for (int m = 0; m < NS; ++m) sq += z[m] * z[m];
+  sq = wave_sum_f64(sq);
+  if (lane == 0) part2[w] = sq;
+  __syncthreads();
+  const double tot = part2[0] + part2[1];
+  const double inv = (tot > 0.0) ? 1.0 / sqrt(tot) : 0.0;
 #pragma unroll
   for (int m = 0; m < NS; ++m) {
     const int i = 64 * m + lane;
-    if (i < k) Z[i + (int64_t)c * ldz] = z[m] * inv;
+    const bool mine_row = (w == 0) ? (i <= r) : (i > r);
+    if (i < k && mine_row) Z[i + (int64_t)c * ldz] = z[m] * inv;
+  }
+}
+
+// Polar (Newton-Schulz) orthonormalisation of the clusters, by GEMMs: with
+// G = Z^T Z, Z <- Z B, B = I + (same cluster ? (I - G) / 2 : 0), twice.  A
+// cluster whose vectors are nearly orthonormal (len * max |G - I| below
+// kPolarTol, the usual case: inverse-iteration and twisted vectors are off
+// by O(eps ||T|| / gap)) then has ||Z^T Z - I|| ~ (3/4)^3 kPolarTol^4, far
+// below roundoff; the others (cl_fail set) keep their vectors for modified
+// Gram-Schmidt.  The polar factor mixes a cluster's vectors least.
+constexpr double kPolarTol = 1e-4;
+
+// cl_of[col] = cluster of kept column col (-1: none of two or more members);
+// cl_fail cleared.  One block.
+__global__ void cluster_index_kernel(int ncol, const int* clusters, const int* cl_count, const int* pos_of,
+                                     int* cl_of, int* cl_fail) {
+  for (int c = threadIdx.x; c < ncol; c += blockDim.x) {
+    cl_of[c] = -1;
+    cl_fail[c] = 0;
+  }
+  __syncthreads();
+  const int nc = cl_count[0];
+  for (int id = threadIdx.x; id < nc; id += blockDim.x) {
+    const int start = clusters[2 * id], len = clusters[2 * id + 1];
+    if (len < 2) continue;
+    for (int q = 0; q < len; ++q) {
+      const int col = pos_of[start + q];
+      if (col >= 0 && col < ncol) cl_of[col] = id;
+    }
+  }
+}
+
+// cl_fail[id] |= 1 when a cluster's Gram matrix is not close enough to I.
+__global__ void polar_check_kernel(const double* G, int ncol, const int* cl_of, const int* clusters,
+                                   int* cl_fail) {
+  const int64_t total = (int64_t)ncol * ncol;
+  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    const int i = (int)(idx % ncol), j = (int)(idx / ncol);
+    const int ci = cl_of[i];
+    if (ci < 0 || ci != cl_of[j]) continue;
+    const double dev = fabs(G[idx] - (i == j ? 1.0 : 0.0));
+    if (!(dev * clusters[2 * ci + 1] < kPolarTol)) atomicOr(&cl_fail[ci], 1);
+  }
+}
+
+// B = I + (i, j in one cluster that passed ? (I - G) / 2 : 0)
+__global__ void polar_b_kernel(const double* G, int ncol, const int* cl_of, const int* cl_fail, double* B) {
+  const int64_t total = (int64_t)ncol * ncol;
+  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    const int i = (int)(idx % ncol), j = (int)(idx / ncol);
+    const int ci = cl_of[i];
+    const double dl = (i == j) ? 1.0 : 0.0;
+    const bool live = ci >= 0 && ci == cl_of[j] && !cl_fail[ci];
+    B[idx] = live ? dl + 0.5 * (dl - G[idx]) : dl;
   }
 }
 
@@ -1007,14 +1119,14 @@ __device__ void orth_cluster(int k, int start, int len, const int* pos_of, doubl
 }
 
 __global__ __launch_bounds__(1024) void orth_kernel(int k, const int* clusters, const int* cl_count,
-                                                    const int* pos_of, double* Z, int64_t ldz,
-                                                    int lds_doubles) {
+                                                    const int* pos_of, const int* cl_fail, double* Z,
+                                                    int64_t ldz, int lds_doubles) {
   extern __shared__ double zs[];
   __shared__ double nrm[2];  // squared norm of the pivot of step j in nrm[j & 1]
   const int cl = blockIdx.x;
   if (cl >= cl_count[0]) return;
   const int start = clusters[2 * cl], len = clusters[2 * cl + 1];
-  if (len < 2) return;
+  if (len < 2 || !cl_fail[cl]) return;
   if ((int64_t)len * k <= (int64_t)lds_doubles) orth_cluster<true>(k, start, len, pos_of, Z, ldz, zs, nrm);
   else orth_cluster<false>(k, start, len, pos_of, Z, ldz, zs, nrm);
 }
@@ -1024,8 +1136,7 @@ __global__ __launch_bounds__(1024) void orth_kernel(int k, const int* clusters, 
 // chunk of kBtChunk reflectors (with the implicit unit entry) and z in LDS,
 // so the reflectors are read from HBM once per block and every wave applies
 // them with wave reductions only; otherwise z stays in its output column and
-// the reflectors are read from A.  Also fixes the sign so that the largest
-// |entry| is positive (the first one on ties).
+// the reflectors are read from A.  (Z == nullptr stands for I, which forms Q.)
 constexpr int kBtCols = 4;
 constexpr int kBtChunk = 16;
 constexpr int kBtLdsMaxK = 960;  // LDS staging up to this k (20 k doubles)
@@ -1034,20 +1145,21 @@ template <bool LDS>
 __global__ __launch_bounds__(64 * kBtCols) void backtr_kernel(const double* A, int64_t lda,
                                                               const double* tau, int k,
                                                               const double* Z, int64_t ldz,
-                                                              const int64_t* keep, double* V,
-                                                              int64_t ldv) {
+                                                              const int64_t* keep, int ncols,
+                                                              double* V, int64_t ldv) {
   constexpr bool use_lds = LDS;
   extern __shared__ double bsh[];  // z of the block's columns, then a chunk of reflectors
   __shared__ double tch[kBtChunk];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int c = blockIdx.x * kBtCols + wv;
-  const bool active = c < keep[0];  // wave-uniform; no early return (barriers below)
+  // columns: ncols, or keep[0] when ncols < 0; Z == nullptr stands for I
+  const bool active = c < (ncols >= 0 ? (int64_t)ncols : keep[0]);  // wave-uniform; no early return
   double* z;
   if constexpr (LDS) z = bsh + (int64_t)wv * k;
   else z = V + (int64_t)c * ldv;
   double* vch = bsh + (int64_t)kBtCols * k;
   if (active)
-    for (int i = lane; i < k; i += 64) z[i] = Z[i + (int64_t)c * ldz];
+    for (int i = lane; i < k; i += 64) z[i] = Z ? Z[i + (int64_t)c * ldz] : (i == c ? 1.0 : 0.0);
   for (int jhi = k - 3; jhi >= 0; jhi -= kBtChunk) {
     const int jlo = max(0, jhi - kBtChunk + 1);
     if (use_lds) {
@@ -1084,7 +1196,15 @@ __global__ __launch_bounds__(64 * kBtCols) void backtr_kernel(const double* A, i
     }
   }
   if (!active) return;
-  // sign convention: largest |entry| positive (first one on ties)
+  for (int i = lane; i < k; i += 64) V[i + (int64_t)c * ldv] = z[i];
+}
+
+// Sign convention of the eigenvectors: in each column c < keep[0] of V the
+// largest |entry| is positive (the first one on ties).  One wave per column.
+__global__ __launch_bounds__(64) void sign_columns_kernel(double* V, int64_t ldv, int k, const int64_t* keep) {
+  const int c = blockIdx.x, lane = threadIdx.x;
+  if (c >= keep[0]) return;
+  double* z = V + (int64_t)c * ldv;
   double best = -1.0;
   int bi = k;
   for (int i = lane; i < k; i += 64) {
@@ -1096,8 +1216,8 @@ __global__ __launch_bounds__(64 * kBtCols) void backtr_kernel(const double* A, i
     const int oi = __shfl_xor(bi, off, 64);
     if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
   }
-  const double sgn = (bi < k && z[bi] < 0.0) ? -1.0 : 1.0;
-  for (int i = lane; i < k; i += 64) V[i + (int64_t)c * ldv] = sgn * z[i];
+  if (bi < k && z[bi] < 0.0)
+    for (int i = lane; i < k; i += 64) z[i] = -z[i];
 }
 
 }  // namespace
@@ -1110,6 +1230,10 @@ size_t syev_workspace(int64_t k) {
   b += (size_t)k * 2 * sizeof(int) + 256;
   b += (size_t)k * kInvitArrays * k * sizeof(double) + 256;  // inverse-iteration arrays
   b += (size_t)k * k * sizeof(double) + 256;      // Zt
+  b += 3 * ((size_t)k * k * sizeof(double) + 256);  // polar steps: G, B, Z1
+  b += 2 * ((size_t)k * sizeof(int) + 256);          // cl_of, cl_fail
+  b += gemm_f64_workspace(k, k, k);
+  b += (size_t)k * k * sizeof(double) + 256;      // Q
   return b;
 }
 
@@ -1158,13 +1282,26 @@ void syev_trunc_f64(hipStream_t s, int64_t k, const double* M, int64_t ldm, doub
     }
     DME_HIP(hipGetLastError());
   }
+  // Q = H_0 ... H_{k-3} (the tridiagonalisation's reflectors applied to I) on
+  // the second stream, beside the eigenvalue and eigenvector work below
+  double* Qm = ws.get<double>((size_t)k * k);
+  AuxStream& ax = aux_stream();
+  DME_HIP(hipStreamWaitEvent(ax.s2, ax.record(s), 0));
+  {
+    const dim3 bt_grid((unsigned)cdiv(k, kBtCols));
+    if (k <= kBtLdsMaxK)
+      hipLaunchKernelGGL(backtr_kernel<true>, bt_grid, dim3(64 * kBtCols),
+                         (size_t)(kBtCols + kBtChunk) * k * sizeof(double), ax.s2, A, k, tau, ki,
+                         (const double*)nullptr, k, keep_dev, ki, Qm, k);
+    else
+      hipLaunchKernelGGL(backtr_kernel<false>, bt_grid, dim3(64 * kBtCols), 0, ax.s2, A, k, tau, ki,
+                         (const double*)nullptr, k, keep_dev, ki, Qm, k);
+    DME_HIP(hipGetLastError());
+  }
+  const hipEvent_t q_done = ax.record(ax.s2);
   hipLaunchKernelGGL(tri_prep_kernel, dim3(1), dim3(256), 0, s, d, e, ki, e2, bounds);
   DME_HIP(hipGetLastError());
-  if (k <= kBisLdsMaxK)
-    hipLaunchKernelGGL(bisect_kernel<true>, dim3((unsigned)k), dim3(64), (size_t)2 * k * sizeof(double), s, d,
-                       e2, ki, bounds, lam);
-  else
-    hipLaunchKernelGGL(bisect_kernel<false>, dim3((unsigned)k), dim3(64), 0, s, d, e2, ki, bounds, lam);
+  hipLaunchKernelGGL(bisect_kernel<false>, dim3((unsigned)k), dim3(64), 0, s, d, e2, ki, bounds, lam);
   DME_HIP(hipGetLastError());
   hipLaunchKernelGGL(select_kernel, dim3(1), dim3(kSelT), 0, s, lam, ki, tol, max_keep, bounds, order,
                      pos_of, lam_out, clusters, cl_count, keep_dev, flag_dev);
@@ -1176,7 +1313,7 @@ void syev_trunc_f64(hipStream_t s, int64_t k, const double* M, int64_t ldm, doub
   switch (cdiv(k, 64)) {
 #define DME_TWIST(NS)                                                                             \
   case NS:                                                                                        \
-    hipLaunchKernelGGL(twist_kernel<NS>, dim3(nkeep), dim3(64), 0, s, d, e, ki, lam, order, keep_dev, \
+    hipLaunchKernelGGL(twist_kernel<NS>, dim3(nkeep), dim3(128), 0, s, d, e, ki, lam, order, keep_dev, \
                        bounds, Zt, k);                                                            \
     break;
     DME_TWIST(1) DME_TWIST(2) DME_TWIST(3) DME_TWIST(4) DME_TWIST(5) DME_TWIST(6) DME_TWIST(7)
@@ -1192,19 +1329,43 @@ void syev_trunc_f64(hipStream_t s, int64_t k, const double* M, int64_t ldm, doub
     hipLaunchKernelGGL(invit_kernel<false>, dim3(nkeep), dim3(64), 0, s, d, e, ki, lam, order, keep_dev,
                        bounds, work, Zt, k, ties_only);
   DME_HIP(hipGetLastError());
-  // cluster staging in LDS: up to 144 KiB, never more than the whole k x k set
-  const int64_t orth_lds = std::min<int64_t>(k * k, (144 * 1024) / (int64_t)sizeof(double));
-  hipLaunchKernelGGL(orth_kernel, dim3((unsigned)k), dim3(1024), (size_t)orth_lds * sizeof(double), s,
-                     ki, clusters, cl_count, pos_of, Zt, k, (int)orth_lds);
-  DME_HIP(hipGetLastError());
-  const dim3 bt_grid((unsigned)cdiv(std::min<int64_t>(k, max_keep), kBtCols));
-  if (k <= kBtLdsMaxK)
-    hipLaunchKernelGGL(backtr_kernel<true>, bt_grid, dim3(64 * kBtCols),
-                       (size_t)(kBtCols + kBtChunk) * k * sizeof(double), s, A, k, tau, ki, Zt, k, keep_dev,
-                       V_out, ldv);
-  else
-    hipLaunchKernelGGL(backtr_kernel<false>, bt_grid, dim3(64 * kBtCols), 0, s, A, k, tau, ki, Zt, k,
-                       keep_dev, V_out, ldv);
+  // clusters: two polar steps where the vectors are nearly orthonormal,
+  // modified Gram-Schmidt for the rest
+  {
+    const int nc = (int)nkeep;
+    double* G = ws.get<double>((size_t)nc * nc);
+    double* Bm = ws.get<double>((size_t)nc * nc);
+    double* Z1 = ws.get<double>((size_t)k * nc);
+    int* cl_of = ws.get<int>(k);
+    int* cl_fail = ws.get<int>(k);
+    const size_t mark = ws.used;
+    const unsigned gb = (unsigned)std::max<int64_t>(1, std::min<int64_t>(cdiv((int64_t)nc * nc, 256), 1024));
+    hipLaunchKernelGGL(cluster_index_kernel, dim3(1), dim3(256), 0, s, nc, clusters, cl_count, pos_of, cl_of,
+                       cl_fail);
+    DME_HIP(hipGetLastError());
+    gemm_f64(s, 'T', 'N', nc, nc, k, 1.0, Zt, k, Zt, k, 0.0, G, nc, &ws);
+    ws.used = mark;
+    hipLaunchKernelGGL(polar_check_kernel, dim3(gb), dim3(256), 0, s, G, nc, cl_of, clusters, cl_fail);
+    hipLaunchKernelGGL(polar_b_kernel, dim3(gb), dim3(256), 0, s, G, nc, cl_of, cl_fail, Bm);
+    DME_HIP(hipGetLastError());
+    gemm_f64(s, 'N', 'N', k, nc, nc, 1.0, Zt, k, Bm, nc, 0.0, Z1, k, &ws);
+    ws.used = mark;
+    gemm_f64(s, 'T', 'N', nc, nc, k, 1.0, Z1, k, Z1, k, 0.0, G, nc, &ws);
+    ws.used = mark;
+    hipLaunchKernelGGL(polar_b_kernel, dim3(gb), dim3(256), 0, s, G, nc, cl_of, cl_fail, Bm);
+    DME_HIP(hipGetLastError());
+    gemm_f64(s, 'N', 'N', k, nc, nc, 1.0, Z1, k, Bm, nc, 0.0, Zt, k, &ws);
+    ws.used = mark;
+    // cluster staging in LDS: up to 144 KiB, never more than the whole k x k set
+    const int64_t orth_lds = std::min<int64_t>(k * k, (144 * 1024) / (int64_t)sizeof(double));
+    hipLaunchKernelGGL(orth_kernel, dim3((unsigned)k), dim3(1024), (size_t)orth_lds * sizeof(double), s,
+                       ki, clusters, cl_count, pos_of, cl_fail, Zt, k, (int)orth_lds);
+    DME_HIP(hipGetLastError());
+  }
+  // V = Q Z with Q formed beside the eigenvalue work
+  DME_HIP(hipStreamWaitEvent(s, q_done, 0));
+  gemm_f64(s, 'N', 'N', k, (int64_t)nkeep, k, 1.0, Qm, k, Zt, k, 0.0, V_out, ldv, &ws);
+  hipLaunchKernelGGL(sign_columns_kernel, dim3(nkeep), dim3(64), 0, s, V_out, ldv, ki, keep_dev);
   DME_HIP(hipGetLastError());
 }
 

@@ -432,27 +432,6 @@ size_t tsqr_workspace(int64_t n, int64_t k) {
   return b + 4096;
 }
 
-namespace {
-
-// A second stream and a ring of events per host thread and device, for the
-// look-ahead of the panel factorisation (default priority, created on first
-// use; they are not destroyed, since a thread's end may come after the
-// runtime's).
-struct AuxStream {
-  int device = -1;
-  hipStream_t s2 = nullptr;
-  std::vector<hipEvent_t> ev;
-  size_t next = 0;
-  // A recorded event is only waited on by calls enqueued right after its
-  // record, so a ring much longer than the waits in flight can be reused.
-  hipEvent_t record(hipStream_t st) {
-    hipEvent_t e = ev[next];
-    next = (next + 1) % ev.size();
-    DME_HIP(hipEventRecord(e, st));
-    return e;
-  }
-};
-
 AuxStream& aux_stream() {
   static thread_local std::vector<std::unique_ptr<AuxStream>> per_device;
   int dev = 0;
@@ -467,8 +446,6 @@ AuxStream& aux_stream() {
   per_device.push_back(std::move(a));
   return *per_device.back();
 }
-
-}  // namespace
 
 // Panels are factored on s.  Q^T of panel p reaches the next panel's columns
 // on s (they are what panel p + 1 factors next) and the columns beyond on a
