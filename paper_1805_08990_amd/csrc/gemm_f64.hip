@@ -153,8 +153,20 @@ __global__ void splitk_reduce_kernel(int M, int N, int nsplit, double alpha,
   const int64_t total = (int64_t)M * N;
   for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
        idx += (int64_t)gridDim.x * blockDim.x) {
-    double s = 0.0;
-    for (int z = 0; z < nsplit; ++z) s += partial[(int64_t)z * total + idx];
+    // eight loads in flight, four chains (the loop is latency-bound otherwise)
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    int z = 0;
+    for (; z + 8 <= nsplit; z += 8) {
+      double v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = partial[(int64_t)(z + u) * total + idx];
+      s0 += v[0] + v[4];
+      s1 += v[1] + v[5];
+      s2 += v[2] + v[6];
+      s3 += v[3] + v[7];
+    }
+    for (; z < nsplit; ++z) s0 += partial[(int64_t)z * total + idx];
+    const double s = (s0 + s1) + (s2 + s3);
     const int64_t m = idx % M, n = idx / M;
     double* c = C + m + n * ldc;
     const double out = alpha * s;
@@ -306,8 +318,20 @@ __global__ void skinny_reduce_kernel(int M, int N, int nsplit, double alpha,
   const int64_t total = (int64_t)M * N;
   for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
        idx += (int64_t)gridDim.x * blockDim.x) {
-    double s = 0.0;
-    for (int z = 0; z < nsplit; ++z) s += partial[(int64_t)z * total + idx];
+    // eight loads in flight, four chains (the loop is latency-bound otherwise)
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    int z = 0;
+    for (; z + 8 <= nsplit; z += 8) {
+      double v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = partial[(int64_t)(z + u) * total + idx];
+      s0 += v[0] + v[4];
+      s1 += v[1] + v[5];
+      s2 += v[2] + v[6];
+      s3 += v[3] + v[7];
+    }
+    for (; z < nsplit; ++z) s0 += partial[(int64_t)z * total + idx];
+    const double s = (s0 + s1) + (s2 + s3);
     const int64_t m = idx % M, n = idx / M;
     double* c = C + m + n * ldc;
     const double out = alpha * s;

@@ -69,8 +69,10 @@ def test_dre_quadrant_random_C(ctx):
     check(ctx, p)
 
 
-def test_dre_nonsymmetric_A_with_P0(ctx):
-    n = 60
+@pytest.mark.parametrize("n", [60, 61, 1001])
+def test_dre_nonsymmetric_A_with_P0(ctx, n):
+    """Odd n and row counts off the kernels' 32- and 64-row tiles (ragged tails,
+    unaligned column starts in the tall-skinny projections)."""
     A = wl.random_nonsymmetric(n, seed=3, scale=5.0)
     C = wl.random_C(3, n, seed=4)
     L0, D0 = wl.random_lowrank_P0(n, 5, seed=6)
