@@ -441,6 +441,7 @@ AuxStream& aux_stream() {
   auto a = std::make_unique<AuxStream>();
   a->device = dev;
   DME_HIP(hipStreamCreateWithFlags(&a->s2, hipStreamNonBlocking));
+  DME_HIP(hipStreamCreateWithFlags(&a->s3, hipStreamNonBlocking));
   a->ev.resize(64);
   for (hipEvent_t& e : a->ev) DME_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
   per_device.push_back(std::move(a));
@@ -448,10 +449,11 @@ AuxStream& aux_stream() {
 }
 
 // Panels are factored on s.  Q^T of panel p reaches the next panel's columns
-// on s (they are what panel p + 1 factors next) and the columns beyond on a
-// second stream, which waits for each tree level's factor and runs behind
-// the factorisation of the following panels; s waits for that stream before
-// it touches those columns (and before returning).
+// on a third stream, level by level as the tree levels are factored (they are
+// what panel p + 1 factors next, so s waits for them), and the columns beyond
+// on a second stream, which waits for each tree level's factor and runs
+// behind the factorisation of the following panels; the next panel's share of
+// the third stream waits for that stream, and so does s before returning.
 void tsqr_factor(hipStream_t s, int64_t n, int64_t k, double* W, TsqrState& st, Arena& ws) {
   DME_REQUIRE(n < (int64_t(1) << 31), DME_EINVAL, "tsqr: n too large");
   const int64_t ld = n;
@@ -515,12 +517,18 @@ void tsqr_factor(hipStream_t s, int64_t n, int64_t k, double* W, TsqrState& st, 
       }
       aux_used = true;
     }
-    // Q^T on the next panel's columns, on s, after the previous panels' share
-    // of the second stream (it updated these columns too)
+    // Q^T on the next panel's columns, on the third stream, level l as soon as
+    // leaf level l is done (beside leaf level l + 1 on s) and after the
+    // previous panels' share of the second stream (it updated these columns
+    // too); the next panel's leaves wait for the last level
     if (near > 0) {
-      if (rest_done) DME_HIP(hipStreamWaitEvent(s, rest_done, 0));
+      if (rest_done) DME_HIP(hipStreamWaitEvent(ax.s3, rest_done, 0));
       double* C = W + c0 + (c0 + pb) * ld;
-      for (int l = 0; l < P.nlev; ++l) launch_apply(s, P.lev[l], l, pb, 1, lr, C, ld, near);
+      for (int l = 0; l < P.nlev; ++l) {
+        DME_HIP(hipStreamWaitEvent(ax.s3, lev_done[l], 0));
+        launch_apply(ax.s3, P.lev[l], l, pb, 1, lr, C, ld, near);
+      }
+      DME_HIP(hipStreamWaitEvent(s, ax.record(ax.s3), 0));
     }
     if (far > 0) rest_done = ax.record(ax.s2);
     st.panels.push_back(P);
