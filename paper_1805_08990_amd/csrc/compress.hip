@@ -17,6 +17,9 @@
 // directions where Y is (numerically) rank-deficient after the projection.
 #include "tsqr.h"
 
+#include <thread>
+#include <vector>
+
 namespace dme {
 namespace {
 
@@ -281,6 +284,60 @@ __global__ __launch_bounds__(256) void ts_update_kernel(int64_t n, int q, int r,
   }
 }
 
+// The compression's rank goes to the host through a pinned, coherent slot:
+// one thread copies it and then bumps the slot's sequence number, and the host
+// polls that number (a stream synchronisation sleeps, which costs tens of
+// microseconds of idle device time per compression).
+struct RankSlot {
+  int64_t value;
+  int64_t seq;
+};
+
+__global__ void rank_to_host_kernel(const int64_t* __restrict__ src, RankSlot* slot, int64_t seq) {
+  if (threadIdx.x == 0) {
+    const int64_t v = *(volatile const int64_t*)src;
+    __hip_atomic_store(&slot->value, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    __hip_atomic_store(&slot->seq, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+  }
+}
+
+int64_t rank_to_host(hipStream_t s, const int64_t* rank_dev) {
+  struct Slots {
+    int device = -1;
+    RankSlot* slot = nullptr;
+    int64_t seq = 0;
+  };
+  static thread_local std::vector<Slots> per_device;  // pinned slots are never freed
+  int dev = 0;
+  DME_HIP(hipGetDevice(&dev));
+  Slots* sl = nullptr;
+  for (Slots& x : per_device)
+    if (x.device == dev) sl = &x;
+  if (!sl) {
+    Slots x;
+    x.device = dev;
+    DME_HIP(hipHostMalloc((void**)&x.slot, sizeof(RankSlot), hipHostMallocCoherent));
+    x.slot->value = 0;
+    x.slot->seq = 0;
+    per_device.push_back(x);
+    sl = &per_device.back();
+  }
+  const int64_t seq = ++sl->seq;
+  hipLaunchKernelGGL(rank_to_host_kernel, dim3(1), dim3(64), 0, s, rank_dev, sl->slot, seq);
+  DME_HIP(hipGetLastError());
+  // poll for up to ~50 ms, then fall back to a synchronisation (which also
+  // reports an error of the stream)
+  for (int it = 0; it < 1000000; ++it) {
+    if (__atomic_load_n(&sl->slot->seq, __ATOMIC_ACQUIRE) == seq) return __atomic_load_n(&sl->slot->value, __ATOMIC_RELAXED);
+    if (it >= 1000) std::this_thread::yield();
+    if (it >= 20000) break;
+  }
+  DME_HIP(hipStreamSynchronize(s));
+  DME_REQUIRE(__atomic_load_n(&sl->slot->seq, __ATOMIC_ACQUIRE) == seq, DME_EINTERNAL,
+              "compression: rank not delivered to the host");
+  return __atomic_load_n(&sl->slot->value, __ATOMIC_RELAXED);
+}
+
 inline unsigned blocks_for(int64_t total) {
   return (unsigned)std::max<int64_t>(1, std::min<int64_t>(cdiv(total, 256), 8192));
 }
@@ -342,9 +399,7 @@ int64_t compress_f64(hipStream_t s, int64_t n, int64_t k, double* W, const doubl
   // ---------------- eigenpairs with truncation
   ws.used = mark_q;
   syev_trunc_f64(s, kr, S, kr, tol, std::min(max_rank, kr), lam, V, kr, rank_dev, flag_dev, ws);
-  int64_t r = 0;
-  DME_HIP(hipMemcpyAsync(&r, rank_dev, sizeof(int64_t), hipMemcpyDeviceToHost, s));
-  DME_HIP(hipStreamSynchronize(s));
+  const int64_t r = rank_to_host(s, rank_dev);
   if (r <= 0) return 0;
   if (ldd <= 0) ldd = r;
 
@@ -434,9 +489,7 @@ int64_t compress_f64_lead(hipStream_t s, int64_t n, int64_t r, double* W, const 
 
   syev_trunc_f64(s, k, S, k, tol, std::min(max_rank, k), lam, V, k, rank_dev, flag_dev, ws);
   ws.used = mark_q;
-  int64_t rr = 0;
-  DME_HIP(hipMemcpyAsync(&rr, rank_dev, sizeof(int64_t), hipMemcpyDeviceToHost, s));
-  DME_HIP(hipStreamSynchronize(s));
+  const int64_t rr = rank_to_host(s, rank_dev);
   if (rr <= 0) return 0;
   if (ldd <= 0) ldd = rr;
 

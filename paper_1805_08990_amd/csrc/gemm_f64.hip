@@ -62,10 +62,9 @@ __global__ __launch_bounds__(kThreads) void gemm_f64_kernel(
       if (!TA) { ml = idx % BM; kl = idx / BM; }
       else     { kl = idx % BK; ml = idx / BK; }
       const int m = m0 + ml, k = k0 + kl;
-      // clamped address, masked value: the loads carry no branch
-      const int mc = min(m, M - 1), kc = min(k, kend - 1);
-      const double v = TA ? A[kc + (int64_t)mc * lda] : A[mc + (int64_t)kc * lda];
-      ra[i] = (m < M && k < kend) ? v : 0.0;
+      double v = 0.0;
+      if (m < M && k < kend) v = TA ? A[k + (int64_t)m * lda] : A[m + (int64_t)k * lda];
+      ra[i] = v;
     }
 #pragma unroll
     for (int i = 0; i < LB; ++i) {
@@ -74,9 +73,9 @@ __global__ __launch_bounds__(kThreads) void gemm_f64_kernel(
       if (!TB) { kl = idx % BK; nl = idx / BK; }
       else     { nl = idx % BN; kl = idx / BN; }
       const int n = n0 + nl, k = k0 + kl;
-      const int nc = min(n, N - 1), kc = min(k, kend - 1);
-      const double v = TB ? B[nc + (int64_t)kc * ldb] : B[kc + (int64_t)nc * ldb];
-      rb[i] = (n < N && k < kend) ? v : 0.0;
+      double v = 0.0;
+      if (n < N && k < kend) v = TB ? B[n + (int64_t)k * ldb] : B[k + (int64_t)n * ldb];
+      rb[i] = v;
     }
   };
   auto store = [&]() {
