@@ -204,7 +204,6 @@ size_t lu_solve_workspace(int64_t n);
 struct AuxStream {
   int device = -1;
   hipStream_t s2 = nullptr;
-  hipStream_t s3 = nullptr;  // a third stream, for short critical-path work beside s
   std::vector<hipEvent_t> ev;
   size_t next = 0;
   // A recorded event is only waited on by calls enqueued right after its

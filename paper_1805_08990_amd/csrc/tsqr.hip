@@ -63,16 +63,15 @@ __device__ inline int64_t phys_row(int64_t s, const LevelRows& lr) {
 // r_mode: 0 = R stays in place (single leaf of level 0); 1 = R_g stacked into
 // Rdst rows 32 g .. 32 g + 31 (zeros below the diagonal); 2 = R's upper
 // triangle written to Rdst (the panel's top rows in W).
-__global__ __launch_bounds__(kLT) void tsqr_leaf_kernel(double* mat, int64_t ld, int64_t M, int pb,
-                                                        double* Tout, double* Rdst, int64_t ld_r,
-                                                        int r_mode) {
+__device__ __forceinline__ void leaf_body(int bx, double* mat, int64_t ld, int64_t M, int pb, double* Tout,
+                                          double* Rdst, int64_t ld_r, int r_mode) {
   __shared__ double xb[2][kLG][kLRows];  // pivot column, [g][m]: 144-byte rows, 16-byte reads conflict-free
   __shared__ double piv[2][2];               // alpha and sigma^2 of the pivot column
   __shared__ double Zs[kTB][kTB + 1];        // Zs[c][j] = v_c^T v_j for c < j, zero elsewhere
   __shared__ double coef[kTB];               // tau of each reflector
   const int t = threadIdx.x;
   const int c = t / kLG, g = t % kLG;
-  const int64_t rbeg = (int64_t)blockIdx.x * kTLeaf;
+  const int64_t rbeg = (int64_t)bx * kTLeaf;
   const int rows = (int)min<int64_t>(kTLeaf, M - rbeg);
   const int nv = min(rows, pb);
   double* base = mat + rbeg;
@@ -118,7 +117,7 @@ __global__ __launch_bounds__(kLT) void tsqr_leaf_kernel(double* mat, int64_t ld,
   // before it.  Thread (c, g) sums over c2 = g + 16 q and keeps T(c, c2) for
   // those c2 in registers.  Formed one step after Zs(:, jj), beside the next
   // column step.  (The reads are unconditional; Zs is zero outside c2 < jj.)
-  double* To = Tout + (int64_t)blockIdx.x * kTB * kTB;
+  double* To = Tout + (int64_t)bx * kTB * kTB;
   double trow[kTB / kLG] = {0.0, 0.0};
   auto t_column = [&](int jj) {
     double s = 0.0;
@@ -205,7 +204,7 @@ __global__ __launch_bounds__(kLT) void tsqr_leaf_kernel(double* mat, int64_t ld,
 #pragma unroll
       for (int m = 0; m < kLHq; ++m) {
         const int i = g + kLG * m;
-        Rdst[(int64_t)blockIdx.x * kTB + i + (int64_t)c * ld_r] = (i <= c && i < rows) ? a[m] : 0.0;
+        Rdst[(int64_t)bx * kTB + i + (int64_t)c * ld_r] = (i <= c && i < rows) ? a[m] : 0.0;
       }
     } else if (r_mode == 2) {
 #pragma unroll
@@ -222,6 +221,12 @@ __global__ __launch_bounds__(kLT) void tsqr_leaf_kernel(double* mat, int64_t ld,
     const int jj = g + kLG * q;
     if (jj >= nv) To[c + jj * kTB] = 0.0;
   }
+}
+
+__global__ __launch_bounds__(kLT) void tsqr_leaf_kernel(double* mat, int64_t ld, int64_t M, int pb,
+                                                        double* Tout, double* Rdst, int64_t ld_r,
+                                                        int r_mode) {
+  leaf_body(blockIdx.x, mat, ld, M, pb, Tout, Rdst, ld_r, r_mode);
 }
 
 // C <- (I - V T' V^T) C for every leaf of one level, T' = T^T (trans: applies
@@ -245,10 +250,9 @@ constexpr int kTRuns = kTLeaf / kTB;        // 32-row runs per leaf (9)
 constexpr int kTHalfSteps = kTLeaf / 8;     // K-steps of 4 rows per row half (36)
 
 template <int LEVEL>
-__global__ __launch_bounds__(kTT) void tsqr_apply_kernel(const double* V, int64_t ldv, int64_t M,
-                                                         int pb, const double* Tin, int trans,
-                                                         LevelRows lr, double* C, int64_t ldc,
-                                                         int64_t ncols) {
+__device__ __forceinline__ void apply_body(int bx, int by, const double* V, int64_t ldv, int64_t M, int pb,
+                                           const double* Tin, int trans, const LevelRows& lr, double* C,
+                                           int64_t ldc, int64_t ncols) {
   __shared__ double Vs[kTLeaf][kTB + 1];
   __shared__ double Yp[2][kTB][kTB + 1];  // Y of each row half
   __shared__ double Zs[kTB][kTB + 1];
@@ -257,14 +261,14 @@ __global__ __launch_bounds__(kTT) void tsqr_apply_kernel(const double* V, int64_
   const int lane = t & 63, w = t >> 6;
   const int li = lane & 15, lk = lane >> 4;
   const int h = w >> 1, e = w & 1;
-  const int64_t rbeg = (int64_t)blockIdx.x * kTLeaf;
+  const int64_t rbeg = (int64_t)bx * kTLeaf;
   const int rows = (int)min<int64_t>(kTLeaf, M - rbeg);
   const int nv = min(rows, pb);
-  const int64_t col = (int64_t)blockIdx.y * kTB + e * 16 + li;
+  const int64_t col = (int64_t)by * kTB + e * 16 + li;
   const bool cok = col < ncols;
   // level-0 base row of each 32-row run (uniform over the block)
   int64_t rb[kTRuns];
-  bool full = rows == kTLeaf && (int64_t)blockIdx.y * kTB + kTB <= ncols;
+  bool full = rows == kTLeaf && (int64_t)by * kTB + kTB <= ncols;
 #pragma unroll
   for (int q = 0; q < kTRuns; ++q) {
     rb[q] = phys_row<LEVEL>(rbeg + kTB * q, lr);
@@ -309,7 +313,7 @@ __global__ __launch_bounds__(kTT) void tsqr_apply_kernel(const double* V, int64_
   if (h == 0) load_c(std::integral_constant<int, 0>{});
   else load_c(std::integral_constant<int, 1>{});
   {
-    const double* Tg = Tin + (int64_t)blockIdx.x * kTB * kTB;
+    const double* Tg = Tin + (int64_t)bx * kTB * kTB;
 #pragma unroll
     for (int m = 0; m < kTB * kTB / kTT; ++m) {
       const int idx = t + kTT * m;
@@ -386,6 +390,34 @@ __global__ __launch_bounds__(kTT) void tsqr_apply_kernel(const double* V, int64_
   else update(std::integral_constant<int, 1>{});
 }
 
+template <int LEVEL>
+__global__ __launch_bounds__(kTT) void tsqr_apply_kernel(const double* V, int64_t ldv, int64_t M,
+                                                         int pb, const double* Tin, int trans,
+                                                         LevelRows lr, double* C, int64_t ldc,
+                                                         int64_t ncols) {
+  apply_body<LEVEL>(blockIdx.x, blockIdx.y, V, ldv, M, pb, Tin, trans, lr, C, ldc, ncols);
+}
+
+// Two independent launches in one: blocks [0, nleaf) factor the leaves of one
+// tree level, the others apply Q^T of the level below to the next panel's
+// columns (block b -> leaf b % agx, column tile b / agx) with the first kTT
+// threads (the rest leave before any barrier of that part).
+template <int LEVEL>
+__global__ __launch_bounds__(kLT) void tsqr_leaf_apply_kernel(double* mat, int64_t ld, int64_t M, int pb,
+                                                              double* Tout, double* Rdst, int64_t ld_r,
+                                                              int r_mode, int nleaf, const double* V,
+                                                              int64_t ldv, int64_t MV, const double* Tin,
+                                                              LevelRows lr, double* C, int64_t ldc,
+                                                              int64_t ncols, int agx) {
+  if ((int)blockIdx.x < nleaf) {
+    leaf_body(blockIdx.x, mat, ld, M, pb, Tout, Rdst, ld_r, r_mode);
+    return;
+  }
+  if (threadIdx.x >= kTT) return;
+  const int b = (int)blockIdx.x - nleaf;
+  apply_body<LEVEL>(b % agx, b / agx, V, ldv, MV, pb, Tin, 1, lr, C, ldc, ncols);
+}
+
 void launch_apply(hipStream_t s, const TsqrLevel& L, int level, int pb, int trans, const LevelRows& lr,
                   double* C, int64_t ldc, int64_t ncols) {
   dim3 grid((unsigned)L.G, (unsigned)cdiv(ncols, kTB));
@@ -398,6 +430,25 @@ void launch_apply(hipStream_t s, const TsqrLevel& L, int level, int pb, int tran
     DME_TSQR_APPLY(0) DME_TSQR_APPLY(1) DME_TSQR_APPLY(2) DME_TSQR_APPLY(3)
     DME_TSQR_APPLY(4) DME_TSQR_APPLY(5) DME_TSQR_APPLY(6) DME_TSQR_APPLY(7)
 #undef DME_TSQR_APPLY
+    default: fail(DME_EINTERNAL, "tsqr: bad level");
+  }
+  DME_HIP(hipGetLastError());
+}
+
+// Leaves of level L (L.G blocks) and Q^T of level A (A.G x column tiles) in one launch.
+void launch_leaf_apply(hipStream_t s, const TsqrLevel& L, int pb, double* Rdst, int64_t ld_r, int r_mode,
+                       const TsqrLevel& A, int alevel, const LevelRows& lr, double* C, int64_t ldc,
+                       int64_t ncols) {
+  const int agx = A.G;
+  const unsigned nblk = (unsigned)(L.G + (int64_t)agx * cdiv(ncols, kTB));
+  switch (alevel) {
+#define DME_TSQR_LA(LV)                                                                                        \
+  case LV:                                                                                                     \
+    hipLaunchKernelGGL(tsqr_leaf_apply_kernel<LV>, dim3(nblk), dim3(kLT), 0, s, L.mat, L.ld, L.M, pb, L.T, Rdst, \
+                       ld_r, r_mode, L.G, A.mat, A.ld, A.M, A.T, lr, C, ldc, ncols, agx);                    \
+    break;
+    DME_TSQR_LA(0) DME_TSQR_LA(1) DME_TSQR_LA(2) DME_TSQR_LA(3) DME_TSQR_LA(4) DME_TSQR_LA(5) DME_TSQR_LA(6)
+#undef DME_TSQR_LA
     default: fail(DME_EINTERNAL, "tsqr: bad level");
   }
   DME_HIP(hipGetLastError());
@@ -441,7 +492,6 @@ AuxStream& aux_stream() {
   auto a = std::make_unique<AuxStream>();
   a->device = dev;
   DME_HIP(hipStreamCreateWithFlags(&a->s2, hipStreamNonBlocking));
-  DME_HIP(hipStreamCreateWithFlags(&a->s3, hipStreamNonBlocking));
   a->ev.resize(64);
   for (hipEvent_t& e : a->ev) DME_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
   per_device.push_back(std::move(a));
@@ -449,11 +499,11 @@ AuxStream& aux_stream() {
 }
 
 // Panels are factored on s.  Q^T of panel p reaches the next panel's columns
-// on a third stream, level by level as the tree levels are factored (they are
-// what panel p + 1 factors next, so s waits for them), and the columns beyond
-// on a second stream, which waits for each tree level's factor and runs
-// behind the factorisation of the following panels; the next panel's share of
-// the third stream waits for that stream, and so does s before returning.
+// on s (they are what panel p + 1 factors next), level l - 1 in the same
+// launch as the leaves of level l, and the columns beyond on a second stream,
+// which waits for each tree level's factor and runs behind the factorisation
+// of the following panels; s waits for that stream before it touches those
+// columns (and before returning).
 void tsqr_factor(hipStream_t s, int64_t n, int64_t k, double* W, TsqrState& st, Arena& ws) {
   DME_REQUIRE(n < (int64_t(1) << 31), DME_EINVAL, "tsqr: n too large");
   const int64_t ld = n;
@@ -473,41 +523,57 @@ void tsqr_factor(hipStream_t s, int64_t n, int64_t k, double* W, TsqrState& st, 
     P.c0 = c0;
     P.pb = (int)std::min<int64_t>(kTB, k - c0);
     const int pb = P.pb;
-    int64_t M = n - c0;
-    double* mat = W + c0 + c0 * ld;  // level 0 is the panel itself, in W
-    int64_t mld = ld;
-    hipEvent_t lev_done[kTsqrMaxLevels] = {};
-    for (int l = 0; l < kTsqrMaxLevels; ++l) {
-      TsqrLevel& L = P.lev[l];
-      L.M = M;
-      L.G = (int)cdiv(M, kTLeaf);
-      L.mat = mat;
-      L.ld = mld;
-      L.T = ws.get<double>((size_t)L.G * kTB * kTB);
-      P.nlev = l + 1;
-      if (L.G == 1) {
-        // top: R into W rows [c0, c0 + pb) (a single leaf of level 0 holds it in place)
-        hipLaunchKernelGGL(tsqr_leaf_kernel, dim3(1), dim3(kLT), 0, s, mat, mld, M, pb, L.T,
-                           W + c0 + c0 * ld, ld, l > 0 ? 2 : 0);
-        DME_HIP(hipGetLastError());
-        lev_done[l] = ax.record(s);
-        break;
+    // the tree of this panel: level 0 is the panel itself, in W
+    {
+      int64_t M = n - c0;
+      double* mat = W + c0 + c0 * ld;
+      int64_t mld = ld;
+      for (int l = 0; l < kTsqrMaxLevels; ++l) {
+        TsqrLevel& L = P.lev[l];
+        L.M = M;
+        L.G = (int)cdiv(M, kTLeaf);
+        L.mat = mat;
+        L.ld = mld;
+        L.T = ws.get<double>((size_t)L.G * kTB * kTB);
+        P.nlev = l + 1;
+        if (L.G == 1) break;
+        if (l + 1 == kTsqrMaxLevels) fail(DME_EINVAL, "tsqr: matrix too tall for the reduction tree");
+        const int64_t Mn = (int64_t)L.G * kTB;
+        M = Mn;
+        mat = ws.get<double>((size_t)Mn * pb);
+        mld = Mn;
       }
-      if (l + 1 == kTsqrMaxLevels) fail(DME_EINVAL, "tsqr: matrix too tall for the reduction tree");
-      const int64_t Mn = (int64_t)L.G * kTB;
-      double* next = ws.get<double>((size_t)Mn * pb);
-      hipLaunchKernelGGL(tsqr_leaf_kernel, dim3((unsigned)L.G), dim3(kLT), 0, s, mat, mld, M, pb, L.T,
-                         next, Mn, 1);
-      DME_HIP(hipGetLastError());
-      lev_done[l] = ax.record(s);
-      M = Mn;
-      mat = next;
-      mld = Mn;
     }
     const LevelRows lr = level_rows(P);
     const int64_t rest = k - c0 - pb;
     const int64_t near = std::min<int64_t>(rest, kTB);  // the next panel's columns
     const int64_t far = rest - near;
+    double* Cnear = W + c0 + (c0 + pb) * ld;
+    // leaves level by level on s; Q^T of level l - 1 reaches the next panel's
+    // columns in the same launch as the leaves of level l (it needs the
+    // previous panel's share of the second stream first)
+    hipEvent_t lev_done[kTsqrMaxLevels] = {};
+    for (int l = 0; l < P.nlev; ++l) {
+      const TsqrLevel& L = P.lev[l];
+      const bool top = (l + 1 == P.nlev);
+      double* Rdst = top ? W + c0 + c0 * ld : P.lev[l + 1].mat;
+      const int64_t ld_r = top ? ld : P.lev[l + 1].ld;
+      const int r_mode = top ? (l > 0 ? 2 : 0) : 1;
+      if (l == 0 || near == 0) {
+        hipLaunchKernelGGL(tsqr_leaf_kernel, dim3((unsigned)L.G), dim3(kLT), 0, s, L.mat, L.ld, L.M, pb, L.T, Rdst,
+                           ld_r, r_mode);
+      } else {
+        if (l == 1 && rest_done) DME_HIP(hipStreamWaitEvent(s, rest_done, 0));
+        launch_leaf_apply(s, L, pb, Rdst, ld_r, r_mode, P.lev[l - 1], l - 1, lr, Cnear, ld, near);
+      }
+      DME_HIP(hipGetLastError());
+      lev_done[l] = ax.record(s);
+    }
+    // Q^T of the top level on the next panel's columns
+    if (near > 0) {
+      if (P.nlev == 1 && rest_done) DME_HIP(hipStreamWaitEvent(s, rest_done, 0));
+      launch_apply(s, P.lev[P.nlev - 1], P.nlev - 1, pb, 1, lr, Cnear, ld, near);
+    }
     // Q^T on the columns beyond the next panel: second stream, level by level
     if (far > 0) {
       double* C = W + c0 + (c0 + pb + near) * ld;
@@ -516,21 +582,8 @@ void tsqr_factor(hipStream_t s, int64_t n, int64_t k, double* W, TsqrState& st, 
         launch_apply(ax.s2, P.lev[l], l, pb, 1, lr, C, ld, far);
       }
       aux_used = true;
+      rest_done = ax.record(ax.s2);
     }
-    // Q^T on the next panel's columns, on the third stream, level l as soon as
-    // leaf level l is done (beside leaf level l + 1 on s) and after the
-    // previous panels' share of the second stream (it updated these columns
-    // too); the next panel's leaves wait for the last level
-    if (near > 0) {
-      if (rest_done) DME_HIP(hipStreamWaitEvent(ax.s3, rest_done, 0));
-      double* C = W + c0 + (c0 + pb) * ld;
-      for (int l = 0; l < P.nlev; ++l) {
-        DME_HIP(hipStreamWaitEvent(ax.s3, lev_done[l], 0));
-        launch_apply(ax.s3, P.lev[l], l, pb, 1, lr, C, ld, near);
-      }
-      DME_HIP(hipStreamWaitEvent(s, ax.record(ax.s3), 0));
-    }
-    if (far > 0) rest_done = ax.record(ax.s2);
     st.panels.push_back(P);
   }
   if (aux_used) DME_HIP(hipStreamWaitEvent(s, ax.record(ax.s2), 0));
