@@ -126,7 +126,9 @@ int dme_solver_setup_info(const dme_solver *sv, double *expm_ms, double *quad_ms
 int dme_solver_result(dme_solver *sv, dme_result **out);
 
 /* Phase timing with HIP events recorded on the solver's stream around each
- * launch group of a phase (enable = 1 turns it on and clears the totals).
+ * launch group of a phase (enable = 1 turns it on and clears the totals;
+ * enable = 2 times DME_PHASE_STEP_KERNEL alone, so that the other phases add
+ * no events to the stream; 0 turns it off; other values: DME_EINVAL).
  * Phases: DME_PHASE_STEP_GEMM (e^{tA^T} L products), DME_PHASE_COMPRESS
  * (QR + eigen compression), DME_PHASE_RICCATI (T3), DME_PHASE_S (S L, S^2 L).
  * For each: number of launches, summed device milliseconds, and the

@@ -390,8 +390,10 @@ class Solver:
                "dme_solver_setup_info")
         return {"expm_ms": e.value, "quad_ms": q.value, "rank_quad": int(rq.value)}
 
-    def profile(self, enable: bool = True):
-        _check(_lib_solver_profile(self._h, 1 if enable else 0), "dme_solver_profile")
+    def profile(self, enable: bool = True, kernel_only: bool = False):
+        """Phase timing on (every phase, or only the step product kernel) or off."""
+        level = (2 if kernel_only else 1) if enable else 0
+        _check(_lib_solver_profile(self._h, level), "dme_solver_profile")
 
     def profile_get(self, phase: str):
         c, ms, fl, by = _i64(), _dbl(), _dbl(), _dbl()

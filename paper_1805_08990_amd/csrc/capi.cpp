@@ -221,7 +221,8 @@ int dme_solver_profile(dme_solver* sv, int enable) {
     DME_REQUIRE(sv != nullptr, DME_EINVAL, "null solver");
     DME_HIP(hipSetDevice(sv->sv.device));
     sv->sv.flush_timings();
-    sv->sv.profiling = (enable != 0);
+    DME_REQUIRE(enable >= 0 && enable <= 2, DME_EINVAL, "profile: enable is 0, 1 or 2");
+    sv->sv.profiling = enable;
     for (auto& a : sv->sv.phase) a = dme::PhaseAcc{};
   });
 }

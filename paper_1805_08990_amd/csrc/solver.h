@@ -113,7 +113,8 @@ struct Solver {
   double expm_ms = 0.0, quad_ms = 0.0;
   int64_t rank_quad = 0;
 
-  bool profiling = false;
+  int profiling = 0;  // 0 off, 1 every phase, 2 the step product kernel alone
+  hipEvent_t mark_phase() { return profiling == 1 ? mark_begin() : nullptr; }
   PhaseAcc phase[5];
   std::vector<PendingTiming> pending;
   std::vector<hipEvent_t> event_pool;

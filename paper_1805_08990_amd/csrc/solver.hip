@@ -428,7 +428,7 @@ void Solver::apply_E(double t, const double* X, int64_t rr, double* Y, int64_t l
   kt.sv = this;
   KernelTimer* prev = kernel_timer();
   if (profiling) kernel_timer() = &kt;
-  hipEvent_t ev = mark_begin();
+  hipEvent_t ev = mark_phase();
   if (opts.precision == DME_MIXED) {
     gemm_mixed(s, *ops.at(t)->mix, X, n, rr, Y, ldy, ws);
     // algorithmic work of Y = E X: 2 n^2 r flops; the FP32 operator read once
@@ -443,7 +443,7 @@ void Solver::apply_E(double t, const double* X, int64_t rr, double* Y, int64_t l
 
 void Solver::compress_into(int64_t k) {
   ws.reset();
-  hipEvent_t ev = mark_begin();
+  hipEvent_t ev = mark_phase();
   const int64_t rn = compress_f64(s, n, k, W.as<double>(), Dhat.as<double>(), opts.tol, max_rank,
                                   Ln(), n, Dn(), 0, rank_dev(), flag_dev(), ws);
   // Householder QR 2 n k^2 - 2/3 k^3, Q application 4 n k r', small eigenproblem ~ 10 k^3
@@ -456,7 +456,7 @@ void Solver::compress_into(int64_t k) {
 
 void Solver::compress_lead_into(int64_t rY, const QuadFactor& f) {
   ws.reset();
-  hipEvent_t ev = mark_begin();
+  hipEvent_t ev = mark_phase();
   const int64_t k = rY + f.r;
   const int64_t rn = compress_f64_lead(s, n, rY, W.as<double>(), f.L.as<double>(), n, f.r,
                                        Dhat.as<double>(), opts.tol, max_rank, Ln(), n, Dn(), 0,
@@ -505,7 +505,7 @@ void Solver::apply_T12(double t, bool ext_product) {
 
 void Solver::apply_T3(double t) {
   if (r == 0) return;
-  hipEvent_t ev = mark_begin();
+  hipEvent_t ev = mark_phase();
   ws.reset();
   gemm_f64(s, 'T', 'N', r, m, n, 1.0, Lc(), n, B.as<double>(), n, 0.0, WB.as<double>(), r, &ws);
   ws.reset();
@@ -516,7 +516,7 @@ void Solver::apply_T3(double t) {
 void Solver::apply_T4(double t) {
   if (r == 0) return;
   double* Wd = W.as<double>();
-  hipEvent_t ev = mark_begin();
+  hipEvent_t ev = mark_phase();
   ws.reset();
   gemm_f64(s, 'N', 'N', n, r, n, 1.0, S.as<double>(), n, Lc(), n, 0.0, SL.as<double>(), n, &ws);
   copy_f64(s, Lc(), n, Wd, n, n, r);

@@ -501,9 +501,9 @@ AuxStream& aux_stream() {
 // Panels are factored on s.  Q^T of panel p reaches the next panel's columns
 // on s (they are what panel p + 1 factors next), level l - 1 in the same
 // launch as the leaves of level l, and the columns beyond on a second stream,
-// which waits for each tree level's factor and runs behind the factorisation
-// of the following panels; s waits for that stream before it touches those
-// columns (and before returning).
+// which waits for the panel's tree and runs behind the factorisation of the
+// following panels; s waits for that stream before it touches those columns
+// (and before returning).
 void tsqr_factor(hipStream_t s, int64_t n, int64_t k, double* W, TsqrState& st, Arena& ws) {
   DME_REQUIRE(n < (int64_t(1) << 31), DME_EINVAL, "tsqr: n too large");
   const int64_t ld = n;
@@ -552,7 +552,6 @@ void tsqr_factor(hipStream_t s, int64_t n, int64_t k, double* W, TsqrState& st, 
     // leaves level by level on s; Q^T of level l - 1 reaches the next panel's
     // columns in the same launch as the leaves of level l (it needs the
     // previous panel's share of the second stream first)
-    hipEvent_t lev_done[kTsqrMaxLevels] = {};
     for (int l = 0; l < P.nlev; ++l) {
       const TsqrLevel& L = P.lev[l];
       const bool top = (l + 1 == P.nlev);
@@ -567,8 +566,10 @@ void tsqr_factor(hipStream_t s, int64_t n, int64_t k, double* W, TsqrState& st, 
         launch_leaf_apply(s, L, pb, Rdst, ld_r, r_mode, P.lev[l - 1], l - 1, lr, Cnear, ld, near);
       }
       DME_HIP(hipGetLastError());
-      lev_done[l] = ax.record(s);
     }
+    // one event per panel, and only where the second stream needs it (a
+    // recorded event costs the stream a few microseconds)
+    hipEvent_t leaves_done = (far > 0) ? ax.record(s) : nullptr;
     // Q^T of the top level on the next panel's columns
     if (near > 0) {
       if (P.nlev == 1 && rest_done) DME_HIP(hipStreamWaitEvent(s, rest_done, 0));
@@ -577,10 +578,8 @@ void tsqr_factor(hipStream_t s, int64_t n, int64_t k, double* W, TsqrState& st, 
     // Q^T on the columns beyond the next panel: second stream, level by level
     if (far > 0) {
       double* C = W + c0 + (c0 + pb + near) * ld;
-      for (int l = 0; l < P.nlev; ++l) {
-        DME_HIP(hipStreamWaitEvent(ax.s2, lev_done[l], 0));
-        launch_apply(ax.s2, P.lev[l], l, pb, 1, lr, C, ld, far);
-      }
+      DME_HIP(hipStreamWaitEvent(ax.s2, leaves_done, 0));
+      for (int l = 0; l < P.nlev; ++l) launch_apply(ax.s2, P.lev[l], l, pb, 1, lr, C, ld, far);
       aux_used = true;
       rest_done = ax.record(ax.s2);
     }
