@@ -516,8 +516,7 @@ void tsqr_factor(hipStream_t s, int64_t n, int64_t k, double* W, TsqrState& st, 
   AuxStream& ax = aux_stream();
   bool aux_used = false;
   hipEvent_t rest_done = nullptr;  // the second stream finished the previous panel's share
-  // the second stream starts after everything s has queued so far (W is ready)
-  DME_HIP(hipStreamWaitEvent(ax.s2, ax.record(s), 0));
+  // (the second stream's first work waits for panel 0's leaves, so for W too)
   for (int64_t c0 = 0; c0 < kr; c0 += kTB) {
     TsqrPanel P;
     P.c0 = c0;

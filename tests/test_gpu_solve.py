@@ -96,6 +96,34 @@ def test_stepwise_equals_whole_solve(ctx):
     sv.close()
 
 
+def test_profiling_levels(ctx):
+    """Level 1 times every phase, level 2 the step product kernel alone; the
+    timing does not change the result; other levels are rejected.  n = 1024,
+    so that the step product takes the skinny kernel that level 2 times."""
+    p = wl.config_dre_halfplane(nx=32, h=1e-2)
+    announce("profiling levels")
+    opts = b.SolveOptions(T=p.T, h=p.h, tol=p.tol, scheme=p.scheme, split=p.split)
+    ref = ctx.solver("dre", opts, p.A, p.C, B=p.B, R=p.R)
+    ref.step(4)
+    L0, D0, _ = ref.result()
+    ref.close()
+    sv = ctx.solver("dre", opts, p.A, p.C, B=p.B, R=p.R)
+    sv.profile(True, kernel_only=True)
+    sv.step(2)
+    assert sv.profile_get("step_kernel")["count"] > 0
+    assert sv.profile_get("compress")["count"] == 0 and sv.profile_get("step_gemm")["count"] == 0
+    sv.profile(True)
+    sv.step(2)
+    assert sv.profile_get("compress")["count"] > 0 and sv.profile_get("step_gemm")["count"] > 0
+    with pytest.raises(b.DmeError) as e:
+        b._check(b._lib_solver_profile(sv._h, 3), "dme_solver_profile")
+    assert e.value.code == b.DME_EINVAL
+    sv.profile(False)
+    L1, D1, _ = sv.result()
+    sv.close()
+    assert np.array_equal(L0, L1) and np.array_equal(D0, D1)
+
+
 def test_errors_are_reported(ctx):
     p = wl.config_dre_halfplane(nx=4, h=1e-2)
     announce("errors")
