@@ -221,7 +221,8 @@ AuxStream& aux_stream();
 size_t compress_workspace(int64_t n, int64_t k);
 // W (n x k, ld n) is destroyed.  Dhat k x k (ld k).  Output L (n x r, ld ldl), Dout (r x r, ld ldd).
 // rank_dev: device int64 receiving r; flag_dev: device int receiving error flags
-// (1: non-finite, 2: rank capped at max_rank).  Synchronises the stream and returns r.
+// (1: non-finite, 2: rank capped at max_rank).  Waits on the host until the rank is
+// known (the stream's earlier work is done) and returns r.
 int64_t compress_f64(hipStream_t s, int64_t n, int64_t k, double* W, const double* Dhat, double tol,
                   int64_t max_rank, double* L, int64_t ldl, double* Dout, int64_t ldd,
                   int64_t* rank_dev, int* flag_dev, Arena& ws);
