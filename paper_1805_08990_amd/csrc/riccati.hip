@@ -16,30 +16,67 @@
 namespace dme {
 namespace {
 
-constexpr int kRT = 256;
+constexpr int kRT = 1024;
 constexpr int kMaxM = 64;
 
+// One workgroup; every loop keeps several independent loads in flight (the
+// step is a latency-bound chain of small products).
 __global__ __launch_bounds__(kRT) void riccati_kernel(int r, int m, double* D, int64_t ldd,
                                                       const double* WB, int64_t ldw, const double* R,
                                                       int64_t ldr, double t, double* Y, double* Dn,
                                                       int* flag) {
   __shared__ double S[kMaxM * kMaxM];
+  __shared__ double part[kRT];
   __shared__ int bad;
   const int tid = threadIdx.x;
-  // Y = D W  (r x m, ld r)
+  // Y = D W  (r x m, ld r): four independent chains over l
   for (int idx = tid; idx < r * m; idx += kRT) {
     const int i = idx % r, a = idx / r;
-    double acc = 0.0;
-    for (int l = 0; l < r; ++l) acc += D[i + (int64_t)l * ldd] * WB[l + (int64_t)a * ldw];
-    Y[i + (int64_t)a * r] = acc;
+    const double* dr = D + i;
+    const double* wc = WB + (int64_t)a * ldw;
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    int l = 0;
+    for (; l + 4 <= r; l += 4) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) acc[u] += dr[(int64_t)(l + u) * ldd] * wc[l + u];
+    }
+    for (; l < r; ++l) acc[0] += dr[(int64_t)l * ldd] * wc[l];
+    Y[i + (int64_t)a * r] = (acc[0] + acc[1]) + (acc[2] + acc[3]);
   }
   __syncthreads();
-  // S = R + t W^T Y
-  for (int idx = tid; idx < m * m; idx += kRT) {
-    const int a = idx % m, b = idx / m;
+  // S = R + t W^T Y: with m^2 <= kRT, slice sl of entry o sums rows i = sl mod ns
+  // and the slices are added in order; otherwise one thread per entry
+  const int mm = m * m;
+  if (mm <= kRT) {
+    const int ns = kRT / mm;
+    const int o = tid % mm, sl = tid / mm;
     double acc = 0.0;
-    for (int i = 0; i < r; ++i) acc += WB[i + (int64_t)a * ldw] * Y[i + (int64_t)b * r];
-    S[a + b * kMaxM] = R[a + (int64_t)b * ldr] + t * acc;
+    if (sl < ns) {
+      const int a = o % m, b = o / m;
+      const double* wa = WB + (int64_t)a * ldw;
+      const double* yb = Y + (int64_t)b * r;
+      for (int i = sl; i < r; i += ns) acc += wa[i] * yb[i];
+    }
+    part[tid] = acc;
+    __syncthreads();
+    if (tid < mm) {
+      double tot = 0.0;
+      for (int q = 0; q < ns; ++q) tot += part[tid + q * mm];
+      const int a = tid % m, b = tid / m;
+      S[a + b * kMaxM] = R[a + (int64_t)b * ldr] + t * tot;
+    }
+  } else {
+    for (int idx = tid; idx < mm; idx += kRT) {
+      const int a = idx % m, b = idx / m;
+      double acc[4] = {0.0, 0.0, 0.0, 0.0};
+      int i = 0;
+      for (; i + 4 <= r; i += 4) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) acc[u] += WB[i + u + (int64_t)a * ldw] * Y[i + u + (int64_t)b * r];
+      }
+      for (; i < r; ++i) acc[0] += WB[i + (int64_t)a * ldw] * Y[i + (int64_t)b * r];
+      S[a + b * kMaxM] = R[a + (int64_t)b * ldr] + t * ((acc[0] + acc[1]) + (acc[2] + acc[3]));
+    }
   }
   __syncthreads();
   // Cholesky (lower) of the symmetrised S, serial: m is tiny
@@ -77,14 +114,17 @@ __global__ __launch_bounds__(kRT) void riccati_kernel(int r, int m, double* D, i
   }
   __syncthreads();
   // Dn = sym(D) - t Z Z^T
-  for (int idx = tid; idx < r * r; idx += kRT) {
+  const int rr = r * r;
+#pragma unroll 4
+  for (int idx = tid; idx < rr; idx += kRT) {
     const int i = idx % r, j = idx / r;
     double acc = 0.0;
     for (int a = 0; a < m; ++a) acc += Y[i + (int64_t)a * r] * Y[j + (int64_t)a * r];
     Dn[idx] = 0.5 * (D[i + (int64_t)j * ldd] + D[j + (int64_t)i * ldd]) - t * acc;
   }
   __syncthreads();
-  for (int idx = tid; idx < r * r; idx += kRT) {
+#pragma unroll 4
+  for (int idx = tid; idx < rr; idx += kRT) {
     const int i = idx % r, j = idx / r;
     D[i + (int64_t)j * ldd] = Dn[idx];
   }
