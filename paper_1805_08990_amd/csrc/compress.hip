@@ -12,7 +12,8 @@
 //   C = U^T Y, Y <- Y - U C, twice (classical Gram-Schmidt, repeated once)
 //   Y = Q2 R2 (tree QR), so [Y, U] = [Q2, U] Rt with Rt = [[R2, 0], [C, I]]
 //   M = Rt Dhat Rt^T, M = V Lam V^T (kept part), as above
-//   L = P Q2 [V(0:r, :); 0] + U V(r:k, :), P = I - U U^T
+//   L = P Q2 [V(0:r, :); 0] + U V(r:k, :), P = I - U U^T, with Q2 [I_r; 0] formed
+//   on a second stream while the k x k eigenproblem runs
 // P removes from Q2's columns the U components that rounding leaves in the
 // directions where Y is (numerically) rank-deficient after the projection.
 #include "tsqr.h"
@@ -51,6 +52,16 @@ __global__ void embed_kernel(const double* V, int64_t ldv, int64_t kr, int64_t n
        idx += (int64_t)gridDim.x * blockDim.x) {
     const int64_t i = idx % n, c = idx / n;
     X[i + c * ldx] = (i < kr) ? V[i + c * ldv] : 0.0;
+  }
+}
+
+// X (n x r, ld ldx) = [I_r; 0]
+__global__ void eye_kernel(int64_t n, int64_t r, double* X, int64_t ldx) {
+  const int64_t total = n * r;
+  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = idx % n, c = idx / n;
+    X[i + c * ldx] = (i == c) ? 1.0 : 0.0;
   }
 }
 
@@ -361,6 +372,7 @@ size_t compress_workspace(int64_t n, int64_t k) {
   // partial products of U^T Y, and its n-deep products
   add(4 * (size_t)k * k * sizeof(double));
   add((size_t)ts_blocks(n) * kTsMaxQ * k * sizeof(double));
+  add((size_t)n * k * sizeof(double));  // Qe = Q2 [I; 0]
   add(std::max(gemm_f64_workspace(k, k, n), gemm_f64_workspace(n, k, k)));
   return b + 4096;
 }
@@ -474,7 +486,16 @@ int64_t compress_f64_lead(hipStream_t s, int64_t n, int64_t r, double* W, const 
   // Y = Q2 R2
   TsqrState tq;
   tsqr_factor(s, n, r, W, tq, ws);
+  // Qe = Q2 [I_r; 0] on the second stream, beside the k x k eigenproblem
+  // below (which needs none of it); L's Q2 part is then one product Qe V_top
+  double* Qe = ws.get<double>((size_t)n * r);
   const size_t mark_q = ws.used;
+  AuxStream& ax = aux_stream();
+  DME_HIP(hipStreamWaitEvent(ax.s2, ax.record(s), 0));
+  hipLaunchKernelGGL(eye_kernel, dim3(blocks_for(n * r)), dim3(256), 0, ax.s2, n, r, Qe, n);
+  DME_HIP(hipGetLastError());
+  tsqr_apply_q(ax.s2, tq, Qe, n, r);
+  hipEvent_t qe_done = ax.record(ax.s2);
 
   // M = Rt Dhat Rt^T, symmetrised
   hipLaunchKernelGGL(build_rt_kernel, dim3(blocks_for(k * k)), dim3(256), 0, s, W, n, r, q, C1, C2, Rt);
@@ -494,9 +515,9 @@ int64_t compress_f64_lead(hipStream_t s, int64_t n, int64_t r, double* W, const 
   if (ldd <= 0) ldd = rr;
 
   // L = P Q2 [V(0:r, :); 0] + U V(r:k, :) = Q2 [...] + U (V(r:k, :) - U^T Q2 [...])
-  hipLaunchKernelGGL(embed_kernel, dim3(blocks_for(n * rr)), dim3(256), 0, s, V, k, r, n, rr, L, ldl);
-  DME_HIP(hipGetLastError());
-  tsqr_apply_q(s, tq, L, ldl, rr);
+  DME_HIP(hipStreamWaitEvent(s, qe_done, 0));
+  gemm_f64(s, 'N', 'N', n, rr, r, 1.0, Qe, n, V, k, 0.0, L, ldl, &ws);
+  ws.used = mark_q;
   if (ts) {
     ts_project(L, ldl, rr, V + r, k, -1.0, B);
     ts_update(B, rr, 1.0, L, ldl);
