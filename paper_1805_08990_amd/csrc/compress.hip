@@ -44,17 +44,6 @@ __global__ void symmetrize_kernel(const double* M, int64_t k, double* S) {
   }
 }
 
-// X (n x r, ld ldx) = [V (kr x r, ld ldv); 0]
-__global__ void embed_kernel(const double* V, int64_t ldv, int64_t kr, int64_t n, int64_t r,
-                             double* X, int64_t ldx) {
-  const int64_t total = n * r;
-  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
-       idx += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t i = idx % n, c = idx / n;
-    X[i + c * ldx] = (i < kr) ? V[i + c * ldv] : 0.0;
-  }
-}
-
 // X (n x r, ld ldx) = [I_r; 0]
 __global__ void eye_kernel(int64_t n, int64_t r, double* X, int64_t ldx) {
   const int64_t total = n * r;
@@ -395,7 +384,15 @@ int64_t compress_f64(hipStream_t s, int64_t n, int64_t k, double* W, const doubl
   // ---------------- Householder QR; the tree's factors stay reserved until Q is applied
   TsqrState tq;
   tsqr_factor(s, n, k, W, tq, ws);
+  // Qe = Q [I_kr; 0] on the second stream, beside the eigenproblem below
+  double* Qe = ws.get<double>((size_t)n * kr);
   const size_t mark_q = ws.used;
+  AuxStream& ax = aux_stream();
+  DME_HIP(hipStreamWaitEvent(ax.s2, ax.record(s), 0));
+  hipLaunchKernelGGL(eye_kernel, dim3(blocks_for(n * kr)), dim3(256), 0, ax.s2, n, kr, Qe, n);
+  DME_HIP(hipGetLastError());
+  tsqr_apply_q(ax.s2, tq, Qe, n, kr);
+  hipEvent_t qe_done = ax.record(ax.s2);
 
   // ---------------- M = R Dhat R^T, symmetrised
   hipLaunchKernelGGL(extract_r_kernel, dim3(blocks_for(kr * k)), dim3(256), 0, s, W, ld, kr, k, R);
@@ -412,13 +409,16 @@ int64_t compress_f64(hipStream_t s, int64_t n, int64_t k, double* W, const doubl
   ws.used = mark_q;
   syev_trunc_f64(s, kr, S, kr, tol, std::min(max_rank, kr), lam, V, kr, rank_dev, flag_dev, ws);
   const int64_t r = rank_to_host(s, rank_dev);
-  if (r <= 0) return 0;
+  if (r <= 0) {
+    DME_HIP(hipStreamWaitEvent(s, qe_done, 0));  // the second stream still reads W
+    return 0;
+  }
   if (ldd <= 0) ldd = r;
 
-  // ---------------- L = Q [V_I; 0], D = diag(lam_I)
-  hipLaunchKernelGGL(embed_kernel, dim3(blocks_for(n * r)), dim3(256), 0, s, V, kr, kr, n, r, L, ldl);
-  DME_HIP(hipGetLastError());
-  tsqr_apply_q(s, tq, L, ldl, r);
+  // ---------------- L = Q [V_I; 0] = Qe V_I, D = diag(lam_I)
+  DME_HIP(hipStreamWaitEvent(s, qe_done, 0));
+  gemm_f64(s, 'N', 'N', n, r, kr, 1.0, Qe, n, V, kr, 0.0, L, ldl, &ws);
+  ws.used = mark_q;
   hipLaunchKernelGGL(diag_kernel, dim3(blocks_for(r * r)), dim3(256), 0, s, lam, r, Dout, ldd);
   DME_HIP(hipGetLastError());
   ws.used = mark_q;
@@ -511,7 +511,10 @@ int64_t compress_f64_lead(hipStream_t s, int64_t n, int64_t r, double* W, const 
   syev_trunc_f64(s, k, S, k, tol, std::min(max_rank, k), lam, V, k, rank_dev, flag_dev, ws);
   ws.used = mark_q;
   const int64_t rr = rank_to_host(s, rank_dev);
-  if (rr <= 0) return 0;
+  if (rr <= 0) {
+    DME_HIP(hipStreamWaitEvent(s, qe_done, 0));  // the second stream still reads W
+    return 0;
+  }
   if (ldd <= 0) ldd = rr;
 
   // L = P Q2 [V(0:r, :); 0] + U V(r:k, :) = Q2 [...] + U (V(r:k, :) - U^T Q2 [...])
