@@ -57,7 +57,7 @@ import numpy as np
 
 __all__ = [
     "THETA", "pade_coefficients", "norm1", "expm_params", "expm", "num_steps", "gauss_legendre",
-    "compress", "quadrature_factor", "t1", "t2", "t12", "t3", "t4",
+    "compress", "quadrature_factor", "t1", "t2", "t12", "t3", "t4", "feedback_gain",
     "step_sequence", "solve", "lowrank_fro", "lowrank_rel_err",
     "laplacian_expm_kron", "kron_apply_expm", "quadrature_factor_kron",
     "OracleError",
@@ -250,6 +250,20 @@ def t3(L, D, B, R, t):
     G = W @ np.linalg.solve(R, W.T)
     X = np.linalg.solve(np.eye(r) + t * D @ G, D)
     return 0.5 * (X + X.T)
+
+
+def feedback_gain(L, D, B, R):
+    """Feedback gain K = R^-1 B^T P (m x n) of the LQR problem behind the DRE
+    (Sec. 1, the LQR setting; the optimal input is u = -K x with P the DRE
+    solution at the remaining horizon), from the factors P = L D L^T.
+
+    Pins: invariant under L -> L G, D -> G^-1 D G^-T (the same P); linear in
+    R^-1; the scalar DRE's closed-form solution gives K = b p(t) / r.
+    """
+    m, n = B.shape[1], B.shape[0]
+    if L.shape[1] == 0:
+        return np.zeros((m, n))
+    return np.linalg.solve(R, ((B.T @ L) @ D) @ L.T)
 
 
 def t4(L, D, S, t, tol):

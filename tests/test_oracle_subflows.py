@@ -101,3 +101,39 @@ def test_t2_and_t1():
     L1 = o.t1(L, E)
     ref = sl.expm(0.1 * A.T) @ P @ sl.expm(0.1 * A)
     assert np.linalg.norm(L1 @ D @ L1.T - ref) < 1e-13 * np.linalg.norm(ref)
+
+
+def test_feedback_gain_basis_invariance_and_R():
+    """K = R^-1 B^T L D L^T depends on P = L D L^T only, and scales as R^-1."""
+    rng = np.random.default_rng(11)
+    n, r, m = 30, 5, 3
+    L = rng.standard_normal((n, r))
+    D = np.diag(rng.uniform(0.5, 2.0, r))
+    B = rng.standard_normal((n, m))
+    R = np.diag([1.0, 2.0, 4.0])
+    K = o.feedback_gain(L, D, B, R)
+    assert K.shape == (m, n)
+    G = np.linalg.qr(rng.standard_normal((r, r)))[0] @ np.diag(np.linspace(1.0, 2.0, r))  # cond 2
+    Gi = np.linalg.inv(G)
+    K2 = o.feedback_gain(L @ G, Gi @ D @ Gi.T, B, R)
+    assert np.allclose(K, K2, rtol=1e-12, atol=1e-12)
+    K3 = o.feedback_gain(L, D, B, 0.5 * R)
+    assert np.allclose(K3, 2.0 * K, rtol=1e-13, atol=1e-13)
+    assert np.array_equal(o.feedback_gain(L[:, :0], D[:0, :0], B, R), np.zeros((m, n)))
+
+
+def test_feedback_gain_scalar_closed_form():
+    """n = 1: p' = 2 a p + c^2 - (b^2 / r) p^2, p(0) = 0, has
+    p(t) = c^2 sinh(mu t) / (mu cosh(mu t) - a sinh(mu t)), mu = sqrt(a^2 + b^2 c^2 / r),
+    and K(t) = b p(t) / r; the Strang solution's gain is second-order close."""
+    a, b, c, r, T = -1.0, 0.7, 1.3, 2.0, 0.5
+    mu = math.sqrt(a * a + b * b * c * c / r)
+    p_exact = c * c * math.sinh(mu * T) / (mu * math.cosh(mu * T) - a * math.sinh(mu * T))
+    errs = []
+    for h in (0.05, 0.025):
+        L, D, _ = o.solve(np.array([[a]]), np.array([[c]]), T, h, kind="dre", B=np.array([[b]]),
+                          R=np.array([[r]]), split="F12", scheme="strang", tol=1e-14)
+        K = o.feedback_gain(L, D, np.array([[b]]), np.array([[r]]))
+        errs.append(abs(K[0, 0] - b * p_exact / r))
+    assert errs[1] < 1e-3 * abs(b * p_exact / r)
+    assert 3.0 < errs[0] / errs[1] < 5.0  # second order
