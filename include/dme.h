@@ -125,6 +125,14 @@ int dme_solver_state(const dme_solver *sv, int64_t *step, int64_t *nsteps_total,
 int dme_solver_setup_info(const dme_solver *sv, double *expm_ms, double *quad_ms, int64_t *rank_quad);
 int dme_solver_result(dme_solver *sv, dme_result **out);
 
+/* LQR feedback gain at the solver's current step (Sec. 1, the LQR setting):
+ * K = R^-1 B^T P with P = L D L^T, written to K (host, m x n, column-major,
+ * ld ldk >= m).  Computed on the device (L^T B, D W, an m x m Cholesky solve
+ * with R, X L^T) and copied out; synchronises the solver's stream.  Errors:
+ * DME_EINVAL for a solver without B and R (DLE), ldk < m, m > 64 or null
+ * pointers; flag bit 4 (R not SPD) is reported like the solver's flags. */
+int dme_solver_gain(dme_solver *sv, double *K, int64_t ldk);
+
 /* Phase timing with HIP events recorded on the solver's stream around each
  * launch group of a phase (enable = 1 turns it on and clears the totals;
  * enable = 2 times DME_PHASE_STEP_KERNEL alone, so that the other phases add

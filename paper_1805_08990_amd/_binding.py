@@ -91,6 +91,7 @@ _lib_solver_setup_info = _sig("dme_solver_setup_info", _int,
 _lib_solver_result = _sig("dme_solver_result", _int, [_p, ctypes.POINTER(_p)])
 _lib_solver_free = _sig("dme_solver_free", None, [_p])
 _lib_solver_profile = _sig("dme_solver_profile", _int, [_p, _int])
+_lib_solver_gain = _sig("dme_solver_gain", _int, [_p, _p, _i64])
 _lib_solver_profile_get = _sig("dme_solver_profile_get", _int,
                                [_p, _int, ctypes.POINTER(_i64), ctypes.POINTER(_dbl),
                                 ctypes.POINTER(_dbl), ctypes.POINTER(_dbl)])
@@ -374,6 +375,8 @@ class Solver:
         _check(_lib_solver_create(ctx._h, ctypes.byref(hp.c), ctypes.byref(o), 1 if kind == "dre" else 0,
                                   ctypes.byref(h)), "dme_solver_create")
         self._h = h
+        self.n = int(np.asarray(A).shape[0])
+        self.m = int(np.asarray(B).shape[1]) if B is not None else 0
 
     def step(self, nsteps: int = 1):
         _check(_lib_solver_step(self._h, int(nsteps)), "dme_solver_step")
@@ -389,6 +392,13 @@ class Solver:
         _check(_lib_solver_setup_info(self._h, ctypes.byref(e), ctypes.byref(q), ctypes.byref(rq)),
                "dme_solver_setup_info")
         return {"expm_ms": e.value, "quad_ms": q.value, "rank_quad": int(rq.value)}
+
+    def gain(self):
+        """Feedback gain K = R^-1 B^T L D L^T (m x n) at the current step."""
+        m, n = self.m, self.n
+        K = np.zeros((max(m, 1), n), order="F")
+        _check(_lib_solver_gain(self._h, K.ctypes.data_as(_p), max(m, 1)), "dme_solver_gain")
+        return K
 
     def profile(self, enable: bool = True, kernel_only: bool = False):
         """Phase timing on (every phase, or only the step product kernel) or off."""

@@ -216,6 +216,26 @@ int dme_solver_result(dme_solver* sv, dme_result** out) {
   });
 }
 
+int dme_solver_gain(dme_solver* sv, double* K, int64_t ldk) {
+  return guarded([&] {
+    DME_REQUIRE(sv != nullptr && K != nullptr, DME_EINVAL, "null argument");
+    dme::Solver& S = sv->sv;
+    DME_REQUIRE(S.is_dre, DME_EINVAL, "gain: the solver has no B and R (not a DRE)");
+    DME_REQUIRE(ldk >= S.m, DME_EINVAL, "gain: ldk < m");
+    DME_HIP(hipSetDevice(S.device));
+    S.ws.reset();
+    double* Kd = S.ws.get<double>((size_t)S.m * S.n);
+    dme::feedback_gain_f64(S.s, S.n, S.r, S.m, S.Lc(), S.n, S.Dc(), S.r, S.B.as<double>(), S.n,
+                           S.R.as<double>(), S.m, Kd, S.m, S.flag_dev(), S.ws);
+    std::vector<double> h((size_t)S.m * S.n);
+    DME_HIP(hipMemcpyAsync(h.data(), Kd, h.size() * sizeof(double), hipMemcpyDeviceToHost, S.s));
+    DME_HIP(hipStreamSynchronize(S.s));
+    S.check_flags("gain");
+    for (int64_t j = 0; j < S.n; ++j)
+      for (int64_t i = 0; i < S.m; ++i) K[i + j * ldk] = h[(size_t)i + (size_t)j * S.m];
+  });
+}
+
 int dme_solver_profile(dme_solver* sv, int enable) {
   return guarded([&] {
     DME_REQUIRE(sv != nullptr, DME_EINVAL, "null solver");

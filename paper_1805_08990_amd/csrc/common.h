@@ -243,6 +243,10 @@ void syev_trunc_f64(hipStream_t s, int64_t k, const double* M, int64_t ldm, doub
                     int64_t* keep_dev, int* flag_dev, Arena& ws);
 
 // Riccati subflow (riccati.hip): D (r x r) <- D - t D W (R + t W^T D W)^-1 W^T D, W = L^T B.
+// LQR feedback gain K (m x n, ld ldk) = R^-1 B^T L D L^T (riccati.hip).
+void feedback_gain_f64(hipStream_t s, int64_t n, int64_t r, int64_t m, const double* L, int64_t ldl,
+                       const double* D, int64_t ldd, const double* B, int64_t ldb, const double* R,
+                       int64_t ldr, double* K, int64_t ldk, int* flag_dev, Arena& ws);
 void riccati_update_f64(hipStream_t s, int64_t r, int64_t m, double* D, int64_t ldd,
                         const double* WB, int64_t ldw, const double* R, int64_t ldr, double t,
                         int* flag_dev, Arena& ws);

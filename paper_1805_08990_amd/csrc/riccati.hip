@@ -130,6 +130,52 @@ __global__ __launch_bounds__(kRT) void riccati_kernel(int r, int m, double* D, i
   }
 }
 
+// X (m x r, ld m) = R^-1 Z^T for Z (r x m, ld r): Cholesky of R (m <= kMaxM)
+// by one thread, then one thread per column of Z^T (forward and backward
+// substitution).  A non-SPD R raises flag bit 4.
+__global__ __launch_bounds__(256) void gain_solve_kernel(int m, int r, const double* R, int64_t ldr,
+                                                         const double* Z, double* X, int* flag) {
+  __shared__ double Lc[kMaxM * kMaxM];
+  __shared__ int bad;
+  const int tid = threadIdx.x;
+  for (int idx = tid; idx < m * m; idx += blockDim.x) {
+    const int a = idx % m, b = idx / m;
+    Lc[a + b * kMaxM] = 0.5 * (R[a + (int64_t)b * ldr] + R[b + (int64_t)a * ldr]);
+  }
+  __syncthreads();
+  if (tid == 0) {
+    bad = 0;
+    for (int j = 0; j < m && !bad; ++j) {
+      double dj = Lc[j + j * kMaxM];
+      for (int q = 0; q < j; ++q) dj -= Lc[j + q * kMaxM] * Lc[j + q * kMaxM];
+      if (!(dj > 0.0)) { bad = 1; break; }
+      const double ljj = sqrt(dj);
+      Lc[j + j * kMaxM] = ljj;
+      for (int i = j + 1; i < m; ++i) {
+        double v = Lc[i + j * kMaxM];
+        for (int q = 0; q < j; ++q) v -= Lc[i + q * kMaxM] * Lc[j + q * kMaxM];
+        Lc[i + j * kMaxM] = v / ljj;
+      }
+    }
+    if (bad) atomicOr(flag, 4);
+  }
+  __syncthreads();
+  if (bad) return;
+  for (int c = tid; c < r; c += blockDim.x) {
+    double* x = X + (int64_t)c * m;
+    for (int a = 0; a < m; ++a) {  // Lc y = z
+      double v = Z[c + (int64_t)a * r];
+      for (int b = 0; b < a; ++b) v -= Lc[a + b * kMaxM] * x[b];
+      x[a] = v / Lc[a + a * kMaxM];
+    }
+    for (int a = m - 1; a >= 0; --a) {  // Lc^T x = y
+      double v = x[a];
+      for (int b = a + 1; b < m; ++b) v -= Lc[b + a * kMaxM] * x[b];
+      x[a] = v / Lc[a + a * kMaxM];
+    }
+  }
+}
+
 }  // namespace
 
 void riccati_update_f64(hipStream_t s, int64_t r, int64_t m, double* D, int64_t ldd,
@@ -142,6 +188,31 @@ void riccati_update_f64(hipStream_t s, int64_t r, int64_t m, double* D, int64_t 
   hipLaunchKernelGGL(riccati_kernel, dim3(1), dim3(kRT), 0, s, (int)r, (int)m, D, ldd, WB, ldw, R,
                      ldr, t, Y, Dn, flag_dev);
   DME_HIP(hipGetLastError());
+}
+
+// K (m x n, ld ldk) = R^-1 B^T L D L^T: W = L^T B, Z = D W, X = R^-1 Z^T,
+// K = X L^T.
+void feedback_gain_f64(hipStream_t s, int64_t n, int64_t r, int64_t m, const double* L, int64_t ldl,
+                       const double* D, int64_t ldd, const double* B, int64_t ldb, const double* R,
+                       int64_t ldr, double* K, int64_t ldk, int* flag_dev, Arena& ws) {
+  if (m <= 0 || n <= 0) return;
+  DME_REQUIRE(m <= kMaxM, DME_EINVAL, "gain: m > 64 inputs is not supported");
+  if (r <= 0) {
+    fill_f64(s, K, m, n, ldk, 0.0);
+    return;
+  }
+  double* W = ws.get<double>((size_t)r * m);
+  double* Z = ws.get<double>((size_t)r * m);
+  double* X = ws.get<double>((size_t)m * r);
+  const size_t mark = ws.used;
+  gemm_f64(s, 'T', 'N', r, m, n, 1.0, L, ldl, B, ldb, 0.0, W, r, &ws);
+  ws.used = mark;
+  gemm_f64(s, 'N', 'N', r, m, r, 1.0, D, ldd, W, r, 0.0, Z, r, &ws);
+  ws.used = mark;
+  hipLaunchKernelGGL(gain_solve_kernel, dim3(1), dim3(256), 0, s, (int)m, (int)r, R, ldr, Z, X, flag_dev);
+  DME_HIP(hipGetLastError());
+  gemm_f64(s, 'N', 'T', m, n, r, 1.0, X, m, L, ldl, 0.0, K, ldk, &ws);
+  ws.used = mark;
 }
 
 }  // namespace dme

@@ -136,3 +136,34 @@ def test_errors_are_reported(ctx):
     with pytest.raises(b.DmeError) as e:
         ctx.solve("dle", b.SolveOptions(T=0.1, h=0.01, max_rank=1), p.A, wl.random_C(3, 16, 1))
     assert e.value.code == b.DME_ERANK
+
+
+@pytest.mark.parametrize("nx", [12, 32])
+def test_feedback_gain(ctx, nx):
+    """K = R^-1 B^T L D L^T on the device against the oracle's gain, both from
+    the GPU factors (element by element) and from the oracle's own solve; a
+    DLE solver has no gain."""
+    p = wl.config_dre_quadrant(nx=nx, seed=0, p=8, m=4, h=1e-2)
+    announce("feedback gain", "n", p.n)
+    opts = b.SolveOptions(T=p.T, h=p.h, tol=p.tol, scheme=p.scheme, split=p.split,
+                          quad_nodes=p.quad_nodes)
+    sv = ctx.solver("dre", opts, p.A, p.C, B=p.B, R=p.R)
+    sv.step(5)
+    K = sv.gain()
+    L, D, _ = sv.result()
+    sv.close()
+    Kf = oracle.feedback_gain(L, D, p.B, p.R)
+    scale = np.abs(Kf).max()
+    assert K.shape == Kf.shape
+    assert np.abs(K - Kf).max() <= 1e-12 * scale
+    Lo, Do, _ = oracle.solve(p.A, p.C, 5 * p.h, p.h, kind="dre", B=p.B, R=p.R, split=p.split,
+                             scheme=p.scheme, tol=p.tol, quad_nodes=p.quad_nodes)
+    Ko = oracle.feedback_gain(Lo, Do, p.B, p.R)
+    err = np.abs(K - Ko).max() / np.abs(Ko).max()
+    print(f"  gain vs oracle solve {err:.3e}", flush=True)
+    assert err < 1e-10
+    dle = ctx.solver("dle", b.SolveOptions(T=p.T, h=p.h), p.A, p.C)
+    with pytest.raises(b.DmeError) as e:
+        b._check(b._lib_solver_gain(dle._h, K.ctypes.data_as(b._p), 4), "dme_solver_gain")
+    assert e.value.code == b.DME_EINVAL
+    dle.close()
