@@ -122,10 +122,17 @@ def run_gpu(ctx, prob, precision, steps, warmup):
         prof[ph] = sv.profile_get(ph)
     prof["phase_steps"] = phase_steps
     sv.profile(False)
+    # LQR feedback gain K = R^-1 B^T L D L^T at the last step (device work and
+    # the m x n copy to the host)
+    sv.gain()
+    t1 = time.perf_counter()
+    for _ in range(3):
+        sv.gain()
+    gain_ms = (time.perf_counter() - t1) / 3 * 1e3
     L, D, _ = sv.result()
     sv.close()
     return {"elapsed_s": elapsed, "setup_s": setup_s, "setup": setup, "rank": rank, "prof": prof,
-            "L": L, "D": D}
+            "L": L, "D": D, "gain_ms": gain_ms}
 
 
 def kernel_source_hash(kernel):
@@ -336,6 +343,7 @@ def main():
     }
     for prec, r in results.items():
         line[f"{prec}_steps_per_s"] = round(args.steps / r["elapsed_s"], 4)
+        line[f"{prec}_gain_ms"] = round(r["gain_ms"], 3)
         pr = r["prof"]
         line[f"{prec}_phase_ms_per_step"] = {
             k: round(v["ms"] / (args.steps if k == "step_kernel" else pr["phase_steps"]), 4)
