@@ -23,8 +23,7 @@ constexpr int kMaxM = 64;
 // step is a latency-bound chain of small products).
 __global__ __launch_bounds__(kRT) void riccati_kernel(int r, int m, double* D, int64_t ldd,
                                                       const double* WB, int64_t ldw, const double* R,
-                                                      int64_t ldr, double t, double* Y, double* Dn,
-                                                      int* flag) {
+                                                      int64_t ldr, double t, double* Y, int* flag) {
   __shared__ double S[kMaxM * kMaxM];
   __shared__ double part[kRT];
   __shared__ int bad;
@@ -113,20 +112,20 @@ __global__ __launch_bounds__(kRT) void riccati_kernel(int r, int m, double* D, i
     }
   }
   __syncthreads();
-  // Dn = sym(D) - t Z Z^T
-  const int rr = r * r;
+  // D <- sym(D) - t Z Z^T in place: one thread per pair i <= j reads D(i, j)
+  // and D(j, i) and writes both (pair p -> column j, row i of the upper triangle)
+  const int np = r * (r + 1) / 2;
 #pragma unroll 4
-  for (int idx = tid; idx < rr; idx += kRT) {
-    const int i = idx % r, j = idx / r;
+  for (int pidx = tid; pidx < np; pidx += kRT) {
+    int j = (int)((sqrt(8.0 * pidx + 1.0) - 1.0) * 0.5);
+    while (j * (j + 1) / 2 > pidx) --j;
+    while ((j + 1) * (j + 2) / 2 <= pidx) ++j;
+    const int i = pidx - j * (j + 1) / 2;  // 0 <= i <= j
     double acc = 0.0;
     for (int a = 0; a < m; ++a) acc += Y[i + (int64_t)a * r] * Y[j + (int64_t)a * r];
-    Dn[idx] = 0.5 * (D[i + (int64_t)j * ldd] + D[j + (int64_t)i * ldd]) - t * acc;
-  }
-  __syncthreads();
-#pragma unroll 4
-  for (int idx = tid; idx < rr; idx += kRT) {
-    const int i = idx % r, j = idx / r;
-    D[i + (int64_t)j * ldd] = Dn[idx];
+    const double v = 0.5 * (D[i + (int64_t)j * ldd] + D[j + (int64_t)i * ldd]) - t * acc;
+    D[i + (int64_t)j * ldd] = v;
+    D[j + (int64_t)i * ldd] = v;
   }
 }
 
@@ -184,9 +183,8 @@ void riccati_update_f64(hipStream_t s, int64_t r, int64_t m, double* D, int64_t 
   if (r <= 0 || m <= 0) return;
   DME_REQUIRE(m <= kMaxM, DME_EINVAL, "riccati: m > 64 inputs is not supported");
   double* Y = ws.get<double>((size_t)r * m);
-  double* Dn = ws.get<double>((size_t)r * r);
   hipLaunchKernelGGL(riccati_kernel, dim3(1), dim3(kRT), 0, s, (int)r, (int)m, D, ldd, WB, ldw, R,
-                     ldr, t, Y, Dn, flag_dev);
+                     ldr, t, Y, flag_dev);
   DME_HIP(hipGetLastError());
 }
 
