@@ -59,7 +59,9 @@ __all__ = [
     "THETA", "pade_coefficients", "norm1", "expm_params", "expm", "num_steps", "gauss_legendre",
     "compress", "quadrature_factor", "t1", "t2", "t12", "t3", "t4", "feedback_gain",
     "step_sequence", "solve", "lowrank_fro", "lowrank_rel_err",
-    "laplacian_expm_kron", "kron_apply_expm", "quadrature_factor_kron",
+    "laplacian_expm_kron", "kron_apply_expm", "quadrature_factor_kron", "KronExpm",
+    "gershgorin_interval", "leja_points", "exp_divided_differences", "newton_eval", "leja_params",
+    "leja_expmv", "LejaExpm", "quadrature_factor_leja",
     "OracleError",
 ]
 
@@ -151,6 +153,161 @@ def expm(X: np.ndarray) -> np.ndarray:
     for _ in range(s):
         F = F @ F
     return F
+
+
+# ----------------------------------------------------------------------------
+# Action e^{tA} V by Newton interpolation at Leja points (the paper's
+# "expleja", Sec. 3 and Sec. 4: a one-time spectral estimate by Gershgorin
+# discs, one-time interpolation parameters, then Newton interpolation built
+# from products with A), for A with a real spectrum (symmetric A).
+#
+# With [a, b] an interval holding the spectrum, c = (a + b) / 2 and
+# g = (b - a) / 4, the matrix As = (A - c I) / g has its spectrum in [-2, 2]
+# and e^{tA} = e^{tc} e^{t g As}.  The time t is cut into S substeps of
+# t / S; in each, e^{rho z} (rho = t g / S) is interpolated at Leja points
+# xi_0 .. xi_m of [-2, 2] in Newton form
+#     p(z) = sum_j d_j w_j(z),  w_0 = 1,  w_{j+1} = (z - xi_j) w_j,
+# with d_j the divided differences of e^{rho z}, and applied to the block:
+#     W <- V, P <- d_0 V;  for j: W <- (As - xi_j I) W, P <- P + d_{j+1} W;
+#     V <- e^{t c / S} P.
+# For a symmetric A the error of one substep is at most
+# max_{z in [-2, 2]} |e^{rho z} - p(z)| times ||V||, so (S, m) are chosen
+# from that scalar error.
+# ----------------------------------------------------------------------------
+def gershgorin_interval(A: np.ndarray):
+    """[a, b] = [min_i (a_ii - R_i), max_i (a_ii + R_i)], R_i the off-diagonal
+    absolute row sum: the union of the Gershgorin discs meets the real line
+    inside it, so for a symmetric A it contains every eigenvalue.
+
+    Pin: contains the eigenvalues of symmetric matrices; equals the closed
+    form [-8/dx^2, 0] for the Dirichlet Laplacian.
+    """
+    A = np.asarray(A, dtype=np.float64)
+    d = np.diag(A)
+    rad = np.sum(np.abs(A), axis=1) - np.abs(d)
+    return float(np.min(d - rad)), float(np.max(d + rad))
+
+
+def leja_points(m: int, grid: int = 20001) -> np.ndarray:
+    """m + 1 (discrete) Leja points of [-2, 2]: xi_0 = 2, then each xi_j is a
+    point of a uniform grid of [-2, 2] where prod_{i<j} |x - xi_i| is largest.
+
+    Pin: every xi_j maximises |w_j| over the grid (w_j = prod_{i<j}(x - xi_i))
+    and the points are distinct.
+    """
+    x = np.linspace(-2.0, 2.0, grid)
+    pts = [2.0]
+    logw = np.log(np.abs(x - 2.0) + 1e-300)
+    for _ in range(m):
+        i = int(np.argmax(logw))
+        pts.append(float(x[i]))
+        logw = logw + np.log(np.abs(x - x[i]) + 1e-300)
+    return np.array(pts)
+
+
+def exp_divided_differences(rho: float, xi: np.ndarray, digits: int = 80) -> np.ndarray:
+    """d_j = f[xi_0, ..., xi_j] of f(z) = e^{rho z}, by the recursive definition
+    f[x_i..x_k] = (f[x_{i+1}..x_k] - f[x_i..x_{k-1}]) / (x_k - x_i), evaluated in
+    decimal arithmetic with `digits` significant digits.
+
+    Pins: two-point closed form; the mean-value bounds
+    rho^j e^{-2 rho} / j! <= d_j <= rho^j e^{2 rho} / j!; the Newton form
+    reproduces e^{rho xi_j} at the nodes.
+    """
+    from decimal import Decimal, localcontext
+    with localcontext() as ctx:
+        ctx.prec = digits
+        X = [Decimal(repr(float(v))) for v in xi]
+        R = Decimal(repr(float(rho)))
+        col = [(R * x).exp() for x in X]
+        d = [col[0]]
+        for k in range(1, len(X)):
+            col = [(col[i + 1] - col[i]) / (X[i + k] - X[i]) for i in range(len(col) - 1)]
+            d.append(col[0])
+        return np.array([float(v) for v in d])
+
+
+def newton_eval(d: np.ndarray, xi: np.ndarray, z: np.ndarray) -> np.ndarray:
+    """p(z) = sum_j d_j prod_{i<j} (z - xi_i) at the points z."""
+    z = np.asarray(z, dtype=np.float64)
+    p = np.zeros_like(z)
+    w = np.ones_like(z)
+    for j in range(len(d)):
+        p = p + d[j] * w
+        w = w * (z - xi[j])
+    return p
+
+
+def leja_params(rho_total: float, tol: float = 1e-14, rho_max: float = 8.0, m_max: int = 100):
+    """Substeps S and degree m for e^{rho_total z} on [-2, 2]: S substeps of
+    rho = rho_total / S <= rho_max, and the smallest m <= m_max whose Newton
+    interpolant at the Leja points has max |e^{rho z} - p(z)| <= tol e^{2 rho}
+    on a fine grid of [-2, 2] (e^{2 rho} = max of e^{rho z} there).
+    Returns (S, m, rho, xi, d)."""
+    S = max(1, int(math.ceil(rho_total / rho_max)))
+    rho = rho_total / S
+    xi = leja_points(m_max)
+    d = exp_divided_differences(rho, xi)
+    z = np.linspace(-2.0, 2.0, 4001)
+    f = np.exp(rho * z)
+    scale = math.exp(2.0 * rho)
+    for m in range(1, m_max + 1):
+        if np.max(np.abs(newton_eval(d[:m + 1], xi, z) - f)) <= tol * scale:
+            return S, m, rho, xi[:m + 1], d[:m + 1]
+    raise OracleError("Leja interpolation: no degree <= m_max meets the tolerance")
+
+
+def leja_expmv(A: np.ndarray, t: float, V: np.ndarray, tol: float = 1e-14) -> np.ndarray:
+    """e^{tA} V for a symmetric A by Newton interpolation at Leja points (see
+    the section comment): Gershgorin interval, shift and scale to [-2, 2], S
+    substeps of degree m.
+
+    Pins: the exact action V e^{t Lam} V^T of the Laplacian's eigenpairs;
+    ``expm(t A) @ V`` on random symmetric matrices, including t g >> rho_max
+    (several substeps).
+    """
+    A = np.asarray(A, dtype=np.float64)
+    V = np.array(V, dtype=np.float64)
+    a, b = gershgorin_interval(A)
+    c = 0.5 * (a + b)
+    g = 0.25 * (b - a)
+    if g == 0.0:
+        return math.exp(t * c) * V
+    S, m, rho, xi, d = leja_params(t * g, tol)
+    n = A.shape[0]
+    As = (A - c * np.eye(n)) / g
+    for _ in range(S):
+        W = V
+        P = d[0] * V
+        for j in range(m):
+            W = As @ W - xi[j] * W
+            P = P + d[j + 1] * W
+        V = math.exp(t * c / S) * P
+    return V
+
+
+class LejaExpm:
+    """e^{tA^T} as an operator whose ``@`` is ``leja_expmv`` (for
+    ``solve(expm_fn=...)``: the paper's action-based step)."""
+
+    def __init__(self, A: np.ndarray, t: float, tol: float = 1e-14):
+        self.AT = np.ascontiguousarray(np.asarray(A, dtype=np.float64).T)
+        self.t = t
+        self.tol = tol
+
+    def __matmul__(self, V: np.ndarray) -> np.ndarray:
+        return leja_expmv(self.AT, self.t, V, self.tol)
+
+
+def quadrature_factor_leja(A, C, t, K, tol, leja_tol: float = 1e-14):
+    """``quadrature_factor`` with the node actions e^{s_k A^T} C^T by
+    ``leja_expmv`` (Alg. 2 with expleja, as in the paper's Sec. 3)."""
+    s, w = gauss_legendre(K, t)
+    p = C.shape[0]
+    AT = np.ascontiguousarray(np.asarray(A, dtype=np.float64).T)
+    cols = [leja_expmv(AT, sk, np.ascontiguousarray(C.T), leja_tol) for sk in s]
+    blocks = [wk * np.eye(p) for wk in w]
+    return compress(np.hstack(cols), _blkdiag(*blocks), tol)
 
 
 # ----------------------------------------------------------------------------
@@ -449,6 +606,19 @@ def kron_apply_expm(E1: np.ndarray, V: np.ndarray) -> np.ndarray:
         X = V[:, j].reshape(nx, nx, order="F")
         out[:, j] = (E1 @ X @ E1.T).reshape(-1, order="F")
     return out
+
+
+class KronExpm:
+    """e^{tA^T} for A = I (x) A1 + A1 (x) I as an operator: ``E @ V`` applies
+    e^{tA1^T} (x) e^{tA1^T} through ``kron_apply_expm`` instead of forming the
+    n x n matrix (for ``solve(expm_fn=...)`` at large n; same values as
+    ``laplacian_expm_kron(A1, t) @ V``)."""
+
+    def __init__(self, A1: np.ndarray, t: float):
+        self.E1 = expm(t * np.ascontiguousarray(A1.T))
+
+    def __matmul__(self, V: np.ndarray) -> np.ndarray:
+        return kron_apply_expm(self.E1, np.asarray(V, dtype=np.float64))
 
 
 def quadrature_factor_kron(A1, C, t, K, tol):

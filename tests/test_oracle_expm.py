@@ -123,3 +123,14 @@ def test_kron_path_equals_generic():
         V = np.random.default_rng(1).standard_normal((nx * nx, 3))
         E1 = o.expm(t * A1.T)
         assert np.abs(o.kron_apply_expm(E1, V) - Eg @ V).max() < 1e-13
+
+
+def test_kron_operator_matches_dense_kron():
+    """KronExpm @ V equals laplacian_expm_kron(A1, t) @ V (the operator form
+    used by the large-n oracle runs)."""
+    nx, t = 9, 7e-4
+    A1 = w.laplacian_1d(nx)
+    V = np.random.default_rng(1).standard_normal((nx * nx, 5))
+    got = o.KronExpm(A1, t) @ V
+    ref = o.laplacian_expm_kron(A1, t) @ V
+    assert np.abs(got - ref).max() < 1e-14 * np.abs(ref).max()

@@ -184,6 +184,16 @@ def config_gdre(nx: int = 64, h: float = 1e-3, T: float = 0.1) -> Problem:
     return p
 
 
+def config_gdle(nx: int = 64, h: float = 1e-3, T: float = 0.1, split: str = "F12",
+                scheme: str = "strang") -> Problem:
+    """Generalized DLE: C = ones, P0 = 0, S = 0.1 tridiag(1,0,1), no B; split
+    F12 (T12 and T4), F1F2 (T1 T2 T4) or F1F3F2 (T1 T4 T2)."""
+    n = nx * nx
+    return Problem(name=f"gdle_{scheme}_{split.lower()}_n{n}_h{h:g}", A=laplacian_2d(nx),
+                   C=ones_C(n), S=tridiag_S(n, 0.1), T=T, h=h, tol=1e-10, kind="dle",
+                   split=split, scheme=scheme, nx=nx, meta={"seed": 0})
+
+
 def config_dre_quadrant(nx: int = 128, seed: int = 0, p: int = 8, m: int = 4,
                         T: float = 0.1, h: float = 1e-3) -> Problem:
     """DRE with B = 4 quadrant indicators, R = I_4, C = 8 x n N(0,1)/sqrt(n) (seed 0)."""
