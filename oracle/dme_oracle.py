@@ -61,7 +61,7 @@ __all__ = [
     "step_sequence", "solve", "lowrank_fro", "lowrank_rel_err",
     "laplacian_expm_kron", "kron_apply_expm", "quadrature_factor_kron", "KronExpm",
     "gershgorin_interval", "leja_points", "exp_divided_differences", "newton_eval", "leja_params",
-    "leja_expmv", "LejaExpm", "quadrature_factor_leja",
+    "leja_expmv", "LejaExpm", "quadrature_factor_leja", "mass_matrix_form",
     "OracleError",
 ]
 
@@ -447,6 +447,27 @@ def _blkdiag(*blocks):
 
 
 # ----------------------------------------------------------------------------
+# Mass-matrix form (Sec. 5.1, Example 4)
+# ----------------------------------------------------------------------------
+def mass_matrix_form(A, C, M):
+    """Standard-form data of M^T dP/dt M = A^T P M + M^T P A + C^T C + G
+    (G = -M^T P B R^-1 B^T P M for the DRE): multiplying by M^-T on the left
+    and M^-1 on the right gives dP/dt = At^T P + P At + Ct^T Ct - P B R^-1 B^T P
+    with At = A M^-1 and Ct = C M^-1 (B, R unchanged).  Returns (At, Ct).
+
+    Pins: At^T P + P At + Ct^T Ct equals M^-T (A^T P M + M^T P A + Q) M^-1 for
+    any P; a brute-force integration of the equation with M reproduces the
+    split solution at its order; M = I changes nothing.
+    """
+    A = np.asarray(A, dtype=np.float64)
+    C = np.asarray(C, dtype=np.float64)
+    M = np.asarray(M, dtype=np.float64)
+    At = np.linalg.solve(M.T, A.T).T   # A M^-1
+    Ct = np.linalg.solve(M.T, C.T).T   # C M^-1
+    return At, Ct
+
+
+# ----------------------------------------------------------------------------
 # Schemes (Sec. 2, Sec. 3)
 # ----------------------------------------------------------------------------
 def step_sequence(kind: str, has_S: bool, split: str, scheme: str):
@@ -506,18 +527,22 @@ def num_steps(T: float, h: float) -> int:
 
 def solve(A, C, T, h, *, kind="dle", B=None, R=None, S=None, L0=None, D0=None,
           split="F12", scheme="strang", tol=1e-10, quad_nodes=7,
-          expm_fn=None, quad_fn=None, record_ranks=False):
+          expm_fn=None, quad_fn=None, record_ranks=False, M=None):
     """Run the splitting scheme from P0 = L0 D0 L0^T to time T with step h.
 
     expm_fn(t) -> e^{tA^T} and quad_fn(t) -> (L_I, D_I) may be supplied (used
     for the Kronecker-structured Laplacian at large n); by default they are
-    the generic ``expm`` and ``quadrature_factor`` above.
+    the generic ``expm`` and ``quadrature_factor`` above.  With a mass matrix
+    M the equation M^T dP/dt M = ... is first put in standard form
+    (``mass_matrix_form``).
 
     Returns (L, D, info) with P(T) ~ L D L^T.
     """
     A = np.asarray(A, dtype=np.float64)
     n = A.shape[0]
     C = np.asarray(C, dtype=np.float64)
+    if M is not None:
+        A, C = mass_matrix_form(A, C, M)
     N = num_steps(T, h)
     seq = step_sequence(kind, S is not None, split, scheme)
     if kind == "dre":

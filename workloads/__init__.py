@@ -54,6 +54,31 @@ def laplacian_1d(nx: int) -> np.ndarray:
     return np.asfortranarray(tridiag_1d(nx) / (dx * dx))
 
 
+def fe_heat_2d(nx: int, grading: float = 1.3):
+    """Bilinear finite elements for the heat equation on the unit square with
+    Dirichlet boundary on a tensor mesh graded towards x = 0 and y = 0 (1-D
+    nodes x_i = (i / (nx + 1))^grading, nx interior nodes per side, x
+    fastest): returns (A, M) with the mass matrix M = M1 (x) M1 and the
+    stiffness A = -(K1 (x) M1 + M1 (x) K1), M1 and K1 the 1-D linear-element
+    mass and stiffness matrices on the interior nodes.  On a graded mesh M1 and
+    K1 do not commute, so A M^-1 differs from M^-1 A.  A synthetic stand-in for
+    the mass / stiffness pair of the steel-cooling example (whose
+    finite-element data is not available)."""
+    x = (np.arange(nx + 2) / (nx + 1.0)) ** grading
+    he = np.diff(x)                      # element lengths, nx + 1 of them
+    M1 = np.zeros((nx, nx))
+    K1 = np.zeros((nx, nx))
+    for i in range(nx):                  # interior node i + 1 between elements i and i + 1
+        M1[i, i] = (he[i] + he[i + 1]) / 3.0
+        K1[i, i] = 1.0 / he[i] + 1.0 / he[i + 1]
+        if i + 1 < nx:
+            M1[i, i + 1] = M1[i + 1, i] = he[i + 1] / 6.0
+            K1[i, i + 1] = K1[i + 1, i] = -1.0 / he[i + 1]
+    M = np.asfortranarray(np.kron(M1, M1))
+    A = np.asfortranarray(-(np.kron(K1, M1) + np.kron(M1, K1)))
+    return A, M
+
+
 def grid_coords(nx: int):
     """x and y coordinates (length n) of the interior grid points, x fastest."""
     dx = 1.0 / (nx + 1)
@@ -138,6 +163,7 @@ class Problem:
     S: Optional[np.ndarray] = None
     L0: Optional[np.ndarray] = None
     D0: Optional[np.ndarray] = None
+    M: Optional[np.ndarray] = None      # mass matrix (None: identity)
     T: float = 0.1
     h: float = 1e-3
     tol: float = 1e-10
@@ -192,6 +218,18 @@ def config_gdle(nx: int = 64, h: float = 1e-3, T: float = 0.1, split: str = "F12
     return Problem(name=f"gdle_{scheme}_{split.lower()}_n{n}_h{h:g}", A=laplacian_2d(nx),
                    C=ones_C(n), S=tridiag_S(n, 0.1), T=T, h=h, tol=1e-10, kind="dle",
                    split=split, scheme=scheme, nx=nx, meta={"seed": 0})
+
+
+def config_dre_mass(nx: int = 8, h: float = 1e-3, T: float = 0.05, scheme: str = "strang",
+                    split: str = "F12", p: int = 3, m: int = 2, seed: int = 0) -> Problem:
+    """DRE in mass-matrix form (M^T dP/dt M = A^T P M + M^T P A + C^T C - ...)
+    with the bilinear finite-element pair of ``fe_heat_2d``, B = the first m
+    quadrant indicators, R = I, C = p x n N(0,1)/sqrt(n)."""
+    n = nx * nx
+    A, M = fe_heat_2d(nx)
+    return Problem(name=f"dre_mass_{scheme}_n{n}", A=A, C=random_C(p, n, seed), B=quadrant_B(nx, m),
+                   R=np.eye(m, order="F"), M=M, T=T, h=h, tol=1e-10, kind="dre", split=split,
+                   scheme=scheme, nx=nx, meta={"seed": seed})
 
 
 def config_dre_quadrant(nx: int = 128, seed: int = 0, p: int = 8, m: int = 4,
