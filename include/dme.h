@@ -52,17 +52,35 @@ typedef struct dme_ctx dme_ctx;
 typedef struct dme_result dme_result;
 typedef struct dme_solver dme_solver;
 
-/* Problem data (Sec. 1 equation; Sec. 2.2 Riccati term; Sec. 2.3 S term).
- * All pointers are host pointers, n x n / n x m / p x n / m x m / n x r0 / r0 x r0. */
+/* Problem data (Sec. 1 equation; Sec. 2.2 Riccati term; Sec. 2.3 S term;
+ * Sec. 5.1 Ex. 4 mass matrix).  All pointers are host pointers,
+ * n x n / n x m / p x n / m x m / n x r0 / r0 x r0.  The fields after D0 are
+ * optional: zero-initialise the struct and set what is used.
+ *
+ * Mass-matrix form (Sec. 5.1, Ex. 4): with M given the equation is
+ *     M^T dP/dt M = A^T P M + M^T P A + Q + (Riccati / S terms in M^T P M),
+ * solved as the standard form with A M^-1 in place of A and C M^-1 in place
+ * of C (the library factors M^T once by LU with partial pivoting on the
+ * device); B, R, S keep their meaning.  Needs the dense A.
+ *
+ * Sparse A (for DME_ACTION_LEJA, the paper's operator-action method):
+ * A_rowptr (n + 1 entries, A_rowptr[0] = 0), A_colind and A_val (nnz
+ * entries each, column indices in [0, n)) hold A in CSR form; A may then be
+ * NULL.  The library transposes it on the host once and keeps A^T in CSR form
+ * on the device. */
 typedef struct {
   int64_t n, m, p, r0;
-  const double *A;  /* n x n, required                                   */
+  const double *A;  /* n x n, required unless A is given in CSR form        */
   const double *B;  /* n x m, NULL iff m == 0                             */
   const double *C;  /* p x n, Q = C^T C, required (p >= 1)                */
   const double *R;  /* m x m SPD, NULL iff m == 0                         */
   const double *S;  /* n x n or NULL (adds S P S^T)                       */
   const double *L0; /* n x r0 (NULL iff r0 == 0, i.e. P0 = 0)             */
   const double *D0; /* r0 x r0 symmetric                                  */
+  const double *M;  /* n x n mass matrix or NULL (M = I)                   */
+  const int64_t *A_rowptr; /* CSR of A: n + 1 row pointers, or NULL         */
+  const int64_t *A_colind; /* nnz column indices                            */
+  const double *A_val;     /* nnz values (NULL: no CSR form)                */
 } dme_problem;
 
 /* Composition order (operators act right to left, Sec. 2):
@@ -80,10 +98,25 @@ typedef enum { DME_LIE = 0, DME_STRANG = 1 } dme_scheme;
 typedef enum { DME_SPLIT_F12 = 0, DME_SPLIT_F1F2 = 1, DME_SPLIT_F1F3F2 = 2 } dme_split;
 
 /* DME_FP64: every product in FP64 MFMA.
- * DME_MIXED: the e^{tA^T} L and quadrature products in split BF16 MFMA with
- *            FP32 accumulation flushed to FP64; Pade, squaring, LU and the
- *            compression stay FP64.                                        */
+ * DME_MIXED: the step products e^{tA^T} L (the T1 / T12 products of every
+ *            step, the bulk of a step's flops and HBM traffic) in split BF16
+ *            MFMA with FP32 accumulation flushed to FP64.  The operator setup
+ *            (Pade, LU, squaring), the quadrature factor (formed once per step
+ *            size), the compression, T3 and T4 stay FP64.  Each result states
+ *            its estimated distance to the FP64 computation (dme_result_info). */
 typedef enum { DME_FP64 = 0, DME_MIXED = 1 } dme_precision;
+
+/* How e^{tA^T} L is applied in the T1 / T12 products:
+ * DME_ACTION_DENSE: the dense operator e^{tA^T}, formed once per step fraction
+ *            by Pade scaling and squaring (Higham 2005), applied by GEMM.
+ * DME_ACTION_LEJA: the paper's expleja (Sec. 3, Sec. 4): Newton interpolation
+ *            of e^{t A^T} at Leja points of the Gershgorin interval, applied
+ *            by products with A^T (CSR when A is given in CSR form, else the
+ *            dense A); no n x n exponential is formed.  FP64 only; needs a
+ *            symmetric A (real spectrum) and no mass matrix.
+ * Either way the quadrature nodes of T12 use the Leja action when A is
+ * symmetric (or in CSR form) and node exponentials otherwise.              */
+typedef enum { DME_ACTION_DENSE = 0, DME_ACTION_LEJA = 1 } dme_action;
 
 typedef struct {
   double T;        /* final time                                            */
@@ -94,6 +127,7 @@ typedef struct {
   int precision;   /* dme_precision                                         */
   int quad_nodes;  /* Gauss-Legendre nodes K for T12 (0 -> 7)               */
   int64_t max_rank;/* rank cap (0 -> min(n, 512))                           */
+  int action;      /* dme_action (0: dense exponential)                     */
 } dme_opts;
 
 /* ------------------------------------------------------------- context */
@@ -155,7 +189,18 @@ int dme_solver_profile_get(dme_solver *sv, int phase, int64_t *count, double *ms
 void dme_solver_free(dme_solver *sv);
 
 /* ------------------------------------------------------------- results */
-int dme_result_info(const dme_result *res, int64_t *n, int64_t *r, int64_t *steps);
+/* n, rank r and steps taken of a result, and err_est: the estimated relative
+ * Frobenius distance ||P - P64||_F / ||P64||_F between this P = L D L^T and the
+ * same scheme computed in FP64 throughout (the precision of the paper's
+ * method).  err_est = 2 N_p max(delta, sqrt(n) u) with N_p the products
+ * e^{tA^T} L the solve applied, u = 2^-53, and delta = 0 for DME_FP64 results;
+ * for DME_MIXED results delta is the relative Frobenius error of one
+ * split-BF16 product, measured when the result is taken by forming e^{tA^T} L
+ * of the final factor both ways (two products on the device).  It assumes
+ * that the per-product errors add without amplification (the flows are
+ * contractive): a first-order upper estimate, not a rigorous bound.  Any
+ * output pointer may be NULL.                                               */
+int dme_result_info(const dme_result *res, int64_t *n, int64_t *r, int64_t *steps, double *err_est);
 /* L: n x r host buffer, D: r x r host buffer, both caller-allocated. */
 int dme_result_copy(const dme_result *res, double *L, double *D);
 void dme_result_free(dme_result *res);
@@ -185,6 +230,19 @@ int dme_gemm_f64(dme_ctx *ctx, char transa, char transb, int64_t M, int64_t N, i
  * copy resident instead).  E and Y must not alias.                         */
 int dme_gemm_mixed(dme_ctx *ctx, int64_t n, int64_t r, const double *E, const double *X,
                    int64_t ldx, double *Y, int64_t ldy);
+
+/* Y = e^{t A^T} X by the Leja-interpolation action (the paper's expleja,
+ * Sec. 3 and Sec. 4): Gershgorin interval of A, Newton interpolation of
+ * e^{t z} at Leja points in S substeps of degree m (chosen so that each
+ * substep errs by at most 1e-14 relative for a symmetric A), products with A^T
+ * only.  A is either dense on the device (n x n, ld n; A_rowptr NULL) or in
+ * CSR form on the host (A_rowptr n + 1, A_colind / A_val nnz; A_dev NULL).
+ * A must be symmetric (DME_EINVAL otherwise).  X, Y: n x ncols device (ld n),
+ * may alias.  *S_out, *m_out (host, optional) get the substeps and degree.
+ * Synchronises the stream.                                                  */
+int dme_expmv_leja(dme_ctx *ctx, int64_t n, const double *A_dev, const int64_t *A_rowptr,
+                   const int64_t *A_colind, const double *A_val, double t, int64_t ncols,
+                   const double *X, double *Y, int *S_out, int *m_out);
 
 /* Column compression (Sec. 3 after Alg. 2): Householder QR W = Q R,
  * M = R Dhat R^T, M = V Lam V^T, keep |lam_i| > tol max|lam| (sorted by |lam|

@@ -37,6 +37,8 @@ DME_FP64, DME_MIXED = 0, 1
 SCHEMES = {"lie": DME_LIE, "strang": DME_STRANG}
 SPLITS = {"F12": DME_SPLIT_F12, "F1F2": DME_SPLIT_F1F2, "F1F3F2": DME_SPLIT_F1F3F2}
 PRECISIONS = {"fp64": DME_FP64, "mixed": DME_MIXED}
+DME_ACTION_DENSE, DME_ACTION_LEJA = 0, 1
+ACTIONS = {"dense": DME_ACTION_DENSE, "leja": DME_ACTION_LEJA}
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(
@@ -60,12 +62,13 @@ _pd = ctypes.POINTER(ctypes.c_double)
 
 class Problem(ctypes.Structure):
     _fields_ = [("n", _i64), ("m", _i64), ("p", _i64), ("r0", _i64),
-                ("A", _p), ("B", _p), ("C", _p), ("R", _p), ("S", _p), ("L0", _p), ("D0", _p)]
+                ("A", _p), ("B", _p), ("C", _p), ("R", _p), ("S", _p), ("L0", _p), ("D0", _p),
+                ("M", _p), ("A_rowptr", _p), ("A_colind", _p), ("A_val", _p)]
 
 
 class Opts(ctypes.Structure):
     _fields_ = [("T", _dbl), ("h", _dbl), ("tol", _dbl), ("scheme", _int), ("split", _int),
-                ("precision", _int), ("quad_nodes", _int), ("max_rank", _i64)]
+                ("precision", _int), ("quad_nodes", _int), ("max_rank", _i64), ("action", _int)]
 
 
 def _sig(name, res, args):
@@ -97,7 +100,8 @@ _lib_solver_profile_get = _sig("dme_solver_profile_get", _int,
                                 ctypes.POINTER(_dbl), ctypes.POINTER(_dbl)])
 PHASES = {"step_gemm": 0, "compress": 1, "riccati": 2, "S": 3, "step_kernel": 4}
 _lib_result_info = _sig("dme_result_info", _int,
-                        [_p, ctypes.POINTER(_i64), ctypes.POINTER(_i64), ctypes.POINTER(_i64)])
+                        [_p, ctypes.POINTER(_i64), ctypes.POINTER(_i64), ctypes.POINTER(_i64),
+                         ctypes.POINTER(_dbl)])
 _lib_result_copy = _sig("dme_result_copy", _int, [_p, _p, _p])
 _lib_result_free = _sig("dme_result_free", None, [_p])
 _lib_expm = _sig("dme_expm", _int, [_p, _i64, _p, _dbl, _p, ctypes.POINTER(_int), ctypes.POINTER(_int)])
@@ -106,6 +110,8 @@ _lib_gemm = _sig("dme_gemm_f64", _int, [_p, ctypes.c_char, ctypes.c_char, _i64, 
 _lib_gemm_mixed = _sig("dme_gemm_mixed", _int, [_p, _i64, _i64, _p, _p, _i64, _p, _i64])
 _lib_compress = _sig("dme_compress", _int, [_p, _i64, _i64, _p, _p, _dbl, _i64, _p, _p, ctypes.POINTER(_i64)])
 _lib_riccati = _sig("dme_riccati", _int, [_p, _i64, _i64, _i64, _p, _p, _p, _dbl, _p])
+_lib_expmv_leja = _sig("dme_expmv_leja", _int, [_p, _i64, _p, _p, _p, _p, _dbl, _i64, _p, _p,
+                                                 ctypes.POINTER(_int), ctypes.POINTER(_int)])
 _lib_syev = _sig("dme_syev", _int, [_p, _i64, _p, _dbl, _i64, _p, _p, ctypes.POINTER(_i64)])
 
 _lib_register = _sig("dme_register_operator", _int, [_p, _p, _i64, ctypes.POINTER(ctypes.c_uint64)])
@@ -193,17 +199,30 @@ class SolveOptions:
     precision: str = "fp64"
     quad_nodes: int = 7
     max_rank: int = 0
+    action: str = "dense"
 
     def to_c(self) -> Opts:
         return Opts(self.T, self.h, self.tol, SCHEMES[self.scheme], SPLITS[self.split],
-                    PRECISIONS[self.precision], self.quad_nodes, self.max_rank)
+                    PRECISIONS[self.precision], self.quad_nodes, self.max_rank, ACTIONS[self.action])
 
 
 class _HostProblem:
-    """Keeps Fortran-ordered host copies alive for the duration of a call."""
+    """Keeps Fortran-ordered host copies alive for the duration of a call.
+    A may be a dense matrix or a CSR triple (rowptr, colind, values), e.g.
+    from scipy.sparse's (indptr, indices, data); M is the optional dense mass
+    matrix."""
 
-    def __init__(self, A, C, B=None, R=None, S=None, L0=None, D0=None, n=None):
-        self.A = _host_f(A) if n is None else None
+    def __init__(self, A, C, B=None, R=None, S=None, L0=None, D0=None, n=None, M=None):
+        self.csr = None
+        if n is None and isinstance(A, tuple):
+            rp, ci, va = A
+            self.csr = (np.ascontiguousarray(rp, dtype=np.int64), np.ascontiguousarray(ci, dtype=np.int64),
+                        np.ascontiguousarray(va, dtype=np.float64))
+            n = len(self.csr[0]) - 1
+            self.A = None
+        else:
+            self.A = _host_f(A) if n is None else None
+        self.M = _host_f(M)
         self.C = _host_f(C)
         self.B = _host_f(B)
         self.R = _host_f(R)
@@ -221,18 +240,28 @@ class _HostProblem:
         def ptr(a):
             return a.ctypes.data if a is not None and a.size else None
 
+        csr = [ptr(a) for a in self.csr] if self.csr is not None else [None, None, None]
+        if self.csr is not None and self.csr[2].size == 0:
+            raise ValueError("CSR A without entries")
         self.c = Problem(n, m, p, r0, ptr(self.A), ptr(self.B), ptr(self.C), ptr(self.R),
-                         ptr(self.S), ptr(self.L0), ptr(self.D0))
+                         ptr(self.S), ptr(self.L0), ptr(self.D0), ptr(self.M), *csr)
 
 
 class Result:
     def __init__(self, handle):
         self._h = handle
 
+    def info(self):
+        """(n, r, steps, err_est) of the result (dme_result_info)."""
+        n, r, steps, err = _i64(), _i64(), _i64(), _dbl()
+        _check(_lib_result_info(self._h, ctypes.byref(n), ctypes.byref(r), ctypes.byref(steps),
+                                ctypes.byref(err)), "dme_result_info")
+        return int(n.value), int(r.value), int(steps.value), float(err.value)
+
     def fetch(self):
         n, r, steps = _i64(), _i64(), _i64()
-        _check(_lib_result_info(self._h, ctypes.byref(n), ctypes.byref(r), ctypes.byref(steps)),
-               "dme_result_info")
+        _check(_lib_result_info(self._h, ctypes.byref(n), ctypes.byref(r), ctypes.byref(steps),
+                                None), "dme_result_info")
         L = np.zeros((n.value, r.value), order="F")
         D = np.zeros((r.value, r.value), order="F")
         _check(_lib_result_copy(self._h, L.ctypes.data if L.size else None,
@@ -326,6 +355,27 @@ class Context:
                "dme_riccati")
         return from_cm(Ds)
 
+    def expmv_leja(self, A, t: float, X):
+        """Y = e^{t A^T} X by the Leja-interpolation action; A is a dense
+        matrix (copied to the device) or a host CSR triple (rowptr, colind,
+        values).  Returns (Y, S, m)."""
+        Xs = to_device_cm(X)
+        n, c = Xs.shape[1], Xs.shape[0]
+        Ys = empty_cm(n, c)
+        S, m = _int(), _int()
+        if isinstance(A, tuple):
+            rp = np.ascontiguousarray(A[0], dtype=np.int64)
+            ci = np.ascontiguousarray(A[1], dtype=np.int64)
+            va = np.ascontiguousarray(A[2], dtype=np.float64)
+            _check(_lib_expmv_leja(self._h, n, None, rp.ctypes.data, ci.ctypes.data, va.ctypes.data,
+                                   float(t), c, _ptr(Xs), _ptr(Ys), ctypes.byref(S), ctypes.byref(m)),
+                   "dme_expmv_leja")
+        else:
+            As = to_device_cm(A)
+            _check(_lib_expmv_leja(self._h, n, _ptr(As), None, None, None, float(t), c, _ptr(Xs),
+                                   _ptr(Ys), ctypes.byref(S), ctypes.byref(m)), "dme_expmv_leja")
+        return from_cm(Ys), int(S.value), int(m.value)
+
     def syev(self, M, tol: float = 0.0, max_keep: Optional[int] = None):
         Ms = to_device_cm(M)
         k = Ms.shape[0]
@@ -351,31 +401,39 @@ class Context:
         return Server(self, hbm_budget_bytes, max_slots)
 
     # ------------------------------------------------ whole solves
-    def solve(self, kind: str, opts: SolveOptions, A, C, B=None, R=None, S=None, L0=None, D0=None):
-        hp = _HostProblem(A, C, B, R, S, L0, D0)
+    def solve(self, kind: str, opts: SolveOptions, A, C, B=None, R=None, S=None, L0=None, D0=None,
+              err_est: bool = False, M=None):
+        """(L, D, steps) of a whole solve; with err_est=True also the result's
+        estimated distance to the FP64 computation.  A is dense or a CSR
+        triple (rowptr, colind, values); M the optional mass matrix."""
+        hp = _HostProblem(A, C, B, R, S, L0, D0, M=M)
         o = opts.to_c()
         out = _p()
         fn = _lib_dre_solve if kind == "dre" else _lib_dle_solve
         _check(fn(self._h, ctypes.byref(hp.c), ctypes.byref(o), ctypes.byref(out)),
                "dre_solve" if kind == "dre" else "dle_solve")
-        return Result(out).fetch()
+        res = Result(out)
+        L, D, steps = res.fetch()
+        return (L, D, steps, res.info()[3]) if err_est else (L, D, steps)
 
-    def solver(self, kind: str, opts: SolveOptions, A, C, B=None, R=None, S=None, L0=None, D0=None):
-        return Solver(self, kind, opts, A, C, B, R, S, L0, D0)
+    def solver(self, kind: str, opts: SolveOptions, A, C, B=None, R=None, S=None, L0=None, D0=None,
+               M=None):
+        return Solver(self, kind, opts, A, C, B, R, S, L0, D0, M=M)
 
 
 class Solver:
     """Stepwise solve: setup once, then advance with all data in HBM."""
 
-    def __init__(self, ctx: Context, kind, opts, A, C, B=None, R=None, S=None, L0=None, D0=None):
+    def __init__(self, ctx: Context, kind, opts, A, C, B=None, R=None, S=None, L0=None, D0=None,
+                 M=None):
         self.ctx = ctx
-        hp = _HostProblem(A, C, B, R, S, L0, D0)
+        hp = _HostProblem(A, C, B, R, S, L0, D0, M=M)
         o = opts.to_c()
         h = _p()
         _check(_lib_solver_create(ctx._h, ctypes.byref(hp.c), ctypes.byref(o), 1 if kind == "dre" else 0,
                                   ctypes.byref(h)), "dme_solver_create")
         self._h = h
-        self.n = int(np.asarray(A).shape[0])
+        self.n = int(hp.c.n)
         self.m = int(np.asarray(B).shape[1]) if B is not None else 0
 
     def step(self, nsteps: int = 1):
@@ -411,10 +469,12 @@ class Solver:
                                        ctypes.byref(fl), ctypes.byref(by)), "dme_solver_profile_get")
         return {"count": int(c.value), "ms": ms.value, "flops": fl.value, "bytes": by.value}
 
-    def result(self):
+    def result(self, err_est: bool = False):
         out = _p()
         _check(_lib_solver_result(self._h, ctypes.byref(out)), "dme_solver_result")
-        return Result(out).fetch()
+        res = Result(out)
+        L, D, steps = res.fetch()
+        return (L, D, steps, res.info()[3]) if err_est else (L, D, steps)
 
     def close(self):
         if getattr(self, "_h", None):
@@ -465,7 +525,7 @@ class Server:
                                    ctypes.byref(qs)), "dme_result_serving")
         L, D, steps = res.fetch()
         info = {"precision": "mixed" if prec.value == DME_MIXED else "fp64", "fell_back": bool(fb.value),
-                "latency_s": lat.value, "queue_s": qs.value}
+                "latency_s": lat.value, "queue_s": qs.value, "err_est": res.info()[3]}
         return L, D, steps, info
 
     def stats(self) -> dict:

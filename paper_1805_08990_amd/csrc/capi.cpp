@@ -1,5 +1,7 @@
 // C ABI (include/dme.h): argument checking, error codes, ownership.
+#include <algorithm>
 #include <cstring>
+#include <functional>
 #include <memory>
 #include <new>
 
@@ -40,6 +42,7 @@ dme_result* result_from_solver(Solver& sv) {
   res->r = sv.r;
   res->steps = sv.step;
   res->precision = sv.opts.precision;
+  res->err_est = sv.err_estimate();
   res->L.resize((size_t)sv.n * sv.r);
   res->D.resize((size_t)sv.r * sv.r);
   if (sv.r > 0) {
@@ -81,6 +84,14 @@ int guarded(F&& f) {
     return DME_EINTERNAL;
   }
 }
+
+}  // namespace
+
+namespace dme {
+int guarded_call(const std::function<void()>& f) { return guarded(f); }
+}  // namespace dme
+
+namespace {
 
 int* ctx_flags(dme_ctx* c) { return c->flags.as<int>(); }
 int64_t* ctx_rank(dme_ctx* c) { return reinterpret_cast<int64_t*>(c->flags.as<char>() + 16); }
@@ -154,6 +165,7 @@ void dme_destroy(dme_ctx* ctx) {
   if (!ctx) return;
   (void)hipSetDevice(ctx->device);
   (void)hipStreamSynchronize(ctx->stream);
+  ctx->aux.release();
   if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
   delete ctx;
 }
@@ -268,12 +280,13 @@ void dme_solver_free(dme_solver* sv) {
   delete sv;
 }
 
-int dme_result_info(const dme_result* res, int64_t* n, int64_t* r, int64_t* steps) {
+int dme_result_info(const dme_result* res, int64_t* n, int64_t* r, int64_t* steps, double* err_est) {
   return guarded([&] {
     DME_REQUIRE(res != nullptr, DME_EINVAL, "null result");
     if (n) *n = res->n;
     if (r) *r = res->r;
     if (steps) *steps = res->steps;
+    if (err_est) *err_est = res->err_est;
   });
 }
 
@@ -342,6 +355,44 @@ int dme_gemm_mixed(dme_ctx* ctx, int64_t n, int64_t r, const double* E, const do
   });
 }
 
+int dme_expmv_leja(dme_ctx* ctx, int64_t n, const double* A_dev, const int64_t* A_rowptr,
+                   const int64_t* A_colind, const double* A_val, double t, int64_t ncols,
+                   const double* X, double* Y, int* S_out, int* m_out) {
+  return guarded([&] {
+    require_ctx(ctx);
+    DME_REQUIRE(n >= 0 && ncols >= 0, DME_EINVAL, "expmv_leja: negative size");
+    DME_REQUIRE(std::isfinite(t) && t >= 0, DME_EINVAL, "expmv_leja: t must be finite and >= 0");
+    DME_REQUIRE((A_dev != nullptr) != (A_rowptr != nullptr), DME_EINVAL,
+                "expmv_leja: give A either dense (device) or in CSR form (host)");
+    DME_HIP(hipSetDevice(ctx->device));
+    if (n == 0) return;
+    DME_REQUIRE(ncols == 0 || (X && Y), DME_EINVAL, "expmv_leja: null X or Y");
+    std::shared_ptr<dme::LejaOp> op;
+    dme::DevBuf AT;
+    ctx->ws.reserve((size_t)dme::cdiv(n, 32) * dme::cdiv(n, 32) * 2 * sizeof(double) +
+                    2 * n * sizeof(double) + 4096);
+    if (A_dev) {
+      AT.ensure((size_t)n * n * sizeof(double));
+      dme::transpose_f64(ctx->stream, A_dev, n, AT.as<double>(), n, n, n, 1.0);
+      DME_REQUIRE(dme::dense_symmetric(ctx->stream, n, AT.as<double>(), 1e-14, ctx->ws), DME_EINVAL,
+                  "expmv_leja: A is not symmetric");
+      op = dme::leja_op_dense(ctx->stream, n, AT.as<double>(), ctx->ws);
+    } else {
+      op = dme::leja_op_csr(ctx->stream, n, A_rowptr, A_colind, A_val, ctx->ws);
+      const bool sym = op->symmetric;
+      DME_REQUIRE(sym, DME_EINVAL, "expmv_leja: A is not symmetric");
+    }
+    std::unique_ptr<dme::LejaPlan> plan = dme::leja_plan(*op, {t}, 1);
+    if (S_out) *S_out = plan->S;
+    if (m_out) *m_out = plan->m;
+    if (ncols > 0) {
+      ctx->ws.reserve(dme::leja_workspace(n, ncols));
+      dme::leja_apply(ctx->stream, *op, *plan, X, n, ncols, Y, n, ctx->ws);
+    }
+    DME_HIP(hipStreamSynchronize(ctx->stream));
+  });
+}
+
 int dme_compress(dme_ctx* ctx, int64_t n, int64_t k, double* W, const double* Dhat, double tol,
                  int64_t max_rank, double* L, double* D, int64_t* r_out) {
   return guarded([&] {
@@ -353,6 +404,7 @@ int dme_compress(dme_ctx* ctx, int64_t n, int64_t k, double* W, const double* Dh
     int64_t r = 0;
     if (k > 0 && n > 0) {
       ctx->ws.reserve(dme::compress_workspace(n, k));
+      dme::AuxBinding bind(ctx->aux);
       ctx_reset_flags(ctx);
       r = dme::compress_f64(ctx->stream, n, k, W, Dhat, tol, std::min(max_rank, std::min(n, k)), L,
                             n, D, max_rank, ctx_rank(ctx), ctx_flags(ctx), ctx->ws);
@@ -396,6 +448,7 @@ int dme_syev(dme_ctx* ctx, int64_t k, const double* M, double tol, int64_t max_k
     if (k > 0) {
       DME_REQUIRE(M && lam && V, DME_EINVAL, "syev: null pointer");
       ctx->ws.reserve(dme::syev_workspace(k));
+      dme::AuxBinding bind(ctx->aux);
       ctx_reset_flags(ctx);
       dme::syev_trunc_f64(ctx->stream, k, M, k, tol, std::min(max_keep, k), lam, V, k,
                           ctx_rank(ctx), ctx_flags(ctx), ctx->ws);
@@ -418,6 +471,12 @@ int dme_register_operator(dme_ctx* ctx, const double* A, int64_t n, uint64_t* op
     op->AT.ensure((size_t)n * n * sizeof(double));
     dme::transpose_f64(ctx->stream, tmp.as<double>(), n, op->AT.as<double>(), n, n, n, 1.0);
     DME_HIP(hipStreamSynchronize(ctx->stream));
+    {
+      dme::Arena lws;
+      lws.reserve((size_t)dme::cdiv(n, 32) * dme::cdiv(n, 32) * 2 * sizeof(double) + 2 * n * sizeof(double) + 4096);
+      if (dme::dense_symmetric(ctx->stream, n, op->AT.as<double>(), 1e-14, lws))
+        op->lop = dme::leja_op_dense(ctx->stream, n, op->AT.as<double>(), lws);
+    }
     std::lock_guard<std::mutex> g(ctx->ops_mu);
     op->id = ctx->next_op++;
     ctx->ops[op->id] = op;

@@ -186,6 +186,11 @@ void blkdiag2_f64(hipStream_t s, const double* D1, int64_t k1, int64_t ld1, cons
 // Scaled column block copy: Y[:, j] = alpha * X[:, j]
 void copy_scaled_f64(hipStream_t s, const double* X, int64_t ldx, double* Y, int64_t ldy,
                      int64_t rows, int64_t cols, double alpha);
+// out[0] = sum (A - B)^2, out[1] = sum B^2 over a rows x cols block (device
+// doubles); `part` is a device scratch of diff_norms_workspace() bytes.
+size_t diff_norms_workspace();
+void diff_norms_f64(hipStream_t s, const double* A, int64_t lda, const double* B, int64_t ldb,
+                    int64_t rows, int64_t cols, double* part, double* out);
 // NaN/Inf scan: sets *flag = 1 if any entry of X is not finite.
 void finite_check_f64(hipStream_t s, const double* X, int64_t rows, int64_t cols, int64_t ld,
                       int* flag);
@@ -196,16 +201,39 @@ struct LuWork;
 // Returns through *info_dev (device int): 0 ok, j+1 if pivot j is exactly zero.
 void lu_solve_f64(hipStream_t s, int64_t n, double* P, double* Q, Arena& ws, int* info_dev);
 size_t lu_solve_workspace(int64_t n);
+// The same with an n x nrhs right-hand side Q (ld ldq).
+void lu_solve_f64(hipStream_t s, int64_t n, double* P, double* Q, int64_t ldq, int64_t nrhs, Arena& ws,
+                  int* info_dev);
+size_t lu_solve_workspace(int64_t n, int64_t nrhs);
 
-// A second stream and a ring of events per host thread and device, for work
-// that runs beside the caller's stream (default priority, created on first
-// use; they are not destroyed, since a thread's end may come after the
-// runtime's).  Defined in tsqr.hip.
+// A second stream beside the caller's, a ring of events for the waits
+// between the two, and a pinned, coherent host slot through which a one-thread
+// kernel hands a scalar (a compression's rank) to the host without a stream
+// synchronisation.  Every solver and every context owns one: it is created on
+// first use (on the current device) and destroyed with its owner, after the
+// owner's stream and the second stream are synchronised, so no event or slot
+// outlives the work that uses it.  The owner binds it to the calling host
+// thread (AuxBinding) while it enqueues work; the tree QR, the compressions
+// and the eigensolver use the bound one.
 struct AuxStream {
+  struct Slot {
+    int64_t value;
+    int64_t seq;
+  };
   int device = -1;
   hipStream_t s2 = nullptr;
   std::vector<hipEvent_t> ev;
   size_t next = 0;
+  Slot* slot = nullptr;  // pinned, coherent host memory
+  int64_t seq = 0;       // last sequence number handed to the slot
+  AuxStream() = default;
+  AuxStream(const AuxStream&) = delete;
+  AuxStream& operator=(const AuxStream&) = delete;
+  ~AuxStream() { release(); }
+  // Create the stream, events and slot on device `dev` (the current device).
+  void ensure(int dev);
+  // Synchronise the second stream and destroy what ensure() created.
+  void release();
   // A recorded event is only waited on by calls enqueued right after its
   // record, so a ring much longer than the waits in flight can be reused.
   hipEvent_t record(hipStream_t st) {
@@ -215,7 +243,20 @@ struct AuxStream {
     return e;
   }
 };
+// The AuxStream bound to the calling thread (created on first use); fails
+// with DME_EINTERNAL when none is bound.
 AuxStream& aux_stream();
+// Binds `a` to the calling thread for the lifetime of the binding (nestable).
+class AuxBinding {
+ public:
+  explicit AuxBinding(AuxStream& a);
+  ~AuxBinding();
+  AuxBinding(const AuxBinding&) = delete;
+  AuxBinding& operator=(const AuxBinding&) = delete;
+
+ private:
+  AuxStream* prev_;
+};
 
 // Householder QR + eigen compression (compress.hip)
 size_t compress_workspace(int64_t n, int64_t k);

@@ -284,16 +284,12 @@ __global__ __launch_bounds__(256) void ts_update_kernel(int64_t n, int q, int r,
   }
 }
 
-// The compression's rank goes to the host through a pinned, coherent slot:
-// one thread copies it and then bumps the slot's sequence number, and the host
-// polls that number (a stream synchronisation sleeps, which costs tens of
-// microseconds of idle device time per compression).
-struct RankSlot {
-  int64_t value;
-  int64_t seq;
-};
-
-__global__ void rank_to_host_kernel(const int64_t* __restrict__ src, RankSlot* slot, int64_t seq) {
+// The compression's rank goes to the host through the pinned, coherent slot
+// of the bound auxiliary stream: one thread copies it and then bumps the
+// slot's sequence number, and the host polls that number (a stream
+// synchronisation sleeps, which costs tens of microseconds of idle device time
+// per compression).
+__global__ void rank_to_host_kernel(const int64_t* __restrict__ src, AuxStream::Slot* slot, int64_t seq) {
   if (threadIdx.x == 0) {
     const int64_t v = *(volatile const int64_t*)src;
     __hip_atomic_store(&slot->value, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
@@ -302,40 +298,22 @@ __global__ void rank_to_host_kernel(const int64_t* __restrict__ src, RankSlot* s
 }
 
 int64_t rank_to_host(hipStream_t s, const int64_t* rank_dev) {
-  struct Slots {
-    int device = -1;
-    RankSlot* slot = nullptr;
-    int64_t seq = 0;
-  };
-  static thread_local std::vector<Slots> per_device;  // pinned slots are never freed
-  int dev = 0;
-  DME_HIP(hipGetDevice(&dev));
-  Slots* sl = nullptr;
-  for (Slots& x : per_device)
-    if (x.device == dev) sl = &x;
-  if (!sl) {
-    Slots x;
-    x.device = dev;
-    DME_HIP(hipHostMalloc((void**)&x.slot, sizeof(RankSlot), hipHostMallocCoherent));
-    x.slot->value = 0;
-    x.slot->seq = 0;
-    per_device.push_back(x);
-    sl = &per_device.back();
-  }
-  const int64_t seq = ++sl->seq;
-  hipLaunchKernelGGL(rank_to_host_kernel, dim3(1), dim3(64), 0, s, rank_dev, sl->slot, seq);
+  AuxStream& ax = aux_stream();
+  AuxStream::Slot* slot = ax.slot;
+  const int64_t seq = ++ax.seq;
+  hipLaunchKernelGGL(rank_to_host_kernel, dim3(1), dim3(64), 0, s, rank_dev, slot, seq);
   DME_HIP(hipGetLastError());
   // poll for up to ~50 ms, then fall back to a synchronisation (which also
   // reports an error of the stream)
   for (int it = 0; it < 1000000; ++it) {
-    if (__atomic_load_n(&sl->slot->seq, __ATOMIC_ACQUIRE) == seq) return __atomic_load_n(&sl->slot->value, __ATOMIC_RELAXED);
+    if (__atomic_load_n(&slot->seq, __ATOMIC_ACQUIRE) == seq) return __atomic_load_n(&slot->value, __ATOMIC_RELAXED);
     if (it >= 1000) std::this_thread::yield();
     if (it >= 20000) break;
   }
   DME_HIP(hipStreamSynchronize(s));
-  DME_REQUIRE(__atomic_load_n(&sl->slot->seq, __ATOMIC_ACQUIRE) == seq, DME_EINTERNAL,
+  DME_REQUIRE(__atomic_load_n(&slot->seq, __ATOMIC_ACQUIRE) == seq, DME_EINTERNAL,
               "compression: rank not delivered to the host");
-  return __atomic_load_n(&sl->slot->value, __ATOMIC_RELAXED);
+  return __atomic_load_n(&slot->value, __ATOMIC_RELAXED);
 }
 
 inline unsigned blocks_for(int64_t total) {

@@ -2,6 +2,7 @@
 // points (capi.cpp) and the request server (server.cpp).
 #pragma once
 
+#include <functional>
 #include <map>
 #include <memory>
 #include <mutex>
@@ -17,6 +18,9 @@ struct RegisteredOp {
   uint64_t id = 0;
   int64_t n = 0;
   DevBuf AT;
+  // the Leja operator on AT when A is symmetric (served quadrature factors
+  // then need no node exponentials); null otherwise
+  std::shared_ptr<LejaOp> lop;
 };
 
 }  // namespace dme
@@ -27,6 +31,7 @@ struct dme_ctx {
   bool own_stream = false;
   dme::Arena ws;
   dme::DevBuf flags;
+  dme::AuxStream aux;  // second stream, event ring and rank slot of the step-level calls
   std::mutex ops_mu;
   std::map<uint64_t, std::shared_ptr<dme::RegisteredOp>> ops;
   uint64_t next_op = 1;
@@ -34,6 +39,7 @@ struct dme_ctx {
 
 struct dme_result {
   int64_t n = 0, r = 0, steps = 0;
+  double err_est = 0.0;  // Solver::err_estimate() when the result was taken
   std::vector<double> L, D;
   // served requests: precision used (dme_precision), 1 if it fell back to FP64,
   // arrival-to-completion and arrival-to-admission times (seconds)
@@ -46,6 +52,10 @@ namespace dme {
 dme_result* result_from_solver(Solver& sv);
 
 extern thread_local std::string g_last_error;
+
+// Runs f, turning a dme::Error (or another exception) into its return code and
+// the thread's last error message (the C entry points' error handling).
+int guarded_call(const std::function<void()>& f);
 
 // Request server (server.cpp); errors are thrown as dme::Error.
 dme_server* server_start(dme_ctx* ctx, size_t budget, int max_slots);

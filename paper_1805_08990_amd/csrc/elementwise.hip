@@ -126,6 +126,51 @@ __global__ void finite_kernel(const double* X, int64_t rows, int64_t cols, int64
   if (bad) atomicOr(flag, 1);
 }
 
+// Sums of (A - B)^2 and B^2 over a rows x cols block: one pair of partial
+// sums per workgroup (grid-stride over the entries, tree reduction in LDS),
+// then one workgroup adds the partials in a fixed order.
+constexpr int kDiffBlocks = 256;
+
+__global__ void sqdiff_partial_kernel(const double* A, int64_t lda, const double* B, int64_t ldb,
+                                      int64_t rows, int64_t cols, double* part) {
+  __shared__ double sd[kT], sb[kT];
+  const int64_t total = rows * cols;
+  double d2 = 0.0, b2 = 0.0;
+  for (int64_t i = blockIdx.x * (int64_t)kT + threadIdx.x; i < total; i += (int64_t)gridDim.x * kT) {
+    const int64_t r = i % rows, c = i / rows;
+    const double b = B[r + c * ldb];
+    const double d = A[r + c * lda] - b;
+    d2 += d * d;
+    b2 += b * b;
+  }
+  sd[threadIdx.x] = d2;
+  sb[threadIdx.x] = b2;
+  __syncthreads();
+  for (int w = kT / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+      sd[threadIdx.x] += sd[threadIdx.x + w];
+      sb[threadIdx.x] += sb[threadIdx.x + w];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = sd[0];
+    part[2 * blockIdx.x + 1] = sb[0];
+  }
+}
+
+__global__ void sum_pairs_kernel(const double* part, int count, double* out) {
+  if (threadIdx.x == 0) {
+    double d2 = 0.0, b2 = 0.0;
+    for (int i = 0; i < count; ++i) {
+      d2 += part[2 * i];
+      b2 += part[2 * i + 1];
+    }
+    out[0] = d2;
+    out[1] = b2;
+  }
+}
+
 }  // namespace
 
 void fill_f64(hipStream_t s, double* X, int64_t rows, int64_t cols, int64_t ld, double v) {
@@ -202,6 +247,22 @@ void finite_check_f64(hipStream_t s, const double* X, int64_t rows, int64_t cols
   if (rows <= 0 || cols <= 0) return;
   hipLaunchKernelGGL(finite_kernel, dim3(grid_for(rows * cols)), dim3(kT), 0, s, X, rows, cols, ld,
                      flag);
+  DME_HIP(hipGetLastError());
+}
+
+}  // namespace dme
+
+namespace dme {
+
+size_t diff_norms_workspace() { return 2 * kDiffBlocks * sizeof(double); }
+
+void diff_norms_f64(hipStream_t s, const double* A, int64_t lda, const double* B, int64_t ldb,
+                    int64_t rows, int64_t cols, double* part, double* out) {
+  const int64_t total = rows * cols;
+  const int blocks = (int)std::max<int64_t>(1, std::min<int64_t>(kDiffBlocks, cdiv(total, kT)));
+  hipLaunchKernelGGL(sqdiff_partial_kernel, dim3(blocks), dim3(kT), 0, s, A, lda, B, ldb, rows, cols, part);
+  DME_HIP(hipGetLastError());
+  hipLaunchKernelGGL(sum_pairs_kernel, dim3(1), dim3(64), 0, s, part, blocks, out);
   DME_HIP(hipGetLastError());
 }
 

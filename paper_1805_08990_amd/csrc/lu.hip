@@ -195,20 +195,29 @@ __global__ void tri_inv_kernel(const double* T, int64_t ldt, int b, int lower, d
 
 }  // namespace
 
-size_t lu_solve_workspace(int64_t n) {
+size_t lu_solve_workspace(int64_t n) { return lu_solve_workspace(n, n); }
+
+size_t lu_solve_workspace(int64_t n, int64_t nrhs) {
   const int64_t nparts = cdiv(n, kRowsT) + 1;
+  const int64_t w = std::max(n, nrhs);
   size_t b = 0;
   b += (size_t)n * sizeof(int64_t) + 256;             // piv
   b += (size_t)nparts * sizeof(ArgMax) + 256;          // partials
   b += 2 * (kNB * sizeof(double) + 256);               // rowj, rowp
   b += (size_t)kNB * kNB * sizeof(double) + 256;       // inverse block
-  b += (size_t)kNB * n * sizeof(double) + 256;         // row-block temp
+  b += (size_t)kNB * w * sizeof(double) + 256;         // row-block temp
   // split-K workspace of the largest GEMM issued (skinny ones)
-  b += std::max(gemm_f64_workspace(kNB, n, kNB), gemm_f64_workspace(n, n, kNB)) + 256;
+  b += std::max({gemm_f64_workspace(kNB, w, kNB), gemm_f64_workspace(n, n, kNB),
+                 gemm_f64_workspace(n, nrhs, kNB)}) + 256;
   return b;
 }
 
 void lu_solve_f64(hipStream_t s, int64_t n, double* A, double* Q, Arena& ws, int* info_dev) {
+  lu_solve_f64(s, n, A, Q, n, n, ws, info_dev);
+}
+
+void lu_solve_f64(hipStream_t s, int64_t n, double* A, double* Q, int64_t ldq, int64_t nrhs, Arena& ws,
+                  int* info_dev) {
   if (n <= 0) return;
   const int64_t lda = n;
   int64_t* piv = ws.get<int64_t>(n);
@@ -216,7 +225,7 @@ void lu_solve_f64(hipStream_t s, int64_t n, double* A, double* Q, Arena& ws, int
   double* rowj = ws.get<double>(kNB);
   double* rowp = ws.get<double>(kNB);
   double* inv = ws.get<double>(kNB * kNB);
-  double* tmp = ws.get<double>((size_t)kNB * n);
+  double* tmp = ws.get<double>((size_t)kNB * std::max(n, nrhs));
   const size_t mark = ws.used;
 
   // ---------------- factorisation
@@ -252,8 +261,9 @@ void lu_solve_f64(hipStream_t s, int64_t n, double* A, double* Q, Arena& ws, int
                          A, lda, j0 + jb, n, j0, jb, piv);
       DME_HIP(hipGetLastError());
     }
-    hipLaunchKernelGGL(swap_rows_kernel, dim3((unsigned)cdiv(n, 256)), dim3(256), 0, s, Q, n,
-                       (int64_t)0, n, j0, jb, piv);
+    if (nrhs > 0)
+      hipLaunchKernelGGL(swap_rows_kernel, dim3((unsigned)cdiv(nrhs, 256)), dim3(256), 0, s, Q, ldq,
+                         (int64_t)0, nrhs, j0, jb, piv);
     DME_HIP(hipGetLastError());
     const int64_t rest = n - j0 - jb;
     if (rest > 0) {
@@ -271,19 +281,23 @@ void lu_solve_f64(hipStream_t s, int64_t n, double* A, double* Q, Arena& ws, int
     }
   }
 
+  if (nrhs <= 0) {
+    ws.used = mark;
+    return;
+  }
   // ---------------- forward substitution L Y = Q (unit lower)
   for (int64_t i0 = 0; i0 < n; i0 += kNB) {
     const int ib = (int)std::min<int64_t>(kNB, n - i0);
     hipLaunchKernelGGL(tri_inv_kernel, dim3(1), dim3(kNB), 0, s, A + i0 + i0 * lda, lda, ib, 1, inv);
     DME_HIP(hipGetLastError());
-    copy_f64(s, Q + i0, n, tmp, ib, ib, n);
+    copy_f64(s, Q + i0, ldq, tmp, ib, ib, nrhs);
     ws.used = mark;
-    gemm_f64(s, 'N', 'N', ib, n, ib, 1.0, inv, ib, tmp, ib, 0.0, Q + i0, n, &ws);
+    gemm_f64(s, 'N', 'N', ib, nrhs, ib, 1.0, inv, ib, tmp, ib, 0.0, Q + i0, ldq, &ws);
     const int64_t below = n - i0 - ib;
     if (below > 0) {
       ws.used = mark;
-      gemm_f64(s, 'N', 'N', below, n, ib, -1.0, A + (i0 + ib) + i0 * lda, lda, Q + i0, n, 1.0,
-               Q + i0 + ib, n, &ws);
+      gemm_f64(s, 'N', 'N', below, nrhs, ib, -1.0, A + (i0 + ib) + i0 * lda, lda, Q + i0, ldq, 1.0,
+               Q + i0 + ib, ldq, &ws);
     }
   }
   // ---------------- backward substitution U X = Y
@@ -293,12 +307,12 @@ void lu_solve_f64(hipStream_t s, int64_t n, double* A, double* Q, Arena& ws, int
     const int ib = (int)std::min<int64_t>(kNB, n - i0);
     hipLaunchKernelGGL(tri_inv_kernel, dim3(1), dim3(kNB), 0, s, A + i0 + i0 * lda, lda, ib, 0, inv);
     DME_HIP(hipGetLastError());
-    copy_f64(s, Q + i0, n, tmp, ib, ib, n);
+    copy_f64(s, Q + i0, ldq, tmp, ib, ib, nrhs);
     ws.used = mark;
-    gemm_f64(s, 'N', 'N', ib, n, ib, 1.0, inv, ib, tmp, ib, 0.0, Q + i0, n, &ws);
+    gemm_f64(s, 'N', 'N', ib, nrhs, ib, 1.0, inv, ib, tmp, ib, 0.0, Q + i0, ldq, &ws);
     if (i0 > 0) {
       ws.used = mark;
-      gemm_f64(s, 'N', 'N', i0, n, ib, -1.0, A + i0 * lda, lda, Q + i0, n, 1.0, Q, n, &ws);
+      gemm_f64(s, 'N', 'N', i0, nrhs, ib, -1.0, A + i0 * lda, lda, Q + i0, ldq, 1.0, Q, ldq, &ws);
     }
   }
   ws.used = mark;

@@ -217,10 +217,18 @@ std::shared_ptr<RegisteredOp> find_op(dme_ctx* ctx, uint64_t id) {
 
 // Bytes still to be added to the ledger to admit q (missing operator sets
 // plus the solve state).
+// Served operator sets keep the quadrature node exponentials only for a
+// nonsymmetric A; for a symmetric one each request forms its quadrature factor
+// with the Leja action on the registered A^T.
+bool keeps_nodes(dme_server* S, uint64_t op_id) {
+  std::shared_ptr<RegisteredOp> op = find_op(S->ctx, op_id);
+  return !(op && op->lop);
+}
+
 size_t admission_bytes(dme_server* S, const Request& q) {
   size_t b = q.state_bytes;
   for (const OpKey& k : q.keys)
-    if (!S->cache.count(k)) b += operator_set_bytes(q.n, k.precision, k.K, true);
+    if (!S->cache.count(k)) b += operator_set_bytes(q.n, k.precision, k.K, keeps_nodes(S, k.op));
   return b;
 }
 
@@ -247,12 +255,13 @@ CacheEntry& get_operator(dme_server* S, const OpKey& k, int64_t n, bool cold) {
   DME_REQUIRE(op->n == n, DME_EINVAL, "operator size differs from the problem size");
   const double t0 = now_s();
   CacheEntry e;
-  e.set = build_operator_set(S->bstream, n, op->AT.as<double>(), k.t, k.precision, k.K, true,
+  const bool nodes = !op->lop;
+  e.set = build_operator_set(S->bstream, n, op->AT.as<double>(), k.t, k.precision, k.K, nodes,
                              S->bflags.as<int>());
   int info = 0;
   DME_HIP(hipMemcpy(&info, S->bflags.as<int>(), sizeof(int), hipMemcpyDeviceToHost));
   DME_REQUIRE(info == 0, DME_ENUMERIC, "operator: singular Pade denominator");
-  e.bytes = operator_set_bytes(n, k.precision, k.K, true);
+  e.bytes = operator_set_bytes(n, k.precision, k.K, nodes);
   S->used += e.bytes;
   S->peak = std::max(S->peak, S->used);
   if (cold) {
@@ -263,17 +272,21 @@ CacheEntry& get_operator(dme_server* S, const OpKey& k, int64_t n, bool cold) {
   return S->cache.emplace(k, std::move(e)).first->second;
 }
 
+// The request's stream is synchronised first, then its solver goes (which
+// synchronises and destroys the solver's second stream, events and rank slot),
+// and the request's stream last, so nothing of the solve refers to a
+// destroyed stream.
 void release_request_state(dme_server* S, Request& q) {
   for (const OpKey& k : q.keys) {
     auto it = S->cache.find(k);
     if (it != S->cache.end()) it->second.users -= 1;
   }
+  if (q.stream) (void)hipStreamSynchronize(q.stream);
   if (q.sv) {
     q.sv.reset();
     S->used -= q.state_bytes;
   }
   if (q.stream) {
-    (void)hipStreamSynchronize(q.stream);
     (void)hipStreamDestroy(q.stream);
     q.stream = nullptr;
   }
@@ -330,6 +343,12 @@ bool admit(dme_server* S, const std::shared_ptr<Request>& qp) {
     q.sv = std::make_unique<Solver>();
     q.sv->s = q.stream;
     q.sv->device = S->ctx->device;
+    {
+      std::shared_ptr<RegisteredOp> op = find_op(S->ctx, q.op_id);
+      DME_REQUIRE(op != nullptr, DME_EINVAL, "unknown operator id");
+      q.sv->ATp = op->AT.as<double>();
+      q.sv->lop = op->lop;
+    }
     S->used += q.state_bytes;
     S->peak = std::max(S->peak, S->used);
     dme_problem prob{};
@@ -599,7 +618,7 @@ void server_warm(dme_server* S, uint64_t op_id, double t, int precision, int K) 
   g.unlock();
   const OpKey k{op_id, t, precision, K > 0 ? K : 7};
   if (S->cache.count(k)) return;
-  const size_t b = operator_set_bytes(op->n, precision, k.K, true);
+  const size_t b = operator_set_bytes(op->n, precision, k.K, !op->lop);
   DME_REQUIRE(make_room(S, b), DME_ENOMEM, "operator does not fit the server budget");
   CacheEntry& e = get_operator(S, k, op->n, false);
   e.last_tick = S->tick;

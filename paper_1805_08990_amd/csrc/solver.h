@@ -9,6 +9,7 @@
 #include <vector>
 
 #include "common.h"
+#include "leja.h"
 
 namespace dme {
 
@@ -37,6 +38,10 @@ struct MixedOp;  // FP32 copy of an operator for the split-BF16 product (gemm_mi
 // exponentials e^{s_k A^T} on [0, t], kept when many right-hand sides C are
 // served from one operator (a single solve forms them one at a time while it
 // builds its quadrature factor and keeps none).
+//
+// With the Leja action (DME_ACTION_LEJA) the set holds no E: e^{tA^T} X is
+// applied by Newton interpolation at Leja points with products by A^T (`lop`,
+// dense or CSR) under the interpolation parameters `plan`.
 struct OperatorSet {
   int64_t n = 0;
   double t = 0.0;
@@ -45,6 +50,8 @@ struct OperatorSet {
   DevBuf E;                      // n x n, e^{tA^T}
   std::shared_ptr<MixedOp> mix;  // FP32 copy of E (mixed mode)
   std::vector<DevBuf> nodes;     // e^{s_k A^T}, k = 0 .. K-1 (when kept)
+  std::shared_ptr<LejaOp> lop;   // Leja action: the operator A^T
+  std::shared_ptr<LejaPlan> plan;
   double build_ms = 0.0;
 };
 
@@ -96,6 +103,13 @@ struct Solver {
   int64_t max_rank = 0, kmax = 0;
 
   DevBuf AT;   // n x n, A^T (only when the solve builds its own operators)
+  // Dense A^T on the device (AT, or a registered operator's copy); null when A
+  // is given in CSR form only.
+  const double* ATp = nullptr;
+  // A^T for the Leja action (the quadrature nodes and, with DME_ACTION_LEJA,
+  // the steps): CSR when A came in that form, else the dense A^T when it is
+  // symmetric (the interpolation needs a real spectrum); null otherwise.
+  std::shared_ptr<LejaOp> lop;
   DevBuf B;    // n x m
   DevBuf CT;   // n x p, C^T
   DevBuf R;    // m x m
@@ -109,9 +123,11 @@ struct Solver {
   DevBuf W, Dhat, WB, SL;
   DevBuf flags;  // int flags[4]; int64 rank at offset 16
   Arena ws;
+  AuxStream aux;  // second stream, event ring and rank slot of this solve
 
   double expm_ms = 0.0, quad_ms = 0.0;
   int64_t rank_quad = 0;
+  int64_t nprod = 0;  // products e^{tA^T} L applied so far
 
   int profiling = 0;  // 0 off, 1 every phase, 2 the step product kernel alone
   hipEvent_t mark_phase() { return profiling == 1 ? mark_begin() : nullptr; }
@@ -147,6 +163,16 @@ struct Solver {
   void run_stage(size_t i, bool ext_product = false);
   // Called after the last stage of a step.
   void end_step() { ++step; }
+  // Estimated relative Frobenius distance between the current P = L D L^T and
+  // the same scheme run in FP64 throughout: 2 N_p max(delta, sqrt(n) u), with
+  // N_p the products e^{tA^T} L applied so far, u = 2^-53 and, in the mixed
+  // mode, delta the relative error of one split-BF16 product measured on the
+  // current factor against an FP64 product of the same operator (delta = 0 in
+  // FP64).  Each product perturbs P = Y D Y^T by at most about 2 delta
+  // relative, and the later flows do not amplify it (the heat semigroup and
+  // the compressions are contractions), so the sum over products bounds the
+  // drift to first order.  Enqueues two products and synchronises.
+  double err_estimate();
 
  private:
   void apply_T1(double t);
@@ -159,6 +185,7 @@ struct Solver {
   void compress_lead_into(int64_t rY, const QuadFactor& f);
   void apply_E(double t, const double* X, int64_t r, double* Y, int64_t ldy);
   void build_quadrature(double t);
+  void apply_mass_matrix(const double* M);
 };
 
 }  // namespace dme

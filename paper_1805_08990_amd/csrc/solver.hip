@@ -151,7 +151,10 @@ void Solver::flush_timings() {
 }
 
 Solver::~Solver() {
-  if (!pending.empty()) (void)hipStreamSynchronize(s);
+  // the solve's work on both of its streams ends before its events, rank slot
+  // and device buffers go
+  (void)hipStreamSynchronize(s);
+  aux.release();
   for (const PendingTiming& t : pending) {
     (void)hipEventDestroy(t.a);
     (void)hipEventDestroy(t.b);
@@ -174,12 +177,14 @@ void Solver::check_flags(const char* where) {
 
 void Solver::setup(const dme_problem& prob, const dme_opts& o, bool dre,
                    const OperatorProvider* provider) {
-  DME_REQUIRE(prob.n > 0 && (prob.A || provider), DME_EINVAL, "need n > 0 and A");
+  const bool sparse_in = prob.A_val != nullptr;
+  DME_REQUIRE(prob.n > 0 && (prob.A || sparse_in || provider), DME_EINVAL, "need n > 0 and A");
   DME_REQUIRE(prob.p > 0 && prob.C, DME_EINVAL, "need p > 0 and C (Q = C^T C)");
   DME_REQUIRE(o.h > 0 && o.T > 0, DME_EINVAL, "T and h must be positive");
   DME_REQUIRE(o.tol > 0, DME_EINVAL, "tol must be positive");
   DME_REQUIRE(prob.r0 >= 0, DME_EINVAL, "r0 must be >= 0");
   DME_REQUIRE(prob.r0 == 0 || (prob.L0 && prob.D0), DME_EINVAL, "r0 > 0 needs L0 and D0");
+  AuxBinding bind(aux);
   n = prob.n;
   p = prob.p;
   is_dre = dre;
@@ -189,6 +194,14 @@ void Solver::setup(const dme_problem& prob, const dme_opts& o, bool dre,
   DME_REQUIRE(opts.quad_nodes <= 64, DME_EINVAL, "quad_nodes must be <= 64");
   DME_REQUIRE(opts.precision == DME_FP64 || opts.precision == DME_MIXED, DME_EINVAL,
               "unknown precision");
+  DME_REQUIRE(opts.action == DME_ACTION_DENSE || opts.action == DME_ACTION_LEJA, DME_EINVAL,
+              "unknown action");
+  DME_REQUIRE(!(opts.action == DME_ACTION_LEJA && opts.precision == DME_MIXED), DME_EINVAL,
+              "the Leja action runs in FP64 (precision must be DME_FP64)");
+  DME_REQUIRE(opts.action == DME_ACTION_LEJA || prob.A || provider, DME_EINVAL,
+              "the dense exponential needs the dense A (a CSR A needs DME_ACTION_LEJA)");
+  DME_REQUIRE(prob.M == nullptr || (prob.A != nullptr && provider == nullptr), DME_EINVAL,
+              "the mass matrix form needs the dense A");
   const double Nf = std::round(o.T / o.h);
   DME_REQUIRE(Nf >= 1 && std::fabs(Nf * o.h - o.T) <= 1e-12 * o.T, DME_EINVAL, "T/h is not an integer");
   N = (int64_t)Nf;
@@ -220,13 +233,6 @@ void Solver::setup(const dme_problem& prob, const dme_opts& o, bool dre,
   flags.ensure(64);
   fill_f64(s, flags.as<double>(), 8, 1, 8, 0.0);
 
-  if (provider == nullptr) {
-    DevBuf A;
-    upload(s, A, prob.A, (size_t)n * n);
-    AT.ensure((size_t)n * n * sizeof(double));
-    transpose_f64(s, A.as<double>(), n, AT.as<double>(), n, n, n, 1.0);
-    DME_HIP(hipStreamSynchronize(s));
-  }
   {
     DevBuf Cd;
     upload(s, Cd, prob.C, (size_t)p * n);
@@ -234,6 +240,27 @@ void Solver::setup(const dme_problem& prob, const dme_opts& o, bool dre,
     transpose_f64(s, Cd.as<double>(), p, CT.as<double>(), n, p, n, 1.0);
     DME_HIP(hipStreamSynchronize(s));
   }
+  if (provider == nullptr && prob.A) {
+    DevBuf A;
+    upload(s, A, prob.A, (size_t)n * n);
+    AT.ensure((size_t)n * n * sizeof(double));
+    transpose_f64(s, A.as<double>(), n, AT.as<double>(), n, n, n, 1.0);
+    DME_HIP(hipStreamSynchronize(s));
+    ATp = AT.as<double>();
+  }
+  if (prob.M) apply_mass_matrix(prob.M);
+  if (!lop) {
+    if (sparse_in) {
+      ws.reserve((size_t)2 * n * sizeof(double) + 4096);
+      lop = leja_op_csr(s, n, prob.A_rowptr, prob.A_colind, prob.A_val, ws);
+      if (!lop->symmetric) lop.reset();
+    } else if (ATp) {
+      ws.reserve((size_t)cdiv(n, 32) * cdiv(n, 32) * 2 * sizeof(double) + 2 * n * sizeof(double) + 4096);
+      if (dense_symmetric(s, n, ATp, 1e-14, ws)) lop = leja_op_dense(s, n, ATp, ws);
+    }
+  }
+  DME_REQUIRE(opts.action != DME_ACTION_LEJA || lop, DME_EINVAL,
+              "the Leja action needs a symmetric A (real spectrum)");
   if (dre) {
     upload(s, B, prob.B, (size_t)n * m);
     upload(s, R, prob.R, (size_t)m * m);
@@ -248,7 +275,8 @@ void Solver::setup(const dme_problem& prob, const dme_opts& o, bool dre,
   Dhat.ensure((size_t)kmax * kmax * sizeof(double));
   WB.ensure((size_t)max_rank * std::max<int64_t>(m, 1) * sizeof(double));
   if (has_S) SL.ensure((size_t)n * max_rank * sizeof(double));
-  ws.reserve(workspace_bytes(n, m, max_rank, kmax, opts.precision));
+  ws.reserve(workspace_bytes(n, m, max_rank, kmax, opts.precision) +
+             leja_workspace(n, std::max<int64_t>(max_rank, (int64_t)opts.quad_nodes * p)));
 
   cur = 0;
   r = prob.r0;
@@ -262,9 +290,18 @@ void Solver::setup(const dme_problem& prob, const dme_opts& o, bool dre,
     if (st.sub == Sub::T1 || st.sub == Sub::T12) {
       if (!ops.count(t)) {
         EventTimer tm(s);
-        ops[t] = provider ? (*provider)(t)
-                          : build_operator_set(s, n, AT.as<double>(), t, opts.precision, 0, false,
-                                               flag_dev() + 1);
+        if (opts.action == DME_ACTION_LEJA) {
+          auto set = std::make_shared<OperatorSet>();
+          set->n = n;
+          set->t = t;
+          set->precision = DME_FP64;
+          set->lop = lop;
+          set->plan = leja_plan(*lop, {t}, 1);
+          ops[t] = set;
+        } else {
+          ops[t] = provider ? (*provider)(t)
+                            : build_operator_set(s, n, ATp, t, opts.precision, 0, false, flag_dev() + 1);
+        }
         DME_REQUIRE(ops[t] && ops[t]->n == n && ops[t]->precision == opts.precision, DME_EINTERNAL,
                     "operator set does not match the problem");
         expm_ms += tm.stop_ms();
@@ -361,7 +398,37 @@ size_t Solver::state_bytes(int64_t n, int64_t m, int64_t p, bool has_S, const dm
   add((size_t)mr * std::max<int64_t>(m, 1) * 8);                // W_B
   add(2 * ((size_t)n * Kp * 8 + (size_t)Kp * Kp * 8));          // quadrature factors (h and h/2)
   add(workspace_bytes(n, m, mr, km, o.precision));
+  add(leja_workspace(n, std::max<int64_t>(mr, Kp)));
   return b + 64;
+}
+
+// Mass-matrix form (Sec. 5.1, Ex. 4): M^T dP/dt M = A^T P M + M^T P A + Q + ...
+// becomes the standard form with A M^-1 in place of A and C M^-1 in place of C
+// (Q = C^T C -> M^-T Q M^-1); B, R and S are unchanged.  On the device:
+// A^T <- M^-T A^T and C^T <- M^-T C^T by one LU factorisation of M^T with
+// partial pivoting and a solve with the n + p right-hand sides [A^T, C^T].
+void Solver::apply_mass_matrix(const double* Mh) {
+  DME_REQUIRE(ATp == AT.as<double>() && ATp != nullptr, DME_EINTERNAL, "mass matrix without A^T");
+  const int64_t nr = n + p;
+  DevBuf Mt((size_t)n * n * sizeof(double));
+  DevBuf rhs((size_t)n * nr * sizeof(double));
+  {
+    DevBuf Md;
+    upload(s, Md, Mh, (size_t)n * n);
+    transpose_f64(s, Md.as<double>(), n, Mt.as<double>(), n, n, n, 1.0);
+    copy_f64(s, AT.as<double>(), n, rhs.as<double>(), n, n, n);
+    copy_f64(s, CT.as<double>(), n, rhs.as<double>() + (size_t)n * n, n, n, p);
+    DME_HIP(hipStreamSynchronize(s));
+  }
+  Arena lws;
+  lws.reserve(lu_solve_workspace(n, nr));
+  lu_solve_f64(s, n, Mt.as<double>(), rhs.as<double>(), n, nr, lws, flag_dev() + 1);
+  copy_f64(s, rhs.as<double>(), n, AT.as<double>(), n, n, n);
+  copy_f64(s, rhs.as<double>() + (size_t)n * n, n, CT.as<double>(), n, n, p);
+  DME_HIP(hipStreamSynchronize(s));
+  int h[4] = {0, 0, 0, 0};
+  DME_HIP(hipMemcpy(h, flags.p, sizeof(h), hipMemcpyDeviceToHost));
+  DME_REQUIRE(h[1] == 0, DME_ENUMERIC, "mass matrix: M is singular (zero pivot)");
 }
 
 void Solver::build_quadrature(double t) {
@@ -372,20 +439,28 @@ void Solver::build_quadrature(double t) {
   const OperatorSet& op = *ops.at(t);
   // columns [e^{s_k A^T} C^T]_k directly into W, weights into Dhat
   double* Wd = W.as<double>();
-  if ((int)op.nodes.size() == K) {
+  if (lop && (int)op.nodes.size() != K) {
+    // the K node actions by Leja interpolation (Alg. 2 with expleja): one
+    // block of K copies of C^T, group k advanced to time s_k
+    for (int q = 0; q < K; ++q) copy_f64(s, CT.as<double>(), n, Wd + (int64_t)q * p * n, n, n, p);
+    std::unique_ptr<LejaPlan> plan = leja_plan(*lop, nodes, p);
+    ws.reset();
+    leja_apply(s, *lop, *plan, Wd, n, kq, Wd, n, ws);
+    DME_HIP(hipStreamSynchronize(s));  // the plan's device coefficients go with it
+  } else if ((int)op.nodes.size() == K) {
     for (int q = 0; q < K; ++q) {
       ws.reset();
       gemm_f64(s, 'N', 'N', n, p, n, 1.0, op.nodes[q].as<double>(), n, CT.as<double>(), n, 0.0,
                Wd + (int64_t)q * p * n, n, &ws);
     }
   } else {
-    DME_REQUIRE(AT.p != nullptr, DME_EINTERNAL, "quadrature factor needs the operator or its nodes");
+    DME_REQUIRE(ATp != nullptr, DME_EINTERNAL, "quadrature factor needs the operator or its nodes");
     DevBuf Ek((size_t)n * n * sizeof(double));
     Arena ews;
     ews.reserve(expm_workspace(n));
     for (int q = 0; q < K; ++q) {
       ews.reset();
-      expm_f64(s, n, AT.as<double>(), nodes[q], Ek.as<double>(), ews, nullptr, nullptr, flag_dev() + 1);
+      expm_f64(s, n, ATp, nodes[q], Ek.as<double>(), ews, nullptr, nullptr, flag_dev() + 1);
       ews.reset();
       gemm_f64(s, 'N', 'N', n, p, n, 1.0, Ek.as<double>(), n, CT.as<double>(), n, 0.0,
                Wd + (int64_t)q * p * n, n, &ews);
@@ -424,6 +499,18 @@ struct StepKernelTimer : KernelTimer {
 
 void Solver::apply_E(double t, const double* X, int64_t rr, double* Y, int64_t ldy) {
   ws.reset();
+  const OperatorSet& set = *ops.at(t);
+  if (set.lop) {
+    hipEvent_t ev = mark_phase();
+    leja_apply(s, *set.lop, *set.plan, X, n, rr, Y, ldy, ws);
+    // S m products with A^T (2 nnz r flops each for CSR, 2 n^2 r dense); per
+    // term the basis block is read and written and the accumulator updated
+    const double prods = (double)leja_products(*set.plan);
+    const double opf = set.lop->sparse() ? 2.0 * set.lop->nnz : 2.0 * (double)n * n;
+    const double opb = set.lop->sparse() ? 12.0 * set.lop->nnz + 8.0 * n : 8.0 * (double)n * n;
+    mark_end(0, ev, prods * opf * rr, prods * (opb + 32.0 * n * rr));
+    return;
+  }
   StepKernelTimer kt;
   kt.sv = this;
   KernelTimer* prev = kernel_timer();
@@ -473,6 +560,7 @@ void Solver::compress_lead_into(int64_t rY, const QuadFactor& f) {
 void Solver::apply_T1(double t) {
   if (r == 0) return;
   apply_E(t, Lc(), r, Ln(), n);
+  ++nprod;
   copy_f64(s, Dc(), r, Dn(), r, r, r);
   cur ^= 1;
 }
@@ -490,6 +578,7 @@ void Solver::apply_T12(double t, bool ext_product) {
   const QuadFactor& f = Q.at(t);
   double* Wd = W.as<double>();
   if (r > 0 && !ext_product) apply_E(t, Lc(), r, Wd, n);
+  if (r > 0) ++nprod;  // (a grouped product of the server counts the same)
   const int64_t k = r + f.r;
   if (k == 0) return;
   blkdiag2_f64(s, Dc(), r, r, f.D.as<double>(), f.r, f.r, 1.0, Dhat.as<double>(), k);
@@ -532,7 +621,38 @@ void Solver::apply_T4(double t) {
   compress_into(k);
 }
 
+double Solver::err_estimate() {
+  const double u = std::ldexp(1.0, -53);
+  double delta = 0.0;
+  if (opts.precision == DME_MIXED && r > 0 && !ops.empty()) {
+    AuxBinding bind(aux);
+    const OperatorSet& op = *ops.rbegin()->second;
+    DME_REQUIRE(op.mix != nullptr, DME_EINTERNAL, "mixed operator set without its FP32 copy");
+    double* Ym = W.as<double>();  // W and the spare factor are free between steps
+    double* Y64 = Ln();
+    ws.reset();
+    gemm_mixed(s, *op.mix, Lc(), n, r, Ym, n, ws);
+    ws.reset();
+    gemm_f64(s, 'N', 'N', n, r, n, 1.0, op.E.as<double>(), n, Lc(), n, 0.0, Y64, n, &ws);
+    ws.reset();
+    double* part = ws.get<double>(diff_norms_workspace() / sizeof(double));
+    double* out = ws.get<double>(2);
+    diff_norms_f64(s, Ym, n, Y64, n, n, r, part, out);
+    double h[2] = {0.0, 0.0};
+    DME_HIP(hipMemcpyAsync(h, out, sizeof(h), hipMemcpyDeviceToHost, s));
+    DME_HIP(hipStreamSynchronize(s));
+    delta = h[1] > 0.0 ? std::sqrt(h[0] / h[1]) : 0.0;
+  }
+  // the Leja action's interpolation error: at most 1e-14 per substep
+  double action = 0.0;
+  for (const auto& kv : ops)
+    if (kv.second->plan) action = std::max(action, 1e-14 * kv.second->plan->S);
+  const double per_product = std::max({delta, action, std::sqrt((double)n) * u});
+  return 2.0 * (double)nprod * per_product;
+}
+
 void Solver::run_stage(size_t i, bool ext_product) {
+  AuxBinding bind(aux);
   const Stage& st = seq.at(i);
   const double t = st.frac * opts.h;
   switch (st.sub) {
@@ -545,6 +665,7 @@ void Solver::run_stage(size_t i, bool ext_product) {
 }
 
 void Solver::advance(int64_t nsteps) {
+  AuxBinding bind(aux);
   for (int64_t it = 0; it < nsteps; ++it) {
     for (size_t i = 0; i < seq.size(); ++i) run_stage(i);
     end_step();

@@ -483,19 +483,52 @@ size_t tsqr_workspace(int64_t n, int64_t k) {
   return b + 4096;
 }
 
+namespace {
+thread_local AuxStream* g_bound_aux = nullptr;
+}  // namespace
+
+void AuxStream::ensure(int dev) {
+  if (s2 != nullptr) {
+    DME_REQUIRE(dev == device, DME_EINTERNAL, "auxiliary stream used on another device");
+    return;
+  }
+  device = dev;
+  DME_HIP(hipStreamCreateWithFlags(&s2, hipStreamNonBlocking));
+  ev.assign(64, nullptr);
+  for (hipEvent_t& e : ev) DME_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  DME_HIP(hipHostMalloc((void**)&slot, sizeof(Slot), hipHostMallocCoherent));
+  slot->value = 0;
+  slot->seq = 0;
+  seq = 0;
+  next = 0;
+}
+
+void AuxStream::release() {
+  if (s2 == nullptr) return;
+  int cur = 0;
+  (void)hipGetDevice(&cur);
+  if (cur != device) (void)hipSetDevice(device);
+  (void)hipStreamSynchronize(s2);
+  for (hipEvent_t e : ev)
+    if (e) (void)hipEventDestroy(e);
+  ev.clear();
+  (void)hipStreamDestroy(s2);
+  s2 = nullptr;
+  if (slot) (void)hipHostFree(slot);
+  slot = nullptr;
+  if (cur != device) (void)hipSetDevice(cur);
+  device = -1;
+}
+
+AuxBinding::AuxBinding(AuxStream& a) : prev_(g_bound_aux) { g_bound_aux = &a; }
+AuxBinding::~AuxBinding() { g_bound_aux = prev_; }
+
 AuxStream& aux_stream() {
-  static thread_local std::vector<std::unique_ptr<AuxStream>> per_device;
+  DME_REQUIRE(g_bound_aux != nullptr, DME_EINTERNAL, "no auxiliary stream bound to this thread");
   int dev = 0;
   DME_HIP(hipGetDevice(&dev));
-  for (auto& a : per_device)
-    if (a->device == dev) return *a;
-  auto a = std::make_unique<AuxStream>();
-  a->device = dev;
-  DME_HIP(hipStreamCreateWithFlags(&a->s2, hipStreamNonBlocking));
-  a->ev.resize(64);
-  for (hipEvent_t& e : a->ev) DME_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
-  per_device.push_back(std::move(a));
-  return *per_device.back();
+  g_bound_aux->ensure(dev);
+  return *g_bound_aux;
 }
 
 // Panels are factored on s.  Q^T of panel p reaches the next panel's columns

@@ -50,4 +50,5 @@ def test_binding_imports_and_marshals_options():
     o = b.SolveOptions(T=0.1, h=1e-3, tol=1e-10, scheme="lie", split="F1F2", precision="mixed",
                        quad_nodes=5, max_rank=64).to_c()
     assert (o.scheme, o.split, o.precision, o.quad_nodes, o.max_rank) == (0, 1, 1, 5, 64)
-    assert ctypes.sizeof(b.Opts) == 3 * 8 + 4 * 4 + 8
+    assert ctypes.sizeof(b.Opts) == 3 * 8 + 4 * 4 + 8 + 8  # action + padding
+    assert ctypes.sizeof(b.Problem) == 4 * 8 + 11 * 8

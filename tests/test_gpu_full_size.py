@@ -7,6 +7,7 @@ import math
 
 import numpy as np
 import pytest
+import scipy.sparse as sp
 
 import oracle
 import workloads as wl
@@ -22,23 +23,32 @@ def gpu_solve(ctx, p, precision="fp64"):
     return ctx.solve(p.kind, opts, p.A, p.C, B=p.B, R=p.R, S=p.S, L0=p.L0, D0=p.D0)
 
 
-def oracle_kron(p):
+def oracle_kron(p, record_ranks=False):
     A1 = wl.laplacian_1d(p.nx)
     return oracle.solve(p.A, p.C, p.T, p.h, kind=p.kind, B=p.B, R=p.R, S=p.S, split=p.split,
                         scheme=p.scheme, tol=p.tol, quad_nodes=p.quad_nodes,
-                        expm_fn=lambda t: oracle.laplacian_expm_kron(A1, t),
+                        expm_fn=lambda t: oracle.KronExpm(A1, t),
                         quad_fn=lambda t: oracle.quadrature_factor_kron(A1, p.C, t, p.quad_nodes,
-                                                                        p.tol))
+                                                                        p.tol),
+                        record_ranks=record_ranks)
 
 
+def gpu_solve_est(ctx, p, precision="fp64"):
+    opts = b.SolveOptions(T=p.T, h=p.h, tol=p.tol, scheme=p.scheme, split=p.split,
+                          quad_nodes=p.quad_nodes, precision=precision)
+    return ctx.solve(p.kind, opts, p.A, p.C, B=p.B, R=p.R, S=p.S, L0=p.L0, D0=p.D0, err_est=True)
+
+
+@pytest.mark.parametrize("h", [1e-2, 5e-3, 2.5e-3])
 @pytest.mark.parametrize("scheme", ["lie", "strang"])
-def test_dre_halfplane_n4096_matches_oracle(ctx, scheme):
-    """64 x 64 Laplacian, B = 1[x < 1/2], R = 1, C = ones, h = 1e-2 (10 steps)."""
-    p = wl.config_dre_halfplane(nx=64, h=1e-2, scheme=scheme)
-    announce("dre n4096", scheme)
+def test_dre_halfplane_n4096_matches_oracle(ctx, scheme, h):
+    """64 x 64 Laplacian, B = 1[x < 1/2], R = 1, C = ones, T = 0.1 at the three
+    step sizes of the order study (10, 20 and 40 steps)."""
+    p = wl.config_dre_halfplane(nx=64, h=h, scheme=scheme)
+    announce("dre n4096", scheme, "h", h)
     L, D, steps = gpu_solve(ctx, p)
     Lo, Do, info = oracle_kron(p)
-    assert steps == info["steps"] == 10
+    assert steps == info["steps"] == int(round(0.1 / h))
     err = oracle.lowrank_rel_err(L, D, Lo, Do)
     print(f"  rank gpu {L.shape[1]} oracle {Lo.shape[1]} rel err {err:.3e}", flush=True)
     assert err < 1e-10
@@ -67,31 +77,77 @@ def test_dre_halfplane_n4096_observed_order(ctx, scheme, order):
         assert abs(r - order) < 0.15
 
 
+@pytest.mark.timeout(600)
 def test_gdre_n4096_matches_oracle(ctx):
-    """Generalized DRE on the 64 x 64 grid, S = 0.1 tridiag(1, 0, 1), h = 1e-3
-    (20 steps of the five-stage Strang composition)."""
-    p = wl.config_gdre(nx=64, h=1e-3, T=0.02)
-    announce("gdre n4096")
+    """Generalized DRE on the 64 x 64 grid, S = 0.1 tridiag(1, 0, 1), h = 1e-3,
+    T = 0.1: all 100 steps of the five-stage Strang composition."""
+    p = wl.config_gdre(nx=64, h=1e-3, T=0.1)
+    announce("gdre n4096 100 steps")
     L, D, steps = gpu_solve(ctx, p)
     Lo, Do, info = oracle_kron(p)
-    assert steps == info["steps"] == 20
+    assert steps == info["steps"] == 100
     err = oracle.lowrank_rel_err(L, D, Lo, Do)
     print(f"  rank gpu {L.shape[1]} oracle {Lo.shape[1]} rel err {err:.3e}", flush=True)
     assert err < 1e-10
 
 
-def test_dre_quadrant_n16384_fp64_and_mixed(ctx):
-    """The 128 x 128 workload of the benchmark (B = quadrant indicators, R = I4,
-    C = 8 x n N(0,1)/sqrt(n), seed 0), first 5 steps of h = 1e-3: FP64 within
-    1e-10 and the split-BF16 products within 1e-6 of the oracle."""
-    p = wl.config_dre_quadrant(nx=128, T=5e-3, h=1e-3)
-    announce("dre n16384 fp64/mixed")
+@pytest.mark.parametrize("scheme", ["lie", "strang"])
+@pytest.mark.parametrize("split", ["F12", "F1F2", "F1F3F2"])
+def test_gdle_n4096_matches_oracle(ctx, split, scheme):
+    """Generalized DLE on the 64 x 64 grid (C = ones, S = 0.1 tridiag(1, 0, 1)):
+    the schemes F12F4, F1F2F4 and F1F4F2 of Sec. 3 (T4 in place of T3), 10
+    steps of h = 1e-3."""
+    p = wl.config_gdle(nx=64, h=1e-3, T=1e-2, split=split, scheme=scheme)
+    announce("gdle n4096", split, scheme)
+    L, D, steps = gpu_solve(ctx, p)
     Lo, Do, info = oracle_kron(p)
-    L, D, steps = gpu_solve(ctx, p, "fp64")
-    assert steps == info["steps"] == 5
+    assert steps == info["steps"] == 10
     err = oracle.lowrank_rel_err(L, D, Lo, Do)
-    Lm, Dm, _ = gpu_solve(ctx, p, "mixed")
-    errm = oracle.lowrank_rel_err(Lm, Dm, Lo, Do)
-    print(f"  rank gpu {L.shape[1]} oracle {Lo.shape[1]} fp64 {err:.3e} mixed {errm:.3e}", flush=True)
+    print(f"  rank gpu {L.shape[1]} oracle {Lo.shape[1]} rel err {err:.3e}", flush=True)
     assert err < 1e-10
-    assert errm < 1e-6
+
+
+@pytest.fixture(scope="module")
+def c4_reference():
+    """The 128 x 128 benchmark workload over all 100 steps (T = 0.1), from the
+    oracle."""
+    p = wl.config_dre_quadrant(nx=128, T=0.1, h=1e-3)
+    announce("dre n16384: oracle, 100 steps")
+    Lo, Do, info = oracle_kron(p, record_ranks=True)
+    return p, Lo, Do, info
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("precision,bar", [("fp64", 1e-10), ("mixed", 1e-6)])
+def test_dre_quadrant_n16384_100_steps(ctx, c4_reference, precision, bar):
+    """The benchmark workload (B = quadrant indicators, R = I4, C = 8 x n
+    N(0,1)/sqrt(n) seed 0, h = 1e-3, T = 0.1) through all 100 steps at the
+    ranks the benchmark times: FP64 within 1e-10 and the split-BF16 products
+    within 1e-6 of the oracle; the stated error estimate is at least the
+    measured distance (and below 1e-4, so that it says something)."""
+    p, Lo, Do, info = c4_reference
+    announce("dre n16384 100 steps", precision)
+    L, D, steps, est = gpu_solve_est(ctx, p, precision)
+    assert steps == info["steps"] == 100
+    err = oracle.lowrank_rel_err(L, D, Lo, Do)
+    print(f"  rank gpu {L.shape[1]} oracle {Lo.shape[1]} (max oracle rank {max(info['ranks'])}) "
+          f"rel err {err:.3e} err_est {est:.3e}", flush=True)
+    assert err < bar
+    assert err <= est < 1e-4
+
+
+@pytest.mark.timeout(900)
+def test_dre_quadrant_n16384_100_steps_leja_csr(ctx, c4_reference):
+    """The benchmark workload with A in CSR form and the Leja action for every
+    step product (the paper's own method, no dense exponential): all 100
+    steps within 1e-10 of the oracle."""
+    p, Lo, Do, info = c4_reference
+    announce("dre n16384 100 steps leja csr")
+    M = sp.csr_matrix(p.A)
+    A = (M.indptr.astype(np.int64), M.indices.astype(np.int64), M.data.astype(np.float64))
+    opts = b.SolveOptions(T=p.T, h=p.h, tol=p.tol, scheme=p.scheme, split=p.split,
+                          quad_nodes=p.quad_nodes, action="leja")
+    L, D, steps, est = ctx.solve(p.kind, opts, A, p.C, B=p.B, R=p.R, err_est=True)
+    err = oracle.lowrank_rel_err(L, D, Lo, Do)
+    print(f"  rank {L.shape[1]} / {Lo.shape[1]} err {err:.3e} err_est {est:.3e}", flush=True)
+    assert steps == 100 and err < 1e-10 and err <= est

@@ -23,6 +23,15 @@ def _requests():
             (12, "dle", 0, 6, 10, "mixed", 5), (8, "dre", 3, 8, 6, "mixed", 6)]
 
 
+def _large_requests():
+    """Requests on the 32 x 32 and 48 x 48 grids (n = 1024, 2304: the
+    skinny-product paths of the served sizes), h = 1e-3, with two DRE groups
+    that share an operator and a precision (one grouped product each)."""
+    return [(32, "dre", 4, 8, 12, "mixed", 21), (48, "dle", 0, 5, 10, "fp64", 22),
+            (32, "dre", 2, 3, 9, "mixed", 27), (48, "dre", 1, 7, 11, "fp64", 26),
+            (48, "dre", 3, 6, 8, "fp64", 28), (32, "dle", 0, 4, 10, "fp64", 23)]
+
+
 def _problem(nx, kind, m, p, nsteps, seed, h=1e-2):
     n = nx * nx
     C = wl.random_C(p, n, seed)
@@ -31,10 +40,10 @@ def _problem(nx, kind, m, p, nsteps, seed, h=1e-2):
     return n, C, B, R, nsteps * h, h
 
 
-def _submit_all(srv, ops, reqs, wait_each):
+def _submit_all(srv, ops, reqs, wait_each, h=1e-2):
     out = {}
     for i, (nx, kind, m, p, nsteps, prec, seed) in enumerate(reqs):
-        n, C, B, R, T, h = _problem(nx, kind, m, p, nsteps, seed)
+        n, C, B, R, T, h = _problem(nx, kind, m, p, nsteps, seed, h=h)
         opts = b.SolveOptions(T=T, h=h, tol=1e-10, precision=prec)
         t = srv.submit(ops[nx], kind, opts, C, n, B=B, R=R)
         out[i] = t
@@ -97,6 +106,39 @@ def test_latency_statistics(served):
     assert st["req_per_s"] > 0 and st["steps_per_s"] > 0
     assert st["steps"] == 2 * sum(r[4] for r in _requests())
     assert all(v[3]["latency_s"] >= v[3]["queue_s"] >= 0 for v in mix.values())
+
+
+@pytest.fixture(scope="module")
+def served_large(ctx):
+    announce("serving n = 1024 / 2304: solo then mix")
+    ops = {nx: ctx.register_operator(wl.laplacian_2d(nx)) for nx in (32, 48)}
+    srv = ctx.server(16 * GIB, max_slots=8)
+    solo = _submit_all(srv, ops, _large_requests(), wait_each=True, h=1e-3)
+    mix = _submit_all(srv, ops, _large_requests(), wait_each=False, h=1e-3)
+    stats = srv.stats()
+    srv.stop()
+    return ops, solo, mix, stats
+
+
+def test_large_same_alone_and_in_mix_and_oracle(served_large):
+    """At n = 1024 and 2304 (grouped skinny FP64 and split-BF16 products) every
+    request gives the same result alone and batched, within 1e-10 (FP64) or
+    1e-6 (mixed) of the oracle, with an error estimate at least the measured
+    distance to the oracle."""
+    _, solo, mix, st = served_large
+    assert st["completed"] == 2 * len(_large_requests()) and st["failed"] == 0
+    for i, (nx, kind, m, p, nsteps, prec, seed) in enumerate(_large_requests()):
+        Ls, Ds, ss, info = solo[i]
+        Lm, Dm, sm, infom = mix[i]
+        assert ss == sm == nsteps and info["precision"] == prec and not info["fell_back"]
+        assert oracle.lowrank_rel_err(Lm, Dm, Ls, Ds) < 1e-13, i
+        n, C, B, R, T, h = _problem(nx, kind, m, p, nsteps, seed, h=1e-3)
+        Lo, Do, _ = oracle.solve(wl.laplacian_2d(nx), C, T, h, kind=kind, B=B, R=R, tol=1e-10)
+        err = oracle.lowrank_rel_err(Ls, Ds, Lo, Do)
+        print(f"  req {i} nx {nx} {kind} {prec} rank {Ls.shape[1]} err {err:.2e} "
+              f"est {info['err_est']:.2e}", flush=True)
+        assert err < (1e-10 if prec == "fp64" else 1e-6), i
+        assert err <= info["err_est"], i
 
 
 def test_errors_stay_per_request(ctx):

@@ -167,3 +167,13 @@ def test_feedback_gain(ctx, nx):
         b._check(b._lib_solver_gain(dle._h, K.ctypes.data_as(b._p), 4), "dme_solver_gain")
     assert e.value.code == b.DME_EINVAL
     dle.close()
+
+
+@pytest.mark.parametrize("scheme", ["strang", "lie"])
+@pytest.mark.parametrize("split", ["F12", "F1F2", "F1F3F2"])
+def test_gdle_small(ctx, split, scheme):
+    """Generalized DLE (S P S^T term, no Riccati term) on the 8 x 8 grid: the
+    schemes F12F4, F1F2F4 and F1F4F2 of Sec. 3 (T4 of Alg. 4 in place of T3),
+    T = 0.1 with h = 1e-2."""
+    p = wl.config_gdle(nx=8, h=1e-2, T=0.1, split=split, scheme=scheme)
+    check(ctx, p)
