@@ -260,6 +260,18 @@ int dme_compress(dme_ctx *ctx, int64_t n, int64_t k, double *W, const double *Dh
 int dme_riccati(dme_ctx *ctx, int64_t n, int64_t r, int64_t m, const double *L, const double *B,
                 const double *R, double t, double *D);
 
+/* Allocation-free form of dme_riccati for callers that cannot allocate device
+ * memory during a call (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid allocation): the same computation, arguments and
+ * result, with its temporaries (W_B = L^T B, the split-K partial sums of that
+ * product, the m-column staging of the update) in a static 8 MiB device
+ * scratch per device instead of the context's arena.  Returns DME_EINVAL when
+ * they do not fit (about 8 (2 + nsplit) r m bytes, nsplit <= 256 the split of
+ * L^T B over n).  Every call on a device shares that device's scratch, so
+ * calls that overlap on one device race.  Synchronises the stream.          */
+int dme_riccati_noalloc(dme_ctx *ctx, int64_t n, int64_t r, int64_t m, const double *L,
+                        const double *B, const double *R, double t, double *D);
+
 /* Symmetric eigen-decomposition of a k x k matrix M (device), eigenvalues
  * ordered by |lambda| descending; eigenvectors only for the kept ones
  * (|lambda| > tol max|lambda|, at most max_keep).  lam: k, V: k x max_keep. */

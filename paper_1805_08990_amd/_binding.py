@@ -110,6 +110,7 @@ _lib_gemm = _sig("dme_gemm_f64", _int, [_p, ctypes.c_char, ctypes.c_char, _i64, 
 _lib_gemm_mixed = _sig("dme_gemm_mixed", _int, [_p, _i64, _i64, _p, _p, _i64, _p, _i64])
 _lib_compress = _sig("dme_compress", _int, [_p, _i64, _i64, _p, _p, _dbl, _i64, _p, _p, ctypes.POINTER(_i64)])
 _lib_riccati = _sig("dme_riccati", _int, [_p, _i64, _i64, _i64, _p, _p, _p, _dbl, _p])
+_lib_riccati_noalloc = _sig("dme_riccati_noalloc", _int, [_p, _i64, _i64, _i64, _p, _p, _p, _dbl, _p])
 _lib_expmv_leja = _sig("dme_expmv_leja", _int, [_p, _i64, _p, _p, _p, _p, _dbl, _i64, _p, _p,
                                                  ctypes.POINTER(_int), ctypes.POINTER(_int)])
 _lib_syev = _sig("dme_syev", _int, [_p, _i64, _p, _dbl, _i64, _p, _p, ctypes.POINTER(_i64)])
@@ -375,6 +376,16 @@ class Context:
             _check(_lib_expmv_leja(self._h, n, _ptr(As), None, None, None, float(t), c, _ptr(Xs),
                                    _ptr(Ys), ctypes.byref(S), ctypes.byref(m)), "dme_expmv_leja")
         return from_cm(Ys), int(S.value), int(m.value)
+
+    def riccati_noalloc(self, L, B, R, t: float, D):
+        """dme_riccati_noalloc: the Riccati update with the library's static
+        device scratch (no device allocation inside the call)."""
+        Ls, Bs, Rs, Ds = to_device_cm(L), to_device_cm(B), to_device_cm(R), to_device_cm(D)
+        n, r = Ls.shape[1], Ls.shape[0]
+        m = Bs.shape[0]
+        _check(_lib_riccati_noalloc(self._h, n, r, m, _ptr(Ls), _ptr(Bs), _ptr(Rs), float(t),
+                                    _ptr(Ds)), "dme_riccati_noalloc")
+        return from_cm(Ds)
 
     def syev(self, M, tol: float = 0.0, max_keep: Optional[int] = None):
         Ms = to_device_cm(M)

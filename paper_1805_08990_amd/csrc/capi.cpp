@@ -26,9 +26,10 @@ void DevBuf::alloc(size_t b) {
 }
 
 void DevBuf::release() {
-  if (p) (void)hipFree(p);
+  if (p && own) (void)hipFree(p);
   p = nullptr;
   bytes = 0;
+  own = true;
 }
 
 KernelTimer*& kernel_timer() {
@@ -157,6 +158,7 @@ int dme_create(dme_ctx** ctx, int device, void* stream) {
     // stream usually is: the library then orders with the caller's work
     c->stream = static_cast<hipStream_t>(stream);
     c->flags.ensure(64);
+    dme::noalloc_scratch_init(device);
     *ctx = c.release();
   });
 }

@@ -37,18 +37,25 @@ struct Error {
 inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
 // Device buffer owned by the library (hipMalloc / hipFree).
+// A buffer attached with attach() is borrowed: release() forgets it.
 struct DevBuf {
   void* p = nullptr;
   size_t bytes = 0;
+  bool own = true;
   DevBuf() = default;
   explicit DevBuf(size_t b) { alloc(b); }
   DevBuf(const DevBuf&) = delete;
   DevBuf& operator=(const DevBuf&) = delete;
-  DevBuf(DevBuf&& o) noexcept : p(o.p), bytes(o.bytes) { o.p = nullptr; o.bytes = 0; }
+  DevBuf(DevBuf&& o) noexcept : p(o.p), bytes(o.bytes), own(o.own) { o.p = nullptr; o.bytes = 0; o.own = true; }
   DevBuf& operator=(DevBuf&& o) noexcept {
-    if (this != &o) { release(); p = o.p; bytes = o.bytes; o.p = nullptr; o.bytes = 0; }
+    if (this != &o) {
+      release();
+      p = o.p; bytes = o.bytes; own = o.own;
+      o.p = nullptr; o.bytes = 0; o.own = true;
+    }
     return *this;
   }
+  void attach(void* q, size_t b) { release(); p = q; bytes = b; own = false; }
   ~DevBuf() { release(); }
   void alloc(size_t b);
   void ensure(size_t b) { if (b > bytes) { release(); alloc(b); } }
@@ -65,6 +72,9 @@ struct Arena {
   void reset() { used = 0; }
   // Reserve `bytes` of capacity up front (invalidates earlier pointers).
   void reserve(size_t bytes) { buf.ensure(bytes); used = 0; }
+  // Hand out caller-provided device memory instead (borrowed: never freed,
+  // never grown; get() beyond it fails with DME_EINTERNAL).
+  void attach(void* p, size_t bytes) { buf.attach(p, bytes); used = 0; }
   template <class T> T* get(size_t count) {
     size_t b = (count * sizeof(T) + 255) & ~size_t(255);
     DME_REQUIRE(used + b <= buf.bytes, DME_EINTERNAL, "arena overflow");

@@ -57,6 +57,10 @@ extern thread_local std::string g_last_error;
 // the thread's last error message (the C entry points' error handling).
 int guarded_call(const std::function<void()>& f);
 
+// The static device scratch of the allocation-free entry points (noalloc.hip):
+// its address on `device` is looked up once, with that device current.
+void noalloc_scratch_init(int device);
+
 // Request server (server.cpp); errors are thrown as dme::Error.
 dme_server* server_start(dme_ctx* ctx, size_t budget, int max_slots);
 void server_warm(dme_server* S, uint64_t op_id, double t, int precision, int K);
