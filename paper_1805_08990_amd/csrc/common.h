@@ -285,6 +285,26 @@ int64_t compress_f64_lead(hipStream_t s, int64_t n, int64_t r, double* W, const 
                           double* L, int64_t ldl, double* Dout, int64_t ldd, int64_t* rank_dev,
                           int* flag_dev, Arena& ws);
 
+// The same compression through the Gram matrix (gram.hip) for a symmetric
+// positive definite Dhat (ld lddh; dhat_diag: Dhat is diagonal): Dhat = F F^T,
+// G = F^T W^T W F, G = V Lam V^T truncated, L = W F V_I Lam_I^-1/2.  W (n x k,
+// ld ldw) is read only.  Returns the kept rank, or -1 (nothing written) when
+// Dhat is not numerically positive definite.
+size_t compress_gram_workspace(int64_t n, int64_t k);
+int64_t compress_gram_f64(hipStream_t s, int64_t n, int64_t k, const double* W, int64_t ldw,
+                          const double* Dhat, int64_t lddh, bool dhat_diag, double tol, int64_t max_rank,
+                          double* L, int64_t ldl, double* Dout, int64_t ldd, int64_t* rank_dev,
+                          int* flag_dev, Arena& ws);
+// A device int64 to the host through the bound auxiliary stream's pinned slot:
+// launch() enqueues the copy on s and returns its sequence number, wait()
+// polls for it (falling back to a stream synchronisation), rank_to_host() does
+// both.
+int64_t value_to_host_launch(hipStream_t s, const int64_t* src);
+int64_t value_to_host_wait(hipStream_t s, int64_t seq);
+inline int64_t rank_to_host(hipStream_t s, const int64_t* rank_dev) {
+  return value_to_host_wait(s, value_to_host_launch(s, rank_dev));
+}
+
 // Symmetric eigen-decomposition of a k x k matrix (syev.hip).
 // Eigenvalues sorted by |lambda| descending; only those with |lambda| > tol*max|lambda|
 // (at most max_keep) get eigenvectors.  Writes kept count to *keep_dev.

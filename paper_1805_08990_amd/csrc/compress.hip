@@ -297,12 +297,18 @@ __global__ void rank_to_host_kernel(const int64_t* __restrict__ src, AuxStream::
   }
 }
 
-int64_t rank_to_host(hipStream_t s, const int64_t* rank_dev) {
+}  // namespace
+
+int64_t value_to_host_launch(hipStream_t s, const int64_t* src) {
   AuxStream& ax = aux_stream();
-  AuxStream::Slot* slot = ax.slot;
   const int64_t seq = ++ax.seq;
-  hipLaunchKernelGGL(rank_to_host_kernel, dim3(1), dim3(64), 0, s, rank_dev, slot, seq);
+  hipLaunchKernelGGL(rank_to_host_kernel, dim3(1), dim3(64), 0, s, src, ax.slot, seq);
   DME_HIP(hipGetLastError());
+  return seq;
+}
+
+int64_t value_to_host_wait(hipStream_t s, int64_t seq) {
+  AuxStream::Slot* slot = aux_stream().slot;
   // poll for up to ~50 ms, then fall back to a synchronisation (which also
   // reports an error of the stream)
   for (int it = 0; it < 1000000; ++it) {
@@ -312,9 +318,11 @@ int64_t rank_to_host(hipStream_t s, const int64_t* rank_dev) {
   }
   DME_HIP(hipStreamSynchronize(s));
   DME_REQUIRE(__atomic_load_n(&slot->seq, __ATOMIC_ACQUIRE) == seq, DME_EINTERNAL,
-              "compression: rank not delivered to the host");
+              "a device value did not reach the host");
   return __atomic_load_n(&slot->value, __ATOMIC_RELAXED);
 }
+
+namespace {
 
 inline unsigned blocks_for(int64_t total) {
   return (unsigned)std::max<int64_t>(1, std::min<int64_t>(cdiv(total, 256), 8192));

@@ -1,0 +1,249 @@
+// Column compression through the Gram matrix (Sec. 3, the compression after
+// Alg. 2) for P = W Dhat W^T with Dhat symmetric positive definite, which is
+// what every compression of a DLE / DRE solve sees (Dhat is block diagonal
+// from D, the weights of the quadrature factor, t I or copies of D, all
+// positive definite when P0 is positive semidefinite):
+//
+//     Dhat = F F^T (Cholesky),  G = F^T (W^T W) F  (k x k),
+//     G = V Lam V^T, keep lam_i > tol max lam (sorted descending),
+//     L = W F V_I Lam_I^-1/2,  D = Lam_I,
+//
+// so P = (W F)(W F)^T = L D L^T on the kept part: the nonzero eigenvalues of
+// G are those of P and L = W F V_I Lam_I^-1/2 its eigenvectors.  Compared with
+// Householder QR of W (M = R Dhat R^T) this needs one product W^T W (an FP64
+// MFMA GEMM, split over n) instead of a tree of column steps, and leaves W
+// intact.  Forming W^T W squares the condition number of W: the eigenvalues of
+// G carry absolute errors of order u ||G||, which is the accuracy the
+// truncation at tol ||G|| >> u ||G|| needs, and P is reproduced to
+// O(u ||P||); the columns of L belonging to eigenvalues near tol max lam are
+// orthonormal only to about u / tol-level accuracy (~1e-7 measured), which no
+// later step relies on (every later compression forms W^T W itself).
+#include <thread>
+
+#include "common.h"
+
+namespace dme {
+namespace {
+
+constexpr int kCT = 1024;  // Cholesky threads
+constexpr int kCB = 32;    // Cholesky block width
+
+// In-place lower Cholesky factor of a k x k symmetric positive definite A (ld
+// lda; only the lower triangle is read), one workgroup, blocked right-looking:
+// per 32-column block the diagonal block is factored in LDS column by column,
+// the rows below are solved against it, and the trailing lower triangle is
+// updated.  The strict upper triangle is set to zero.  A non-positive (or
+// non-finite) pivot sets *status = -1 and zeroes the whole of A (so that what
+// follows sees a zero matrix, not NaNs); otherwise *status = 0.
+__global__ __launch_bounds__(kCT) void chol_lower_kernel(int k, double* A, int64_t lda, int64_t* status) {
+  __shared__ double blk[kCB][kCB + 1];
+  __shared__ int bad;
+  const int tid = threadIdx.x;
+  if (tid == 0) bad = 0;
+  for (int64_t idx = tid; idx < (int64_t)k * k; idx += kCT) {
+    const int i = (int)(idx % k), j = (int)(idx / k);
+    if (i < j) A[i + (int64_t)j * lda] = 0.0;
+  }
+  __syncthreads();
+  for (int j0 = 0; j0 < k; j0 += kCB) {
+    const int jb = min(kCB, k - j0);
+    for (int idx = tid; idx < jb * jb; idx += kCT) {
+      const int r = idx % jb, c = idx / jb;
+      blk[r][c] = (r >= c) ? A[(j0 + r) + (int64_t)(j0 + c) * lda] : 0.0;
+    }
+    __syncthreads();
+    // the diagonal block, column by column
+    for (int c = 0; c < jb; ++c) {
+      if (tid == 0) {
+        const double p = blk[c][c];
+        if (!(p > 0.0) || !isfinite(p)) bad = 1;
+        blk[c][c] = (p > 0.0 && isfinite(p)) ? sqrt(p) : 1.0;
+      }
+      __syncthreads();
+      const double dc = blk[c][c];
+      // column c below the pivot, then the rest of the block's lower triangle
+      if (tid > c && tid < jb) blk[tid][c] /= dc;
+      __syncthreads();
+      for (int idx = tid; idx < jb * jb; idx += kCT) {
+        const int r = idx % jb, l = idx / jb;
+        if (l > c && r >= l) blk[r][l] -= blk[r][c] * blk[l][c];
+      }
+      __syncthreads();
+    }
+    for (int idx = tid; idx < jb * jb; idx += kCT) {
+      const int r = idx % jb, c = idx / jb;
+      if (r >= c) A[(j0 + r) + (int64_t)(j0 + c) * lda] = blk[r][c];
+    }
+    const int rest = k - j0 - jb;
+    if (rest > 0) {
+      // rows below the block: x = a L11^-T, row by row (one thread per row)
+      for (int i = tid; i < rest; i += kCT) {
+        double x[kCB];
+        const int64_t row = j0 + jb + i;
+#pragma unroll
+        for (int c = 0; c < kCB; ++c) x[c] = (c < jb) ? A[row + (int64_t)(j0 + c) * lda] : 0.0;
+#pragma unroll
+        for (int c = 0; c < kCB; ++c) {
+          if (c < jb) {
+            double v = x[c];
+            for (int l = 0; l < c; ++l) v -= x[l] * blk[c][l];
+            x[c] = v / blk[c][c];
+          }
+        }
+#pragma unroll
+        for (int c = 0; c < kCB; ++c)
+          if (c < jb) A[row + (int64_t)(j0 + c) * lda] = x[c];
+      }
+      __syncthreads();
+      // trailing lower triangle: A22 -= L21 L21^T
+      const int64_t tri = (int64_t)rest * (rest + 1) / 2;
+      for (int64_t idx = tid; idx < tri; idx += kCT) {
+        // idx -> (r, l) with r >= l, column-wise packing of the lower triangle
+        int l = (int)((2.0 * rest + 1.0 - sqrt((2.0 * rest + 1.0) * (2.0 * rest + 1.0) - 8.0 * idx)) / 2.0);
+        while (l > 0 && (int64_t)l * (2 * rest - l + 1) / 2 > idx) --l;
+        while ((int64_t)(l + 1) * (2 * rest - l) / 2 <= idx) ++l;
+        const int r = l + (int)(idx - (int64_t)l * (2 * rest - l + 1) / 2);
+        const int64_t gr = j0 + jb + r, gl = j0 + jb + l;
+        double acc = 0.0;
+        for (int c = 0; c < jb; ++c) acc += A[gr + (int64_t)(j0 + c) * lda] * A[gl + (int64_t)(j0 + c) * lda];
+        A[gr + gl * lda] -= acc;
+      }
+    }
+    __syncthreads();
+  }
+  if (bad) {
+    for (int64_t idx = tid; idx < (int64_t)k * k; idx += kCT) {
+      const int i = (int)(idx % k), j = (int)(idx / k);
+      A[i + (int64_t)j * lda] = 0.0;
+    }
+  }
+  if (tid == 0) *status = bad ? -1 : 0;
+}
+
+// F = diag(sqrt(Dhat_ii)) for a diagonal Dhat (zero elsewhere); a non-positive
+// entry makes *status = -1 (and F zero).
+__global__ void sqrt_diag_kernel(int k, const double* Dhat, int64_t ldd, double* F, int64_t* status) {
+  __shared__ int bad;
+  if (threadIdx.x == 0) bad = 0;
+  __syncthreads();
+  for (int i = threadIdx.x; i < k; i += blockDim.x) {
+    const double d = Dhat[i + (int64_t)i * ldd];
+    if (!(d > 0.0) || !isfinite(d)) bad = 1;
+  }
+  __syncthreads();
+  for (int64_t idx = threadIdx.x; idx < (int64_t)k * k; idx += blockDim.x) {
+    const int i = (int)(idx % k), j = (int)(idx / k);
+    F[idx] = (!bad && i == j) ? sqrt(Dhat[i + (int64_t)i * ldd]) : 0.0;
+  }
+  if (threadIdx.x == 0) *status = bad ? -1 : 0;
+}
+
+__global__ void copy_lower_kernel(int k, const double* Dhat, int64_t ldd, double* F) {
+  for (int64_t idx = blockIdx.x * 256 + threadIdx.x; idx < (int64_t)k * k; idx += (int64_t)gridDim.x * 256) {
+    const int i = (int)(idx % k), j = (int)(idx / k);
+    F[idx] = Dhat[i + (int64_t)j * ldd];
+  }
+}
+
+// S = (G + G^T) / 2
+__global__ void sym_kernel(int k, const double* G, double* S) {
+  for (int64_t idx = blockIdx.x * 256 + threadIdx.x; idx < (int64_t)k * k; idx += (int64_t)gridDim.x * 256) {
+    const int i = (int)(idx % k), j = (int)(idx / k);
+    S[idx] = 0.5 * (G[idx] + G[j + (int64_t)i * k]);
+  }
+}
+
+// T(:, j) /= sqrt(lam_j), j < r (k x r, ld k)
+__global__ void scale_cols_kernel(int k, int r, const double* lam, double* T) {
+  for (int64_t idx = blockIdx.x * 256 + threadIdx.x; idx < (int64_t)k * r; idx += (int64_t)gridDim.x * 256) {
+    const int j = (int)(idx / k);
+    T[idx] /= sqrt(lam[j]);
+  }
+}
+
+__global__ void diag_out_kernel(const double* lam, int r, double* D, int64_t ldd) {
+  for (int64_t idx = blockIdx.x * 256 + threadIdx.x; idx < (int64_t)r * r; idx += (int64_t)gridDim.x * 256) {
+    const int i = (int)(idx % r), j = (int)(idx / r);
+    D[i + (int64_t)j * ldd] = (i == j) ? lam[i] : 0.0;
+  }
+}
+
+inline unsigned blocks(int64_t total) {
+  return (unsigned)std::max<int64_t>(1, std::min<int64_t>(cdiv(total, 256), 4096));
+}
+
+}  // namespace
+
+size_t compress_gram_workspace(int64_t n, int64_t k) {
+  size_t b = 0;
+  auto add = [&](size_t bytes) { b += (bytes + 255) & ~size_t(255); };
+  add(6 * (size_t)k * k * sizeof(double));  // F, G, T1, S, V, T
+  add((size_t)k * sizeof(double) + 64);     // lam, status
+  add(syev_workspace(k));
+  add(std::max({gemm_f64_workspace(k, k, n), gemm_f64_workspace(n, k, k), gemm_f64_workspace(k, k, k)}));
+  return b + 4096;
+}
+
+int64_t compress_gram_f64(hipStream_t s, int64_t n, int64_t k, const double* W, int64_t ldw,
+                          const double* Dhat, int64_t lddh, bool dhat_diag, double tol, int64_t max_rank,
+                          double* L, int64_t ldl, double* Dout, int64_t ldd, int64_t* rank_dev,
+                          int* flag_dev, Arena& ws) {
+  if (k <= 0 || n <= 0) return 0;
+  const size_t mark = ws.used;
+  double* F = ws.get<double>((size_t)k * k);
+  double* G = ws.get<double>((size_t)k * k);
+  double* T1 = ws.get<double>((size_t)k * k);
+  double* S = ws.get<double>((size_t)k * k);
+  double* V = ws.get<double>((size_t)k * k);
+  double* T = ws.get<double>((size_t)k * k);
+  double* lam = ws.get<double>(k);
+  int64_t* status = ws.get<int64_t>(8);
+  const size_t mark_g = ws.used;
+
+  // Dhat = F F^T; its status reaches the host while W^T W runs
+  if (dhat_diag) {
+    hipLaunchKernelGGL(sqrt_diag_kernel, dim3(1), dim3(1024), 0, s, (int)k, Dhat, lddh, F, status);
+  } else {
+    hipLaunchKernelGGL(copy_lower_kernel, dim3(blocks(k * k)), dim3(256), 0, s, (int)k, Dhat, lddh, F);
+    DME_HIP(hipGetLastError());
+    hipLaunchKernelGGL(chol_lower_kernel, dim3(1), dim3(kCT), 0, s, (int)k, F, k, status);
+  }
+  DME_HIP(hipGetLastError());
+  const int64_t seq = value_to_host_launch(s, status);
+  ws.used = mark_g;
+  gemm_f64(s, 'T', 'N', k, k, n, 1.0, W, ldw, W, ldw, 0.0, G, k, &ws);
+  if (value_to_host_wait(s, seq) != 0) {
+    ws.used = mark;
+    return -1;  // Dhat is not positive definite: the caller compresses by Householder QR
+  }
+  // G <- F^T G F, symmetrised
+  ws.used = mark_g;
+  gemm_f64(s, 'N', 'N', k, k, k, 1.0, G, k, F, k, 0.0, T1, k, &ws);
+  ws.used = mark_g;
+  gemm_f64(s, 'T', 'N', k, k, k, 1.0, F, k, T1, k, 0.0, G, k, &ws);
+  hipLaunchKernelGGL(sym_kernel, dim3(blocks(k * k)), dim3(256), 0, s, (int)k, G, S);
+  DME_HIP(hipGetLastError());
+  finite_check_f64(s, S, k, k, k, flag_dev);
+  ws.used = mark_g;
+  syev_trunc_f64(s, k, S, k, tol, std::min(max_rank, k), lam, V, k, rank_dev, flag_dev, ws);
+  ws.used = mark_g;
+  const int64_t rr = rank_to_host(s, rank_dev);
+  if (rr <= 0) {
+    ws.used = mark;
+    return 0;
+  }
+  if (ldd <= 0) ldd = rr;
+  // L = W (F V_I Lam_I^-1/2), D = Lam_I
+  gemm_f64(s, 'N', 'N', k, rr, k, 1.0, F, k, V, k, 0.0, T, k, &ws);
+  ws.used = mark_g;
+  hipLaunchKernelGGL(scale_cols_kernel, dim3(blocks(k * rr)), dim3(256), 0, s, (int)k, (int)rr, lam, T);
+  DME_HIP(hipGetLastError());
+  gemm_f64(s, 'N', 'N', n, rr, k, 1.0, W, ldw, T, k, 0.0, L, ldl, &ws);
+  ws.used = mark_g;
+  hipLaunchKernelGGL(diag_out_kernel, dim3(blocks(rr * rr)), dim3(256), 0, s, lam, (int)rr, Dout, ldd);
+  DME_HIP(hipGetLastError());
+  ws.used = mark;
+  return rr;
+}
+
+}  // namespace dme

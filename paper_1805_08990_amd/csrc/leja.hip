@@ -20,7 +20,7 @@ namespace {
 
 constexpr int kT = 256;
 constexpr int kMMax = 100;        // largest interpolation degree
-constexpr double kRhoMax = 16.0;  // largest t g per substep
+constexpr double kRhoMax = 24.0;  // largest t g per substep
 
 inline unsigned grid_for(int64_t count) {
   return (unsigned)std::max<int64_t>(1, std::min<int64_t>(cdiv(count, kT), 16384));

@@ -120,6 +120,7 @@ struct Solver {
   DevBuf L[2], D[2];
   int cur = 0;
   int64_t r = 0;
+  bool d_diag = true;  // D is diagonal (a compression's output; T3 fills it)
   DevBuf W, Dhat, WB, SL;
   DevBuf flags;  // int flags[4]; int64 rank at offset 16
   Arena ws;

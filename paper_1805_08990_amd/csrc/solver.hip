@@ -280,6 +280,7 @@ void Solver::setup(const dme_problem& prob, const dme_opts& o, bool dre,
 
   cur = 0;
   r = prob.r0;
+  d_diag = (r == 0);
   if (r > 0) {
     DME_HIP(hipMemcpyAsync(L[0].p, prob.L0, (size_t)n * r * sizeof(double), hipMemcpyHostToDevice, s));
     DME_HIP(hipMemcpyAsync(D[0].p, prob.D0, (size_t)r * r * sizeof(double), hipMemcpyHostToDevice, s));
@@ -370,6 +371,7 @@ size_t Solver::workspace_bytes(int64_t n, int64_t m, int64_t max_rank, int64_t k
   wsb += gemm_f64_workspace(n, max_rank, n) + 4096;
   if (precision == DME_MIXED) wsb += gemm_mixed_workspace(n, max_rank) + 4096;
   wsb += (size_t)max_rank * (max_rank + 64) * sizeof(double) + 4096;  // riccati scratch
+  wsb += compress_gram_workspace(n, kmax);
   return wsb;
 }
 
@@ -531,14 +533,26 @@ void Solver::apply_E(double t, const double* X, int64_t rr, double* Y, int64_t l
 void Solver::compress_into(int64_t k) {
   ws.reset();
   hipEvent_t ev = mark_phase();
-  const int64_t rn = compress_f64(s, n, k, W.as<double>(), Dhat.as<double>(), opts.tol, max_rank,
-                                  Ln(), n, Dn(), 0, rank_dev(), flag_dev(), ws);
-  // Householder QR 2 n k^2 - 2/3 k^3, Q application 4 n k r', small eigenproblem ~ 10 k^3
+  // through the Gram matrix while Dhat is positive definite (every DLE / DRE
+  // compression from a positive semidefinite P0), by Householder QR otherwise
+  int64_t rn = compress_gram_f64(s, n, k, W.as<double>(), n, Dhat.as<double>(), k, d_diag, opts.tol,
+                                 max_rank, Ln(), n, Dn(), 0, rank_dev(), flag_dev(), ws);
   const double kk = (double)k;
-  mark_end(1, ev, 2.0 * n * kk * kk + 4.0 * n * kk * rn + 10.0 * kk * kk * kk,
-           8.0 * (2.0 * n * kk + 2.0 * n * rn));
+  if (rn >= 0) {
+    // W^T W 2 n k^2, L = W T 2 n k r', the k x k products and eigenproblem ~ 14 k^3
+    mark_end(1, ev, 2.0 * n * kk * kk + 2.0 * n * kk * rn + 14.0 * kk * kk * kk,
+             8.0 * (2.0 * n * kk + n * rn));
+  } else {
+    ws.reset();
+    rn = compress_f64(s, n, k, W.as<double>(), Dhat.as<double>(), opts.tol, max_rank, Ln(), n, Dn(), 0,
+                      rank_dev(), flag_dev(), ws);
+    // Householder QR 2 n k^2 - 2/3 k^3, Q application 4 n k r', small eigenproblem ~ 10 k^3
+    mark_end(1, ev, 2.0 * n * kk * kk + 4.0 * n * kk * rn + 10.0 * kk * kk * kk,
+             8.0 * (2.0 * n * kk + 2.0 * n * rn));
+  }
   cur ^= 1;
   r = rn;
+  d_diag = true;
 }
 
 void Solver::compress_lead_into(int64_t rY, const QuadFactor& f) {
@@ -555,6 +569,7 @@ void Solver::compress_lead_into(int64_t rY, const QuadFactor& f) {
            8.0 * (2.0 * n * kk + 2.0 * n * rr));
   cur ^= 1;
   r = rn;
+  d_diag = true;
 }
 
 void Solver::apply_T1(double t) {
@@ -582,12 +597,6 @@ void Solver::apply_T12(double t, bool ext_product) {
   const int64_t k = r + f.r;
   if (k == 0) return;
   blkdiag2_f64(s, Dc(), r, r, f.D.as<double>(), f.r, f.r, 1.0, Dhat.as<double>(), k);
-  if (r > 0 && f.r > 0 && n >= k) {
-    // L_I has orthonormal columns (it is a compression output): it takes no
-    // Householder panels of its own
-    compress_lead_into(r, f);
-    return;
-  }
   if (f.r > 0) copy_f64(s, f.L.as<double>(), n, Wd + r * n, n, n, f.r);
   compress_into(k);
 }
@@ -599,6 +608,7 @@ void Solver::apply_T3(double t) {
   gemm_f64(s, 'T', 'N', r, m, n, 1.0, Lc(), n, B.as<double>(), n, 0.0, WB.as<double>(), r, &ws);
   ws.reset();
   riccati_update_f64(s, r, m, Dc(), r, WB.as<double>(), r, R.as<double>(), m, t, flag_dev(), ws);
+  d_diag = false;
   mark_end(2, ev, 2.0 * n * r * m + 2.0 * r * r * m, 8.0 * ((double)n * r + (double)n * m));
 }
 

@@ -177,3 +177,30 @@ def test_gdle_small(ctx, split, scheme):
     T = 0.1 with h = 1e-2."""
     p = wl.config_gdle(nx=8, h=1e-2, T=0.1, split=split, scheme=scheme)
     check(ctx, p)
+
+
+@pytest.mark.parametrize("split", ["F12", "F1F2"])
+def test_dle_indefinite_P0(ctx, split):
+    """P0 = L0 D0 L0^T with an indefinite D0: the compressions see an
+    indefinite Dhat, which the Gram-matrix route declines, so the Householder
+    route compresses; the P of both schemes matches the oracle."""
+    n = 100
+    A = wl.laplacian_2d(10)
+    C = wl.random_C(2, n, seed=8)
+    L0, _ = wl.random_lowrank_P0(n, 4, seed=9)
+    D0 = np.diag([1.0, -0.5, 0.25, -2.0])
+    p = wl.Problem(name="dle_indefinite", A=A, C=C, L0=L0, D0=D0, T=0.02, h=2e-3, tol=1e-12,
+                   kind="dle", split=split, scheme="strang")
+    check(ctx, p)
+
+
+def test_gram_compression_orthonormality(ctx):
+    """The compression through the Gram matrix leaves L orthonormal to well
+    below the square root of the unit roundoff times 1/tol (the columns of the
+    smallest kept eigenvalues are the least orthonormal); P itself matches the
+    oracle at 1e-10 (the check above)."""
+    p = wl.config_dre_quadrant(nx=16, T=2e-2, h=1e-3)
+    L, D, Lo, Do = check(ctx, p)
+    off = np.abs(L.T @ L - np.eye(L.shape[1])).max()
+    print(f"  max |L^T L - I| = {off:.2e}", flush=True)
+    assert off < 1e-5
