@@ -44,6 +44,7 @@ GIB = 1 << 30
 KERNEL_SOURCES = {
     "gemm_mixed_kernel": "paper_1805_08990_amd/csrc/gemm_mixed.hip",
     "gemm_f64_skinny_kernel": "paper_1805_08990_amd/csrc/gemm_f64.hip",
+    "leja_csr_term_kernel": "paper_1805_08990_amd/csrc/leja.hip",
 }
 
 
@@ -131,7 +132,7 @@ def run_gpu(ctx, prob, precision, steps, warmup):
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     st, tot, rank = sv.state()
-    prof = {"step_kernel": sv.profile_get("step_kernel")} if precision != "leja" else {}
+    prof = {"step_kernel": sv.profile_get("step_kernel")}
     log(f"{precision}: {steps} steps in {elapsed:.3f} s ({steps / elapsed:.1f} steps/s), rank {rank}")
     # phase breakdown from a few more steps with events around every phase
     # (outside the timed region: the events cost the stream a little time)
@@ -185,6 +186,13 @@ def roofline_from(prof, precision):
         achieved = g["flops"] / g["count"] / avg_s / 1e12
         out = {"bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK_FP64_TFLOPS,
                "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP64_TFLOPS, 4)}
+    elif precision == "leja":
+        # one Newton term of the Leja action: the CSR operator, the basis block
+        # read and written, the accumulator read and written (HBM-bound form)
+        kernel = "leja_csr_term_kernel"
+        achieved = g["bytes"] / g["count"] / avg_s / 1e9
+        out = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+               "frac": round(achieved / PEAK_HBM_GBS, 4)}
     else:
         # the FP32 operator is streamed once per launch: HBM-bound form on the
         # algorithmic bytes; the six BF16 piece products it executes (12 n^2 r
@@ -463,7 +471,7 @@ def main():
         line[f"{prec}_phase_ms_per_step"] = {
             k: round(v["ms"] / (args.steps if k == "step_kernel" else pr["phase_steps"]), 4)
             for k, v in pr.items() if k != "phase_steps"}
-        if prec != main_prec and prec != "leja":
+        if prec != main_prec:
             line[f"roofline_{prec}"] = roofline_from(r["prof"], prec)
     for prec, r in results.items():
         line[f"{prec}_err_est"] = r["err_est"]

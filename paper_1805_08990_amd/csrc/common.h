@@ -277,14 +277,6 @@ size_t compress_workspace(int64_t n, int64_t k);
 int64_t compress_f64(hipStream_t s, int64_t n, int64_t k, double* W, const double* Dhat, double tol,
                   int64_t max_rank, double* L, int64_t ldl, double* Dout, int64_t ldd,
                   int64_t* rank_dev, int* flag_dev, Arena& ws);
-// The same for W = [Y, U] (Y n x r in W, ld n, destroyed; U n x q, ld ldu, with
-// orthonormal columns, read only) and Dhat k x k (k = r + q, ld k): U takes no
-// Householder panels.  Needs n >= r + q, r > 0, q > 0.
-int64_t compress_f64_lead(hipStream_t s, int64_t n, int64_t r, double* W, const double* U,
-                          int64_t ldu, int64_t q, const double* Dhat, double tol, int64_t max_rank,
-                          double* L, int64_t ldl, double* Dout, int64_t ldd, int64_t* rank_dev,
-                          int* flag_dev, Arena& ws);
-
 // The same compression through the Gram matrix (gram.hip) for a symmetric
 // positive definite Dhat (ld lddh; dhat_diag: Dhat is diagonal): Dhat = F F^T,
 // G = F^T W^T W F, G = V Lam V^T truncated, L = W F V_I Lam_I^-1/2.  W (n x k,

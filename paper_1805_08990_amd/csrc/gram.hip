@@ -25,58 +25,89 @@
 namespace dme {
 namespace {
 
-constexpr int kCT = 1024;  // Cholesky threads
-constexpr int kCB = 32;    // Cholesky block width
+constexpr int kCT = 256;    // Cholesky threads (4 waves)
+
+// v from lane `l` (a constant) to every lane, through the scalar unit
+__device__ __forceinline__ double readlane_f64(double v, int l) {
+  const uint64_t b = (uint64_t)__double_as_longlong(v);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)b, l);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(b >> 32), l);
+  return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+constexpr int kCB = 32;     // Cholesky block width
+constexpr int kCPanel = 192;  // rows below a block staged in LDS (larger k read them from L2)
 
 // In-place lower Cholesky factor of a k x k symmetric positive definite A (ld
-// lda; only the lower triangle is read), one workgroup, blocked right-looking:
-// per 32-column block the diagonal block is factored in LDS column by column,
-// the rows below are solved against it, and the trailing lower triangle is
-// updated.  The strict upper triangle is set to zero.  A non-positive (or
-// non-finite) pivot sets *status = -1 and zeroes the whole of A (so that what
-// follows sees a zero matrix, not NaNs); otherwise *status = 0.
+// lda; only the lower triangle is read), one workgroup, blocked right-looking,
+// three barriers per 32-column block:
+//   (a) wave 0 factors the diagonal block column by column with row i in
+//       lane i's registers, column c of L broadcast by readlane (no
+//       workgroup barrier inside the block);
+//   (b) every thread solves rows below the block against it (one row each)
+//       and stages them in LDS;
+//   (c) the trailing lower triangle is updated in 4 x 4 register tiles
+//       (A22 -= L21 L21^T, 32 terms per entry).
+// The strict upper triangle is set to zero.  A non-positive (or non-finite)
+// pivot sets *status = -1 and zeroes A (what follows then sees a zero matrix,
+// not NaNs); otherwise *status = 0.
 __global__ __launch_bounds__(kCT) void chol_lower_kernel(int k, double* A, int64_t lda, int64_t* status) {
   __shared__ double blk[kCB][kCB + 1];
+  __shared__ double pan[kCPanel][kCB + 1];
   __shared__ int bad;
   const int tid = threadIdx.x;
+  const int lane = tid & 63;
   if (tid == 0) bad = 0;
-  for (int64_t idx = tid; idx < (int64_t)k * k; idx += kCT) {
-    const int i = (int)(idx % k), j = (int)(idx / k);
-    if (i < j) A[i + (int64_t)j * lda] = 0.0;
-  }
+  for (int j = 1; j < k; ++j)
+    for (int i = tid; i < j; i += kCT) A[i + (int64_t)j * lda] = 0.0;
   __syncthreads();
   for (int j0 = 0; j0 < k; j0 += kCB) {
     const int jb = min(kCB, k - j0);
-    for (int idx = tid; idx < jb * jb; idx += kCT) {
-      const int r = idx % jb, c = idx / jb;
-      blk[r][c] = (r >= c) ? A[(j0 + r) + (int64_t)(j0 + c) * lda] : 0.0;
+    const int rest = k - j0 - jb;
+    // (a) diagonal block: loaded by every thread, factored by wave 0
+    for (int idx = tid; idx < kCB * kCB; idx += kCT) {
+      const int r = idx % kCB, c = idx / kCB;
+      blk[r][c] = (r < jb && c <= r) ? A[(j0 + r) + (int64_t)(j0 + c) * lda] : 0.0;
     }
     __syncthreads();
-    // the diagonal block, column by column
-    for (int c = 0; c < jb; ++c) {
-      if (tid == 0) {
-        const double p = blk[c][c];
-        if (!(p > 0.0) || !isfinite(p)) bad = 1;
-        blk[c][c] = (p > 0.0 && isfinite(p)) ? sqrt(p) : 1.0;
+    if (tid < 64) {
+      // lane i holds row i of the block in registers; column c of L reaches
+      // the other lanes by readlane (constant lane index: no LDS round trip)
+      double row[kCB];
+#pragma unroll
+      for (int c = 0; c < kCB; ++c) row[c] = (lane < jb) ? blk[lane][c] : 0.0;
+      bool okall = true;
+#pragma unroll
+      for (int c = 0; c < kCB; ++c) {
+        if (c < jb) {
+          const double p = readlane_f64(row[c], c);
+          const bool ok = p > 0.0 && isfinite(p);
+          okall = okall && ok;
+          const double dc = ok ? sqrt(p) : 1.0;
+          if (lane == c) row[c] = dc;
+          if (lane > c) row[c] = row[c] / dc;
+#pragma unroll
+          for (int l = c + 1; l < kCB; ++l) {
+            if (l < jb) {
+              const double llc = readlane_f64(row[c], l);
+              if (lane >= l) row[l] -= row[c] * llc;
+            }
+          }
+        }
       }
-      __syncthreads();
-      const double dc = blk[c][c];
-      // column c below the pivot, then the rest of the block's lower triangle
-      if (tid > c && tid < jb) blk[tid][c] /= dc;
-      __syncthreads();
-      for (int idx = tid; idx < jb * jb; idx += kCT) {
-        const int r = idx % jb, l = idx / jb;
-        if (l > c && r >= l) blk[r][l] -= blk[r][c] * blk[l][c];
+      if (lane == 0 && !okall) bad = 1;
+      if (lane < jb) {
+#pragma unroll
+        for (int c = 0; c < kCB; ++c) blk[lane][c] = (c <= lane) ? row[c] : 0.0;
       }
-      __syncthreads();
     }
+    __syncthreads();
     for (int idx = tid; idx < jb * jb; idx += kCT) {
       const int r = idx % jb, c = idx / jb;
       if (r >= c) A[(j0 + r) + (int64_t)(j0 + c) * lda] = blk[r][c];
     }
-    const int rest = k - j0 - jb;
     if (rest > 0) {
-      // rows below the block: x = a L11^-T, row by row (one thread per row)
+      // (b) rows below the block: x L11^T = a, one thread per row
+      const bool staged = rest <= kCPanel;
       for (int i = tid; i < rest; i += kCT) {
         double x[kCB];
         const int64_t row = j0 + jb + i;
@@ -86,36 +117,68 @@ __global__ __launch_bounds__(kCT) void chol_lower_kernel(int k, double* A, int64
         for (int c = 0; c < kCB; ++c) {
           if (c < jb) {
             double v = x[c];
+#pragma unroll
             for (int l = 0; l < c; ++l) v -= x[l] * blk[c][l];
             x[c] = v / blk[c][c];
           }
         }
 #pragma unroll
-        for (int c = 0; c < kCB; ++c)
-          if (c < jb) A[row + (int64_t)(j0 + c) * lda] = x[c];
+        for (int c = 0; c < kCB; ++c) {
+          if (c < jb) {
+            A[row + (int64_t)(j0 + c) * lda] = x[c];
+            if (staged) pan[i][c] = x[c];
+          }
+        }
       }
       __syncthreads();
-      // trailing lower triangle: A22 -= L21 L21^T
-      const int64_t tri = (int64_t)rest * (rest + 1) / 2;
-      for (int64_t idx = tid; idx < tri; idx += kCT) {
-        // idx -> (r, l) with r >= l, column-wise packing of the lower triangle
-        int l = (int)((2.0 * rest + 1.0 - sqrt((2.0 * rest + 1.0) * (2.0 * rest + 1.0) - 8.0 * idx)) / 2.0);
-        while (l > 0 && (int64_t)l * (2 * rest - l + 1) / 2 > idx) --l;
-        while ((int64_t)(l + 1) * (2 * rest - l) / 2 <= idx) ++l;
-        const int r = l + (int)(idx - (int64_t)l * (2 * rest - l + 1) / 2);
-        const int64_t gr = j0 + jb + r, gl = j0 + jb + l;
-        double acc = 0.0;
-        for (int c = 0; c < jb; ++c) acc += A[gr + (int64_t)(j0 + c) * lda] * A[gl + (int64_t)(j0 + c) * lda];
-        A[gr + gl * lda] -= acc;
+      // (c) trailing lower triangle in 4 x 4 tiles (tile (ti, tl), ti >= tl)
+      const int nt = (rest + 3) / 4;
+      const int ntiles = nt * (nt + 1) / 2;
+      for (int t = tid; t < ntiles; t += kCT) {
+        int tl = (int)((2.0 * nt + 1.0 - sqrt((2.0 * nt + 1.0) * (2.0 * nt + 1.0) - 8.0 * t)) / 2.0);
+        while (tl > 0 && tl * (2 * nt - tl + 1) / 2 > t) --tl;
+        while ((tl + 1) * (2 * nt - tl) / 2 <= t) ++tl;
+        const int ti = tl + (t - tl * (2 * nt - tl + 1) / 2);
+        double acc[4][4];
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+          for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
+        for (int c = 0; c < jb; ++c) {
+          double xi[4], xl[4];
+#pragma unroll
+          for (int a = 0; a < 4; ++a) {
+            const int ri = 4 * ti + a, rl = 4 * tl + a;
+            if (staged) {
+              xi[a] = ri < rest ? pan[ri][c] : 0.0;
+              xl[a] = rl < rest ? pan[rl][c] : 0.0;
+            } else {
+              xi[a] = ri < rest ? A[(j0 + jb + ri) + (int64_t)(j0 + c) * lda] : 0.0;
+              xl[a] = rl < rest ? A[(j0 + jb + rl) + (int64_t)(j0 + c) * lda] : 0.0;
+            }
+          }
+#pragma unroll
+          for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int b = 0; b < 4; ++b) acc[a][b] += xi[a] * xl[b];
+        }
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+          for (int b = 0; b < 4; ++b) {
+            const int ri = 4 * ti + a, rl = 4 * tl + b;
+            if (ri < rest && rl < rest && ri >= rl) {
+              const int64_t gi = j0 + jb + ri, gl = j0 + jb + rl;
+              A[gi + gl * lda] -= acc[a][b];
+            }
+          }
       }
     }
     __syncthreads();
   }
   if (bad) {
-    for (int64_t idx = tid; idx < (int64_t)k * k; idx += kCT) {
-      const int i = (int)(idx % k), j = (int)(idx / k);
-      A[i + (int64_t)j * lda] = 0.0;
-    }
+    for (int j = 0; j < k; ++j)
+      for (int i = tid; i < k; i += kCT) A[i + (int64_t)j * lda] = 0.0;
   }
   if (tid == 0) *status = bad ? -1 : 0;
 }

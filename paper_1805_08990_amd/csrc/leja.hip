@@ -157,54 +157,106 @@ __global__ void leja_dense_term_kernel(int64_t n, int64_t ncols, const double* _
   }
 }
 
-// CSR operator, one thread per row and kCsrCols columns: the row's entries are
-// read once into registers (up to kCsrReg of them), then each column's
-// product, next basis entry and accumulator update.
-constexpr int kCsrCols = 8;
-constexpr int kCsrReg = 8;
+// CSR operator, blocks stored row-major (n x cp, cp = ncols rounded up to
+// even): one wave per row, each lane two adjacent columns (and further pairs
+// 128 columns apart), so every load and store of a wave is one contiguous run
+// of 16-byte pairs; the row's entries are wave-uniform (scalar loads).  Forms
+// (A^T W)(i, :), the next basis row W'(i, :) = (A^T W)(i, :) / g - shift
+// W(i, :), and P(i, :) += d_{j+1} W'(i, :).
+constexpr int kRowsPerBlock = 4;
 
-__global__ __launch_bounds__(kT) void leja_csr_term_kernel(
-    int64_t n, int64_t ncols, const int64_t* __restrict__ rowptr, const int* __restrict__ colind,
-    const double* __restrict__ val, const double* __restrict__ Win, double* __restrict__ Wout,
-    double* __restrict__ P, double inv_g, double shift, const double* __restrict__ coef, int m1,
-    int j1, int64_t gcols) {
-  const int64_t i = blockIdx.x * (int64_t)kT + threadIdx.x;
-  if (i >= n) return;
-  const int64_t q0 = (int64_t)blockIdx.y * kCsrCols;
+__device__ __forceinline__ void leja_csr_row(int64_t i, int64_t cp, int64_t ncols, int lane,
+                                             const int64_t* __restrict__ rowptr, const int* __restrict__ colind,
+                                             const double* __restrict__ val, const double* __restrict__ Win,
+                                             double* __restrict__ Wout, double* __restrict__ P, double inv_g,
+                                             double shift, const double* __restrict__ coef, int m1, int j1,
+                                             int64_t gcols) {
   const int64_t k0 = rowptr[i], k1 = rowptr[i + 1];
-  const int64_t nk = k1 - k0;
-  if (nk <= kCsrReg) {
-    int cidx[kCsrReg];
-    double cval[kCsrReg];
-#pragma unroll
-    for (int u = 0; u < kCsrReg; ++u) {
-      const bool in = u < nk;
-      cidx[u] = in ? colind[k0 + u] : 0;
-      cval[u] = in ? val[k0 + u] : 0.0;
+  for (int64_t q = 2 * (int64_t)lane; q < ncols; q += 128) {
+    double2 acc = make_double2(0.0, 0.0);
+    for (int64_t kk = k0; kk < k1; ++kk) {
+      const double a = val[kk];
+      const double2 w = *reinterpret_cast<const double2*>(Win + (int64_t)colind[kk] * cp + q);
+      acc.x += a * w.x;
+      acc.y += a * w.y;
     }
-#pragma unroll 2
-    for (int qq = 0; qq < kCsrCols; ++qq) {
-      const int64_t q = q0 + qq;
-      if (q >= ncols) break;
-      const double* wc = Win + q * n;
-      double acc = 0.0;
-#pragma unroll
-      for (int u = 0; u < kCsrReg; ++u) acc += cval[u] * wc[cidx[u]];
-      const double w = acc * inv_g - shift * wc[i];
-      Wout[i + q * n] = w;
-      P[i + q * n] += coef[group_of(q, gcols) * m1 + j1] * w;
+    const int64_t o = i * cp + q;
+    const double2 wi = *reinterpret_cast<const double2*>(Win + o);
+    double2 wn;
+    wn.x = acc.x * inv_g - shift * wi.x;
+    wn.y = acc.y * inv_g - shift * wi.y;
+    *reinterpret_cast<double2*>(Wout + o) = wn;
+    double2 pp = *reinterpret_cast<const double2*>(P + o);
+    pp.x += coef[group_of(q, gcols) * m1 + j1] * wn.x;
+    if (q + 1 < ncols) pp.y += coef[group_of(q + 1, gcols) * m1 + j1] * wn.y;
+    *reinterpret_cast<double2*>(P + o) = pp;
+  }
+}
+
+__global__ __launch_bounds__(64 * kRowsPerBlock) void leja_csr_term_kernel(
+    int64_t n, int64_t cp, int64_t ncols, const int64_t* __restrict__ rowptr, const int* __restrict__ colind,
+    const double* __restrict__ val, const double* __restrict__ Win, double* __restrict__ Wout,
+    double* __restrict__ P, double inv_g, double shift, const double* __restrict__ coef, int m1, int j1,
+    int64_t gcols) {
+  const int64_t i = (int64_t)blockIdx.x * kRowsPerBlock + (threadIdx.x >> 6);
+  if (i >= n) return;
+  leja_csr_row(i, cp, ncols, threadIdx.x & 63, rowptr, colind, val, Win, Wout, P, inv_g, shift, coef, m1, j1,
+               gcols);
+}
+
+// Column-major X (ld ldx) -> row-major W (ld cp) and P = d_0 X, through 32 x 32
+// LDS tiles (coalesced on both sides); pad columns [ncols, cp) are zero.
+__global__ void leja_init_rm_kernel(int64_t n, int64_t ncols, int64_t cp, const double* __restrict__ X,
+                                    int64_t ldx, double* __restrict__ W, double* __restrict__ P,
+                                    const double* __restrict__ coef, int m1, int64_t gcols) {
+  __shared__ double tile[32][33];
+  const int64_t r0 = (int64_t)blockIdx.x * 32, c0 = (int64_t)blockIdx.y * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8
+  for (int j = ty; j < 32; j += 8) {
+    const int64_t r = r0 + tx, c = c0 + j;
+    tile[j][tx] = (r < n && c < ncols) ? X[r + c * ldx] : 0.0;
+  }
+  __syncthreads();
+  for (int j = ty; j < 32; j += 8) {
+    const int64_t r = r0 + j, c = c0 + tx;
+    if (r < n && c < cp) {
+      const double x = tile[tx][j];
+      W[r * cp + c] = x;
+      P[r * cp + c] = (c < ncols) ? coef[group_of(c, gcols) * m1] * x : 0.0;
     }
-  } else {
-    for (int qq = 0; qq < kCsrCols; ++qq) {
-      const int64_t q = q0 + qq;
-      if (q >= ncols) break;
-      const double* wc = Win + q * n;
-      double acc = 0.0;
-      for (int64_t k = k0; k < k1; ++k) acc += val[k] * wc[colind[k]];
-      const double w = acc * inv_g - shift * wc[i];
-      Wout[i + q * n] = w;
-      P[i + q * n] += coef[group_of(q, gcols) * m1 + j1] * w;
-    }
+  }
+}
+
+// end of a substep that is not the last, row-major blocks
+__global__ void leja_restart_rm_kernel(int64_t n, int64_t ncols, int64_t cp, double* __restrict__ W,
+                                       double* __restrict__ P, const double* __restrict__ coef,
+                                       const double* __restrict__ scale, int m1, int64_t gcols) {
+  const int64_t total = n * cp;
+  for (int64_t idx = blockIdx.x * (int64_t)kT + threadIdx.x; idx < total; idx += (int64_t)gridDim.x * kT) {
+    const int64_t c = idx % cp;
+    if (c >= ncols) continue;
+    const int g = group_of(c, gcols);
+    const double x = scale[g] * P[idx];
+    W[idx] = x;
+    P[idx] = coef[g * m1] * x;
+  }
+}
+
+// end of the last substep: Y (column-major, ld ldy) = e^{t c / S} P (row-major)
+__global__ void leja_finish_rm_kernel(int64_t n, int64_t ncols, int64_t cp, const double* __restrict__ P,
+                                      double* __restrict__ Y, int64_t ldy, const double* __restrict__ scale,
+                                      int64_t gcols) {
+  __shared__ double tile[32][33];
+  const int64_t r0 = (int64_t)blockIdx.x * 32, c0 = (int64_t)blockIdx.y * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  for (int j = ty; j < 32; j += 8) {
+    const int64_t r = r0 + j, c = c0 + tx;
+    tile[j][tx] = (r < n && c < ncols) ? scale[group_of(c, gcols)] * P[r * cp + c] : 0.0;
+  }
+  __syncthreads();
+  for (int j = ty; j < 32; j += 8) {
+    const int64_t r = r0 + tx, c = c0 + j;
+    if (r < n && c < ncols) Y[r + c * ldy] = tile[tx][j];
   }
 }
 
@@ -474,7 +526,7 @@ std::unique_ptr<LejaPlan> leja_plan(const LejaOp& op, const std::vector<double>&
 }
 
 size_t leja_workspace(int64_t n, int64_t ncols) {
-  const size_t blk = ((size_t)n * ncols * sizeof(double) + 255) & ~size_t(255);
+  const size_t blk = ((size_t)n * ((ncols + 1) & ~int64_t(1)) * sizeof(double) + 255) & ~size_t(255);
   return 3 * blk + gemm_f64_workspace(n, ncols, n) + 1024;
 }
 
@@ -489,31 +541,50 @@ void leja_apply(hipStream_t s, const LejaOp& op, const LejaPlan& plan, const dou
   const double* coef = plan.coef_dev.as<double>();
   const double* scale = plan.scale_dev.as<double>();
   const size_t mark = ws.used;
-  double* W = ws.get<double>((size_t)n * ncols);
-  double* W2 = ws.get<double>((size_t)n * ncols);  // CSR: the other half of the ping-pong; dense: A^T W
-  double* P = ws.get<double>((size_t)n * ncols);
+  const size_t blk = (size_t)n * ((ncols + 1) & ~int64_t(1));
+  double* W = ws.get<double>(blk);
+  double* W2 = ws.get<double>(blk);  // CSR: the other half of the ping-pong; dense: A^T W
+  double* P = ws.get<double>(blk);
   const size_t mark_gemm = ws.used;
   const unsigned gb = grid_for(n * ncols);
   const double inv_g = plan.g > 0.0 ? 1.0 / plan.g : 0.0;
+  if (op.sparse()) {
+    // row-major blocks, n x cp
+    const int64_t cp = (ncols + 1) & ~int64_t(1);
+    const dim3 tgrid((unsigned)cdiv(n, 32), (unsigned)cdiv(cp, 32));
+    hipLaunchKernelGGL(leja_init_rm_kernel, tgrid, dim3(256), 0, s, n, ncols, cp, X, ldx, W, P, coef, m1, gcols);
+    DME_HIP(hipGetLastError());
+    const unsigned rgrid = (unsigned)cdiv(n, kRowsPerBlock);
+    for (int sub = 0; sub < plan.S; ++sub) {
+      for (int j = 0; j < plan.m; ++j) {
+        const double shift = plan.c * inv_g + plan.xi[j];
+        hipLaunchKernelGGL(leja_csr_term_kernel, dim3(rgrid), dim3(64 * kRowsPerBlock), 0, s, n, cp, ncols,
+                           op.rowptr.as<int64_t>(), op.colind.as<int>(), op.val.as<double>(), W, W2, P, inv_g,
+                           shift, coef, m1, j + 1, gcols);
+        DME_HIP(hipGetLastError());
+        std::swap(W, W2);
+      }
+      if (sub + 1 < plan.S) {
+        hipLaunchKernelGGL(leja_restart_rm_kernel, dim3(grid_for(n * cp)), dim3(kT), 0, s, n, ncols, cp, W, P,
+                           coef, scale, m1, gcols);
+        DME_HIP(hipGetLastError());
+      }
+    }
+    hipLaunchKernelGGL(leja_finish_rm_kernel, tgrid, dim3(256), 0, s, n, ncols, cp, P, Y, ldy, scale, gcols);
+    DME_HIP(hipGetLastError());
+    ws.used = mark;
+    return;
+  }
   hipLaunchKernelGGL(leja_init_kernel, dim3(gb), dim3(kT), 0, s, n, ncols, X, ldx, W, P, coef, m1, gcols);
   DME_HIP(hipGetLastError());
   for (int sub = 0; sub < plan.S; ++sub) {
     for (int j = 0; j < plan.m; ++j) {
       const double shift = plan.c * inv_g + plan.xi[j];
-      if (op.sparse()) {
-        dim3 grid((unsigned)cdiv(n, kT), (unsigned)cdiv(ncols, kCsrCols));
-        hipLaunchKernelGGL(leja_csr_term_kernel, grid, dim3(kT), 0, s, n, ncols, op.rowptr.as<int64_t>(),
-                           op.colind.as<int>(), op.val.as<double>(), W, W2, P, inv_g, shift, coef, m1,
-                           j + 1, gcols);
-        DME_HIP(hipGetLastError());
-        std::swap(W, W2);
-      } else {
-        ws.used = mark_gemm;
-        gemm_f64(s, 'N', 'N', n, ncols, n, 1.0, op.dense, n, W, n, 0.0, W2, n, &ws);
-        hipLaunchKernelGGL(leja_dense_term_kernel, dim3(gb), dim3(kT), 0, s, n, ncols, W2, W, P, inv_g,
-                           shift, coef, m1, j + 1, gcols);
-        DME_HIP(hipGetLastError());
-      }
+      ws.used = mark_gemm;
+      gemm_f64(s, 'N', 'N', n, ncols, n, 1.0, op.dense, n, W, n, 0.0, W2, n, &ws);
+      hipLaunchKernelGGL(leja_dense_term_kernel, dim3(gb), dim3(kT), 0, s, n, ncols, W2, W, P, inv_g,
+                         shift, coef, m1, j + 1, gcols);
+      DME_HIP(hipGetLastError());
     }
     if (sub + 1 < plan.S) {
       hipLaunchKernelGGL(leja_restart_kernel, dim3(gb), dim3(kT), 0, s, n, ncols, W, P, coef, scale, m1, gcols);

@@ -90,6 +90,7 @@ struct PendingTiming {
   int phase;
   hipEvent_t a, b;
   double flops, bytes;
+  int64_t launches;
 };
 
 struct Solver {
@@ -136,7 +137,8 @@ struct Solver {
   std::vector<PendingTiming> pending;
   std::vector<hipEvent_t> event_pool;
   hipEvent_t mark_begin();
-  void mark_end(int ph, hipEvent_t a, double flops, double bytes);
+  // launches: how many launches of the phase's kernel the interval holds
+  void mark_end(int ph, hipEvent_t a, double flops, double bytes, int64_t launches = 1);
   void flush_timings();
   ~Solver();
 
@@ -182,8 +184,6 @@ struct Solver {
   void apply_T3(double t);
   void apply_T4(double t);
   void compress_into(int64_t k);  // W (n x k), Dhat (k x k) -> new (L, D)
-  // W[:, 0:rY] = e^{tA} L and the quadrature factor f (orthonormal L_I) -> new (L, D)
-  void compress_lead_into(int64_t rY, const QuadFactor& f);
   void apply_E(double t, const double* X, int64_t r, double* Y, int64_t ldy);
   void build_quadrature(double t);
   void apply_mass_matrix(const double* M);

@@ -127,10 +127,10 @@ hipEvent_t Solver::mark_begin() {
   return e;
 }
 
-void Solver::mark_end(int ph, hipEvent_t a, double flops, double bytes) {
+void Solver::mark_end(int ph, hipEvent_t a, double flops, double bytes, int64_t launches) {
   if (!profiling || a == nullptr) return;
   hipEvent_t b = mark_begin();
-  pending.push_back({ph, a, b, flops, bytes});
+  pending.push_back({ph, a, b, flops, bytes, launches});
 }
 
 void Solver::flush_timings() {
@@ -140,7 +140,7 @@ void Solver::flush_timings() {
     float ms = 0.f;
     DME_HIP(hipEventElapsedTime(&ms, t.a, t.b));
     PhaseAcc& acc = phase[t.phase];
-    acc.count += 1;
+    acc.count += t.launches;
     acc.ms += ms;
     acc.flops += t.flops;
     acc.bytes += t.bytes;
@@ -503,14 +503,18 @@ void Solver::apply_E(double t, const double* X, int64_t rr, double* Y, int64_t l
   ws.reset();
   const OperatorSet& set = *ops.at(t);
   if (set.lop) {
-    hipEvent_t ev = mark_phase();
+    // profiling level 1 times the action as the step-product phase, level 2
+    // as its Newton-term launches (the events bracket the whole action, so
+    // the block transposes at its ends count against the terms)
+    hipEvent_t ev = profiling ? mark_begin() : nullptr;
     leja_apply(s, *set.lop, *set.plan, X, n, rr, Y, ldy, ws);
     // S m products with A^T (2 nnz r flops each for CSR, 2 n^2 r dense); per
     // term the basis block is read and written and the accumulator updated
-    const double prods = (double)leja_products(*set.plan);
+    const int64_t prods = leja_products(*set.plan);
     const double opf = set.lop->sparse() ? 2.0 * set.lop->nnz : 2.0 * (double)n * n;
     const double opb = set.lop->sparse() ? 12.0 * set.lop->nnz + 8.0 * n : 8.0 * (double)n * n;
-    mark_end(0, ev, prods * opf * rr, prods * (opb + 32.0 * n * rr));
+    mark_end(profiling == 2 ? DME_PHASE_STEP_KERNEL : DME_PHASE_STEP_GEMM, ev, (double)prods * opf * rr,
+             (double)prods * (opb + 32.0 * n * rr), prods);
     return;
   }
   StepKernelTimer kt;
@@ -550,23 +554,6 @@ void Solver::compress_into(int64_t k) {
     mark_end(1, ev, 2.0 * n * kk * kk + 4.0 * n * kk * rn + 10.0 * kk * kk * kk,
              8.0 * (2.0 * n * kk + 2.0 * n * rn));
   }
-  cur ^= 1;
-  r = rn;
-  d_diag = true;
-}
-
-void Solver::compress_lead_into(int64_t rY, const QuadFactor& f) {
-  ws.reset();
-  hipEvent_t ev = mark_phase();
-  const int64_t k = rY + f.r;
-  const int64_t rn = compress_f64_lead(s, n, rY, W.as<double>(), f.L.as<double>(), n, f.r,
-                                       Dhat.as<double>(), opts.tol, max_rank, Ln(), n, Dn(), 0,
-                                       rank_dev(), flag_dev(), ws);
-  // projections 8 n q r, Householder QR 2 n r^2 - 2/3 r^3, Q application 4 n r r',
-  // U terms 4 n q r', small eigenproblem ~ 10 k^3
-  const double kk = (double)k, ry = (double)rY, qq = (double)f.r, rr = (double)rn;
-  mark_end(1, ev, 8.0 * n * qq * ry + 2.0 * n * ry * ry + 4.0 * n * ry * rr + 4.0 * n * qq * rr + 10.0 * kk * kk * kk,
-           8.0 * (2.0 * n * kk + 2.0 * n * rr));
   cur ^= 1;
   r = rn;
   d_diag = true;
