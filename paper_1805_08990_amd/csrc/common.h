@@ -108,8 +108,9 @@ template <int CTRL>
 __device__ inline double dpp_mov_f64(double v) {
 #if defined(__HIP_DEVICE_COMPILE__)
   const uint64_t b = (uint64_t)__double_as_longlong(v);
-  const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)b, CTRL, 0xF, 0xF, false);
-  const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(b >> 32), CTRL, 0xF, 0xF, false);
+  // every pattern used reads a valid lane, so no old value is kept (bound_ctrl)
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)b, CTRL, 0xF, 0xF, true);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)(b >> 32), CTRL, 0xF, 0xF, true);
   return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
 #else
   return v;
@@ -119,6 +120,7 @@ constexpr int kDppXor1 = 0xB1;        // quad_perm [1, 0, 3, 2]
 constexpr int kDppXor2 = 0x4E;        // quad_perm [2, 3, 0, 1]
 constexpr int kDppHalfMirror = 0x141; // lane i <-> 7 - i within 8
 constexpr int kDppMirror = 0x140;     // lane i <-> 15 - i within 16
+constexpr int kDppRor8 = 0x128;       // lane i <- lane i ^ 8 within 16 (rotate by 8)
 
 // v + (v of the lane 16 (S = 16) or 32 (S = 32) away), by a permlane swap
 template <int S>
@@ -281,12 +283,30 @@ int64_t compress_f64(hipStream_t s, int64_t n, int64_t k, double* W, const doubl
 // positive definite Dhat (ld lddh; dhat_diag: Dhat is diagonal): Dhat = F F^T,
 // G = F^T W^T W F, G = V Lam V^T truncated, L = W F V_I Lam_I^-1/2.  W (n x k,
 // ld ldw) is read only.  Returns the kept rank, or -1 (nothing written) when
-// Dhat is not numerically positive definite.
+// Dhat is not numerically positive definite.  L must hold min(max_rank, k)
+// columns: the products forming L are queued for a guessed width (rank_hint +
+// 16 columns, rank_hint <= 0: every column) before the rank reaches the host,
+// so that the round trip overlaps them; columns from the rank on come out zero,
+// and a rank above the guess is served by a second product.
+//
+// lowrank (optional): the D blocks of Dhat (rows and columns [c r, (c + 1) r)
+// for c < ncopies; the rest of Dhat is diagonal) are diag(lam) - t Z Z^T, the
+// Riccati update of a diagonal D (lam r, Z r x m with m <= 8, device).  Their
+// factor is then formed directly, F_D = Lam^1/2 (I - Zh K Zh^T) with
+// Zh = sqrt(t) Lam^-1/2 Z and K = (I + (I - Zh^T Zh)^1/2)^-1 (an m x m matrix
+// function): F_D F_D^T = Lam^1/2 (I - Zh Zh^T) Lam^1/2, with no Cholesky.
+struct LowRankD {
+  const double* lam;
+  const double* Z;
+  double t;
+  int64_t r, m;
+  int ncopies;
+};
 size_t compress_gram_workspace(int64_t n, int64_t k);
 int64_t compress_gram_f64(hipStream_t s, int64_t n, int64_t k, const double* W, int64_t ldw,
-                          const double* Dhat, int64_t lddh, bool dhat_diag, double tol, int64_t max_rank,
-                          double* L, int64_t ldl, double* Dout, int64_t ldd, int64_t* rank_dev,
-                          int* flag_dev, Arena& ws);
+                          const double* Dhat, int64_t lddh, bool dhat_diag, const LowRankD* lowrank,
+                          double tol, int64_t max_rank, double* L, int64_t ldl, double* Dout, int64_t ldd,
+                          int64_t* rank_dev, int* flag_dev, Arena& ws, int64_t rank_hint = 0);
 // A device int64 to the host through the bound auxiliary stream's pinned slot:
 // launch() enqueues the copy on s and returns its sequence number, wait()
 // polls for it (falling back to a stream synchronisation), rank_to_host() does
@@ -310,8 +330,9 @@ void syev_trunc_f64(hipStream_t s, int64_t k, const double* M, int64_t ldm, doub
 void feedback_gain_f64(hipStream_t s, int64_t n, int64_t r, int64_t m, const double* L, int64_t ldl,
                        const double* D, int64_t ldd, const double* B, int64_t ldb, const double* R,
                        int64_t ldr, double* K, int64_t ldk, int* flag_dev, Arena& ws);
+// Zout (optional, r x m, ld r): receives Z with D_new = sym(D) - t Z Z^T.
 void riccati_update_f64(hipStream_t s, int64_t r, int64_t m, double* D, int64_t ldd,
                         const double* WB, int64_t ldw, const double* R, int64_t ldr, double t,
-                        int* flag_dev, Arena& ws);
+                        int* flag_dev, Arena& ws, double* Zout = nullptr);
 
 }  // namespace dme

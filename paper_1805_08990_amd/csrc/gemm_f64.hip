@@ -174,6 +174,63 @@ __global__ void splitk_reduce_kernel(int M, int N, int nsplit, double alpha,
   }
 }
 
+// Small products (M, N <= kSmallMaxMN, K <= kSmallMaxK: the k x k products of
+// the compression and the eigensolver).  The tiled kernel gives them only a
+// few 64 x 64 tiles, each a long chain of slabs; here a 4-wave workgroup owns
+// a 16 x 16 tile of C and its waves take every fourth 4-deep step of K, with
+// operands loaded straight from global memory (they are L2-resident) four
+// steps ahead, and the four partial tiles are added in wave order through LDS
+// (deterministic).  Same lane layout and epilogue as gemm_f64_kernel.
+constexpr int kSmallMaxMN = 256;
+constexpr int kSmallMaxK = 2048;
+constexpr int kSmallUnroll = 4;
+
+template <bool TA, bool TB>
+__global__ __launch_bounds__(256) void gemm_f64_small_kernel(int M, int N, int K, double alpha,
+                                                             const double* __restrict__ A, int64_t lda,
+                                                             const double* __restrict__ B, int64_t ldb,
+                                                             double beta, double* __restrict__ C, int64_t ldc) {
+  __shared__ v4d red[3][64];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int r16 = lane & 15, kq = lane >> 4;
+  const int m = blockIdx.x * 16 + r16, n = blockIdx.y * 16 + r16;
+  const bool min_ = m < M, nin = n < N;
+  auto opA = [&](int k) -> double {
+    return (min_ && k < K) ? (TA ? A[k + (int64_t)m * lda] : A[m + (int64_t)k * lda]) : 0.0;
+  };
+  auto opB = [&](int k) -> double {
+    return (nin && k < K) ? (TB ? B[n + (int64_t)k * ldb] : B[k + (int64_t)n * ldb]) : 0.0;
+  };
+  v4d acc = v4d{0.0, 0.0, 0.0, 0.0};
+  // wave w: steps k0 = 4 (w + 4 s); kSmallUnroll steps loaded before they are used
+  for (int k0 = 4 * wave; k0 < K; k0 += 16 * kSmallUnroll) {
+    double fa[kSmallUnroll], fb[kSmallUnroll];
+#pragma unroll
+    for (int u = 0; u < kSmallUnroll; ++u) {
+      const int k = k0 + 16 * u + kq;
+      fa[u] = opB(k);
+      fb[u] = opA(k);
+    }
+#pragma unroll
+    for (int u = 0; u < kSmallUnroll; ++u) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[u], fb[u], acc, 0, 0, 0);
+  }
+  if (wave > 0) red[wave - 1][lane] = acc;
+  __syncthreads();
+  if (wave == 0) {
+#pragma unroll
+    for (int w = 0; w < 3; ++w) acc += red[w][lane];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int nn = blockIdx.y * 16 + v * 4 + kq;
+      if (min_ && nn < N) {
+        double* c = C + m + (int64_t)nn * ldc;
+        const double out = alpha * acc[v];
+        *c = (beta == 0.0) ? out : out + beta * (*c);
+      }
+    }
+  }
+}
+
 template <int BM, int BN, int BK, bool TA, bool TB>
 void launch_tile(hipStream_t s, int M, int N, int K, int nsplit, int kchunk, double alpha,
                  const double* A, int64_t lda, const double* B, int64_t ldb, double beta,
@@ -456,6 +513,21 @@ void gemm_f64(hipStream_t s, char ta, char tb, int64_t M, int64_t N, int64_t K, 
     const int ns = skinny_nsplit(M, K);
     double* partial = ws->get<double>((size_t)ns * M * N);
     gemm_f64_skinny(s, (int)M, (int)N, (int)K, alpha, A, lda, B, ldb, beta, C, ldc, partial);
+    return;
+  }
+  if (M <= kSmallMaxMN && N <= kSmallMaxMN && K <= kSmallMaxK) {
+    const dim3 grid((unsigned)cdiv(M, 16), (unsigned)cdiv(N, 16));
+    const bool TA = (ta == 'T' || ta == 't'), TB = (tb == 'T' || tb == 't');
+    const int iM = (int)M, iN = (int)N, iK = (int)K;
+    if (!TA && !TB)
+      hipLaunchKernelGGL((gemm_f64_small_kernel<false, false>), grid, dim3(256), 0, s, iM, iN, iK, alpha, A, lda, B, ldb, beta, C, ldc);
+    else if (TA && !TB)
+      hipLaunchKernelGGL((gemm_f64_small_kernel<true, false>), grid, dim3(256), 0, s, iM, iN, iK, alpha, A, lda, B, ldb, beta, C, ldc);
+    else if (!TA && TB)
+      hipLaunchKernelGGL((gemm_f64_small_kernel<false, true>), grid, dim3(256), 0, s, iM, iN, iK, alpha, A, lda, B, ldb, beta, C, ldc);
+    else
+      hipLaunchKernelGGL((gemm_f64_small_kernel<true, true>), grid, dim3(256), 0, s, iM, iN, iK, alpha, A, lda, B, ldb, beta, C, ldc);
+    DME_HIP(hipGetLastError());
     return;
   }
   Plan p = plan_for(M, N, K);

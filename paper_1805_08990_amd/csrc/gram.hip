@@ -201,6 +201,136 @@ __global__ void sqrt_diag_kernel(int k, const double* Dhat, int64_t ldd, double*
   if (threadIdx.x == 0) *status = bad ? -1 : 0;
 }
 
+// F for a Dhat whose D blocks are diag(lam) - t Z Z^T (see LowRankD), one
+// workgroup: Zh = sqrt(t) Lam^-1/2 Z and G = Zh^T Zh (m x m) in LDS, G = U g U^T
+// by cyclic Jacobi in one thread (m <= 8), K = U diag(1 / (1 + sqrt(1 - g))) U^T,
+// M = Zh K, then F_D(i, j) = sqrt(lam_i) (delta_ij - M(i, :) Zh(j, :)^T) in
+// every D block and sqrt(Dhat_ii) on the rest of the diagonal.  lam <= 0,
+// g >= 1 or a non-positive diagonal entry make *status = -1 (and F zero).
+constexpr int kLrMaxM = 8;
+constexpr int kLrMaxR = 256;
+
+__global__ __launch_bounds__(1024) void lowrank_factor_kernel(int k, const double* Dhat, int64_t lddh,
+                                                             const double* lam, const double* Z, double t,
+                                                             int r, int m, int ncopies, double* F,
+                                                             int64_t* status) {
+  __shared__ double Zh[kLrMaxR][kLrMaxM];
+  __shared__ double Mz[kLrMaxR][kLrMaxM];
+  __shared__ double sl[kLrMaxR];
+  __shared__ double part[16][kLrMaxM * kLrMaxM];
+  __shared__ double G[kLrMaxM][kLrMaxM], U[kLrMaxM][kLrMaxM], K[kLrMaxM][kLrMaxM];
+  __shared__ int bad;
+  const int tid = threadIdx.x;
+  if (tid == 0) bad = 0;
+  __syncthreads();
+  const double st = sqrt(t);
+  for (int i = tid; i < r; i += 1024) {
+    const double l = lam[i];
+    if (!(l > 0.0) || !isfinite(l)) bad = 1;
+    const double s = (l > 0.0) ? sqrt(l) : 1.0;
+    sl[i] = s;
+    for (int a = 0; a < m; ++a) Zh[i][a] = st * Z[i + (int64_t)a * r] / s;
+  }
+  __syncthreads();
+  // G = Zh^T Zh: 16 slices of the rows per entry, then the slices in order
+  {
+    const int mm = m * m, e = tid % 64, sli = tid / 64;
+    double acc = 0.0;
+    if (e < mm) {
+      const int a = e % m, b = e / m;
+      for (int i = sli; i < r; i += 16) acc += Zh[i][a] * Zh[i][b];
+    }
+    if (e < kLrMaxM * kLrMaxM) part[sli][e] = acc;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    for (int a = 0; a < m; ++a)
+      for (int b = 0; b < m; ++b) {
+        double v = 0.0;
+        for (int q = 0; q < 16; ++q) v += part[q][a + b * m];
+        G[a][b] = v;
+        U[a][b] = (a == b) ? 1.0 : 0.0;
+      }
+    // cyclic Jacobi on the symmetric m x m G; a rotation zeroes its pair
+    // exactly, and pairs below 1e-17 sqrt(|G_pp G_qq|) are dropped, so the
+    // sweeps end once every off-diagonal entry is at that level
+    for (int sweep = 0; sweep < 30; ++sweep) {
+      bool rotated = false;
+      for (int p = 0; p < m; ++p)
+        for (int q = p + 1; q < m; ++q) {
+          if (fabs(G[p][q]) <= 1e-17 * sqrt(fabs(G[p][p] * G[q][q]))) {
+            G[p][q] = G[q][p] = 0.0;
+            continue;
+          }
+          rotated = true;
+          const double theta = (G[q][q] - G[p][p]) / (2.0 * G[p][q]);
+          const double tn = copysign(1.0, theta) / (fabs(theta) + sqrt(theta * theta + 1.0));
+          const double c = 1.0 / sqrt(tn * tn + 1.0), sn = tn * c;
+          for (int x = 0; x < m; ++x) {  // G <- J^T G J, U <- U J
+            const double gp = G[x][p], gq = G[x][q];
+            G[x][p] = c * gp - sn * gq;
+            G[x][q] = sn * gp + c * gq;
+          }
+          for (int x = 0; x < m; ++x) {
+            const double gp = G[p][x], gq = G[q][x];
+            G[p][x] = c * gp - sn * gq;
+            G[q][x] = sn * gp + c * gq;
+          }
+          for (int x = 0; x < m; ++x) {
+            const double up = U[x][p], uq = U[x][q];
+            U[x][p] = c * up - sn * uq;
+            U[x][q] = sn * up + c * uq;
+          }
+          G[p][q] = G[q][p] = 0.0;
+        }
+      if (!rotated) break;
+    }
+    double f[kLrMaxM];
+    for (int a = 0; a < m; ++a) {
+      const double g = G[a][a];
+      if (!(g < 1.0) || !isfinite(g)) bad = 1;
+      f[a] = 1.0 / (1.0 + sqrt(fmax(1.0 - g, 0.0)));
+    }
+    for (int a = 0; a < m; ++a)
+      for (int b = 0; b < m; ++b) {
+        double v = 0.0;
+        for (int q = 0; q < m; ++q) v += U[a][q] * f[q] * U[b][q];
+        K[a][b] = v;
+      }
+  }
+  __syncthreads();
+  for (int i = tid; i < r; i += 1024)
+    for (int a = 0; a < m; ++a) {
+      double v = 0.0;
+      for (int b = 0; b < m; ++b) v += Zh[i][b] * K[b][a];
+      Mz[i][a] = v;
+    }
+  // the rest of the diagonal
+  const int nd = ncopies * r;
+  for (int i = nd + tid; i < k; i += 1024) {
+    const double d = Dhat[i + (int64_t)i * lddh];
+    if (!(d > 0.0) || !isfinite(d)) bad = 1;
+  }
+  __syncthreads();
+  const bool ok = !bad;
+  for (int j = tid >> 6; j < k; j += 16)  // a wave per column
+    for (int i = tid & 63; i < k; i += 64) {
+      double v = 0.0;
+      if (ok) {
+        if (i < nd && j < nd && i / r == j / r) {
+          const int ii = i % r, jj = j % r;
+          double acc = 0.0;
+          for (int a = 0; a < m; ++a) acc += Mz[ii][a] * Zh[jj][a];
+          v = sl[ii] * ((ii == jj ? 1.0 : 0.0) - acc);
+        } else if (i == j) {
+          v = sqrt(Dhat[i + (int64_t)i * lddh]);
+        }
+      }
+      F[i + (int64_t)j * k] = v;
+    }
+  if (tid == 0) *status = ok ? 0 : -1;
+}
+
 __global__ void copy_lower_kernel(int k, const double* Dhat, int64_t ldd, double* F) {
   for (int64_t idx = blockIdx.x * 256 + threadIdx.x; idx < (int64_t)k * k; idx += (int64_t)gridDim.x * 256) {
     const int i = (int)(idx % k), j = (int)(idx / k);
@@ -217,10 +347,16 @@ __global__ void sym_kernel(int k, const double* G, double* S) {
 }
 
 // T(:, j) /= sqrt(lam_j), j < r (k x r, ld k)
-__global__ void scale_cols_kernel(int k, int r, const double* lam, double* T) {
-  for (int64_t idx = blockIdx.x * 256 + threadIdx.x; idx < (int64_t)k * r; idx += (int64_t)gridDim.x * 256) {
-    const int j = (int)(idx / k);
-    T[idx] /= sqrt(lam[j]);
+// T(:, j) /= sqrt(lam_j) for j < *rank, T(:, j) = 0 for rank <= j < r (the
+// columns past the kept rank may hold anything)
+__global__ void scale_cols_kernel(int k, int r, const double* lam, const int64_t* rank, double* T) {
+  const int64_t rk = *rank;
+  for (int j = blockIdx.y; j < r; j += gridDim.y) {
+    const double f = (j < rk) ? 1.0 / sqrt(lam[j]) : 0.0;
+    for (int i = blockIdx.x * 256 + threadIdx.x; i < k; i += gridDim.x * 256) {
+      double* t = T + i + (int64_t)j * k;
+      *t = (j < rk) ? *t * f : 0.0;
+    }
   }
 }
 
@@ -248,9 +384,9 @@ size_t compress_gram_workspace(int64_t n, int64_t k) {
 }
 
 int64_t compress_gram_f64(hipStream_t s, int64_t n, int64_t k, const double* W, int64_t ldw,
-                          const double* Dhat, int64_t lddh, bool dhat_diag, double tol, int64_t max_rank,
-                          double* L, int64_t ldl, double* Dout, int64_t ldd, int64_t* rank_dev,
-                          int* flag_dev, Arena& ws) {
+                          const double* Dhat, int64_t lddh, bool dhat_diag, const LowRankD* lowrank,
+                          double tol, int64_t max_rank, double* L, int64_t ldl, double* Dout, int64_t ldd,
+                          int64_t* rank_dev, int* flag_dev, Arena& ws, int64_t rank_hint) {
   if (k <= 0 || n <= 0) return 0;
   const size_t mark = ws.used;
   double* F = ws.get<double>((size_t)k * k);
@@ -266,6 +402,9 @@ int64_t compress_gram_f64(hipStream_t s, int64_t n, int64_t k, const double* W, 
   // Dhat = F F^T; its status reaches the host while W^T W runs
   if (dhat_diag) {
     hipLaunchKernelGGL(sqrt_diag_kernel, dim3(1), dim3(1024), 0, s, (int)k, Dhat, lddh, F, status);
+  } else if (lowrank && lowrank->m <= kLrMaxM && lowrank->r <= kLrMaxR && lowrank->ncopies * lowrank->r <= k) {
+    hipLaunchKernelGGL(lowrank_factor_kernel, dim3(1), dim3(1024), 0, s, (int)k, Dhat, lddh, lowrank->lam,
+                       lowrank->Z, lowrank->t, (int)lowrank->r, (int)lowrank->m, lowrank->ncopies, F, status);
   } else {
     hipLaunchKernelGGL(copy_lower_kernel, dim3(blocks(k * k)), dim3(256), 0, s, (int)k, Dhat, lddh, F);
     DME_HIP(hipGetLastError());
@@ -290,19 +429,28 @@ int64_t compress_gram_f64(hipStream_t s, int64_t n, int64_t k, const double* W, 
   ws.used = mark_g;
   syev_trunc_f64(s, k, S, k, tol, std::min(max_rank, k), lam, V, k, rank_dev, flag_dev, ws);
   ws.used = mark_g;
-  const int64_t rr = rank_to_host(s, rank_dev);
+  const int64_t seq_rank = value_to_host_launch(s, rank_dev);
+  // L = W (F V_I Lam_I^-1/2), D = Lam_I: the products for a guessed width go
+  // ahead of the rank's round trip to the host
+  const int64_t kmax = std::min(max_rank, k);
+  const int64_t ks = (rank_hint > 0) ? std::min(kmax, rank_hint + 16) : kmax;
+  auto form_L = [&](int64_t w) {
+    gemm_f64(s, 'N', 'N', k, w, k, 1.0, F, k, V, k, 0.0, T, k, &ws);
+    ws.used = mark_g;
+    const dim3 sg(cdiv(k, 256), (unsigned)std::min<int64_t>(w, 1024));
+    hipLaunchKernelGGL(scale_cols_kernel, sg, dim3(256), 0, s, (int)k, (int)w, lam, rank_dev, T);
+    DME_HIP(hipGetLastError());
+    gemm_f64(s, 'N', 'N', n, w, k, 1.0, W, ldw, T, k, 0.0, L, ldl, &ws);
+    ws.used = mark_g;
+  };
+  form_L(ks);
+  const int64_t rr = value_to_host_wait(s, seq_rank);
   if (rr <= 0) {
     ws.used = mark;
     return 0;
   }
+  if (rr > ks) form_L(rr);  // the guess fell short
   if (ldd <= 0) ldd = rr;
-  // L = W (F V_I Lam_I^-1/2), D = Lam_I
-  gemm_f64(s, 'N', 'N', k, rr, k, 1.0, F, k, V, k, 0.0, T, k, &ws);
-  ws.used = mark_g;
-  hipLaunchKernelGGL(scale_cols_kernel, dim3(blocks(k * rr)), dim3(256), 0, s, (int)k, (int)rr, lam, T);
-  DME_HIP(hipGetLastError());
-  gemm_f64(s, 'N', 'N', n, rr, k, 1.0, W, ldw, T, k, 0.0, L, ldl, &ws);
-  ws.used = mark_g;
   hipLaunchKernelGGL(diag_out_kernel, dim3(blocks(rr * rr)), dim3(256), 0, s, lam, (int)rr, Dout, ldd);
   DME_HIP(hipGetLastError());
   ws.used = mark;

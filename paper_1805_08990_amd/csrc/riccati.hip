@@ -179,10 +179,10 @@ __global__ __launch_bounds__(256) void gain_solve_kernel(int m, int r, const dou
 
 void riccati_update_f64(hipStream_t s, int64_t r, int64_t m, double* D, int64_t ldd,
                         const double* WB, int64_t ldw, const double* R, int64_t ldr, double t,
-                        int* flag_dev, Arena& ws) {
+                        int* flag_dev, Arena& ws, double* Zout) {
   if (r <= 0 || m <= 0) return;
   DME_REQUIRE(m <= kMaxM, DME_EINVAL, "riccati: m > 64 inputs is not supported");
-  double* Y = ws.get<double>((size_t)r * m);
+  double* Y = Zout ? Zout : ws.get<double>((size_t)r * m);
   hipLaunchKernelGGL(riccati_kernel, dim3(1), dim3(kRT), 0, s, (int)r, (int)m, D, ldd, WB, ldw, R,
                      ldr, t, Y, flag_dev);
   DME_HIP(hipGetLastError());

@@ -122,6 +122,10 @@ struct Solver {
   int cur = 0;
   int64_t r = 0;
   bool d_diag = true;  // D is diagonal (a compression's output; T3 fills it)
+  // D = diag(lamT3) - t3 Z Z^T with Z in ZT3 (T3 applied to a diagonal D)
+  bool d_lowrank = false;
+  double t3 = 0.0;
+  DevBuf lamT3, ZT3;
   DevBuf W, Dhat, WB, SL;
   DevBuf flags;  // int flags[4]; int64 rank at offset 16
   Arena ws;
@@ -183,7 +187,9 @@ struct Solver {
   void apply_T12(double t, bool ext_product);
   void apply_T3(double t);
   void apply_T4(double t);
-  void compress_into(int64_t k);  // W (n x k), Dhat (k x k) -> new (L, D)
+  // W (n x k), Dhat (k x k) -> new (L, D); Dhat holds ncopies copies of D
+  // (from row 0), the rest of it is diagonal
+  void compress_into(int64_t k, int ncopies = 1);
   void apply_E(double t, const double* X, int64_t r, double* Y, int64_t ldy);
   void build_quadrature(double t);
   void apply_mass_matrix(const double* M);

@@ -274,6 +274,8 @@ void Solver::setup(const dme_problem& prob, const dme_opts& o, bool dre,
   W.ensure((size_t)n * kmax * sizeof(double));
   Dhat.ensure((size_t)kmax * kmax * sizeof(double));
   WB.ensure((size_t)max_rank * std::max<int64_t>(m, 1) * sizeof(double));
+  lamT3.ensure((size_t)max_rank * sizeof(double));
+  ZT3.ensure((size_t)max_rank * std::max<int64_t>(m, 1) * sizeof(double));
   if (has_S) SL.ensure((size_t)n * max_rank * sizeof(double));
   ws.reserve(workspace_bytes(n, m, max_rank, kmax, opts.precision) +
              leja_workspace(n, std::max<int64_t>(max_rank, (int64_t)opts.quad_nodes * p)));
@@ -281,6 +283,7 @@ void Solver::setup(const dme_problem& prob, const dme_opts& o, bool dre,
   cur = 0;
   r = prob.r0;
   d_diag = (r == 0);
+  d_lowrank = false;
   if (r > 0) {
     DME_HIP(hipMemcpyAsync(L[0].p, prob.L0, (size_t)n * r * sizeof(double), hipMemcpyHostToDevice, s));
     DME_HIP(hipMemcpyAsync(D[0].p, prob.D0, (size_t)r * r * sizeof(double), hipMemcpyHostToDevice, s));
@@ -398,6 +401,7 @@ size_t Solver::state_bytes(int64_t n, int64_t m, int64_t p, bool has_S, const dm
   add(2 * ((size_t)n * mr * 8 + (size_t)mr * mr * 8));          // L, D ping-pong
   add((size_t)n * km * 8 + (size_t)km * km * 8);                // W, Dhat
   add((size_t)mr * std::max<int64_t>(m, 1) * 8);                // W_B
+  add((size_t)mr * (std::max<int64_t>(m, 1) + 1) * 8);          // lam and Z of a T3 update
   add(2 * ((size_t)n * Kp * 8 + (size_t)Kp * Kp * 8));          // quadrature factors (h and h/2)
   add(workspace_bytes(n, m, mr, km, o.precision));
   add(leja_workspace(n, std::max<int64_t>(mr, Kp)));
@@ -534,13 +538,15 @@ void Solver::apply_E(double t, const double* X, int64_t rr, double* Y, int64_t l
   kernel_timer() = prev;
 }
 
-void Solver::compress_into(int64_t k) {
+void Solver::compress_into(int64_t k, int ncopies) {
   ws.reset();
   hipEvent_t ev = mark_phase();
   // through the Gram matrix while Dhat is positive definite (every DLE / DRE
   // compression from a positive semidefinite P0), by Householder QR otherwise
-  int64_t rn = compress_gram_f64(s, n, k, W.as<double>(), n, Dhat.as<double>(), k, d_diag, opts.tol,
-                                 max_rank, Ln(), n, Dn(), 0, rank_dev(), flag_dev(), ws);
+  LowRankD lr{lamT3.as<double>(), ZT3.as<double>(), t3, r, m, ncopies};
+  int64_t rn = compress_gram_f64(s, n, k, W.as<double>(), n, Dhat.as<double>(), k, d_diag,
+                                 d_lowrank ? &lr : nullptr, opts.tol, max_rank, Ln(), n, Dn(), 0, rank_dev(),
+                                 flag_dev(), ws, r);  // the rank before: the guess for the new one
   const double kk = (double)k;
   if (rn >= 0) {
     // W^T W 2 n k^2, L = W T 2 n k r', the k x k products and eigenproblem ~ 14 k^3
@@ -557,6 +563,7 @@ void Solver::compress_into(int64_t k) {
   cur ^= 1;
   r = rn;
   d_diag = true;
+  d_lowrank = false;
 }
 
 void Solver::apply_T1(double t) {
@@ -594,8 +601,15 @@ void Solver::apply_T3(double t) {
   ws.reset();
   gemm_f64(s, 'T', 'N', r, m, n, 1.0, Lc(), n, B.as<double>(), n, 0.0, WB.as<double>(), r, &ws);
   ws.reset();
-  riccati_update_f64(s, r, m, Dc(), r, WB.as<double>(), r, R.as<double>(), m, t, flag_dev(), ws);
+  // T3 on a diagonal D keeps D = diag(lam) - t Z Z^T in factored form for the
+  // next compression (its factor then needs no Cholesky)
+  const bool lowrank = d_diag && m <= 8;
+  if (lowrank) copy_f64(s, Dc(), r + 1, lamT3.as<double>(), 1, 1, r);  // the diagonal of D
+  riccati_update_f64(s, r, m, Dc(), r, WB.as<double>(), r, R.as<double>(), m, t, flag_dev(), ws,
+                     lowrank ? ZT3.as<double>() : nullptr);
   d_diag = false;
+  d_lowrank = lowrank;
+  t3 = t;
   mark_end(2, ev, 2.0 * n * r * m + 2.0 * r * r * m, 8.0 * ((double)n * r + (double)n * m));
 }
 
@@ -615,7 +629,7 @@ void Solver::apply_T4(double t) {
   double* Dh = Dhat.as<double>();
   fill_f64(s, Dh, k, k, k, 0.0);
   for (int q = 0; q < 3; ++q) copy_f64(s, Dc(), r, Dh + q * r * (k + 1), k, r, r);
-  compress_into(k);
+  compress_into(k, 3);
 }
 
 double Solver::err_estimate() {

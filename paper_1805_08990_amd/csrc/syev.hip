@@ -3,8 +3,8 @@
 // |lambda| > tol * max|lambda| are formed, ordered by |lambda| descending.
 //
 //   1. tridiagonalisation: Householder reduction to tridiagonal form in one
-//                         workgroup: tridiag_rows_kernel holds the matrix in
-//                         registers by rows (k <= 192), tridiag_small_kernel
+//                         workgroup: tridiag_tiles_kernel holds the matrix in
+//                         registers by tiles (k <= 192), tridiag_small_kernel
 //                         keeps the vectors in LDS (k <= 512), tridiag_kernel
 //                         works from global memory (larger k).
 //   2. bisect_kernel    : every eigenvalue by Sturm-count multisection, one
@@ -58,141 +58,235 @@ __device__ inline double block_sum_1024(double v, double* red) {
   return tot;
 }
 
-// Householder tridiagonalisation with the whole matrix in registers, by rows:
-// 4 adjacent lanes own row i (i = t / 4), lane q of them the columns
-// 32 c + 8 q + m (chunk c < NCH, m < 8), so a chunk spans a whole 32-column
-// stretch (a wave skips the chunks, and rows, that lie before the trailing
-// part) and a lane's columns of a chunk are contiguous in LDS.  Because A is
-// symmetric, column j is row j: its four owners publish it to LDS, and every
-// wave forms the reflector from it redundantly.  A step then takes three
-// barriers: v into LDS; p = tau A v (row sums over the 4 lanes by DPP) and the
-// per-wave parts of p^T v; the rank-2 update A -= v w^T + w v^T,
-// w = p - (tau/2)(p^T v) v, with row j + 1 published for the next step.  The
+// sum over aligned groups of G lanes (G = 4, 8 or 16), the same in every lane
+template <int G>
+__device__ inline double group_sum_f64(double v) {
+  static_assert(G == 4 || G == 8 || G == 16, "group size");
+  if constexpr (G == 16) return group16_sum_f64(v);
+  if constexpr (G == 8) return group8_sum_f64(v);
+  v += dpp_mov_f64<kDppXor1>(v);
+  return v + dpp_mov_f64<kDppXor2>(v);
+}
+
+// Reduce-scatter steps over a half-wave (32 lanes).  rs16: lanes 0-15 of the
+// half get a + a of the lane 16 away, lanes 16-31 get b + b of theirs (one
+// permlane swap per dword).  rs_dpp: lanes whose bit `hi` is clear get
+// a + a of the partner lane, the others b + b of theirs, the partner given by
+// the DPP pattern CTRL.
+__device__ __forceinline__ double rs16(double a, double b) {
+  const uint64_t ua = (uint64_t)__double_as_longlong(a), ub = (uint64_t)__double_as_longlong(b);
+  const auto lo = __builtin_amdgcn_permlane16_swap((uint32_t)ua, (uint32_t)ub, false, false);
+  const auto hi = __builtin_amdgcn_permlane16_swap((uint32_t)(ua >> 32), (uint32_t)(ub >> 32), false, false);
+  const double x = __longlong_as_double((long long)(((uint64_t)hi[0] << 32) | lo[0]));
+  const double y = __longlong_as_double((long long)(((uint64_t)hi[1] << 32) | lo[1]));
+  return x + y;
+}
+template <int CTRL>
+__device__ __forceinline__ double rs_dpp(double a, double b, bool hi) {
+  const double send = hi ? a : b;  // what the partner keeps
+  return (hi ? b : a) + dpp_mov_f64<CTRL>(send);
+}
+// Row sums of an RT-row tile (RT <= 8) over the 32 lanes of a half-wave: on
+// return lane c holds the sum of row c >> 2 (zero for c >> 2 >= RT).
+template <int RT>
+__device__ __forceinline__ double tile_row_sums(const double (&sp)[RT], int c) {
+  static_assert(RT <= 8, "rows per tile");
+  double x[8];
+#pragma unroll
+  for (int u = 0; u < 8; ++u) x[u] = (u < RT) ? sp[u] : 0.0;
+  double y[4], z[2];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) y[t] = rs16(x[t], x[t + 4]);          // bit 4 picks t or t + 4
+  const bool b3 = (c >> 3) & 1, b2 = (c >> 2) & 1;
+#pragma unroll
+  for (int t = 0; t < 2; ++t) z[t] = rs_dpp<kDppRor8>(y[t], y[t + 2], b3);  // bit 3: + 2
+  double w = rs_dpp<kDppHalfMirror>(z[0], z[1], b2);                    // bit 2: + 1
+  w += dpp_mov_f64<kDppXor1>(w);
+  return w + dpp_mov_f64<kDppXor2>(w);
+}
+// sp[u] = sum over m >= M0 of a[u][m] x[m], for the first live chunk m0
+// (uniform) taken as a compile-time start by dispatch, so that the skipped
+// chunks cost no instructions.
+template <int NC, int RT, int M0 = 0>
+__device__ __forceinline__ void tile_matvec(int m0, const double (&a)[RT][NC], const double (&x)[NC],
+                                            double (&sp)[RT]) {
+  if constexpr (M0 + 1 < NC) {
+    if (m0 > M0) {
+      tile_matvec<NC, RT, M0 + 1>(m0, a, x, sp);
+      return;
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < RT; ++u) {
+    double acc = 0.0;
+#pragma unroll
+    for (int m = M0; m < NC; ++m) acc += a[u][m] * x[m];
+    sp[u] = acc;
+  }
+}
+// The rank-2 update of a tile, a[u][m] -= v_u w_m + w_u v_m, with the row
+// values v_u (from vr) and w_u = p_u - K v_u (p_u from pr) read from LDS a pair
+// of rows at a time, so that only the column values stay in registers.  The
+// chunks before the trailing part change by zero (v and w vanish there); they
+// are updated anyway: skipping them by a branch or a dispatch costs more in
+// selects or registers than the fused multiply-adds it saves.
+template <int NC, int RT>
+__device__ __forceinline__ void tile_rank2(double (&a)[RT][NC], const double* vr, const double* pr, double K,
+                                           const double (&vC)[NC], const double (&wC)[NC]) {
+  static_assert(RT % 2 == 0, "row pairs");
+#pragma unroll
+  for (int u = 0; u < RT; u += 2) {
+    const double2 v2 = *reinterpret_cast<const double2*>(vr + u);
+    const double2 p2 = *reinterpret_cast<const double2*>(pr + u);
+    const double w0 = p2.x - K * v2.x, w1 = p2.y - K * v2.y;
+#pragma unroll
+    for (int m = 0; m < NC; ++m) {  // two fused steps in place: no temporaries
+      a[u][m] = fma(-v2.x, wC[m], fma(-w0, vC[m], a[u][m]));
+      a[u + 1][m] = fma(-v2.y, wC[m], fma(-w1, vC[m], a[u + 1][m]));
+    }
+  }
+}
+
+// Householder tridiagonalisation with the whole matrix in registers, in
+// RT x NC tiles: the 32 lanes of a half-wave share the rows RT h .. RT h + RT - 1
+// (h = 2 wave + half) and lane c of them holds the columns c + 32 m (m < NC),
+// so a half-wave holds whole rows.  Because A is symmetric, row q is column q:
+// the half-wave holding row q forms the reflector of step q from it (norms by
+// half-wave sums) and puts v and tau in LDS.  A step then takes two barriers:
+// after the row sums p = tau A v (a reduce-scatter over the 32 lanes, after
+// which lane c holds the sum of row c / 4) and the per-wave parts of p^T v
+// reach LDS, and after the rank-2 update A -= v w^T + w v^T,
+// w = p - (tau/2)(p^T v) v, has brought the next reflector.  Between the
+// barriers every wave runs the same phase, so a step costs the VALU work of
+// the waves that share a SIMD (about 2.3 us at k = 180 on 16 waves).  The
 // reflector of step j goes to A(j+2:, j) and d, e, tau as in tridiag_kernel.
-template <int NCH>
-__global__ __launch_bounds__(128 * NCH) void tridiag_rows_kernel(double* A, int64_t lda, int k,
-                                                                 double* d, double* e, double* tau) {
-  constexpr int KM = 32 * NCH;  // largest k
-  constexpr int NT = 4 * KM;
-  constexpr int NW = NT / 64;
-  __shared__ double xrow[2][KM];  // row j of step j in xrow[j & 1]
-  __shared__ double vb[KM];
+template <int NC, int RT>
+__global__ __launch_bounds__(32 * 32 * NC / RT) void tridiag_tiles_kernel(double* A, int64_t lda, int k,
+                                                                          double* d, double* e, double* tau) {
+  constexpr int KM = 32 * NC;        // largest k
+  constexpr int NW = KM / (2 * RT);  // waves: two RT-row tiles each
+  static_assert(KM % (2 * RT) == 0 && NW <= 16, "whole waves, at most 16");
+  __shared__ double vbuf[2][KM];  // reflector of step j in vbuf[j & 1]
+  __shared__ double tjs[2];       // and its tau
   __shared__ double pb[KM];
   __shared__ double wpart[NW];
   const int t = threadIdx.x;
-  const int i = t >> 2, q = t & 3;
   const int lane = t & 63, wv = t >> 6;
-  const int wrow_last = wv * 16 + 15;  // last row of this wave
-  double a[NCH][8];
+  const int c = lane & 31;
+  const int rbase = RT * (2 * wv + (lane >> 5));
+  const int wrow_last = 2 * RT * wv + 2 * RT - 1;  // last row of this wave
+  double a[RT][NC];
+  // entry (rbase + u, c + 32 m), read as A(c + 32 m, rbase + u) by symmetry so
+  // that the lanes of a half-wave read consecutive addresses
 #pragma unroll
-  for (int c = 0; c < NCH; ++c)
+  for (int u = 0; u < RT; ++u) {
+    const int i = rbase + u;
+    const double* Ai = A + (int64_t)i * lda + c;
 #pragma unroll
-    for (int m = 0; m < 8; ++m) {
-      const int l = 32 * c + 8 * q + m;
-      const double v = A[min(i, k - 1) + (int64_t)min(l, k - 1) * lda];  // unconditional load
-      a[c][m] = (i < k && l < k) ? v : 0.0;
-    }
-  if (i == 0) {
-#pragma unroll
-    for (int c = 0; c < NCH; ++c)
-#pragma unroll
-      for (int m = 0; m < 8; ++m) xrow[0][32 * c + 8 * q + m] = a[c][m];
+    for (int m = 0; m < NC; ++m) a[u][m] = (i < k && c + 32 * m < k) ? Ai[32 * m] : 0.0;
   }
+  // Row q (held by this half-wave) as it stands: d[q], and the reflector of
+  // step q (q + 2 < k) or the last 2 x 2 block (q = k - 2).
+  auto publish = [&](int q) {
+    const int uu = q - rbase;
+    double xr[NC];
+#pragma unroll
+    for (int m = 0; m < NC; ++m) xr[m] = 0.0;
+#pragma unroll
+    for (int u = 0; u < RT; ++u)
+      if (u == uu) {
+#pragma unroll
+        for (int m = 0; m < NC; ++m) xr[m] = a[u][m];
+      }
+    double s2 = 0.0, al = 0.0;
+#pragma unroll
+    for (int m = 0; m < NC; ++m) {
+      const int l = c + 32 * m;
+      if (l >= q + 2 && l < k) s2 += xr[m] * xr[m];
+      if (l == q + 1) al = xr[m];
+      if (l == q) d[q] = xr[m];
+    }
+    const double alpha = half_wave_sum_f64(al);  // one nonzero term: exact
+    if (q + 2 < k) {
+      s2 = half_wave_sum_f64(s2);
+      double beta = alpha, tj = 0.0, sc = 0.0;
+      if (s2 != 0.0) {
+        beta = -copysign(sqrt(alpha * alpha + s2), alpha);
+        tj = (beta - alpha) / beta;
+        sc = 1.0 / (alpha - beta);
+      }
+      if (c == 0) {
+        e[q] = beta;
+        tau[q] = tj;
+        tjs[q & 1] = tj;
+      }
+#pragma unroll
+      for (int m = 0; m < NC; ++m) {
+        const int l = c + 32 * m;
+        const bool below = l > q + 1 && l < k;
+        const double v = (l == q + 1) ? 1.0 : (below ? sc * xr[m] : 0.0);
+        vbuf[q & 1][l] = v;
+        if (below && tj != 0.0) A[l + (int64_t)q * lda] = v;
+      }
+    } else if (c == 0) {
+      e[q] = alpha;
+      tau[q] = 0.0;
+    }
+  };
+  if (rbase == 0) publish(0);
   __syncthreads();
   for (int j = 0; j + 2 < k; ++j) {
     const int r0 = j + 1;
-    const double* x = xrow[j & 1];
-    // reflector from row j (= column j), formed by every wave
-    double s2 = 0.0;
-#pragma unroll
-    for (int mm = 0; mm < KM / 64 + 1; ++mm) {
-      const int l = lane + 64 * mm;
-      if (l < KM && l >= j + 2 && l < k) s2 += x[l] * x[l];
-    }
-    s2 = wave_sum_f64(s2);
-    const double alpha = x[r0];
-    double beta = alpha, tj = 0.0, sc = 0.0;
-    if (s2 != 0.0) {
-      beta = -copysign(sqrt(alpha * alpha + s2), alpha);
-      tj = (beta - alpha) / beta;
-      sc = 1.0 / (alpha - beta);
-    }
-    if (t == 0) {
-      d[j] = x[j];
-      e[j] = beta;
-      tau[j] = tj;
-    }
+    const double tj = tjs[j & 1];
     if (tj != 0.0) {  // uniform across the workgroup
-      if (q == 0 && i < KM) {
-        const double vi = (i == r0) ? 1.0 : ((i > r0 && i < k) ? sc * x[i] : 0.0);
-        vb[i] = vi;
-        if (i > r0 && i < k) A[i + (int64_t)j * lda] = vi;
-      }
-      __syncthreads();
+      const double* v = vbuf[j & 1];
+      const int m0 = r0 >> 5;  // chunks m < m0 lie before the trailing part (v zero there)
+      double vC[NC];
+#pragma unroll
+      for (int m = 0; m < NC; ++m) vC[m] = v[c + 32 * m];
       const bool live = wrow_last >= r0;  // wave-uniform
-      double pi = 0.0;
+      const int srow = c >> 2;            // the row whose sum this lane gets
+      double pu = 0.0;                    // p of row rbase + srow (zero before the trailing part)
       if (live) {
-        double sp[4] = {0.0, 0.0, 0.0, 0.0};  // independent chains
-#pragma unroll
-        for (int c = 0; c < NCH; ++c) {
-          if (32 * c + 31 < r0) continue;  // uniform: v is zero there
-#pragma unroll
-          for (int m = 0; m < 8; ++m) sp[m & 3] += a[c][m] * vb[32 * c + 8 * q + m];
-        }
-        double s = (sp[0] + sp[1]) + (sp[2] + sp[3]);
-        s += dpp_mov_f64<kDppXor1>(s);
-        s += dpp_mov_f64<kDppXor2>(s);
-        pi = (i >= r0 && i < k) ? tj * s : 0.0;
+        double sp[RT];
+        tile_matvec<NC, RT>(m0, a, vC, sp);
+        const double sum = tile_row_sums<RT>(sp, c);
+        const int i = rbase + srow;
+        pu = (srow < RT && i >= r0 && i < k) ? tj * sum : 0.0;
       }
-      if (q == 0) pb[i] = pi;  // zero on rows before the trailing part
-      double pv = (q == 0 && live) ? pi * vb[i] : 0.0;
-      pv = wave_sum_f64(pv);
+      if ((c & 3) == 0 && srow < RT) pb[rbase + srow] = pu;
+      const double vs = (srow < RT) ? v[rbase + min(srow, RT - 1)] : 0.0;
+      const double pv = wave_sum_f64((c & 3) == 0 ? pu * vs : 0.0);  // both half-waves
       if (lane == 0) wpart[wv] = pv;
       __syncthreads();
-      double pvt = 0.0;
-#pragma unroll
-      for (int w = 0; w < NW; ++w) pvt += wpart[w];
+      constexpr int G = NW <= 4 ? 4 : (NW <= 8 ? 8 : 16);  // NW <= 16
+      const int gi = lane & (G - 1);
+      const double pvt = group_sum_f64<G>(gi < NW ? wpart[gi] : 0.0);
       const double Kc = 0.5 * tj * pvt;
       if (live) {
-        const double vi = vb[i];
-        const double wi = pb[i] - Kc * vi;
+        double vC2[NC], wC[NC];
 #pragma unroll
-        for (int c = 0; c < NCH; ++c) {
-          if (32 * c + 31 < r0) continue;
-#pragma unroll
-          for (int m = 0; m < 8; ++m) {
-            const int l = 32 * c + 8 * q + m;
-            const double vl = vb[l];
-            const double wl = pb[l] - Kc * vl;
-            a[c][m] -= vi * wl + wi * vl;
-          }
+        for (int m = 0; m < NC; ++m) {
+          vC2[m] = v[c + 32 * m];  // read again rather than held across the barrier
+          wC[m] = pb[c + 32 * m] - Kc * vC2[m];
         }
+        tile_rank2<NC, RT>(a, v + rbase, pb + rbase, Kc, vC2, wC);
       }
     }
-    // publish row j + 1 (updated, or unchanged when the reflector is trivial)
-    if (i == j + 1) {
-#pragma unroll
-      for (int c = 0; c < NCH; ++c)
-#pragma unroll
-        for (int m = 0; m < 8; ++m) xrow[(j + 1) & 1][32 * c + 8 * q + m] = a[c][m];
-    }
+    if (r0 >= rbase && r0 < rbase + RT) publish(r0);
     __syncthreads();
   }
-  // the last 2 x 2 block: row k - 2 is published; row k - 1 goes to vb
-  if (i == k - 1) {
+  // the last diagonal entry
+  if (k - 1 >= rbase && k - 1 < rbase + RT) {
+    const int uu = k - 1 - rbase;
 #pragma unroll
-    for (int c = 0; c < NCH; ++c)
+    for (int u = 0; u < RT; ++u)
+      if (u == uu) {
 #pragma unroll
-      for (int m = 0; m < 8; ++m) vb[32 * c + 8 * q + m] = a[c][m];
-  }
-  __syncthreads();
-  if (t == 0) {
-    const double* x = xrow[(k - 2) & 1];
-    d[k - 2] = x[k - 2];
-    e[k - 2] = x[k - 1];
-    tau[k - 2] = 0.0;
-    d[k - 1] = vb[k - 1];
-    tau[k - 1] = 0.0;
+        for (int m = 0; m < NC; ++m)
+          if (c + 32 * m == k - 1) d[k - 1] = a[u][m];
+      }
+    if (c == 0) tau[k - 1] = 0.0;
   }
 }
 
@@ -1268,12 +1362,14 @@ void syev_trunc_f64(hipStream_t s, int64_t k, const double* M, int64_t ldm, doub
     fill_f64(s, e, 1, 1, 1, 0.0);
     fill_f64(s, tau, 1, 1, 1, 0.0);
   } else {
-    if (k <= 128) {
-      hipLaunchKernelGGL((tridiag_rows_kernel<4>), dim3(1), dim3(512), 0, s, A, k, ki, d, e, tau);
+    if (k <= 64) {
+      hipLaunchKernelGGL((tridiag_tiles_kernel<2, 8>), dim3(1), dim3(256), 0, s, A, k, ki, d, e, tau);
+    } else if (k <= 128) {
+      hipLaunchKernelGGL((tridiag_tiles_kernel<4, 8>), dim3(1), dim3(512), 0, s, A, k, ki, d, e, tau);
     } else if (k <= 160) {
-      hipLaunchKernelGGL((tridiag_rows_kernel<5>), dim3(1), dim3(640), 0, s, A, k, ki, d, e, tau);
+      hipLaunchKernelGGL((tridiag_tiles_kernel<5, 8>), dim3(1), dim3(640), 0, s, A, k, ki, d, e, tau);
     } else if (k <= 192) {
-      hipLaunchKernelGGL((tridiag_rows_kernel<6>), dim3(1), dim3(768), 0, s, A, k, ki, d, e, tau);
+      hipLaunchKernelGGL((tridiag_tiles_kernel<6, 6>), dim3(1), dim3(1024), 0, s, A, k, ki, d, e, tau);
     } else if (k <= kTriMaxK) {
       const size_t lds = (size_t)(3 + kTriT / 64) * k * sizeof(double);
       hipLaunchKernelGGL(tridiag_small_kernel, dim3(1), dim3(kTriT), lds, s, A, k, ki, d, e, tau);

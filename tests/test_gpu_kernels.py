@@ -13,6 +13,8 @@ pytestmark = pytest.mark.gpu
     (64, 64, 64, "N", "N"), (200, 150, 130, "N", "N"), (129, 65, 300, "T", "N"),
     (33, 257, 17, "N", "T"), (70, 90, 1000, "T", "T"), (1, 1, 1, "N", "N"),
     (32, 40, 5000, "T", "N"), (1000, 7, 1000, "N", "N"), (256, 256, 0, "N", "N"),
+    # the small-product path at its limits (M, N <= 256, K <= 2048), ragged
+    (256, 256, 2048, "T", "T"), (250, 17, 2047, "N", "T"), (178, 178, 178, "T", "N"),
     # tall-square times narrow: the skinny split-K path (ragged rows, K and N)
     (2048, 150, 2048, "N", "N"), (1500, 7, 1100, "N", "N"), (4097, 256, 3000, "N", "N"),
     (1024, 33, 1024, "N", "N"),
@@ -118,6 +120,23 @@ def test_syev(ctx, case):
     drop = np.sqrt(np.sum(ref[kk:] ** 2))
     assert np.linalg.norm(Mk - M) <= 1e-12 * np.linalg.norm(M) + 1.01 * drop
     assert np.max(np.abs(V.T @ V - np.eye(kk))) < 1e-10
+
+
+@pytest.mark.parametrize("k", [3, 33, 64, 65, 96, 128, 129, 160, 161, 191, 192, 193])
+def test_syev_tile_sizes(ctx, k):
+    """Sizes at the edges of the register-tiled reductions (k <= 64, 128, 160, 192)."""
+    announce("syev size", k)
+    rng = np.random.default_rng(100 + k)
+    X = rng.standard_normal((k, k))
+    M = 0.5 * (X + X.T)
+    lam, V, kk = ctx.syev(M, tol=1e-14)
+    lam, V = to_np(lam), to_np(V)
+    ref = np.linalg.eigvalsh(M)
+    assert kk == k
+    bound = 1e-13 * np.abs(ref).max() * np.sqrt(k)
+    assert np.max(np.abs(np.sort(lam) - np.sort(ref))) < bound
+    assert np.linalg.norm((V * lam) @ V.T - M) <= 1e-12 * np.linalg.norm(M) * np.sqrt(k)
+    assert np.max(np.abs(V.T @ V - np.eye(k))) < 1e-10
 
 
 def _compress_case(name):
