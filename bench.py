@@ -72,6 +72,10 @@ def parse():
     ap.add_argument("--serve-sweep", type=int, default=0, metavar="COUNT",
                     help="instead of the steps/s line: serve COUNT requests at 0.5, 0.7 and 0.9 x "
                          "the measured capacity and the same stream one request at a time (FIFO)")
+    ap.add_argument("--sweep-parts", default="0.5,0.7,0.9,fifo",
+                    help="which parts of the serving sweep run (comma list of 0.5, 0.7, 0.9, fifo)")
+    ap.add_argument("--serve-capacity", type=float, default=None,
+                    help="capacity (requests/s) the sweep's rates are fractions of, instead of a burst")
     return ap.parse_args()
 
 
@@ -292,8 +296,9 @@ def _serving_setup(ctx, max_slots):
     return srv, ops, time.perf_counter() - t0
 
 
-def _serve_stream(srv, ops, stream):
-    """Submit the stream at its arrival times, wait for every result."""
+def _serve_stream(srv, ops, stream, label=None):
+    """Submit the stream at its arrival times, wait for every result (with a
+    progress line every 64 results when `label` is given)."""
     import numpy as np
     import workloads as wl
     from paper_1805_08990_amd import _binding as b
@@ -306,24 +311,28 @@ def _serve_stream(srv, ops, stream):
 
     t0 = time.perf_counter()
     tickets, res = {}, {}
+    reported = [0]
+
+    def collect():
+        for i, tk in list(tickets.items()):
+            if i not in res:
+                got = srv.poll(tk)
+                if got is not None:
+                    res[i] = got
+        if label and len(res) >= reported[0] + 64:
+            reported[0] = len(res) // 64 * 64
+            log(f"{label}: {len(res)} of {len(stream)} done at {time.perf_counter() - t0:.0f} s")
+
     for r in stream:
         while True:  # collect finished requests while waiting for the next arrival
             wait = r.arrival_s - (time.perf_counter() - t0)
-            for i, tk in list(tickets.items()):
-                if i not in res:
-                    got = srv.poll(tk)
-                    if got is not None:
-                        res[i] = got
+            collect()
             if wait <= 0:
                 break
             time.sleep(min(wait, 0.002))
         tickets[r.index] = submit(r)
     while len(res) < len(tickets):
-        for i, tk in tickets.items():
-            if i not in res:
-                got = srv.poll(tk)
-                if got is not None:
-                    res[i] = got
+        collect()
         time.sleep(0.001)
     span = time.perf_counter() - t0
     lat = np.array([res[r.index][3]["latency_s"] for r in stream])
@@ -369,34 +378,45 @@ def serve_mix(ctx, count, seed=7):
     return out
 
 
-def serve_sweep(ctx, count, seed=7):
-    """The served mix at its full size: warm capacity from a burst, then
-    `count` Poisson arrivals at 0.5, 0.7 and 0.9 x capacity with continuous
-    batching (16 slots), and the 0.7 stream served one request at a time in
-    arrival order (one slot: FIFO, no batching) as the baseline."""
+def serve_sweep(ctx, count, parts=("0.5", "0.7", "0.9", "fifo"), capacity=None, seed=7):
+    """The served mix at its full size: capacity from a burst of 64 (or as
+    given), then `count` Poisson arrivals at 0.5, 0.7 and 0.9 x capacity with
+    continuous batching (16 slots), and the 0.7 stream served one request at
+    a time in arrival order (one slot: FIFO, no batching) as the baseline.
+    `parts` picks which of these run (each takes minutes at count = 512)."""
     import workloads as wl
     srv, ops, warm_s = _serving_setup(ctx, 16)
-    cap = _capacity(srv, ops, 64, seed)
-    log(f"serving sweep: capacity {cap:.2f} requests/s (burst of 64)")
-    out = {"requests": count, "capacity_req_per_s": round(cap, 3), "warm_operators_s": round(warm_s, 1),
-           "batched": {}, "max_slots": 16, "hbm_budget_gib": 160}
-    for frac in (0.5, 0.7, 0.9):
-        stream = wl.request_stream(count, rate_per_s=frac * cap, base_seed=1000, stream_seed=seed)
-        res = _serve_stream(srv, ops, stream)
-        res["arrival_rate_per_s"] = round(frac * cap, 3)
-        out["batched"][str(frac)] = res
+    if capacity is None:
+        cap = _capacity(srv, ops, 64, seed)
+        log(f"serving sweep: capacity {cap:.2f} requests/s (burst of 64)")
+    else:
+        cap = float(capacity)
+        log(f"serving sweep: capacity {cap:.2f} requests/s (given)")
+    out = {"requests": count, "capacity_req_per_s": round(cap, 3), "capacity_given": capacity is not None,
+           "warm_operators_s": round(warm_s, 1), "batched": {}, "max_slots": 16, "hbm_budget_gib": 160}
+    for frac in ("0.5", "0.7", "0.9"):
+        if frac not in parts:
+            continue
+        rate = float(frac) * cap
+        stream = wl.request_stream(count, rate_per_s=rate, base_seed=1000, stream_seed=seed)
+        res = _serve_stream(srv, ops, stream, label=f"serving sweep {frac} x capacity")
+        res["arrival_rate_per_s"] = round(rate, 3)
+        out["batched"][frac] = res
         log(f"serving sweep: {frac} x capacity: p50 {res['p50_s']:.3f} s p99 {res['p99_s']:.3f} s "
             f"{res['req_per_s']:.2f} req/s")
     st = srv.stats()
     out["failed"] = st["failed"]
+    out["peak_ledger_gib"] = round(st["peak_bytes"] / GIB, 2)
     srv.stop()
-    fifo, fops, _ = _serving_setup(ctx, 1)
-    stream = wl.request_stream(count, rate_per_s=0.7 * cap, base_seed=1000, stream_seed=seed)
-    res = _serve_stream(fifo, fops, stream)
-    res["arrival_rate_per_s"] = round(0.7 * cap, 3)
-    fifo.stop()
-    out["fifo_0.7"] = res
-    log(f"serving sweep: FIFO at 0.7 x capacity: p50 {res['p50_s']:.3f} s p99 {res['p99_s']:.3f} s")
+    if "fifo" in parts:
+        fifo, fops, _ = _serving_setup(ctx, 1)
+        stream = wl.request_stream(count, rate_per_s=0.7 * cap, base_seed=1000, stream_seed=seed)
+        res = _serve_stream(fifo, fops, stream, label="serving sweep FIFO")
+        res["arrival_rate_per_s"] = round(0.7 * cap, 3)
+        out["failed"] += fifo.stats()["failed"]
+        fifo.stop()
+        out["fifo_0.7"] = res
+        log(f"serving sweep: FIFO at 0.7 x capacity: p50 {res['p50_s']:.3f} s p99 {res['p99_s']:.3f} s")
     return out
 
 
@@ -435,7 +455,9 @@ def main():
                                            "precision": args.product_precision}}), flush=True)
         return
     if args.serve_sweep > 0:
-        print(json.dumps({"serving_sweep": serve_sweep(ctx, args.serve_sweep)}), flush=True)
+        parts = tuple(x.strip() for x in args.sweep_parts.split(","))
+        print(json.dumps({"serving_sweep": serve_sweep(ctx, args.serve_sweep, parts, args.serve_capacity)}),
+              flush=True)
         ctx.close()
         return
     prob = workload(args.nx)

@@ -24,14 +24,16 @@
 //          columns, zero padded.
 //   partial FP64, [split][col][row].
 //
-// Work decomposition: a 512-thread workgroup (8 wave64s, 4 row groups x 2
-// column halves) owns 128 rows of Y and every column (TN 16-column tiles).
+// Work decomposition: a 256-thread workgroup (4 wave64s, 32 rows each) owns
+// 128 rows of Y and every column (TN 16-column tiles).  The FP64 accumulators
+// of a wave's 32 x 16 TN tile keep it at one wave per SIMD; splitting the
+// columns over two waves per SIMD doubles the E loads and splits and measured
+// slower.
 // The K range is split into nsplit chunks; workgroup b takes chunk b % nsplit,
 // so every chunk is handled by the same one or two XCDs and the chunk's slice
 // of Xs (lde/nsplit x rpad x 3 pieces) stays in their L2.  The Xs tile of a K
-// step is staged once in LDS (double-buffered) and read by all 8 waves; E
-// fragments go straight from HBM to registers (the two waves of a row group
-// read the same rows, the second from cache) and are split into pieces in
+// step is staged once in LDS (double-buffered) and read by all 4 waves; E
+// fragments go straight from HBM to registers and are split into pieces in
 // registers.
 #include "solver.h"
 
@@ -264,22 +266,30 @@ __global__ __launch_bounds__(kMT) void gemm_mixed_kernel(int n, int lde, int rpa
         for (int pc = 0; pc < 3; ++pc) ef[t][pc].q = u32x4{w[pc][0], w[pc][1], w[pc][2], w[pc][3]};
       }
       load_e(s + kMPD, ering[slot]);
+      // column tiles in pairs: four independent accumulation chains between
+      // dependent MFMAs (each accumulator still takes its six products in
+      // the order below: smallest first)
 #pragma unroll
-      for (int j = 0; j < TN; ++j) {
-        Frag xf[3];
+      for (int j = 0; j < TN; j += 2) {
+        constexpr int pe[6] = {2, 1, 0, 1, 0, 0}, px[6] = {0, 1, 2, 0, 1, 0};  // pieces of E and X
+        const int nj = (j + 1 < TN) ? 2 : 1;
+        Frag xf[2][3];
 #pragma unroll
-        for (int pc = 0; pc < 3; ++pc) xf[pc].q = sX[buf][pc][j * 16 + row_l][kg];
+        for (int jj = 0; jj < 2; ++jj)
+          if (jj < nj) {
 #pragma unroll
-        for (int t = 0; t < 2; ++t) {
-          f32x4 a = fa[t][j];
-          a = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ef[t][2].v, xf[0].v, a, 0, 0, 0);
-          a = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ef[t][1].v, xf[1].v, a, 0, 0, 0);
-          a = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ef[t][0].v, xf[2].v, a, 0, 0, 0);
-          a = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ef[t][1].v, xf[0].v, a, 0, 0, 0);
-          a = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ef[t][0].v, xf[1].v, a, 0, 0, 0);
-          a = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ef[t][0].v, xf[0].v, a, 0, 0, 0);
-          fa[t][j] = a;
-        }
+            for (int pc = 0; pc < 3; ++pc) xf[jj][pc].q = sX[buf][pc][(j + jj) * 16 + row_l][kg];
+          }
+#pragma unroll
+        for (int p = 0; p < 6; ++p)
+#pragma unroll
+          for (int jj = 0; jj < 2; ++jj)
+            if (jj < nj) {
+#pragma unroll
+              for (int t = 0; t < 2; ++t)
+                fa[t][j + jj] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ef[t][pe[p]].v, xf[jj][px[p]].v,
+                                                                        fa[t][j + jj], 0, 0, 0);
+            }
       }
       if (u == kMFl - 1) {
 #pragma unroll
