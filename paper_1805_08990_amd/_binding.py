@@ -309,7 +309,9 @@ class Context:
         return from_cm(Es), int(m.value), int(s.value)
 
     def gemm(self, A, B, alpha=1.0, beta=0.0, C=None, transa="N", transb="N"):
-        As, Bs = to_device_cm(A), to_device_cm(B)
+        # the same array twice is passed as one buffer (A^T A takes the library's Gram path)
+        As = to_device_cm(A)
+        Bs = As if B is A else to_device_cm(B)
         ra, ca = As.shape[1], As.shape[0]
         rb, cb = Bs.shape[1], Bs.shape[0]
         M, K = (ca, ra) if transa == "T" else (ra, ca)

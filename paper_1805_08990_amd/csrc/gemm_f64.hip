@@ -231,6 +231,107 @@ __global__ __launch_bounds__(256) void gemm_f64_small_kernel(int M, int N, int K
   }
 }
 
+// Gram products C = alpha W^T W + beta C of a tall W (n x k, k <= 192, n >=
+// kSyMinK): the compression's W^T W.  A workgroup stages 64-row blocks of W in
+// LDS (each row block read from HBM once) and accumulates the upper 16 x 16
+// tiles of W_b^T W_b on FP64 MFMA, a wave taking every fourth tile pair, so
+// that a tile's accumulator is updated once per 4-deep step with the other
+// pairs' MFMAs between (no dependent issue).  Workgroup b adds row blocks
+// b, b + grid, ... and writes its upper tiles to partial[b]; a second kernel
+// sums the partials in workgroup order and writes both triangles from the
+// upper one (C is exactly symmetric).
+constexpr int kSyMaxT = 12;     // k <= 192
+constexpr int kSyRows = 64;     // rows of W per LDS stage
+constexpr int kSyMinK = 2048;   // rows of W from which this path is taken
+constexpr int kSyMaxGrid = 256;
+
+template <int T>
+__global__ __launch_bounds__(256) void syrk_tn_kernel(int n, int k, const double* __restrict__ W, int64_t ldw,
+                                                      double* __restrict__ partial) {
+  constexpr int NP = T * (T + 1) / 2;  // upper tile pairs
+  constexpr int PW = (NP + 3) / 4;     // pairs per wave
+  constexpr int LD = 16 * T + 1;       // LDS row stride (doubles)
+  extern __shared__ double sW[];       // kSyRows x LD
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int r16 = lane & 15, kq = lane >> 4;
+  int ta[PW], tb[PW];
+#pragma unroll
+  for (int q = 0; q < PW; ++q) {
+    int p = wave + 4 * q, b = 0;
+    while (p >= b + 1) {  // pair p = b (b + 1) / 2 + a, a <= b
+      p -= b + 1;
+      ++b;
+    }
+    ta[q] = p;
+    tb[q] = b;
+  }
+  v4d acc[PW];
+#pragma unroll
+  for (int q = 0; q < PW; ++q) acc[q] = v4d{0.0, 0.0, 0.0, 0.0};
+  for (int blk = blockIdx.x; (int64_t)blk * kSyRows < n; blk += gridDim.x) {
+    const int64_t r0 = (int64_t)blk * kSyRows;
+    __syncthreads();  // the previous stage is consumed
+    for (int idx = tid; idx < kSyRows * 16 * T; idx += 256) {
+      const int row = idx % kSyRows, col = idx / kSyRows;
+      sW[row * LD + col] = (r0 + row < n && col < k) ? W[r0 + row + (int64_t)col * ldw] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll 4
+    for (int kk = 0; kk < kSyRows / 4; ++kk) {
+      const double* rowp = sW + (4 * kk + kq) * LD + r16;
+#pragma unroll
+      for (int q = 0; q < PW; ++q)
+        if (wave + 4 * q < NP)
+          acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(rowp[16 * tb[q]], rowp[16 * ta[q]], acc[q], 0, 0, 0);
+    }
+  }
+  // lane holds C(m = 16 ta + r16, n = 16 tb + 4 v + kq) of each of its tiles
+  double* out = partial + (int64_t)blockIdx.x * k * k;
+#pragma unroll
+  for (int q = 0; q < PW; ++q)
+    if (wave + 4 * q < NP) {
+      const int m = 16 * ta[q] + r16;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int nn = 16 * tb[q] + 4 * v + kq;
+        if (m < k && nn < k) out[m + (int64_t)nn * k] = acc[q][v];
+      }
+    }
+}
+
+// C(m, n) = C(n, m) = alpha sum_b partial[b](min, max) (+ beta C), summed in b order.
+__global__ void syrk_reduce_kernel(int k, int nb, double alpha, const double* __restrict__ partial, double beta,
+                                   double* __restrict__ C, int64_t ldc) {
+  const int64_t kk = (int64_t)k * k;
+  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < kk;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    const int i = (int)(idx % k), j = (int)(idx / k);
+    if (i > j) continue;
+    double s = 0.0;
+    for (int b = 0; b < nb; ++b) s += partial[b * kk + idx];
+    const double out = alpha * s;
+    double* c1 = C + i + (int64_t)j * ldc;
+    double* c2 = C + j + (int64_t)i * ldc;
+    if (beta == 0.0) {
+      *c1 = out;
+      *c2 = out;
+    } else {
+      const double v1 = out + beta * (*c1);
+      const double v2 = (i == j) ? v1 : out + beta * (*c2);
+      *c1 = v1;
+      *c2 = v2;
+    }
+  }
+}
+
+int syrk_grid(int64_t n) { return (int)std::min<int64_t>(cdiv(n, kSyRows), kSyMaxGrid); }
+
+bool use_syrk(char ta, char tb, int64_t M, int64_t N, int64_t K, const double* A, int64_t lda,
+              const double* B, int64_t ldb) {
+  return (ta == 'T' || ta == 't') && (tb == 'N' || tb == 'n') && A == B && lda == ldb && M == N &&
+         M <= 16 * kSyMaxT && K >= kSyMinK;
+}
+
 template <int BM, int BN, int BK, bool TA, bool TB>
 void launch_tile(hipStream_t s, int M, int N, int K, int nsplit, int kchunk, double alpha,
                  const double* A, int64_t lda, const double* B, int64_t ldb, double beta,
@@ -297,7 +398,10 @@ __global__ __launch_bounds__(kSkThreads) void gemm_f64_skinny_kernel(
 #pragma unroll
   for (int j = 0; j < TN; ++j) acc[j] = v4d{0.0, 0.0, 0.0, 0.0};
 
-  double ra[4], rb_[LB];
+  // A (the n x n operator, streamed from HBM) passes through a two-slab ring:
+  // a slab's fragments are loaded two slabs ahead, about 3 us at this shape,
+  // beyond the loaded HBM latency
+  double ra[2][4], rb_[LB];
   auto load_a = [&](int k0, double (&dst)[4]) {
 #pragma unroll
     for (int s4 = 0; s4 < 4; ++s4) {
@@ -328,32 +432,32 @@ __global__ __launch_bounds__(kSkThreads) void gemm_f64_skinny_kernel(
   if (kbeg < kend) {
     load_b(kbeg);
     store_b(0);
-    load_a(kbeg, ra);
+    load_a(kbeg, ra[0]);
+    load_a(kbeg + kSkBK, ra[1]);
   }
   __syncthreads();
   int buf = 0;
-  for (int k0 = kbeg; k0 < kend; k0 += kSkBK) {
-    const bool more = (k0 + kSkBK) < kend;
-    double an[4];
-    if (more) {
-      load_b(k0 + kSkBK);
-      load_a(k0 + kSkBK, an);
-    }
+  for (int k0 = kbeg; k0 < kend; k0 += 2 * kSkBK) {
 #pragma unroll
-    for (int s4 = 0; s4 < 4; ++s4) {
+    for (int u = 0; u < 2; ++u) {
+      const int kc = k0 + u * kSkBK;
+      if (kc < kend) {  // uniform
+        const bool more = (kc + kSkBK) < kend;
+        if (more) load_b(kc + kSkBK);
 #pragma unroll
-      for (int j = 0; j < TN; ++j) {
-        const double bv = sB[buf][s4 * 4 + kq][j * 16 + r16];
-        acc[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ra[s4], bv, acc[j], 0, 0, 0);
+        for (int s4 = 0; s4 < 4; ++s4) {
+#pragma unroll
+          for (int j = 0; j < TN; ++j) {
+            const double bv = sB[buf][s4 * 4 + kq][j * 16 + r16];
+            acc[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ra[u][s4], bv, acc[j], 0, 0, 0);
+          }
+        }
+        if (kc + 2 * kSkBK < kend) load_a(kc + 2 * kSkBK, ra[u]);
+        if (more) store_b(buf ^ 1);
+        __syncthreads();
+        buf ^= 1;
       }
     }
-    if (more) {
-      store_b(buf ^ 1);
-#pragma unroll
-      for (int s4 = 0; s4 < 4; ++s4) ra[s4] = an[s4];
-    }
-    __syncthreads();
-    buf ^= 1;
   }
 
   // element v of lane l holds row 4 v + l / 16 (of the wave's 16) of column
@@ -407,8 +511,8 @@ bool use_skinny(char ta, char tb, int64_t M, int64_t N, int64_t K) {
 
 int skinny_nsplit(int64_t M, int64_t K) {
   const int64_t rowblocks = cdiv(M, kSkRows);
-  int64_t ns = 8;
-  while (rowblocks * ns < 1024 && K / (ns * 2) >= 256) ns *= 2;
+  int64_t ns = 4;  // two workgroups per CU at n = 16384; fewer partials to write and sum
+  while (rowblocks * ns < 512 && K / (ns * 2) >= 256) ns *= 2;
   while (ns > 1 && K / ns < kSkBK) ns /= 2;
   return (int)ns;
 }
@@ -486,6 +590,10 @@ size_t gemm_f64_workspace_tiled(int64_t M, int64_t N, int64_t K);
 // path serves every width up to kSkMaxN).
 size_t gemm_f64_workspace(int64_t M, int64_t N, int64_t K) {
   size_t w = gemm_f64_workspace_tiled(M, N, K);
+  if (M == N && K >= kSyMinK) {  // a Gram product W^T W of up to M columns may take the syrk path
+    const size_t ms = (size_t)std::min<int64_t>(M, 16 * kSyMaxT);
+    w = std::max(w, (size_t)syrk_grid(K) * ms * ms * sizeof(double) + 256);
+  }
   const int64_t nn = std::min<int64_t>(N, kSkMaxN);
   if (use_skinny('N', 'N', M, nn, K))
     w = std::max(w, (size_t)skinny_nsplit(M, K) * (size_t)M * (size_t)nn * sizeof(double) + 256);
@@ -513,6 +621,26 @@ void gemm_f64(hipStream_t s, char ta, char tb, int64_t M, int64_t N, int64_t K, 
     const int ns = skinny_nsplit(M, K);
     double* partial = ws->get<double>((size_t)ns * M * N);
     gemm_f64_skinny(s, (int)M, (int)N, (int)K, alpha, A, lda, B, ldb, beta, C, ldc, partial);
+    return;
+  }
+  if (use_syrk(ta, tb, M, N, K, A, lda, B, ldb) && ws != nullptr) {
+    const int T = (int)cdiv(M, 16), grid = syrk_grid(K);
+    double* partial = ws->get<double>((size_t)grid * M * M);
+    const size_t lds = (size_t)kSyRows * (16 * T + 1) * sizeof(double);
+    switch (T) {
+#define DME_SYRK(TT)                                                                                    \
+  case TT:                                                                                              \
+    hipLaunchKernelGGL((syrk_tn_kernel<TT>), dim3(grid), dim3(256), lds, s, (int)K, (int)M, A, lda, partial); \
+    break;
+      DME_SYRK(1) DME_SYRK(2) DME_SYRK(3) DME_SYRK(4) DME_SYRK(5) DME_SYRK(6)
+      DME_SYRK(7) DME_SYRK(8) DME_SYRK(9) DME_SYRK(10) DME_SYRK(11) DME_SYRK(12)
+#undef DME_SYRK
+      default: fail(DME_EINTERNAL, "syrk: bad tile count");
+    }
+    DME_HIP(hipGetLastError());
+    hipLaunchKernelGGL(syrk_reduce_kernel, dim3((unsigned)std::min<int64_t>(cdiv(M * M, 256), 1024)), dim3(256), 0,
+                       s, (int)M, grid, alpha, partial, beta, C, ldc);
+    DME_HIP(hipGetLastError());
     return;
   }
   if (M <= kSmallMaxMN && N <= kSmallMaxMN && K <= kSmallMaxK) {

@@ -32,6 +32,22 @@ def test_gemm_f64(ctx, M, N, K, ta, tb):
     assert rel_fro(got, ref) < 1e-13
 
 
+@pytest.mark.parametrize("n,k,beta", [(2048, 178, 0.0), (16384, 192, 0.0), (5000, 33, -0.5), (3001, 1, 0.0),
+                                       (70000, 120, 0.0)])
+def test_gemm_gram(ctx, n, k, beta):
+    """A^T A of a tall A (the compression's W^T W): the symmetric Gram path,
+    ragged row blocks and tiles; the result is exactly symmetric."""
+    announce("gemm gram", n, k, beta)
+    rng = np.random.default_rng(n + k)
+    W = rng.standard_normal((n, k))
+    C = rng.standard_normal((k, k))
+    C = C + C.T
+    got = to_np(ctx.gemm(W, W, alpha=0.75, beta=beta, C=C, transa="T"))
+    ref = 0.75 * W.T @ W + beta * C
+    assert rel_fro(got, ref) < 1e-13
+    assert np.array_equal(got, got.T)
+
+
 def test_gemm_beta_zero_ignores_nan(ctx):
     announce("gemm beta0 nan")
     rng = np.random.default_rng(1)
