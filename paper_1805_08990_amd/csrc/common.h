@@ -285,7 +285,7 @@ int64_t compress_f64(hipStream_t s, int64_t n, int64_t k, double* W, const doubl
 // ld ldw) is read only.  Returns the kept rank, or -1 (nothing written) when
 // Dhat is not numerically positive definite.  L must hold min(max_rank, k)
 // columns: the products forming L are queued for a guessed width (rank_hint +
-// 16 columns, rank_hint <= 0: every column) before the rank reaches the host,
+// 8 columns, rank_hint <= 0: every column) before the rank reaches the host,
 // so that the round trip overlaps them; columns from the rank on come out zero,
 // and a rank above the guess is served by a second product.
 //

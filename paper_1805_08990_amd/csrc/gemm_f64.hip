@@ -181,29 +181,36 @@ __global__ void splitk_reduce_kernel(int M, int N, int nsplit, double alpha,
 // operands loaded straight from global memory (they are L2-resident) four
 // steps ahead, and the four partial tiles are added in wave order through LDS
 // (deterministic).  Same lane layout and epilogue as gemm_f64_kernel.
+// Longer K with at most kSmallSplitTiles tiles of C (the r x m product L^T B
+// of the Riccati step): the grid also splits K into chunks of about
+// kSmallChunk, whose partial tiles splitk_reduce_kernel adds in chunk order.
 constexpr int kSmallMaxMN = 256;
 constexpr int kSmallMaxK = 2048;
 constexpr int kSmallUnroll = 4;
+constexpr int kSmallSplitTiles = 16;
+constexpr int kSmallChunk = 512;
 
 template <bool TA, bool TB>
-__global__ __launch_bounds__(256) void gemm_f64_small_kernel(int M, int N, int K, double alpha,
+__global__ __launch_bounds__(256) void gemm_f64_small_kernel(int M, int N, int K, int kchunk, double alpha,
                                                              const double* __restrict__ A, int64_t lda,
                                                              const double* __restrict__ B, int64_t ldb,
-                                                             double beta, double* __restrict__ C, int64_t ldc) {
+                                                             double beta, double* __restrict__ C, int64_t ldc,
+                                                             double* __restrict__ partial) {
   __shared__ v4d red[3][64];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int r16 = lane & 15, kq = lane >> 4;
   const int m = blockIdx.x * 16 + r16, n = blockIdx.y * 16 + r16;
   const bool min_ = m < M, nin = n < N;
+  const int kbeg = blockIdx.z * kchunk, kend = min(K, kbeg + kchunk);
   auto opA = [&](int k) -> double {
-    return (min_ && k < K) ? (TA ? A[k + (int64_t)m * lda] : A[m + (int64_t)k * lda]) : 0.0;
+    return (min_ && k < kend) ? (TA ? A[k + (int64_t)m * lda] : A[m + (int64_t)k * lda]) : 0.0;
   };
   auto opB = [&](int k) -> double {
-    return (nin && k < K) ? (TB ? B[n + (int64_t)k * ldb] : B[k + (int64_t)n * ldb]) : 0.0;
+    return (nin && k < kend) ? (TB ? B[n + (int64_t)k * ldb] : B[k + (int64_t)n * ldb]) : 0.0;
   };
   v4d acc = v4d{0.0, 0.0, 0.0, 0.0};
-  // wave w: steps k0 = 4 (w + 4 s); kSmallUnroll steps loaded before they are used
-  for (int k0 = 4 * wave; k0 < K; k0 += 16 * kSmallUnroll) {
+  // wave w: steps k0 = kbeg + 4 (w + 4 s); kSmallUnroll steps loaded before they are used
+  for (int k0 = kbeg + 4 * wave; k0 < kend; k0 += 16 * kSmallUnroll) {
     double fa[kSmallUnroll], fb[kSmallUnroll];
 #pragma unroll
     for (int u = 0; u < kSmallUnroll; ++u) {
@@ -223,9 +230,13 @@ __global__ __launch_bounds__(256) void gemm_f64_small_kernel(int M, int N, int K
     for (int v = 0; v < 4; ++v) {
       const int nn = blockIdx.y * 16 + v * 4 + kq;
       if (min_ && nn < N) {
-        double* c = C + m + (int64_t)nn * ldc;
-        const double out = alpha * acc[v];
-        *c = (beta == 0.0) ? out : out + beta * (*c);
+        if (partial) {
+          partial[(int64_t)blockIdx.z * M * N + m + (int64_t)nn * M] = acc[v];
+        } else {
+          double* c = C + m + (int64_t)nn * ldc;
+          const double out = alpha * acc[v];
+          *c = (beta == 0.0) ? out : out + beta * (*c);
+        }
       }
     }
   }
@@ -299,7 +310,9 @@ __global__ __launch_bounds__(256) void syrk_tn_kernel(int n, int k, const double
     }
 }
 
-// C(m, n) = C(n, m) = alpha sum_b partial[b](min, max) (+ beta C), summed in b order.
+// C(m, n) = C(n, m) = alpha sum_b partial[b](min, max) (+ beta C): one thread
+// per upper-triangle entry, eight partials in flight over eight chains added
+// in a fixed order (deterministic).
 __global__ void syrk_reduce_kernel(int k, int nb, double alpha, const double* __restrict__ partial, double beta,
                                    double* __restrict__ C, int64_t ldc) {
   const int64_t kk = (int64_t)k * k;
@@ -307,9 +320,18 @@ __global__ void syrk_reduce_kernel(int k, int nb, double alpha, const double* __
        idx += (int64_t)gridDim.x * blockDim.x) {
     const int i = (int)(idx % k), j = (int)(idx / k);
     if (i > j) continue;
-    double s = 0.0;
-    for (int b = 0; b < nb; ++b) s += partial[b * kk + idx];
-    const double out = alpha * s;
+    double sc[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    int b = 0;
+    for (; b + 8 <= nb; b += 8) {
+      double v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = partial[(b + u) * kk + idx];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) sc[u] += v[u];
+    }
+    for (; b < nb; ++b) sc[0] += partial[b * kk + idx];
+    const double sum = ((sc[0] + sc[1]) + (sc[2] + sc[3])) + ((sc[4] + sc[5]) + (sc[6] + sc[7]));
+    const double out = alpha * sum;
     double* c1 = C + i + (int64_t)j * ldc;
     double* c2 = C + j + (int64_t)i * ldc;
     if (beta == 0.0) {
@@ -565,7 +587,8 @@ Plan plan_for(int64_t M, int64_t N, int64_t K) {
   Plan p;
   // the largest tile that still gives every CU a tile (small products are
   // latency-bound: more, smaller tiles finish sooner)
-  if (M >= 128 && N >= 128 && cdiv(M, 128) * cdiv(N, 128) >= kMinTiles) { p.bm = 128; p.bn = 128; }
+  if (N <= 256 && K <= 512)                                              { p.bm = 64;  p.bn = 64; }  // tall x narrow, short K: latency-bound tiles
+  else if (M >= 128 && N >= 128 && cdiv(M, 128) * cdiv(N, 128) >= kMinTiles) { p.bm = 128; p.bn = 128; }
   else if (M >= 128 && cdiv(M, 128) * cdiv(N, 64) >= kMinTiles)         { p.bm = 128; p.bn = 64; }
   else                                                                   { p.bm = 64;  p.bn = 64; }
   const int64_t tiles = cdiv(M, p.bm) * cdiv(N, p.bn);
@@ -590,6 +613,9 @@ size_t gemm_f64_workspace_tiled(int64_t M, int64_t N, int64_t K);
 // path serves every width up to kSkMaxN).
 size_t gemm_f64_workspace(int64_t M, int64_t N, int64_t K) {
   size_t w = gemm_f64_workspace_tiled(M, N, K);
+  if (K > kSmallMaxK)  // the small path's K chunks: at most kSmallSplitTiles 16 x 16 tiles of C
+    w = std::max(w, (size_t)std::min<int64_t>(cdiv(K, kSmallChunk), 256) * (size_t)(kSmallSplitTiles * 256) *
+                        sizeof(double) + 256);
   if (M == N && K >= kSyMinK) {  // a Gram product W^T W of up to M columns may take the syrk path
     const size_t ms = (size_t)std::min<int64_t>(M, 16 * kSyMaxT);
     w = std::max(w, (size_t)syrk_grid(K) * ms * ms * sizeof(double) + 256);
@@ -643,19 +669,34 @@ void gemm_f64(hipStream_t s, char ta, char tb, int64_t M, int64_t N, int64_t K, 
     DME_HIP(hipGetLastError());
     return;
   }
-  if (M <= kSmallMaxMN && N <= kSmallMaxMN && K <= kSmallMaxK) {
-    const dim3 grid((unsigned)cdiv(M, 16), (unsigned)cdiv(N, 16));
+  const int64_t small_tiles = cdiv(M, 16) * cdiv(N, 16);
+  if (M <= kSmallMaxMN && N <= kSmallMaxMN &&
+      (K <= kSmallMaxK || (small_tiles <= kSmallSplitTiles && ws != nullptr))) {
+    int nsplit = 1, kchunk = (int)K;
+    double* partial = nullptr;
+    if (K > kSmallMaxK) {
+      nsplit = (int)std::min<int64_t>(cdiv(K, kSmallChunk), 256);
+      kchunk = (int)(cdiv(cdiv(K, nsplit), 64) * 64);
+      nsplit = (int)cdiv(K, kchunk);
+      partial = ws->get<double>((size_t)nsplit * M * N);
+    }
+    const dim3 grid((unsigned)cdiv(M, 16), (unsigned)cdiv(N, 16), (unsigned)nsplit);
     const bool TA = (ta == 'T' || ta == 't'), TB = (tb == 'T' || tb == 't');
     const int iM = (int)M, iN = (int)N, iK = (int)K;
     if (!TA && !TB)
-      hipLaunchKernelGGL((gemm_f64_small_kernel<false, false>), grid, dim3(256), 0, s, iM, iN, iK, alpha, A, lda, B, ldb, beta, C, ldc);
+      hipLaunchKernelGGL((gemm_f64_small_kernel<false, false>), grid, dim3(256), 0, s, iM, iN, iK, kchunk, alpha, A, lda, B, ldb, beta, C, ldc, partial);
     else if (TA && !TB)
-      hipLaunchKernelGGL((gemm_f64_small_kernel<true, false>), grid, dim3(256), 0, s, iM, iN, iK, alpha, A, lda, B, ldb, beta, C, ldc);
+      hipLaunchKernelGGL((gemm_f64_small_kernel<true, false>), grid, dim3(256), 0, s, iM, iN, iK, kchunk, alpha, A, lda, B, ldb, beta, C, ldc, partial);
     else if (!TA && TB)
-      hipLaunchKernelGGL((gemm_f64_small_kernel<false, true>), grid, dim3(256), 0, s, iM, iN, iK, alpha, A, lda, B, ldb, beta, C, ldc);
+      hipLaunchKernelGGL((gemm_f64_small_kernel<false, true>), grid, dim3(256), 0, s, iM, iN, iK, kchunk, alpha, A, lda, B, ldb, beta, C, ldc, partial);
     else
-      hipLaunchKernelGGL((gemm_f64_small_kernel<true, true>), grid, dim3(256), 0, s, iM, iN, iK, alpha, A, lda, B, ldb, beta, C, ldc);
+      hipLaunchKernelGGL((gemm_f64_small_kernel<true, true>), grid, dim3(256), 0, s, iM, iN, iK, kchunk, alpha, A, lda, B, ldb, beta, C, ldc, partial);
     DME_HIP(hipGetLastError());
+    if (partial) {
+      hipLaunchKernelGGL(splitk_reduce_kernel, dim3((unsigned)std::min<int64_t>(cdiv(M * N, 256), 4096)), dim3(256),
+                         0, s, iM, iN, nsplit, alpha, partial, beta, C, ldc);
+      DME_HIP(hipGetLastError());
+    }
     return;
   }
   Plan p = plan_for(M, N, K);

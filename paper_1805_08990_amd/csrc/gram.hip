@@ -338,15 +338,18 @@ __global__ void copy_lower_kernel(int k, const double* Dhat, int64_t ldd, double
   }
 }
 
-// S = (G + G^T) / 2
-__global__ void sym_kernel(int k, const double* G, double* S) {
+// S = (G + G^T) / 2; a non-finite entry sets bit 1 of *flag
+__global__ void sym_kernel(int k, const double* G, double* S, int* flag) {
+  bool bad = false;
   for (int64_t idx = blockIdx.x * 256 + threadIdx.x; idx < (int64_t)k * k; idx += (int64_t)gridDim.x * 256) {
     const int i = (int)(idx % k), j = (int)(idx / k);
-    S[idx] = 0.5 * (G[idx] + G[j + (int64_t)i * k]);
+    const double v = 0.5 * (G[idx] + G[j + (int64_t)i * k]);
+    S[idx] = v;
+    if (!isfinite(v)) bad = true;
   }
+  if (bad) atomicOr(flag, 1);
 }
 
-// T(:, j) /= sqrt(lam_j), j < r (k x r, ld k)
 // T(:, j) /= sqrt(lam_j) for j < *rank, T(:, j) = 0 for rank <= j < r (the
 // columns past the kept rank may hold anything)
 __global__ void scale_cols_kernel(int k, int r, const double* lam, const int64_t* rank, double* T) {
@@ -423,9 +426,8 @@ int64_t compress_gram_f64(hipStream_t s, int64_t n, int64_t k, const double* W, 
   gemm_f64(s, 'N', 'N', k, k, k, 1.0, G, k, F, k, 0.0, T1, k, &ws);
   ws.used = mark_g;
   gemm_f64(s, 'T', 'N', k, k, k, 1.0, F, k, T1, k, 0.0, G, k, &ws);
-  hipLaunchKernelGGL(sym_kernel, dim3(blocks(k * k)), dim3(256), 0, s, (int)k, G, S);
+  hipLaunchKernelGGL(sym_kernel, dim3(blocks(k * k)), dim3(256), 0, s, (int)k, G, S, flag_dev);
   DME_HIP(hipGetLastError());
-  finite_check_f64(s, S, k, k, k, flag_dev);
   ws.used = mark_g;
   syev_trunc_f64(s, k, S, k, tol, std::min(max_rank, k), lam, V, k, rank_dev, flag_dev, ws);
   ws.used = mark_g;
@@ -433,7 +435,7 @@ int64_t compress_gram_f64(hipStream_t s, int64_t n, int64_t k, const double* W, 
   // L = W (F V_I Lam_I^-1/2), D = Lam_I: the products for a guessed width go
   // ahead of the rank's round trip to the host
   const int64_t kmax = std::min(max_rank, k);
-  const int64_t ks = (rank_hint > 0) ? std::min(kmax, rank_hint + 16) : kmax;
+  const int64_t ks = (rank_hint > 0) ? std::min(kmax, rank_hint + 8) : kmax;
   auto form_L = [&](int64_t w) {
     gemm_f64(s, 'N', 'N', k, w, k, 1.0, F, k, V, k, 0.0, T, k, &ws);
     ws.used = mark_g;

@@ -147,6 +147,54 @@ __device__ __forceinline__ void tile_rank2(double (&a)[RT][NC], const double* vr
   }
 }
 
+// e2 = e^2 and the spectrum bounds of the tridiagonal (d, e) (what
+// tri_prep_kernel computes), by the whole workgroup from d and e in LDS;
+// red holds at least 4 x (waves) doubles.  Called after a barrier.
+__device__ inline void tri_bounds_block(const double* sd, const double* se, int k, double* e2, double* bounds,
+                                        double* red) {
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6, nw = blockDim.x >> 6;
+  double lo = INFINITY, hi = -INFINITY, me2 = 0.0, nrm = 0.0;
+  for (int i = t; i < k; i += blockDim.x) {
+    const double el = (i > 0) ? fabs(se[i - 1]) : 0.0;
+    const double er = (i + 1 < k) ? fabs(se[i]) : 0.0;
+    lo = fmin(lo, sd[i] - el - er);
+    hi = fmax(hi, sd[i] + el + er);
+    nrm = fmax(nrm, fabs(sd[i]) + el + er);
+    if (i + 1 < k) {
+      const double v = se[i] * se[i];
+      e2[i] = v;
+      me2 = fmax(me2, v);
+    }
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    lo = fmin(lo, __shfl_xor(lo, off, 64));
+    hi = fmax(hi, __shfl_xor(hi, off, 64));
+    me2 = fmax(me2, __shfl_xor(me2, off, 64));
+    nrm = fmax(nrm, __shfl_xor(nrm, off, 64));
+  }
+  __syncthreads();  // red may alias LDS the caller used before
+  if (lane == 0) {
+    red[4 * w] = lo;
+    red[4 * w + 1] = hi;
+    red[4 * w + 2] = me2;
+    red[4 * w + 3] = nrm;
+  }
+  __syncthreads();
+  if (t == 0) {
+    for (int q = 1; q < nw; ++q) {
+      lo = fmin(lo, red[4 * q]);
+      hi = fmax(hi, red[4 * q + 1]);
+      me2 = fmax(me2, red[4 * q + 2]);
+      nrm = fmax(nrm, red[4 * q + 3]);
+    }
+    const double slack = 2.0 * DBL_EPSILON * nrm * k + 1e-300;
+    bounds[0] = lo - slack;
+    bounds[1] = hi + slack;
+    bounds[2] = DBL_MIN * fmax(1.0, me2);
+    bounds[3] = nrm;
+  }
+}
+
 // Householder tridiagonalisation with the whole matrix in registers, in
 // RT x NC tiles: the 32 lanes of a half-wave share the rows RT h .. RT h + RT - 1
 // (h = 2 wave + half) and lane c of them holds the columns c + 32 m (m < NC),
@@ -162,7 +210,8 @@ __device__ __forceinline__ void tile_rank2(double (&a)[RT][NC], const double* vr
 // reflector of step j goes to A(j+2:, j) and d, e, tau as in tridiag_kernel.
 template <int NC, int RT>
 __global__ __launch_bounds__(32 * 32 * NC / RT) void tridiag_tiles_kernel(double* A, int64_t lda, int k,
-                                                                          double* d, double* e, double* tau) {
+                                                                          double* d, double* e, double* tau,
+                                                                          double* e2, double* bounds) {
   constexpr int KM = 32 * NC;        // largest k
   constexpr int NW = KM / (2 * RT);  // waves: two RT-row tiles each
   static_assert(KM % (2 * RT) == 0 && NW <= 16, "whole waves, at most 16");
@@ -170,6 +219,7 @@ __global__ __launch_bounds__(32 * 32 * NC / RT) void tridiag_tiles_kernel(double
   __shared__ double tjs[2];       // and its tau
   __shared__ double pb[KM];
   __shared__ double wpart[NW];
+  __shared__ double sd[KM], se[KM];  // d and e as published, for the bounds at the end
   const int t = threadIdx.x;
   const int lane = t & 63, wv = t >> 6;
   const int c = lane & 31;
@@ -204,7 +254,10 @@ __global__ __launch_bounds__(32 * 32 * NC / RT) void tridiag_tiles_kernel(double
       const int l = c + 32 * m;
       if (l >= q + 2 && l < k) s2 += xr[m] * xr[m];
       if (l == q + 1) al = xr[m];
-      if (l == q) d[q] = xr[m];
+      if (l == q) {
+        d[q] = xr[m];
+        sd[q] = xr[m];
+      }
     }
     const double alpha = half_wave_sum_f64(al);  // one nonzero term: exact
     if (q + 2 < k) {
@@ -217,6 +270,7 @@ __global__ __launch_bounds__(32 * 32 * NC / RT) void tridiag_tiles_kernel(double
       }
       if (c == 0) {
         e[q] = beta;
+        se[q] = beta;
         tau[q] = tj;
         tjs[q & 1] = tj;
       }
@@ -230,6 +284,7 @@ __global__ __launch_bounds__(32 * 32 * NC / RT) void tridiag_tiles_kernel(double
       }
     } else if (c == 0) {
       e[q] = alpha;
+      se[q] = alpha;
       tau[q] = 0.0;
     }
   };
@@ -284,10 +339,15 @@ __global__ __launch_bounds__(32 * 32 * NC / RT) void tridiag_tiles_kernel(double
       if (u == uu) {
 #pragma unroll
         for (int m = 0; m < NC; ++m)
-          if (c + 32 * m == k - 1) d[k - 1] = a[u][m];
+          if (c + 32 * m == k - 1) {
+            d[k - 1] = a[u][m];
+            sd[k - 1] = a[u][m];
+          }
       }
     if (c == 0) tau[k - 1] = 0.0;
   }
+  __syncthreads();
+  tri_bounds_block(sd, se, k, e2, bounds, pb);  // pb (KM >= 4 NW doubles) is free by now
 }
 
 // Householder tridiagonalisation for k <= kTriMaxK, same outputs as
@@ -633,6 +693,8 @@ __global__ __launch_bounds__(64) void bisect_kernel(const double* __restrict__ d
 //               with consecutive gaps <= kOrtol ||T||;
 //               cl_count[0] = number of clusters
 //   keep[0]   : kept count (capped at max_keep, flag |= 2 when capped)
+//   cl_of[c]  : cluster of kept column c (c < ncol) when it has two or more
+//               members, else -1; cl_fail[0 .. ncol) cleared
 // The counts that place the unkept eigenvalues and the clusters come from
 // block-wide prefix sums over contiguous chunks of the index range.
 constexpr int kSelT = 1024;
@@ -659,9 +721,13 @@ __global__ __launch_bounds__(kSelT) void select_kernel(const double* lam, int k,
                                                        int64_t max_keep, const double* bounds,
                                                        int* order, int* pos_of, double* lam_out,
                                                        int* clusters, int* cl_count, int64_t* keep,
-                                                       int* flag) {
+                                                       int* flag, int ncol, int* cl_of, int* cl_fail) {
   __shared__ int sh[kSelT];
   const int t = threadIdx.x;
+  for (int c = t; c < ncol; c += kSelT) {  // cluster of each kept column: none yet
+    cl_of[c] = -1;
+    cl_fail[c] = 0;
+  }
   // eigenvalues are known to about u ||T||; a zero matrix has no nonzero ones
   const double nrmT = bounds[3];
   double amax = 0.0;
@@ -729,6 +795,13 @@ __global__ __launch_bounds__(kSelT) void select_kernel(const double* lam, int k,
   if (t == kSelT - 1) {
     cl_count[0] = runs;
     keep[0] = cap;
+  }
+  __syncthreads();  // run lengths final
+  // cl_of[col] = run of kept column col when the run has two or more members
+  id = incl - ns;
+  for (int i = i0; i < i1; ++i) {
+    if (starts(i)) ++id;
+    if (pos_of[i] >= 0 && pos_of[i] < ncol && clusters[2 * (id - 1) + 1] >= 2) cl_of[pos_of[i]] = id - 1;
   }
 }
 
@@ -1086,26 +1159,6 @@ __global__ __launch_bounds__(128) void twist_kernel(const double* __restrict__ d
 // Gram-Schmidt.  The polar factor mixes a cluster's vectors least.
 constexpr double kPolarTol = 1e-4;
 
-// cl_of[col] = cluster of kept column col (-1: none of two or more members);
-// cl_fail cleared.  One block.
-__global__ void cluster_index_kernel(int ncol, const int* clusters, const int* cl_count, const int* pos_of,
-                                     int* cl_of, int* cl_fail) {
-  for (int c = threadIdx.x; c < ncol; c += blockDim.x) {
-    cl_of[c] = -1;
-    cl_fail[c] = 0;
-  }
-  __syncthreads();
-  const int nc = cl_count[0];
-  for (int id = threadIdx.x; id < nc; id += blockDim.x) {
-    const int start = clusters[2 * id], len = clusters[2 * id + 1];
-    if (len < 2) continue;
-    for (int q = 0; q < len; ++q) {
-      const int col = pos_of[start + q];
-      if (col >= 0 && col < ncol) cl_of[col] = id;
-    }
-  }
-}
-
 // cl_fail[id] |= 1 when a cluster's Gram matrix is not close enough to I.
 __global__ void polar_check_kernel(const double* G, int ncol, const int* cl_of, const int* clusters,
                                    int* cl_fail) {
@@ -1363,13 +1416,13 @@ void syev_trunc_f64(hipStream_t s, int64_t k, const double* M, int64_t ldm, doub
     fill_f64(s, tau, 1, 1, 1, 0.0);
   } else {
     if (k <= 64) {
-      hipLaunchKernelGGL((tridiag_tiles_kernel<2, 8>), dim3(1), dim3(256), 0, s, A, k, ki, d, e, tau);
+      hipLaunchKernelGGL((tridiag_tiles_kernel<2, 8>), dim3(1), dim3(256), 0, s, A, k, ki, d, e, tau, e2, bounds);
     } else if (k <= 128) {
-      hipLaunchKernelGGL((tridiag_tiles_kernel<4, 8>), dim3(1), dim3(512), 0, s, A, k, ki, d, e, tau);
+      hipLaunchKernelGGL((tridiag_tiles_kernel<4, 8>), dim3(1), dim3(512), 0, s, A, k, ki, d, e, tau, e2, bounds);
     } else if (k <= 160) {
-      hipLaunchKernelGGL((tridiag_tiles_kernel<5, 8>), dim3(1), dim3(640), 0, s, A, k, ki, d, e, tau);
+      hipLaunchKernelGGL((tridiag_tiles_kernel<5, 8>), dim3(1), dim3(640), 0, s, A, k, ki, d, e, tau, e2, bounds);
     } else if (k <= 192) {
-      hipLaunchKernelGGL((tridiag_tiles_kernel<6, 6>), dim3(1), dim3(1024), 0, s, A, k, ki, d, e, tau);
+      hipLaunchKernelGGL((tridiag_tiles_kernel<6, 6>), dim3(1), dim3(1024), 0, s, A, k, ki, d, e, tau, e2, bounds);
     } else if (k <= kTriMaxK) {
       const size_t lds = (size_t)(3 + kTriT / 64) * k * sizeof(double);
       hipLaunchKernelGGL(tridiag_small_kernel, dim3(1), dim3(kTriT), lds, s, A, k, ki, d, e, tau);
@@ -1395,12 +1448,17 @@ void syev_trunc_f64(hipStream_t s, int64_t k, const double* M, int64_t ldm, doub
     DME_HIP(hipGetLastError());
   }
   const hipEvent_t q_done = ax.record(ax.s2);
-  hipLaunchKernelGGL(tri_prep_kernel, dim3(1), dim3(256), 0, s, d, e, ki, e2, bounds);
-  DME_HIP(hipGetLastError());
+  if (k == 1 || k > 192) {  // the register-tiled reductions leave e2 and the bounds themselves
+    hipLaunchKernelGGL(tri_prep_kernel, dim3(1), dim3(256), 0, s, d, e, ki, e2, bounds);
+    DME_HIP(hipGetLastError());
+  }
   hipLaunchKernelGGL(bisect_kernel<false>, dim3((unsigned)k), dim3(64), 0, s, d, e2, ki, bounds, lam);
   DME_HIP(hipGetLastError());
+  const unsigned nkeep_sel = (unsigned)std::min<int64_t>(k, max_keep);
+  int* cl_of = ws.get<int>(k);
+  int* cl_fail = ws.get<int>(k);
   hipLaunchKernelGGL(select_kernel, dim3(1), dim3(kSelT), 0, s, lam, ki, tol, max_keep, bounds, order,
-                     pos_of, lam_out, clusters, cl_count, keep_dev, flag_dev);
+                     pos_of, lam_out, clusters, cl_count, keep_dev, flag_dev, (int)nkeep_sel, cl_of, cl_fail);
   DME_HIP(hipGetLastError());
   // Z: k x (kept) column-major with ld = k (kept <= k)
   const unsigned nkeep = (unsigned)std::min<int64_t>(k, max_keep);
@@ -1432,13 +1490,8 @@ void syev_trunc_f64(hipStream_t s, int64_t k, const double* M, int64_t ldm, doub
     double* G = ws.get<double>((size_t)nc * nc);
     double* Bm = ws.get<double>((size_t)nc * nc);
     double* Z1 = ws.get<double>((size_t)k * nc);
-    int* cl_of = ws.get<int>(k);
-    int* cl_fail = ws.get<int>(k);
     const size_t mark = ws.used;
     const unsigned gb = (unsigned)std::max<int64_t>(1, std::min<int64_t>(cdiv((int64_t)nc * nc, 256), 1024));
-    hipLaunchKernelGGL(cluster_index_kernel, dim3(1), dim3(256), 0, s, nc, clusters, cl_count, pos_of, cl_of,
-                       cl_fail);
-    DME_HIP(hipGetLastError());
     gemm_f64(s, 'T', 'N', nc, nc, k, 1.0, Zt, k, Zt, k, 0.0, G, nc, &ws);
     ws.used = mark;
     hipLaunchKernelGGL(polar_check_kernel, dim3(gb), dim3(256), 0, s, G, nc, cl_of, clusters, cl_fail);

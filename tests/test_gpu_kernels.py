@@ -15,6 +15,8 @@ pytestmark = pytest.mark.gpu
     (32, 40, 5000, "T", "N"), (1000, 7, 1000, "N", "N"), (256, 256, 0, "N", "N"),
     # the small-product path at its limits (M, N <= 256, K <= 2048), ragged
     (256, 256, 2048, "T", "T"), (250, 17, 2047, "N", "T"), (178, 178, 178, "T", "N"),
+    # few tiles and a long K (L^T B of the Riccati step): K split over the grid
+    (122, 4, 16384, "T", "N"), (33, 40, 5000, "T", "N"), (16, 16, 2049, "N", "N"), (64, 64, 70001, "T", "T"),
     # tall-square times narrow: the skinny split-K path (ragged rows, K and N)
     (2048, 150, 2048, "N", "N"), (1500, 7, 1100, "N", "N"), (4097, 256, 3000, "N", "N"),
     (1024, 33, 1024, "N", "N"),
