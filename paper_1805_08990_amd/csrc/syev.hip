@@ -7,8 +7,11 @@
 //                         registers by tiles (k <= 192), tridiag_small_kernel
 //                         keeps the vectors in LDS (k <= 512), tridiag_kernel
 //                         works from global memory (larger k).
-//   2. bisect_kernel    : every eigenvalue by Sturm-count multisection, one
-//                         wave per eigenvalue index (all independent).
+//   2. bisect_wg_kernel : every eigenvalue by Sturm-count multisection, one
+//                         four-wave workgroup per eigenvalue index (all
+//                         independent); the tiled tridiagonalisation leaves
+//                         its spectrum bounds, tri_prep_kernel forms them
+//                         otherwise.
 //   3. select_kernel    : threshold, |lambda|-descending order of the kept set
 //                         and the clusters of kept eigenvalues whose gaps are
 //                         below 1e-3 ||T|| (the absolute criterion of LAPACK's
@@ -43,7 +46,6 @@ constexpr double kOrtol = 1e-3;  // gaps below kOrtol ||T|| join a cluster
 constexpr int kInvitIters = 3;
 constexpr int kInvitLdsMaxK = 2048;  // inverse-iteration arrays in LDS up to this k
 constexpr int kInvitArrays = 8;      // k-long arrays per inverse iteration
-constexpr int kBisLdsMaxK = 4096;    // bisection reads d, e^2 from LDS up to this k
 
 __device__ inline double block_sum_1024(double v, double* red) {
   // red: kTriT doubles of LDS; returns the total to every thread
@@ -631,56 +633,54 @@ __device__ inline void sturm_count2(const double* __restrict__ d, const double* 
   c2 = n2;
 }
 
-// Eigenvalue i (ascending) by multisection on the Sturm count: wave i
-// evaluates the count at 127 interior points of its interval (two per lane)
-// and keeps the sub-interval where the count passes i, so each round shrinks
-// the interval 128-fold.  Stops at the width the reduction determines the
-// eigenvalue to.  d and e2 are staged in LDS when LDS; otherwise the loop
-// reads them with scalar loads (the same entry for every lane), which costs
-// the wave far less than an LDS read per row.
-// (LDS is a template parameter so that every access has a known address
-// space: a pointer that may be either becomes a slow generic access.)
-template <bool LDS>
-__global__ __launch_bounds__(64) void bisect_kernel(const double* __restrict__ d,
-                                                    const double* __restrict__ e2, int k,
-                                                    const double* __restrict__ bounds, double* lam) {
-  extern __shared__ double bsh[];
+// Eigenvalue i (ascending) by multisection on the Sturm count: workgroup i
+// (four waves) evaluates the count at 511 interior points of its interval (two
+// per lane, p = t + 1 and t + 257 for thread t; p = 512 is hi) and keeps the
+// sub-interval where the count passes i, so each round shrinks the interval
+// 512-fold (four waves gain 9 bits a round where one gains 7, for the same
+// Sturm-count work per wave).  Each wave's first point above the index goes
+// through LDS and one barrier.  Stops at the width the reduction determines the
+// eigenvalue to.  d and e2 are read with scalar loads (the same entry for
+// every lane of a wave).
+constexpr int kBisWaves = 4;
+__global__ __launch_bounds__(64 * kBisWaves) void bisect_wg_kernel(const double* __restrict__ d,
+                                                                   const double* __restrict__ e2, int k,
+                                                                   const double* __restrict__ bounds,
+                                                                   double* lam) {
+  constexpr int P = 128 * kBisWaves;  // points per round
+  __shared__ int first[2][2][kBisWaves];  // [round parity][half][wave]: first point above, or P
   const int i = blockIdx.x;
-  const int lane = threadIdx.x;
-  if (i >= k) return;
-  const double* dd = d;
-  const double* ee = e2;
-  if constexpr (LDS) {
-    for (int q = lane; q < k; q += 64) {
-      bsh[q] = d[q];
-      bsh[k + q] = (q + 1 < k) ? e2[q] : 0.0;
-    }
-    __syncthreads();
-    dd = bsh;
-    ee = bsh + k;
-  }
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   double lo = bounds[0], hi = bounds[1];
   const double pivmin = bounds[2];
   const double atol = DBL_EPSILON * bounds[3] + 2.0 * DBL_MIN;
   for (int it = 0; it < 64; ++it) {
     if (hi - lo <= 2.0 * DBL_EPSILON * fmax(fabs(lo), fabs(hi)) + atol) break;
-    const double h = (hi - lo) / 128.0;
-    // points p = 1 .. 128 at lo + h p (p = 128 is hi): lane takes p = lane + 1, lane + 65
-    const double x1 = lo + h * (double)(lane + 1);
-    const double x2 = (lane < 63) ? lo + h * (double)(lane + 65) : hi;
+    const double h = (hi - lo) / (double)P;
+    const double x1 = lo + h * (double)(t + 1);
+    const double x2 = (t < P / 2 - 1) ? lo + h * (double)(t + P / 2 + 1) : hi;
     int c1, c2;
-    sturm_count2(dd, ee, k, x1, x2, pivmin, c1, c2);
+    sturm_count2(d, e2, k, x1, x2, pivmin, c1, c2);
     const uint64_t m1 = __ballot(c1 > i);
-    const uint64_t m2 = __ballot(lane == 63 || c2 > i);  // hi is always above
-    const int f = (m1 != 0) ? __ffsll((unsigned long long)m1) - 1
-                            : 64 + __ffsll((unsigned long long)m2) - 1;  // first point above, 0-based
+    const uint64_t m2 = __ballot((t == P / 2 - 1) || c2 > i);  // hi is always above
+    const int par = it & 1;
+    if (lane == 0) {
+      first[par][0][w] = (m1 != 0) ? 64 * w + __ffsll((unsigned long long)m1) - 1 : P;
+      first[par][1][w] = (m2 != 0) ? P / 2 + 64 * w + __ffsll((unsigned long long)m2) - 1 : P;
+    }
+    __syncthreads();
+    int f = P;
+    for (int q = 0; q < kBisWaves; ++q) f = min(f, first[par][0][q]);
+    if (f == P)
+      for (int q = 0; q < kBisWaves; ++q) f = min(f, first[par][1][q]);
+    // f: first point above (0-based), the same in every thread
     const double nlo = (f == 0) ? lo : lo + h * (double)f;
-    const double nhi = (f == 127) ? hi : lo + h * (double)(f + 1);
-    if (!(nhi - nlo < hi - lo)) break;  // no progress in floating point
+    const double nhi = (f == P - 1) ? hi : lo + h * (double)(f + 1);
+    if (!(nhi - nlo < hi - lo)) break;  // no progress in floating point (uniform)
     lo = nlo;
     hi = nhi;
   }
-  if (lane == 0) lam[i] = 0.5 * (lo + hi);
+  if (t == 0) lam[i] = 0.5 * (lo + hi);
 }
 
 // Selection, by one block of kSelT threads.  Outputs:
@@ -698,6 +698,7 @@ __global__ __launch_bounds__(64) void bisect_kernel(const double* __restrict__ d
 // The counts that place the unkept eigenvalues and the clusters come from
 // block-wide prefix sums over contiguous chunks of the index range.
 constexpr int kSelT = 1024;
+constexpr int kSelLds = 4096;  // eigenvalues staged in LDS up to this k
 
 __device__ inline int block_scan_incl(int v, int* sh) {
   // inclusive prefix sum of v over the block: within each wave by lane
@@ -723,11 +724,17 @@ __global__ __launch_bounds__(kSelT) void select_kernel(const double* lam, int k,
                                                        int* clusters, int* cl_count, int64_t* keep,
                                                        int* flag, int ncol, int* cl_of, int* cl_fail) {
   __shared__ int sh[kSelT];
+  __shared__ double slam[kSelLds];  // the eigenvalues, for the O(k) rank loops
   const int t = threadIdx.x;
   for (int c = t; c < ncol; c += kSelT) {  // cluster of each kept column: none yet
     cl_of[c] = -1;
     cl_fail[c] = 0;
   }
+  const bool staged = k <= kSelLds;
+  if (staged)
+    for (int j = t; j < k; j += kSelT) slam[j] = lam[j];
+  __syncthreads();
+  const double* lamv = staged ? (const double*)slam : lam;
   // eigenvalues are known to about u ||T||; a zero matrix has no nonzero ones
   const double nrmT = bounds[3];
   double amax = 0.0;
@@ -753,7 +760,7 @@ __global__ __launch_bounds__(kSelT) void select_kernel(const double* lam, int k,
     if (any && a > thr) {
       int rk = 0;
       for (int j = 0; j < k; ++j) {
-        const double b = fabs(lam[j]);
+        const double b = fabs(lamv[j]);
         rk += (b > a || (b == a && j < i)) ? 1 : 0;
       }
       if (rk < cap) {
@@ -1452,7 +1459,7 @@ void syev_trunc_f64(hipStream_t s, int64_t k, const double* M, int64_t ldm, doub
     hipLaunchKernelGGL(tri_prep_kernel, dim3(1), dim3(256), 0, s, d, e, ki, e2, bounds);
     DME_HIP(hipGetLastError());
   }
-  hipLaunchKernelGGL(bisect_kernel<false>, dim3((unsigned)k), dim3(64), 0, s, d, e2, ki, bounds, lam);
+  hipLaunchKernelGGL(bisect_wg_kernel, dim3((unsigned)k), dim3(64 * kBisWaves), 0, s, d, e2, ki, bounds, lam);
   DME_HIP(hipGetLastError());
   const unsigned nkeep_sel = (unsigned)std::min<int64_t>(k, max_keep);
   int* cl_of = ws.get<int>(k);
