@@ -208,7 +208,7 @@ __device__ inline void tri_bounds_block(const double* sd, const double* se, int 
 // reach LDS, and after the rank-2 update A -= v w^T + w v^T,
 // w = p - (tau/2)(p^T v) v, has brought the next reflector.  Between the
 // barriers every wave runs the same phase, so a step costs the VALU work of
-// the waves that share a SIMD (about 2.3 us at k = 180 on 16 waves).  The
+// the waves that share a SIMD (about 2.25 us at k = 178 on 12 waves).  The
 // reflector of step j goes to A(j+2:, j) and d, e, tau as in tridiag_kernel.
 template <int NC, int RT>
 __global__ __launch_bounds__(32 * 32 * NC / RT) void tridiag_tiles_kernel(double* A, int64_t lda, int k,
@@ -311,9 +311,10 @@ __global__ __launch_bounds__(32 * 32 * NC / RT) void tridiag_tiles_kernel(double
         const int i = rbase + srow;
         pu = (srow < RT && i >= r0 && i < k) ? tj * sum : 0.0;
       }
-      if ((c & 3) == 0 && srow < RT) pb[rbase + srow] = pu;
+      const bool lead = (c & 3) == 0;     // one lane per row
+      if (lead && srow < RT) pb[rbase + srow] = pu;
       const double vs = (srow < RT) ? v[rbase + min(srow, RT - 1)] : 0.0;
-      const double pv = wave_sum_f64((c & 3) == 0 ? pu * vs : 0.0);  // both half-waves
+      const double pv = wave_sum_f64(lead ? pu * vs : 0.0);  // both half-waves
       if (lane == 0) wpart[wv] = pv;
       __syncthreads();
       constexpr int G = NW <= 4 ? 4 : (NW <= 8 ? 8 : 16);  // NW <= 16
@@ -1429,7 +1430,7 @@ void syev_trunc_f64(hipStream_t s, int64_t k, const double* M, int64_t ldm, doub
     } else if (k <= 160) {
       hipLaunchKernelGGL((tridiag_tiles_kernel<5, 8>), dim3(1), dim3(640), 0, s, A, k, ki, d, e, tau, e2, bounds);
     } else if (k <= 192) {
-      hipLaunchKernelGGL((tridiag_tiles_kernel<6, 6>), dim3(1), dim3(1024), 0, s, A, k, ki, d, e, tau, e2, bounds);
+      hipLaunchKernelGGL((tridiag_tiles_kernel<6, 8>), dim3(1), dim3(768), 0, s, A, k, ki, d, e, tau, e2, bounds);
     } else if (k <= kTriMaxK) {
       const size_t lds = (size_t)(3 + kTriT / 64) * k * sizeof(double);
       hipLaunchKernelGGL(tridiag_small_kernel, dim3(1), dim3(kTriT), lds, s, A, k, ki, d, e, tau);
