@@ -99,11 +99,13 @@ typedef enum { DME_SPLIT_F12 = 0, DME_SPLIT_F1F2 = 1, DME_SPLIT_F1F3F2 = 2 } dme
 
 /* DME_FP64: every product in FP64 MFMA.
  * DME_MIXED: the step products e^{tA^T} L (the T1 / T12 products of every
- *            step, the bulk of a step's flops and HBM traffic) in split BF16
+ *            step, the bulk of a step's flops and HBM traffic) and, where the
+ *            quadrature nodes are dense operators (a nonsymmetric A), the node
+ *            products e^{s_k A^T} C^T of the quadrature factor in split BF16
  *            MFMA with FP32 accumulation flushed to FP64.  The operator setup
- *            (Pade, LU, squaring), the quadrature factor (formed once per step
- *            size), the compression, T3 and T4 stay FP64.  Each result states
- *            its estimated distance to the FP64 computation (dme_result_info). */
+ *            (Pade, LU, squaring), the Leja node actions of a symmetric A, the
+ *            compression, T3 and T4 stay FP64.  Each result states its
+ *            estimated distance to the FP64 computation (dme_result_info). */
 typedef enum { DME_FP64 = 0, DME_MIXED = 1 } dme_precision;
 
 /* How e^{tA^T} L is applied in the T1 / T12 products:

@@ -134,6 +134,7 @@ struct Solver {
   double expm_ms = 0.0, quad_ms = 0.0;
   int64_t rank_quad = 0;
   int64_t nprod = 0;  // products e^{tA^T} L applied so far
+  double quad_delta = 0.0;  // relative error of split-BF16 quadrature node products (DME_MIXED)
 
   int profiling = 0;  // 0 off, 1 every phase, 2 the step product kernel alone
   hipEvent_t mark_phase() { return profiling == 1 ? mark_begin() : nullptr; }

@@ -453,23 +453,52 @@ void Solver::build_quadrature(double t) {
     ws.reset();
     leja_apply(s, *lop, *plan, Wd, n, kq, Wd, n, ws);
     DME_HIP(hipStreamSynchronize(s));  // the plan's device coefficients go with it
-  } else if ((int)op.nodes.size() == K) {
-    for (int q = 0; q < K; ++q) {
-      ws.reset();
-      gemm_f64(s, 'N', 'N', n, p, n, 1.0, op.nodes[q].as<double>(), n, CT.as<double>(), n, 0.0,
-               Wd + (int64_t)q * p * n, n, &ws);
-    }
   } else {
-    DME_REQUIRE(ATp != nullptr, DME_EINTERNAL, "quadrature factor needs the operator or its nodes");
-    DevBuf Ek((size_t)n * n * sizeof(double));
-    Arena ews;
-    ews.reserve(expm_workspace(n));
-    for (int q = 0; q < K; ++q) {
-      ews.reset();
-      expm_f64(s, n, ATp, nodes[q], Ek.as<double>(), ews, nullptr, nullptr, flag_dev() + 1);
-      ews.reset();
-      gemm_f64(s, 'N', 'N', n, p, n, 1.0, Ek.as<double>(), n, CT.as<double>(), n, 0.0,
-               Wd + (int64_t)q * p * n, n, &ews);
+    // dense node operators e^{s_k A^T}: the products e^{s_k A^T} C^T in FP64,
+    // or in DME_MIXED through the split-BF16 product (an FP32 copy of each
+    // node operator); the first node's product is also formed in FP64 there,
+    // and its relative distance enters the error estimate
+    const bool mixedq = opts.precision == DME_MIXED;
+    std::shared_ptr<MixedOp> mq = mixedq ? mixed_op_new() : nullptr;
+    Arena qa;  // the node products (and, in DME_MIXED, the first one's FP64 twin)
+    qa.reserve(gemm_f64_workspace(n, p, n) + (mixedq ? gemm_mixed_workspace(n, p) : 0) +
+               (size_t)n * p * sizeof(double) + diff_norms_workspace() + 16384);
+    auto node_product = [&](const double* Ek, int q) {
+      double* dst = Wd + (int64_t)q * p * n;
+      qa.reset();
+      if (!mixedq) {
+        gemm_f64(s, 'N', 'N', n, p, n, 1.0, Ek, n, CT.as<double>(), n, 0.0, dst, n, &qa);
+        return;
+      }
+      mixed_op_build(s, n, Ek, *mq);
+      gemm_mixed(s, *mq, CT.as<double>(), n, p, dst, n, qa);
+      if (q == 0) {
+        qa.reset();
+        double* y64 = qa.get<double>((size_t)n * p);
+        const size_t mark = qa.used;
+        gemm_f64(s, 'N', 'N', n, p, n, 1.0, Ek, n, CT.as<double>(), n, 0.0, y64, n, &qa);
+        qa.used = mark;
+        double* part = qa.get<double>(diff_norms_workspace() / sizeof(double));
+        double* out = qa.get<double>(2);
+        diff_norms_f64(s, dst, n, y64, n, n, p, part, out);
+        double h2[2] = {0.0, 0.0};
+        DME_HIP(hipMemcpyAsync(h2, out, sizeof(h2), hipMemcpyDeviceToHost, s));
+        DME_HIP(hipStreamSynchronize(s));
+        quad_delta = std::max(quad_delta, h2[1] > 0.0 ? std::sqrt(h2[0] / h2[1]) : 0.0);
+      }
+    };
+    if ((int)op.nodes.size() == K) {
+      for (int q = 0; q < K; ++q) node_product(op.nodes[q].as<double>(), q);
+    } else {
+      DME_REQUIRE(ATp != nullptr, DME_EINTERNAL, "quadrature factor needs the operator or its nodes");
+      DevBuf Ek((size_t)n * n * sizeof(double));
+      Arena ews;
+      ews.reserve(expm_workspace(n));
+      for (int q = 0; q < K; ++q) {
+        ews.reset();
+        expm_f64(s, n, ATp, nodes[q], Ek.as<double>(), ews, nullptr, nullptr, flag_dev() + 1);
+        node_product(Ek.as<double>(), q);
+      }
     }
   }
   double* Dh = Dhat.as<double>();
@@ -659,7 +688,9 @@ double Solver::err_estimate() {
   for (const auto& kv : ops)
     if (kv.second->plan) action = std::max(action, 1e-14 * kv.second->plan->S);
   const double per_product = std::max({delta, action, std::sqrt((double)n) * u});
-  return 2.0 * (double)nprod * per_product;
+  // a quadrature factor formed by split-BF16 products adds its relative error
+  // with every application of the quadrature term (at most one per product)
+  return 2.0 * (double)nprod * per_product + (double)nprod * quad_delta;
 }
 
 void Solver::run_stage(size_t i, bool ext_product) {

@@ -81,6 +81,28 @@ def test_dre_nonsymmetric_A_with_P0(ctx, n):
     check(ctx, p)
 
 
+@pytest.mark.parametrize("n", [200, 1030])
+def test_dre_nonsymmetric_mixed(ctx, n):
+    """DME_MIXED with a nonsymmetric A: the quadrature node products
+    e^{s_k A^T} C^T go through the split-BF16 product as well as the step
+    products; within 1e-6 of the oracle, and the stated estimate bounds the
+    measured distance."""
+    A = wl.random_nonsymmetric(n, seed=3, scale=5.0)
+    C = wl.random_C(3, n, seed=4)
+    p = wl.Problem(name="nonsym mixed", A=A, C=C, B=wl.random_C(2, n, seed=7).T.copy(order="F"),
+                   R=np.diag([1.0, 2.0]), T=0.05, h=5e-3, tol=1e-12)
+    announce(p.name, "n", n)
+    opts = b.SolveOptions(T=p.T, h=p.h, tol=p.tol, scheme=p.scheme, split=p.split,
+                          quad_nodes=p.quad_nodes, precision="mixed")
+    L, D, steps, est = ctx.solve(p.kind, opts, p.A, p.C, B=p.B, R=p.R, err_est=True)
+    Lo, Do, info = run_oracle(p)
+    assert steps == info["steps"]
+    err = oracle.lowrank_rel_err(L, D, Lo, Do)
+    print(f"  rank gpu {L.shape[1]} oracle {Lo.shape[1]} rel err {err:.3e} err_est {est:.3e}", flush=True)
+    assert err < 1e-6
+    assert err <= est < 1e-3
+
+
 def test_stepwise_equals_whole_solve(ctx):
     p = wl.config_dre_halfplane(nx=8, h=1e-2)
     announce("stepwise")
