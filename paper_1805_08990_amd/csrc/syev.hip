@@ -88,23 +88,34 @@ __device__ __forceinline__ double rs_dpp(double a, double b, bool hi) {
   const double send = hi ? a : b;  // what the partner keeps
   return (hi ? b : a) + dpp_mov_f64<CTRL>(send);
 }
-// Row sums of an RT-row tile (RT <= 8) over the 32 lanes of a half-wave: on
-// return lane c holds the sum of row c >> 2 (zero for c >> 2 >= RT).
+// Row sums of an RT-row tile (RT <= 16) over the 32 lanes of a half-wave: on
+// return lane c holds the sum of row c / (32 / S) for S = 8 slots (RT <= 8)
+// or 16 slots, zero for the slots past RT.
 template <int RT>
 __device__ __forceinline__ double tile_row_sums(const double (&sp)[RT], int c) {
-  static_assert(RT <= 8, "rows per tile");
-  double x[8];
+  static_assert(RT <= 16, "rows per tile");
+  constexpr int S = (RT <= 8) ? 8 : 16;
+  double x[S];
 #pragma unroll
-  for (int u = 0; u < 8; ++u) x[u] = (u < RT) ? sp[u] : 0.0;
-  double y[4], z[2];
+  for (int u = 0; u < S; ++u) x[u] = (u < RT) ? sp[u] : 0.0;
+  double y[S / 2];
 #pragma unroll
-  for (int t = 0; t < 4; ++t) y[t] = rs16(x[t], x[t + 4]);          // bit 4 picks t or t + 4
+  for (int t = 0; t < S / 2; ++t) y[t] = rs16(x[t], x[t + S / 2]);  // bit 4 picks t or t + S/2
   const bool b3 = (c >> 3) & 1, b2 = (c >> 2) & 1;
+  double z[S / 4];
 #pragma unroll
-  for (int t = 0; t < 2; ++t) z[t] = rs_dpp<kDppRor8>(y[t], y[t + 2], b3);  // bit 3: + 2
-  double w = rs_dpp<kDppHalfMirror>(z[0], z[1], b2);                    // bit 2: + 1
-  w += dpp_mov_f64<kDppXor1>(w);
-  return w + dpp_mov_f64<kDppXor2>(w);
+  for (int t = 0; t < S / 4; ++t) z[t] = rs_dpp<kDppRor8>(y[t], y[t + S / 4], b3);  // bit 3
+  double w[S / 8];
+#pragma unroll
+  for (int t = 0; t < S / 8; ++t) w[t] = rs_dpp<kDppHalfMirror>(z[t], z[t + S / 8], b2);  // bit 2
+  double v;
+  if constexpr (S == 16) {
+    v = rs_dpp<kDppXor2>(w[0], w[1], (c >> 1) & 1);  // bit 1
+  } else {
+    v = w[0];
+    v += dpp_mov_f64<kDppXor2>(v);
+  }
+  return v + dpp_mov_f64<kDppXor1>(v);
 }
 // sp[u] = sum over m >= M0 of a[u][m] x[m], for the first live chunk m0
 // (uniform) taken as a compile-time start by dispatch, so that the skipped
@@ -200,28 +211,34 @@ __device__ inline void tri_bounds_block(const double* sd, const double* se, int 
 // Householder tridiagonalisation with the whole matrix in registers, in
 // RT x NC tiles: the 32 lanes of a half-wave share the rows RT h .. RT h + RT - 1
 // (h = 2 wave + half) and lane c of them holds the columns c + 32 m (m < NC),
-// so a half-wave holds whole rows.  Because A is symmetric, row q is column q:
-// the half-wave holding row q forms the reflector of step q from it (norms by
-// half-wave sums) and puts v and tau in LDS.  A step then takes two barriers:
-// after the row sums p = tau A v (a reduce-scatter over the 32 lanes, after
-// which lane c holds the sum of row c / 4) and the per-wave parts of p^T v
-// reach LDS, and after the rank-2 update A -= v w^T + w v^T,
-// w = p - (tau/2)(p^T v) v, has brought the next reflector.  Between the
-// barriers every wave runs the same phase, so a step costs the VALU work of
-// the waves that share a SIMD (about 2.25 us at k = 178 on 12 waves).  The
-// reflector of step j goes to A(j+2:, j) and d, e, tau as in tridiag_kernel.
+// so a half-wave holds whole rows.  Step j takes two barriers:
+//   product phase: p = tau A v by row sums (a reduce-scatter over the 32
+//     lanes), the per-wave parts of p^T v, and column j + 1 as it stands
+//     (by symmetry the lane q & 31 of every half-wave holds its rows), all to
+//     LDS;
+//   update phase: every wave applies A -= v w^T + w v^T,
+//     w = p - (tau/2)(p^T v) v, to its tiles, while wave 0 forms the
+//     reflector of step j + 1 from the column in LDS with the same update
+//     applied to it (so the reflector does not wait for the owner of the row).
+// The product and the update are issue-bound on the SIMDs' FP64 VALU; the
+// reflector (a wave sum, a reciprocal square root and a reciprocal) runs
+// beside the update.  The reflector of step j goes to A(j+2:, j) and d, e,
+// tau as in tridiag_kernel.
 template <int NC, int RT>
 __global__ __launch_bounds__(32 * 32 * NC / RT) void tridiag_tiles_kernel(double* A, int64_t lda, int k,
                                                                           double* d, double* e, double* tau,
                                                                           double* e2, double* bounds) {
   constexpr int KM = 32 * NC;        // largest k
   constexpr int NW = KM / (2 * RT);  // waves: two RT-row tiles each
-  static_assert(KM % (2 * RT) == 0 && NW <= 16, "whole waves, at most 16");
-  __shared__ double vbuf[2][KM];  // reflector of step j in vbuf[j & 1]
+  static_assert(KM % (2 * RT) == 0 && NW <= 16 && RT % 2 == 0, "whole waves, at most 16, row pairs");
+  constexpr int NC2 = (KM + 63) / 64;  // entries per lane of wave 0 when it forms a reflector
+  constexpr int KP = 64 * NC2;
+  __shared__ double vbuf[2][KP];  // reflector of step j in vbuf[j & 1]
   __shared__ double tjs[2];       // and its tau
-  __shared__ double pb[KM];
+  __shared__ double pb[KP];       // p
+  __shared__ double cb[KP];       // column j + 1 before the update of step j
   __shared__ double wpart[NW];
-  __shared__ double sd[KM], se[KM];  // d and e as published, for the bounds at the end
+  __shared__ double sd[KM], se[KM];  // d and e as formed, for the bounds at the end
   const int t = threadIdx.x;
   const int lane = t & 63, wv = t >> 6;
   const int c = lane & 31;
@@ -237,101 +254,149 @@ __global__ __launch_bounds__(32 * 32 * NC / RT) void tridiag_tiles_kernel(double
 #pragma unroll
     for (int m = 0; m < NC; ++m) a[u][m] = (i < k && c + 32 * m < k) ? Ai[32 * m] : 0.0;
   }
-  // Row q (held by this half-wave) as it stands: d[q], and the reflector of
-  // step q (q + 2 < k) or the last 2 x 2 block (q = k - 2).
-  auto publish = [&](int q) {
-    const int uu = q - rbase;
-    double xr[NC];
+  // Reflector of step q (by wave 0) from column q as it stands, entries
+  // l = lane + 64 m in y, with its diagonal entry dq and subdiagonal entry
+  // alpha; q = k - 2 leaves the last 2 x 2 block.  With S = alpha^2 + s2,
+  // r = 1/sqrt(S) and n = S r: beta = -sign(alpha) n,
+  // tau = (beta - alpha)/beta = 1 + |alpha| r and
+  // 1/(alpha - beta) = sign(alpha)/(|alpha| + n), the reciprocal square root
+  // and the reciprocal from the hardware estimates by two Newton steps each.
+  auto form = [&](int q, const double (&y)[NC2], double dq, double alpha) {
+    const bool refl = q + 2 < k;
+    double s2 = 0.0;
 #pragma unroll
-    for (int m = 0; m < NC; ++m) xr[m] = 0.0;
-#pragma unroll
-    for (int u = 0; u < RT; ++u)
-      if (u == uu) {
-#pragma unroll
-        for (int m = 0; m < NC; ++m) xr[m] = a[u][m];
-      }
-    double s2 = 0.0, al = 0.0;
-#pragma unroll
-    for (int m = 0; m < NC; ++m) {
-      const int l = c + 32 * m;
-      if (l >= q + 2 && l < k) s2 += xr[m] * xr[m];
-      if (l == q + 1) al = xr[m];
-      if (l == q) {
-        d[q] = xr[m];
-        sd[q] = xr[m];
-      }
+    for (int m = 0; m < NC2; ++m) {
+      const int l = lane + 64 * m;
+      s2 += (l >= q + 2 && l < k) ? y[m] * y[m] : 0.0;
     }
-    const double alpha = half_wave_sum_f64(al);  // one nonzero term: exact
-    if (q + 2 < k) {
-      s2 = half_wave_sum_f64(s2);
-      double beta = alpha, tj = 0.0, sc = 0.0;
-      if (s2 != 0.0) {
-        beta = -copysign(sqrt(alpha * alpha + s2), alpha);
-        tj = (beta - alpha) / beta;
-        sc = 1.0 / (alpha - beta);
-      }
-      if (c == 0) {
-        e[q] = beta;
-        se[q] = beta;
-        tau[q] = tj;
-        tjs[q & 1] = tj;
-      }
+    s2 = wave_sum_f64(s2);
+    double beta = alpha, tq = 0.0, sc = 0.0;
+    if (refl && s2 != 0.0) {
+      const double S = fma(alpha, alpha, s2), hS = 0.5 * S;
+      double r = __builtin_amdgcn_rsq(S);
+      r = r * fma(-hS * r, r, 1.5);
+      r = r * fma(-hS * r, r, 1.5);
+      const double n = S * r, aa = fabs(alpha);
+      beta = -copysign(n, alpha);
+      tq = fma(aa, r, 1.0);
+      const double den = aa + n;
+      double ri = __builtin_amdgcn_rcp(den);
+      ri = fma(ri, fma(-den, ri, 1.0), ri);
+      ri = fma(ri, fma(-den, ri, 1.0), ri);
+      sc = copysign(ri, alpha);
+    }
+    double vv[NC2];
 #pragma unroll
-      for (int m = 0; m < NC; ++m) {
-        const int l = c + 32 * m;
-        const bool below = l > q + 1 && l < k;
-        const double v = (l == q + 1) ? 1.0 : (below ? sc * xr[m] : 0.0);
-        vbuf[q & 1][l] = v;
-        if (below && tj != 0.0) A[l + (int64_t)q * lda] = v;
+    for (int m = 0; m < NC2; ++m) {
+      const int l = lane + 64 * m;
+      vv[m] = (l == q + 1) ? 1.0 : ((l > q + 1 && l < k) ? sc * y[m] : 0.0);
+    }
+    if (refl) {
+#pragma unroll
+      for (int m = 0; m < NC2; ++m) vbuf[q & 1][lane + 64 * m] = vv[m];
+    }
+    if (lane == 0) {
+      d[q] = dq;
+      sd[q] = dq;
+      e[q] = beta;
+      se[q] = beta;
+      tau[q] = tq;
+      if (refl) tjs[q & 1] = tq;
+    }
+    if (tq != 0.0) {
+#pragma unroll
+      for (int m = 0; m < NC2; ++m) {
+        const int l = lane + 64 * m;
+        if (l > q + 1 && l < k) A[l + (int64_t)q * lda] = vv[m];
       }
-    } else if (c == 0) {
-      e[q] = alpha;
-      se[q] = alpha;
-      tau[q] = 0.0;
     }
   };
-  if (rbase == 0) publish(0);
+  if (c == 0) {  // column 0 (every half-wave its rows)
+#pragma unroll
+    for (int u = 0; u < RT; ++u) cb[rbase + u] = a[u][0];
+  }
+  __syncthreads();
+  if (wv == 0) {
+    double y0[NC2];
+#pragma unroll
+    for (int m = 0; m < NC2; ++m) y0[m] = cb[lane + 64 * m];
+    form(0, y0, cb[0], k > 1 ? cb[1] : 0.0);
+  }
   __syncthreads();
   for (int j = 0; j + 2 < k; ++j) {
-    const int r0 = j + 1;
+    const int r0 = j + 1, q = j + 1;
+    const int mq = q >> 5;  // chunk of column q (chunks m < mq lie before the trailing part)
     const double tj = tjs[j & 1];
-    if (tj != 0.0) {  // uniform across the workgroup
-      const double* v = vbuf[j & 1];
-      const int m0 = r0 >> 5;  // chunks m < m0 lie before the trailing part (v zero there)
+    const double* v = vbuf[j & 1];
+    const bool live = wrow_last >= r0;  // wave-uniform
+    if (tj != 0.0) {                    // uniform across the workgroup
       double vC[NC];
 #pragma unroll
       for (int m = 0; m < NC; ++m) vC[m] = v[c + 32 * m];
-      const bool live = wrow_last >= r0;  // wave-uniform
-      const int srow = c >> 2;            // the row whose sum this lane gets
-      double pu = 0.0;                    // p of row rbase + srow (zero before the trailing part)
+      constexpr int SL = (RT <= 8) ? 4 : 2;  // lanes per row sum
+      const int srow = c / SL;               // the row whose sum this lane gets
+      double pu = 0.0;                       // p of row rbase + srow (zero before the trailing part)
       if (live) {
         double sp[RT];
-        tile_matvec<NC, RT>(m0, a, vC, sp);
+        tile_matvec<NC, RT>(mq, a, vC, sp);
         const double sum = tile_row_sums<RT>(sp, c);
         const int i = rbase + srow;
         pu = (srow < RT && i >= r0 && i < k) ? tj * sum : 0.0;
       }
-      const bool lead = (c & 3) == 0;     // one lane per row
+      const bool lead = (c % SL) == 0;  // one lane per row
       if (lead && srow < RT) pb[rbase + srow] = pu;
       const double vs = (srow < RT) ? v[rbase + min(srow, RT - 1)] : 0.0;
       const double pv = wave_sum_f64(lead ? pu * vs : 0.0);  // both half-waves
       if (lane == 0) wpart[wv] = pv;
-      __syncthreads();
+    }
+    if (live && c == (q & 31)) {
+#pragma unroll
+      for (int m = 0; m < NC; ++m)
+        if (m == mq) {
+#pragma unroll
+          for (int u = 0; u < RT; ++u) cb[rbase + u] = a[u][m];
+        }
+    }
+    __syncthreads();
+    double Kc = 0.0;
+    if (tj != 0.0) {
       constexpr int G = NW <= 4 ? 4 : (NW <= 8 ? 8 : 16);  // NW <= 16
       const int gi = lane & (G - 1);
       const double pvt = group_sum_f64<G>(gi < NW ? wpart[gi] : 0.0);
-      const double Kc = 0.5 * tj * pvt;
-      if (live) {
-        double vC2[NC], wC[NC];
-#pragma unroll
-        for (int m = 0; m < NC; ++m) {
-          vC2[m] = v[c + 32 * m];  // read again rather than held across the barrier
-          wC[m] = pb[c + 32 * m] - Kc * vC2[m];
-        }
-        tile_rank2<NC, RT>(a, v + rbase, pb + rbase, Kc, vC2, wC);
-      }
+      Kc = 0.5 * tj * pvt;
     }
-    if (r0 >= rbase && r0 < rbase + RT) publish(r0);
+    if (wv == 0) {
+      // column q after step j: y_l = x_l - v_l w_q - w_l v_q with v_q = 1
+      // (the entry (l, q) of the tile update); unchanged when the step had no
+      // reflector.  Every load is issued before the arithmetic.
+      const bool upd = tj != 0.0;
+      const double pq = pb[q], vq1 = v[q + 1], pq1 = pb[q + 1], cq = cb[q], cq1 = cb[q + 1];
+      double xl[NC2], vl[NC2], pl[NC2];
+#pragma unroll
+      for (int m = 0; m < NC2; ++m) {
+        const int l = lane + 64 * m;
+        xl[m] = cb[l];
+        vl[m] = v[l];
+        pl[m] = pb[l];
+      }
+      const double wq = pq - Kc, wq1 = pq1 - Kc * vq1;
+      const double dq = upd ? fma(-1.0, wq, fma(-wq, 1.0, cq)) : cq;
+      const double alpha = upd ? fma(-vq1, wq, fma(-wq1, 1.0, cq1)) : cq1;
+      double y[NC2];
+#pragma unroll
+      for (int m = 0; m < NC2; ++m)
+        y[m] = upd ? fma(-vl[m], wq, fma(-(pl[m] - Kc * vl[m]), 1.0, xl[m])) : xl[m];
+      form(q, y, dq, alpha);
+    }
+    if (tj != 0.0 && live) {
+      double vC2[NC], wC[NC];
+#pragma unroll
+      for (int m = 0; m < NC; ++m) {
+        vC2[m] = v[c + 32 * m];  // read again rather than held across the barrier
+        wC[m] = pb[c + 32 * m] - Kc * vC2[m];
+      }
+      tile_rank2<NC, RT>(a, v + rbase, pb + rbase, Kc, vC2, wC);
+    }
     __syncthreads();
   }
   // the last diagonal entry
@@ -1430,7 +1495,7 @@ void syev_trunc_f64(hipStream_t s, int64_t k, const double* M, int64_t ldm, doub
     } else if (k <= 160) {
       hipLaunchKernelGGL((tridiag_tiles_kernel<5, 8>), dim3(1), dim3(640), 0, s, A, k, ki, d, e, tau, e2, bounds);
     } else if (k <= 192) {
-      hipLaunchKernelGGL((tridiag_tiles_kernel<6, 8>), dim3(1), dim3(768), 0, s, A, k, ki, d, e, tau, e2, bounds);
+      hipLaunchKernelGGL((tridiag_tiles_kernel<6, 12>), dim3(1), dim3(512), 0, s, A, k, ki, d, e, tau, e2, bounds);
     } else if (k <= kTriMaxK) {
       const size_t lds = (size_t)(3 + kTriT / 64) * k * sizeof(double);
       hipLaunchKernelGGL(tridiag_small_kernel, dim3(1), dim3(kTriT), lds, s, A, k, ki, d, e, tau);
