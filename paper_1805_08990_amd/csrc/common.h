@@ -308,10 +308,10 @@ int64_t compress_gram_f64(hipStream_t s, int64_t n, int64_t k, const double* W, 
                           double tol, int64_t max_rank, double* L, int64_t ldl, double* Dout, int64_t ldd,
                           int64_t* rank_dev, int* flag_dev, Arena& ws, int64_t rank_hint = 0);
 // A device int64 to the host through the bound auxiliary stream's pinned slot:
-// launch() enqueues the copy on s and returns its sequence number, wait()
-// polls for it (falling back to a stream synchronisation), rank_to_host() does
-// both.
-int64_t value_to_host_launch(hipStream_t s, const int64_t* src);
+// launch() enqueues the copy on s and returns its sequence number (the value
+// sent is -1 instead when *veto is nonzero), wait() polls for it (falling back
+// to a stream synchronisation), rank_to_host() does both.
+int64_t value_to_host_launch(hipStream_t s, const int64_t* src, const int64_t* veto = nullptr);
 int64_t value_to_host_wait(hipStream_t s, int64_t seq);
 inline int64_t rank_to_host(hipStream_t s, const int64_t* rank_dev) {
   return value_to_host_wait(s, value_to_host_launch(s, rank_dev));

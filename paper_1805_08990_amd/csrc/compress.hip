@@ -61,9 +61,11 @@ __global__ void diag_kernel(const double* lam, int64_t r, double* D, int64_t ldd
 // bound auxiliary stream: one thread copies it and then bumps the slot's
 // sequence number, and the host polls that number (a stream synchronisation
 // sleeps, which costs tens of microseconds of idle device time per call).
-__global__ void rank_to_host_kernel(const int64_t* __restrict__ src, AuxStream::Slot* slot, int64_t seq) {
+__global__ void rank_to_host_kernel(const int64_t* __restrict__ src, const int64_t* __restrict__ veto,
+                                    AuxStream::Slot* slot, int64_t seq) {
   if (threadIdx.x == 0) {
-    const int64_t v = *(volatile const int64_t*)src;
+    int64_t v = *(volatile const int64_t*)src;
+    if (veto && *(volatile const int64_t*)veto != 0) v = -1;
     __hip_atomic_store(&slot->value, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
     __hip_atomic_store(&slot->seq, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
   }
@@ -71,10 +73,10 @@ __global__ void rank_to_host_kernel(const int64_t* __restrict__ src, AuxStream::
 
 }  // namespace
 
-int64_t value_to_host_launch(hipStream_t s, const int64_t* src) {
+int64_t value_to_host_launch(hipStream_t s, const int64_t* src, const int64_t* veto) {
   AuxStream& ax = aux_stream();
   const int64_t seq = ++ax.seq;
-  hipLaunchKernelGGL(rank_to_host_kernel, dim3(1), dim3(64), 0, s, src, ax.slot, seq);
+  hipLaunchKernelGGL(rank_to_host_kernel, dim3(1), dim3(64), 0, s, src, veto, ax.slot, seq);
   DME_HIP(hipGetLastError());
   return seq;
 }

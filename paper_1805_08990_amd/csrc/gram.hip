@@ -202,62 +202,65 @@ __global__ void sqrt_diag_kernel(int k, const double* Dhat, int64_t ldd, double*
 }
 
 // F for a Dhat whose D blocks are diag(lam) - t Z Z^T (see LowRankD), one
-// workgroup: Zh = sqrt(t) Lam^-1/2 Z and G = Zh^T Zh (m x m) in LDS, G = U g U^T
-// by cyclic Jacobi in one thread (m <= 8), K = U diag(1 / (1 + sqrt(1 - g))) U^T,
-// M = Zh K, then F_D(i, j) = sqrt(lam_i) (delta_ij - M(i, :) Zh(j, :)^T) in
+// workgroup: Zh = sqrt(t) Lam^-1/2 Z and G = Zh^T Zh (m x m, one lane per
+// entry) in LDS, G = U g U^T by cyclic Jacobi in registers of one thread
+// (m = M <= 8 at compile time), K = U diag(1 / (1 + sqrt(1 - g))) U^T,
+// Mz = Zh K, then F_D(i, j) = sqrt(lam_i) (delta_ij - Mz(i, :) Zh(j, :)^T) in
 // every D block and sqrt(Dhat_ii) on the rest of the diagonal.  lam <= 0,
 // g >= 1 or a non-positive diagonal entry make *status = -1 (and F zero).
 constexpr int kLrMaxM = 8;
 constexpr int kLrMaxR = 256;
+constexpr int kLrT = 256;
 
-__global__ __launch_bounds__(1024) void lowrank_factor_kernel(int k, const double* Dhat, int64_t lddh,
-                                                             const double* lam, const double* Z, double t,
-                                                             int r, int m, int ncopies, double* F,
-                                                             int64_t* status) {
-  __shared__ double Zh[kLrMaxR][kLrMaxM];
-  __shared__ double Mz[kLrMaxR][kLrMaxM];
+template <int M>
+__global__ __launch_bounds__(kLrT) void lowrank_factor_kernel(int k, const double* Dhat, int64_t lddh,
+                                                              const double* lam, const double* Z, double t,
+                                                              int r, int ncopies, double* F, int64_t* status) {
+  static_assert(M >= 1 && M <= kLrMaxM, "m");
+  __shared__ double Zh[kLrMaxR][M];
+  __shared__ double Mz[kLrMaxR][M];
   __shared__ double sl[kLrMaxR];
-  __shared__ double part[16][kLrMaxM * kLrMaxM];
-  __shared__ double G[kLrMaxM][kLrMaxM], U[kLrMaxM][kLrMaxM], K[kLrMaxM][kLrMaxM];
+  __shared__ double Gs[M * M];
+  __shared__ double Ks[M][M];
   __shared__ int bad;
   const int tid = threadIdx.x;
   if (tid == 0) bad = 0;
   __syncthreads();
   const double st = sqrt(t);
-  for (int i = tid; i < r; i += 1024) {
+  for (int i = tid; i < r; i += kLrT) {
     const double l = lam[i];
     if (!(l > 0.0) || !isfinite(l)) bad = 1;
     const double s = (l > 0.0) ? sqrt(l) : 1.0;
     sl[i] = s;
-    for (int a = 0; a < m; ++a) Zh[i][a] = st * Z[i + (int64_t)a * r] / s;
+#pragma unroll
+    for (int a = 0; a < M; ++a) Zh[i][a] = st * Z[i + (int64_t)a * r] / s;
   }
   __syncthreads();
-  // G = Zh^T Zh: 16 slices of the rows per entry, then the slices in order
-  {
-    const int mm = m * m, e = tid % 64, sli = tid / 64;
+  if (tid < M * M) {  // G = Zh^T Zh, entry (a, b) by lane a + M b
+    const int a = tid % M, b = tid / M;
     double acc = 0.0;
-    if (e < mm) {
-      const int a = e % m, b = e / m;
-      for (int i = sli; i < r; i += 16) acc += Zh[i][a] * Zh[i][b];
-    }
-    if (e < kLrMaxM * kLrMaxM) part[sli][e] = acc;
+    for (int i = 0; i < r; ++i) acc = fma(Zh[i][a], Zh[i][b], acc);
+    Gs[tid] = acc;
   }
   __syncthreads();
   if (tid == 0) {
-    for (int a = 0; a < m; ++a)
-      for (int b = 0; b < m; ++b) {
-        double v = 0.0;
-        for (int q = 0; q < 16; ++q) v += part[q][a + b * m];
-        G[a][b] = v;
+    double G[M][M], U[M][M];
+#pragma unroll
+    for (int a = 0; a < M; ++a)
+#pragma unroll
+      for (int b = 0; b < M; ++b) {
+        G[a][b] = Gs[a + b * M];
         U[a][b] = (a == b) ? 1.0 : 0.0;
       }
-    // cyclic Jacobi on the symmetric m x m G; a rotation zeroes its pair
+    // cyclic Jacobi on the symmetric M x M G; a rotation zeroes its pair
     // exactly, and pairs below 1e-17 sqrt(|G_pp G_qq|) are dropped, so the
     // sweeps end once every off-diagonal entry is at that level
     for (int sweep = 0; sweep < 30; ++sweep) {
       bool rotated = false;
-      for (int p = 0; p < m; ++p)
-        for (int q = p + 1; q < m; ++q) {
+#pragma unroll
+      for (int p = 0; p < M; ++p)
+#pragma unroll
+        for (int q = p + 1; q < M; ++q) {
           if (fabs(G[p][q]) <= 1e-17 * sqrt(fabs(G[p][p] * G[q][q]))) {
             G[p][q] = G[q][p] = 0.0;
             continue;
@@ -266,17 +269,20 @@ __global__ __launch_bounds__(1024) void lowrank_factor_kernel(int k, const doubl
           const double theta = (G[q][q] - G[p][p]) / (2.0 * G[p][q]);
           const double tn = copysign(1.0, theta) / (fabs(theta) + sqrt(theta * theta + 1.0));
           const double c = 1.0 / sqrt(tn * tn + 1.0), sn = tn * c;
-          for (int x = 0; x < m; ++x) {  // G <- J^T G J, U <- U J
+#pragma unroll
+          for (int x = 0; x < M; ++x) {  // G <- J^T G J, U <- U J
             const double gp = G[x][p], gq = G[x][q];
             G[x][p] = c * gp - sn * gq;
             G[x][q] = sn * gp + c * gq;
           }
-          for (int x = 0; x < m; ++x) {
+#pragma unroll
+          for (int x = 0; x < M; ++x) {
             const double gp = G[p][x], gq = G[q][x];
             G[p][x] = c * gp - sn * gq;
             G[q][x] = sn * gp + c * gq;
           }
-          for (int x = 0; x < m; ++x) {
+#pragma unroll
+          for (int x = 0; x < M; ++x) {
             const double up = U[x][p], uq = U[x][q];
             U[x][p] = c * up - sn * uq;
             U[x][q] = sn * up + c * uq;
@@ -285,42 +291,54 @@ __global__ __launch_bounds__(1024) void lowrank_factor_kernel(int k, const doubl
         }
       if (!rotated) break;
     }
-    double f[kLrMaxM];
-    for (int a = 0; a < m; ++a) {
+    double f[M];
+#pragma unroll
+    for (int a = 0; a < M; ++a) {
       const double g = G[a][a];
       if (!(g < 1.0) || !isfinite(g)) bad = 1;
       f[a] = 1.0 / (1.0 + sqrt(fmax(1.0 - g, 0.0)));
     }
-    for (int a = 0; a < m; ++a)
-      for (int b = 0; b < m; ++b) {
+#pragma unroll
+    for (int a = 0; a < M; ++a)
+#pragma unroll
+      for (int b = 0; b < M; ++b) {
         double v = 0.0;
-        for (int q = 0; q < m; ++q) v += U[a][q] * f[q] * U[b][q];
-        K[a][b] = v;
+#pragma unroll
+        for (int q = 0; q < M; ++q) v += U[a][q] * f[q] * U[b][q];
+        Ks[a][b] = v;
       }
   }
   __syncthreads();
-  for (int i = tid; i < r; i += 1024)
-    for (int a = 0; a < m; ++a) {
+  for (int i = tid; i < r; i += kLrT)
+#pragma unroll
+    for (int a = 0; a < M; ++a) {
       double v = 0.0;
-      for (int b = 0; b < m; ++b) v += Zh[i][b] * K[b][a];
+#pragma unroll
+      for (int b = 0; b < M; ++b) v += Zh[i][b] * Ks[b][a];
       Mz[i][a] = v;
     }
   // the rest of the diagonal
   const int nd = ncopies * r;
-  for (int i = nd + tid; i < k; i += 1024) {
+  for (int i = nd + tid; i < k; i += kLrT) {
     const double d = Dhat[i + (int64_t)i * lddh];
     if (!(d > 0.0) || !isfinite(d)) bad = 1;
   }
   __syncthreads();
   const bool ok = !bad;
-  for (int j = tid >> 6; j < k; j += 16)  // a wave per column
+  for (int j = tid >> 6; j < k; j += kLrT / 64) {  // a wave per column
+    const bool inblk = j < nd;                     // D block jb, rows i0 .. i0 + r - 1
+    const int jb = inblk ? j / r : 0, jj = j - jb * r, i0 = jb * r;
+    double zj[M];
+#pragma unroll
+    for (int a = 0; a < M; ++a) zj[a] = inblk ? Zh[jj][a] : 0.0;
     for (int i = tid & 63; i < k; i += 64) {
       double v = 0.0;
       if (ok) {
-        if (i < nd && j < nd && i / r == j / r) {
-          const int ii = i % r, jj = j % r;
+        if (inblk && i >= i0 && i < i0 + r) {
+          const int ii = i - i0;
           double acc = 0.0;
-          for (int a = 0; a < m; ++a) acc += Mz[ii][a] * Zh[jj][a];
+#pragma unroll
+          for (int a = 0; a < M; ++a) acc += Mz[ii][a] * zj[a];
           v = sl[ii] * ((ii == jj ? 1.0 : 0.0) - acc);
         } else if (i == j) {
           v = sqrt(Dhat[i + (int64_t)i * lddh]);
@@ -328,6 +346,7 @@ __global__ __launch_bounds__(1024) void lowrank_factor_kernel(int k, const doubl
       }
       F[i + (int64_t)j * k] = v;
     }
+  }
   if (tid == 0) *status = ok ? 0 : -1;
 }
 
@@ -402,25 +421,35 @@ int64_t compress_gram_f64(hipStream_t s, int64_t n, int64_t k, const double* W, 
   int64_t* status = ws.get<int64_t>(8);
   const size_t mark_g = ws.used;
 
-  // Dhat = F F^T; its status reaches the host while W^T W runs
+  // Dhat = F F^T on the second stream, beside W^T W on s.  A factor that
+  // fails (Dhat not positive definite) leaves F = 0, so what follows sees a
+  // zero matrix; its status vetoes the rank on its way to the host, which
+  // then returns -1 for the caller to compress by Householder QR.
+  AuxStream& ax = aux_stream();
+  DME_HIP(hipStreamWaitEvent(ax.s2, ax.record(s), 0));
   if (dhat_diag) {
-    hipLaunchKernelGGL(sqrt_diag_kernel, dim3(1), dim3(1024), 0, s, (int)k, Dhat, lddh, F, status);
-  } else if (lowrank && lowrank->m <= kLrMaxM && lowrank->r <= kLrMaxR && lowrank->ncopies * lowrank->r <= k) {
-    hipLaunchKernelGGL(lowrank_factor_kernel, dim3(1), dim3(1024), 0, s, (int)k, Dhat, lddh, lowrank->lam,
-                       lowrank->Z, lowrank->t, (int)lowrank->r, (int)lowrank->m, lowrank->ncopies, F, status);
+    hipLaunchKernelGGL(sqrt_diag_kernel, dim3(1), dim3(1024), 0, ax.s2, (int)k, Dhat, lddh, F, status);
+  } else if (lowrank && lowrank->m >= 1 && lowrank->m <= kLrMaxM && lowrank->r <= kLrMaxR && lowrank->ncopies * lowrank->r <= k) {
+    switch (lowrank->m) {
+#define DME_LRF(MM)                                                                                      \
+  case MM:                                                                                               \
+    hipLaunchKernelGGL(lowrank_factor_kernel<MM>, dim3(1), dim3(kLrT), 0, ax.s2, (int)k, Dhat, lddh,    \
+                       lowrank->lam, lowrank->Z, lowrank->t, (int)lowrank->r, lowrank->ncopies, F, status); \
+    break;
+      DME_LRF(1) DME_LRF(2) DME_LRF(3) DME_LRF(4) DME_LRF(5) DME_LRF(6) DME_LRF(7) DME_LRF(8)
+#undef DME_LRF
+      default: DME_REQUIRE(false, DME_EINTERNAL, "low-rank factor: m out of range");
+    }
   } else {
-    hipLaunchKernelGGL(copy_lower_kernel, dim3(blocks(k * k)), dim3(256), 0, s, (int)k, Dhat, lddh, F);
+    hipLaunchKernelGGL(copy_lower_kernel, dim3(blocks(k * k)), dim3(256), 0, ax.s2, (int)k, Dhat, lddh, F);
     DME_HIP(hipGetLastError());
-    hipLaunchKernelGGL(chol_lower_kernel, dim3(1), dim3(kCT), 0, s, (int)k, F, k, status);
+    hipLaunchKernelGGL(chol_lower_kernel, dim3(1), dim3(kCT), 0, ax.s2, (int)k, F, k, status);
   }
   DME_HIP(hipGetLastError());
-  const int64_t seq = value_to_host_launch(s, status);
+  const hipEvent_t f_done = ax.record(ax.s2);
   ws.used = mark_g;
   gemm_f64(s, 'T', 'N', k, k, n, 1.0, W, ldw, W, ldw, 0.0, G, k, &ws);
-  if (value_to_host_wait(s, seq) != 0) {
-    ws.used = mark;
-    return -1;  // Dhat is not positive definite: the caller compresses by Householder QR
-  }
+  DME_HIP(hipStreamWaitEvent(s, f_done, 0));
   // G <- F^T G F, symmetrised
   ws.used = mark_g;
   gemm_f64(s, 'N', 'N', k, k, k, 1.0, G, k, F, k, 0.0, T1, k, &ws);
@@ -431,7 +460,7 @@ int64_t compress_gram_f64(hipStream_t s, int64_t n, int64_t k, const double* W, 
   ws.used = mark_g;
   syev_trunc_f64(s, k, S, k, tol, std::min(max_rank, k), lam, V, k, rank_dev, flag_dev, ws);
   ws.used = mark_g;
-  const int64_t seq_rank = value_to_host_launch(s, rank_dev);
+  const int64_t seq_rank = value_to_host_launch(s, rank_dev, status);
   // L = W (F V_I Lam_I^-1/2), D = Lam_I: the products for a guessed width go
   // ahead of the rank's round trip to the host
   const int64_t kmax = std::min(max_rank, k);
@@ -449,7 +478,7 @@ int64_t compress_gram_f64(hipStream_t s, int64_t n, int64_t k, const double* W, 
   const int64_t rr = value_to_host_wait(s, seq_rank);
   if (rr <= 0) {
     ws.used = mark;
-    return 0;
+    return rr < 0 ? -1 : 0;  // -1: Dhat is not positive definite
   }
   if (rr > ks) form_L(rr);  // the guess fell short
   if (ldd <= 0) ldd = rr;

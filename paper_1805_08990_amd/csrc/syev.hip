@@ -21,7 +21,7 @@
 //      invit_kernel     : inverse iteration with a partially pivoted
 //                         tridiagonal LU for tied eigenvalues (and k > 512).
 //   5. polar steps      : clusters whose vectors are nearly orthonormal get
-//                         two Newton-Schulz steps Z <- Z (3I - Z^T Z) / 2 by
+//                         three Newton-Schulz steps Z <- Z (3I - Z^T Z) / 2 by
 //                         GEMMs (restricted to each cluster's block);
 //      orth_kernel      : one workgroup per remaining cluster orthonormalises
 //                         its vectors (right-looking modified Gram-Schmidt,
@@ -222,10 +222,11 @@ __device__ inline void tri_bounds_block(const double* sd, const double* se, int 
 //     applied to it (so the reflector does not wait for the owner of the row).
 // The product and the update are issue-bound on the SIMDs' FP64 VALU; the
 // reflector (a wave sum, a reciprocal square root and a reciprocal) runs
-// beside the update.  The reflector of step j goes to A(j+2:, j) and d, e,
-// tau as in tridiag_kernel.
+// beside the update.  The input Min is read once, into the registers; the
+// reflector of step j goes to A(j+2:, j) and d, e, tau as in tridiag_kernel.
 template <int NC, int RT>
-__global__ __launch_bounds__(32 * 32 * NC / RT) void tridiag_tiles_kernel(double* A, int64_t lda, int k,
+__global__ __launch_bounds__(32 * 32 * NC / RT) void tridiag_tiles_kernel(const double* Min, int64_t ldm,
+                                                                          double* A, int64_t lda, int k,
                                                                           double* d, double* e, double* tau,
                                                                           double* e2, double* bounds) {
   constexpr int KM = 32 * NC;        // largest k
@@ -245,14 +246,14 @@ __global__ __launch_bounds__(32 * 32 * NC / RT) void tridiag_tiles_kernel(double
   const int rbase = RT * (2 * wv + (lane >> 5));
   const int wrow_last = 2 * RT * wv + 2 * RT - 1;  // last row of this wave
   double a[RT][NC];
-  // entry (rbase + u, c + 32 m), read as A(c + 32 m, rbase + u) by symmetry so
-  // that the lanes of a half-wave read consecutive addresses
+  // entry (rbase + u, c + 32 m) of the input, read as Min(c + 32 m, rbase + u)
+  // by symmetry so that the lanes of a half-wave read consecutive addresses
 #pragma unroll
   for (int u = 0; u < RT; ++u) {
     const int i = rbase + u;
-    const double* Ai = A + (int64_t)i * lda + c;
+    const double* Mi = Min + (int64_t)i * ldm + c;
 #pragma unroll
-    for (int m = 0; m < NC; ++m) a[u][m] = (i < k && c + 32 * m < k) ? Ai[32 * m] : 0.0;
+    for (int m = 0; m < NC; ++m) a[u][m] = (i < k && c + 32 * m < k) ? Mi[32 * m] : 0.0;
   }
   // Reflector of step q (by wave 0) from column q as it stands, entries
   // l = lane + 64 m in y, with its diagonal entry dq and subdiagonal entry
@@ -1224,13 +1225,14 @@ __global__ __launch_bounds__(128) void twist_kernel(const double* __restrict__ d
 }
 
 // Polar (Newton-Schulz) orthonormalisation of the clusters, by GEMMs: with
-// G = Z^T Z, Z <- Z B, B = I + (same cluster ? (I - G) / 2 : 0), twice.  A
-// cluster whose vectors are nearly orthonormal (len * max |G - I| below
-// kPolarTol, the usual case: inverse-iteration and twisted vectors are off
-// by O(eps ||T|| / gap)) then has ||Z^T Z - I|| ~ (3/4)^3 kPolarTol^4, far
-// below roundoff; the others (cl_fail set) keep their vectors for modified
+// G = Z^T Z, Z <- Z B, B = I + (same cluster ? (I - G) / 2 : 0), three times.
+// A step takes e = ||Z^T Z - I|| to about (3/4) e^2, so a cluster whose
+// vectors are nearly orthonormal (len * max |G - I| below kPolarTol; the
+// vectors are off by O(eps ||T|| / gap)) ends below 1e-16 (1e-2, 7.5e-5,
+// 4.2e-9, 1.3e-17); the others (cl_fail set) keep their vectors for modified
 // Gram-Schmidt.  The polar factor mixes a cluster's vectors least.
-constexpr double kPolarTol = 1e-4;
+constexpr double kPolarTol = 1e-2;
+constexpr int kPolarSteps = 3;
 
 // cl_fail[id] |= 1 when a cluster's Gram matrix is not close enough to I.
 __global__ void polar_check_kernel(const double* G, int ncol, const int* cl_of, const int* clusters,
@@ -1481,7 +1483,8 @@ void syev_trunc_f64(hipStream_t s, int64_t k, const double* M, int64_t ldm, doub
   double* work = ws.get<double>((size_t)k * kInvitArrays * k);
   double* Zt = ws.get<double>((size_t)k * k);
 
-  copy_f64(s, M, ldm, A, k, k, k);
+  const bool tiles = k >= 2 && k <= 192;  // the register-tiled reduction reads M itself
+  if (!tiles) copy_f64(s, M, ldm, A, k, k, k);
   if (k == 1) {
     // trivial: d = M(0,0)
     copy_f64(s, A, 1, d, 1, 1, 1);
@@ -1489,13 +1492,17 @@ void syev_trunc_f64(hipStream_t s, int64_t k, const double* M, int64_t ldm, doub
     fill_f64(s, tau, 1, 1, 1, 0.0);
   } else {
     if (k <= 64) {
-      hipLaunchKernelGGL((tridiag_tiles_kernel<2, 8>), dim3(1), dim3(256), 0, s, A, k, ki, d, e, tau, e2, bounds);
+      hipLaunchKernelGGL((tridiag_tiles_kernel<2, 8>), dim3(1), dim3(256), 0, s, M, ldm, A, k, ki, d, e, tau,
+                         e2, bounds);
     } else if (k <= 128) {
-      hipLaunchKernelGGL((tridiag_tiles_kernel<4, 8>), dim3(1), dim3(512), 0, s, A, k, ki, d, e, tau, e2, bounds);
+      hipLaunchKernelGGL((tridiag_tiles_kernel<4, 8>), dim3(1), dim3(512), 0, s, M, ldm, A, k, ki, d, e, tau,
+                         e2, bounds);
     } else if (k <= 160) {
-      hipLaunchKernelGGL((tridiag_tiles_kernel<5, 8>), dim3(1), dim3(640), 0, s, A, k, ki, d, e, tau, e2, bounds);
+      hipLaunchKernelGGL((tridiag_tiles_kernel<5, 8>), dim3(1), dim3(640), 0, s, M, ldm, A, k, ki, d, e, tau,
+                         e2, bounds);
     } else if (k <= 192) {
-      hipLaunchKernelGGL((tridiag_tiles_kernel<6, 12>), dim3(1), dim3(512), 0, s, A, k, ki, d, e, tau, e2, bounds);
+      hipLaunchKernelGGL((tridiag_tiles_kernel<6, 12>), dim3(1), dim3(512), 0, s, M, ldm, A, k, ki, d, e, tau,
+                         e2, bounds);
     } else if (k <= kTriMaxK) {
       const size_t lds = (size_t)(3 + kTriT / 64) * k * sizeof(double);
       hipLaunchKernelGGL(tridiag_small_kernel, dim3(1), dim3(kTriT), lds, s, A, k, ki, d, e, tau);
@@ -1556,8 +1563,9 @@ void syev_trunc_f64(hipStream_t s, int64_t k, const double* M, int64_t ldm, doub
     hipLaunchKernelGGL(invit_kernel<false>, dim3(nkeep), dim3(64), 0, s, d, e, ki, lam, order, keep_dev,
                        bounds, work, Zt, k, ties_only);
   DME_HIP(hipGetLastError());
-  // clusters: two polar steps where the vectors are nearly orthonormal,
-  // modified Gram-Schmidt for the rest
+  // clusters: polar steps where the vectors are nearly orthonormal,
+  // modified Gram-Schmidt for the rest; the result ends in Zf
+  double* Zf = Zt;
   {
     const int nc = (int)nkeep;
     double* G = ws.get<double>((size_t)nc * nc);
@@ -1565,28 +1573,27 @@ void syev_trunc_f64(hipStream_t s, int64_t k, const double* M, int64_t ldm, doub
     double* Z1 = ws.get<double>((size_t)k * nc);
     const size_t mark = ws.used;
     const unsigned gb = (unsigned)std::max<int64_t>(1, std::min<int64_t>(cdiv((int64_t)nc * nc, 256), 1024));
-    gemm_f64(s, 'T', 'N', nc, nc, k, 1.0, Zt, k, Zt, k, 0.0, G, nc, &ws);
-    ws.used = mark;
-    hipLaunchKernelGGL(polar_check_kernel, dim3(gb), dim3(256), 0, s, G, nc, cl_of, clusters, cl_fail);
-    hipLaunchKernelGGL(polar_b_kernel, dim3(gb), dim3(256), 0, s, G, nc, cl_of, cl_fail, Bm);
-    DME_HIP(hipGetLastError());
-    gemm_f64(s, 'N', 'N', k, nc, nc, 1.0, Zt, k, Bm, nc, 0.0, Z1, k, &ws);
-    ws.used = mark;
-    gemm_f64(s, 'T', 'N', nc, nc, k, 1.0, Z1, k, Z1, k, 0.0, G, nc, &ws);
-    ws.used = mark;
-    hipLaunchKernelGGL(polar_b_kernel, dim3(gb), dim3(256), 0, s, G, nc, cl_of, cl_fail, Bm);
-    DME_HIP(hipGetLastError());
-    gemm_f64(s, 'N', 'N', k, nc, nc, 1.0, Z1, k, Bm, nc, 0.0, Zt, k, &ws);
-    ws.used = mark;
+    double* Zo = Z1;  // Zf -> Zo each step
+    for (int step = 0; step < kPolarSteps; ++step) {
+      gemm_f64(s, 'T', 'N', nc, nc, k, 1.0, Zf, k, Zf, k, 0.0, G, nc, &ws);
+      ws.used = mark;
+      if (step == 0)
+        hipLaunchKernelGGL(polar_check_kernel, dim3(gb), dim3(256), 0, s, G, nc, cl_of, clusters, cl_fail);
+      hipLaunchKernelGGL(polar_b_kernel, dim3(gb), dim3(256), 0, s, G, nc, cl_of, cl_fail, Bm);
+      DME_HIP(hipGetLastError());
+      gemm_f64(s, 'N', 'N', k, nc, nc, 1.0, Zf, k, Bm, nc, 0.0, Zo, k, &ws);
+      ws.used = mark;
+      std::swap(Zf, Zo);
+    }
     // cluster staging in LDS: up to 144 KiB, never more than the whole k x k set
     const int64_t orth_lds = std::min<int64_t>(k * k, (144 * 1024) / (int64_t)sizeof(double));
     hipLaunchKernelGGL(orth_kernel, dim3((unsigned)k), dim3(1024), (size_t)orth_lds * sizeof(double), s,
-                       ki, clusters, cl_count, pos_of, cl_fail, Zt, k, (int)orth_lds);
+                       ki, clusters, cl_count, pos_of, cl_fail, Zf, k, (int)orth_lds);
     DME_HIP(hipGetLastError());
   }
   // V = Q Z with Q formed beside the eigenvalue work
   DME_HIP(hipStreamWaitEvent(s, q_done, 0));
-  gemm_f64(s, 'N', 'N', k, (int64_t)nkeep, k, 1.0, Qm, k, Zt, k, 0.0, V_out, ldv, &ws);
+  gemm_f64(s, 'N', 'N', k, (int64_t)nkeep, k, 1.0, Qm, k, Zf, k, 0.0, V_out, ldv, &ws);
   hipLaunchKernelGGL(sign_columns_kernel, dim3(nkeep), dim3(64), 0, s, V_out, ldv, ki, keep_dev);
   DME_HIP(hipGetLastError());
 }

@@ -81,6 +81,19 @@ def test_dre_nonsymmetric_A_with_P0(ctx, n):
     check(ctx, p)
 
 
+@pytest.mark.parametrize("m", [1, 3, 5, 8])
+def test_dre_input_widths(ctx, m):
+    """m = 1 .. 8 input columns: every width of the compile-time factor of the
+    Riccati-updated D (the compression's D-hat), against the oracle."""
+    n = 144
+    A = wl.laplacian_2d(12)
+    C = wl.random_C(3, n, seed=11)
+    B = wl.random_C(m, n, seed=12).T.copy(order="F")
+    R = np.diag(1.0 + 0.25 * np.arange(m))
+    p = wl.Problem(name=f"dre m={m}", A=A, C=C, B=B, R=R, T=0.03, h=3e-3, tol=1e-12)
+    check(ctx, p)
+
+
 @pytest.mark.parametrize("n", [200, 1030])
 def test_dre_nonsymmetric_mixed(ctx, n):
     """DME_MIXED with a nonsymmetric A: the quadrature node products
