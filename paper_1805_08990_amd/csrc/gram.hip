@@ -370,22 +370,20 @@ __global__ void sym_kernel(int k, const double* G, double* S, int* flag) {
 }
 
 // T(:, j) /= sqrt(lam_j) for j < *rank, T(:, j) = 0 for rank <= j < r (the
-// columns past the kept rank may hold anything)
-__global__ void scale_cols_kernel(int k, int r, const double* lam, const int64_t* rank, double* T) {
+// columns past the kept rank may hold anything); and the columns j < min(r,
+// rank) of D = diag(lam) (rank x rank, ld ldd, or the rank when ldd is 0).
+// The grid covers k >= rank rows.
+__global__ void scale_cols_kernel(int k, int r, const double* lam, const int64_t* rank, double* T, double* D,
+                                  int64_t ldd) {
   const int64_t rk = *rank;
+  const int64_t ld = (ldd > 0) ? ldd : rk;
   for (int j = blockIdx.y; j < r; j += gridDim.y) {
     const double f = (j < rk) ? 1.0 / sqrt(lam[j]) : 0.0;
     for (int i = blockIdx.x * 256 + threadIdx.x; i < k; i += gridDim.x * 256) {
       double* t = T + i + (int64_t)j * k;
       *t = (j < rk) ? *t * f : 0.0;
+      if (j < rk && i < rk) D[i + j * ld] = (i == j) ? lam[j] : 0.0;
     }
-  }
-}
-
-__global__ void diag_out_kernel(const double* lam, int r, double* D, int64_t ldd) {
-  for (int64_t idx = blockIdx.x * 256 + threadIdx.x; idx < (int64_t)r * r; idx += (int64_t)gridDim.x * 256) {
-    const int i = (int)(idx % r), j = (int)(idx / r);
-    D[i + (int64_t)j * ldd] = (i == j) ? lam[i] : 0.0;
   }
 }
 
@@ -461,15 +459,15 @@ int64_t compress_gram_f64(hipStream_t s, int64_t n, int64_t k, const double* W, 
   syev_trunc_f64(s, k, S, k, tol, std::min(max_rank, k), lam, V, k, rank_dev, flag_dev, ws);
   ws.used = mark_g;
   const int64_t seq_rank = value_to_host_launch(s, rank_dev, status);
-  // L = W (F V_I Lam_I^-1/2), D = Lam_I: the products for a guessed width go
-  // ahead of the rank's round trip to the host
+  // L = W (F V_I Lam_I^-1/2), D = Lam_I: the products (and D) for a guessed
+  // width go ahead of the rank's round trip to the host
   const int64_t kmax = std::min(max_rank, k);
   const int64_t ks = (rank_hint > 0) ? std::min(kmax, rank_hint + 8) : kmax;
   auto form_L = [&](int64_t w) {
     gemm_f64(s, 'N', 'N', k, w, k, 1.0, F, k, V, k, 0.0, T, k, &ws);
     ws.used = mark_g;
     const dim3 sg(cdiv(k, 256), (unsigned)std::min<int64_t>(w, 1024));
-    hipLaunchKernelGGL(scale_cols_kernel, sg, dim3(256), 0, s, (int)k, (int)w, lam, rank_dev, T);
+    hipLaunchKernelGGL(scale_cols_kernel, sg, dim3(256), 0, s, (int)k, (int)w, lam, rank_dev, T, Dout, ldd);
     DME_HIP(hipGetLastError());
     gemm_f64(s, 'N', 'N', n, w, k, 1.0, W, ldw, T, k, 0.0, L, ldl, &ws);
     ws.used = mark_g;
@@ -480,10 +478,7 @@ int64_t compress_gram_f64(hipStream_t s, int64_t n, int64_t k, const double* W, 
     ws.used = mark;
     return rr < 0 ? -1 : 0;  // -1: Dhat is not positive definite
   }
-  if (rr > ks) form_L(rr);  // the guess fell short
-  if (ldd <= 0) ldd = rr;
-  hipLaunchKernelGGL(diag_out_kernel, dim3(blocks(rr * rr)), dim3(256), 0, s, lam, (int)rr, Dout, ldd);
-  DME_HIP(hipGetLastError());
+  if (rr > ks) form_L(rr);  // the guess fell short (D's remaining columns too)
   ws.used = mark;
   return rr;
 }
