@@ -1041,19 +1041,14 @@ __global__ __launch_bounds__(64) void invit_kernel(const double* d, const double
 // (T - lam I = N_r diag(..., gamma_r, ...) N_r^T twisted at r), and with
 // r = argmin |gamma_i|: z_r = 1, z_i = -e_i z_{i+1} / dp_i below the twist,
 // z_i = -e_{i-1} z_{i-1} / dm_i above it.  Two sweeps down and up instead of
-// a factorisation and repeated solves.  Row i of every k-vector sits in lane
-// i mod 64, slot i / 64 of the wave; the sweeps read the current row's values
-// with lane reads (no LDS), and store results by selecting the owning lane.
-// Pivots below eps ||T|| in magnitude are replaced by +-eps ||T||, as in the
-// LU of the inverse iteration.  Tied eigenvalues (within 4 ulps of ||T|| of
-// the previous one) are left to the inverse iteration, whose distinct start
-// vectors separate them.
-__device__ inline double lane_read_f64(double v, int l) {
-  const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
-  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
-  return __hiloint2double(hi, lo);
-}
-
+// a factorisation and repeated solves.  d - lam and e are staged in LDS; the
+// sweeps are scalar recurrences that every lane of a wave runs alike, reading
+// the current row's values by LDS broadcast (independent of the recurrence,
+// so they are read ahead) and leaving their results (1 / dp, 1 / dm, the two
+// parts of gamma, z) in LDS by lane 0.  Pivots below eps ||T|| in magnitude
+// are replaced by +-eps ||T||, as in the LU of the inverse iteration.  Tied
+// eigenvalues (within 4 ulps of ||T|| of the previous one) are left to the
+// inverse iteration, whose distinct start vectors separate them.
 template <int NS>
 __global__ __launch_bounds__(128) void twist_kernel(const double* __restrict__ d, const double* __restrict__ e,
                                                     int k, const double* __restrict__ lam,
@@ -1062,10 +1057,17 @@ __global__ __launch_bounds__(128) void twist_kernel(const double* __restrict__ d
                                                     const double* __restrict__ bounds, double* Z,
                                                     int64_t ldz) {
   // wave 0 runs the forward sweep and then z below the twist, wave 1 the
-  // backward sweep and then z above it; gamma and the norm meet in LDS
-  __shared__ double gsh[64 * NS];  // dp_i - (d_i - lam), from wave 0
-  __shared__ double dsh[64 * NS];  // dm_i, from wave 1
+  // backward sweep and then z above it
+  constexpr int KM = 64 * NS;
+  __shared__ double dn[KM];   // d_i - lam
+  __shared__ double en[KM];   // e_i (0 past the last coupling)
+  __shared__ double rf[KM];   // 1 / dp_i (wave 0)
+  __shared__ double rb[KM];   // 1 / dm_i (wave 1)
+  __shared__ double gsh[KM];  // dp_i - (d_i - lam) (wave 0)
+  __shared__ double dsh[KM];  // dm_i (wave 1)
+  __shared__ double zs[KM];   // z
   __shared__ double part2[2];
+  __shared__ double spow[2];
   __shared__ int rsh;
   const int c = blockIdx.x;
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -1078,56 +1080,99 @@ __global__ __launch_bounds__(128) void twist_kernel(const double* __restrict__ d
   const double small = DBL_EPSILON * fmax(nrmT, DBL_MIN);
   if (idx > 0 && lam[idx] - lam[idx - 1] <= 4.0 * DBL_EPSILON * nrmT) return;  // a tie
   const double lamq = lam[idx];
-  double dn[NS], en[NS], rp[NS], z[NS];
-#pragma unroll
-  for (int m = 0; m < NS; ++m) {
-    const int i = 64 * m + lane;
-    dn[m] = (i < k) ? d[i] - lamq : 0.0;
-    en[m] = (i + 1 < k) ? e[i] : 0.0;
-    rp[m] = z[m] = 0.0;
+  for (int i = threadIdx.x; i < KM; i += 128) {
+    dn[i] = (i < k) ? d[i] - lamq : 0.0;
+    en[i] = (i + 1 < k) ? e[i] : 0.0;
   }
+  __syncthreads();
   auto guard = [&](double p) { return (fabs(p) < small) ? copysign(small, p) : p; };
+  // The sweeps take the rows in blocks of kTwB: a block's inputs are read from
+  // LDS one block ahead (LDS latency off the recurrence) and its results are
+  // gathered into lanes 0 .. kTwB - 1 and stored once per block.
+  constexpr int kTwB = 8;
+  auto put = [&](double acc, double v, int u) { return (lane == u) ? v : acc; };  // lane u takes v
   if (w == 0) {
-    // forward: dp (kept as 1 / dp); gamma part dp_i - (d_i - lam) into LDS
+    // forward: dp (kept as 1 / dp) and the gamma part dp_i - (d_i - lam)
     double ep = 0.0, rprev = 0.0;
+    double dA[kTwB], eA[kTwB];
 #pragma unroll
-    for (int m = 0; m < NS; ++m) {
-      double gm = 0.0;
-      for (int j = 0; j < 64; ++j) {
-        const int i = 64 * m + j;
-        if (i >= k) break;
-        const double di = lane_read_f64(dn[m], j);
-        const double p = guard(di - ep * ep * rprev);
-        const double r = rcp_f64(p);
-        rp[m] = (lane == j) ? r : rp[m];
-        gm = (lane == j) ? p - di : gm;
-        ep = lane_read_f64(en[m], j);
-        rprev = r;
+    for (int u = 0; u < kTwB; ++u) {
+      dA[u] = dn[u];
+      eA[u] = en[u];
+    }
+    for (int i0 = 0; i0 < k; i0 += kTwB) {
+      double dB[kTwB], eB[kTwB];
+#pragma unroll
+      for (int u = 0; u < kTwB; ++u) {
+        const int ii = min(i0 + kTwB + u, KM - 1);
+        dB[u] = dn[ii];
+        eB[u] = en[ii];
       }
-      gsh[64 * m + lane] = gm;
+      double rr = 0.0, gg = 0.0;
+#pragma unroll
+      for (int u = 0; u < kTwB; ++u) {
+        if (i0 + u < k) {  // uniform
+          const double di = dA[u];
+          const double p = guard(di - ep * ep * rprev);
+          const double r = rcp_f64(p);
+          rr = put(rr, r, u);
+          gg = put(gg, p - di, u);
+          ep = eA[u];
+          rprev = r;
+        }
+      }
+      if (lane < kTwB && i0 + lane < k) {
+        rf[i0 + lane] = rr;
+        gsh[i0 + lane] = gg;
+      }
+#pragma unroll
+      for (int u = 0; u < kTwB; ++u) {
+        dA[u] = dB[u];
+        eA[u] = eB[u];
+      }
     }
   } else {
-    // backward: dm (kept as 1 / dm)
+    // backward: dm (kept as 1 / dm); blocks from the top
     double rprev = 0.0;
-    double dmv[NS];
+    const int top = k - 1;
+    double dA[kTwB], eA[kTwB];
 #pragma unroll
-    for (int m = 0; m < NS; ++m) dmv[m] = 0.0;
+    for (int u = 0; u < kTwB; ++u) {
+      const int ii = max(top - u, 0);
+      dA[u] = dn[ii];
+      eA[u] = en[ii];
+    }
+    for (int i0 = top; i0 >= 0; i0 -= kTwB) {
+      double dB[kTwB], eB[kTwB];
 #pragma unroll
-    for (int m = NS - 1; m >= 0; --m) {
-      for (int j = 63; j >= 0; --j) {
-        const int i = 64 * m + j;
-        if (i >= k) continue;
-        const double di = lane_read_f64(dn[m], j);
-        const double ei = lane_read_f64(en[m], j);  // coupling of rows i and i + 1 (0 for the last)
-        const double p = guard(di - ei * ei * rprev);
-        const double r = rcp_f64(p);
-        rp[m] = (lane == j) ? r : rp[m];
-        dmv[m] = (lane == j) ? p : dmv[m];
-        rprev = r;
+      for (int u = 0; u < kTwB; ++u) {
+        const int ii = max(i0 - kTwB - u, 0);
+        dB[u] = dn[ii];
+        eB[u] = en[ii];
+      }
+      double rr = 0.0, pp = 0.0;
+#pragma unroll
+      for (int u = 0; u < kTwB; ++u) {
+        if (i0 - u >= 0) {  // uniform
+          const double di = dA[u];
+          const double ei = eA[u];  // coupling of rows i and i + 1 (0 for the last)
+          const double p = guard(di - ei * ei * rprev);
+          const double r = rcp_f64(p);
+          rr = put(rr, r, u);
+          pp = put(pp, p, u);
+          rprev = r;
+        }
+      }
+      if (lane < kTwB && i0 - lane >= 0) {
+        rb[i0 - lane] = rr;
+        dsh[i0 - lane] = pp;
+      }
+#pragma unroll
+      for (int u = 0; u < kTwB; ++u) {
+        dA[u] = dB[u];
+        eA[u] = eB[u];
       }
     }
-#pragma unroll
-    for (int m = 0; m < NS; ++m) dsh[64 * m + lane] = dmv[m];
   }
   __syncthreads();  // both parts of gamma are in LDS
   // twist r = argmin |gamma_i| (lowest i among equals), by wave 1
@@ -1137,7 +1182,7 @@ __global__ __launch_bounds__(128) void twist_kernel(const double* __restrict__ d
 #pragma unroll
     for (int m = 0; m < NS; ++m) {
       const int i = 64 * m + lane;
-      const double g = fabs(gsh[i] + dsh[i]);
+      const double g = (i < k) ? fabs(gsh[i] + dsh[i]) : DBL_MAX;
       if (i < k && (g < best || (g == best && i < bi))) { best = g; bi = i; }
     }
     for (int off = 32; off >= 1; off >>= 1) {
@@ -1149,68 +1194,103 @@ __global__ __launch_bounds__(128) void twist_kernel(const double* __restrict__ d
   }
   __syncthreads();
   const int r = rsh;
-  const int rm = r >> 6, rl = r & 63;
-  // z_r = 1 (wave 0 holds it); z below the twist by wave 0 (1 / dp), above by
-  // wave 1 (1 / dm); a running rescale keeps the entries in range
+  // z_r = 1; z below the twist by wave 0 (1 / dp), above by wave 1 (1 / dm);
+  // a running rescale keeps the entries in range (the stored part of the
+  // sweep is rescaled with it)
   double scale_pow = 0.0;  // number of 1e-150 rescales of this wave's part
   if (w == 0) {
-#pragma unroll
-    for (int m = 0; m < NS; ++m) z[m] = (m == rm && lane == rl) ? 1.0 : 0.0;
+    if (lane == 0) zs[r] = 1.0;
     double zc = 1.0;  // z_{i+1}
+    double fA[kTwB], eA[kTwB];
 #pragma unroll
-    for (int m = NS - 1; m >= 0; --m) {
-      for (int j = 63; j >= 0; --j) {
-        const int i = 64 * m + j;
-        if (i >= r) continue;
-        const double ei = lane_read_f64(en[m], j);
-        const double ri = lane_read_f64(rp[m], j);
-        zc = -ei * zc * ri;
-        z[m] = (lane == j) ? zc : z[m];
-        if (fabs(zc) > 1e150) {  // uniform
+    for (int u = 0; u < kTwB; ++u) {
+      const int ii = max(r - 1 - u, 0);
+      fA[u] = rf[ii];
+      eA[u] = en[ii];
+    }
+    for (int i0 = r - 1; i0 >= 0; i0 -= kTwB) {
+      double fB[kTwB], eB[kTwB];
 #pragma unroll
-          for (int q = 0; q < NS; ++q) z[q] *= 1e-150;
-          zc *= 1e-150;
-          scale_pow += 1.0;
+      for (int u = 0; u < kTwB; ++u) {
+        const int ii = max(i0 - kTwB - u, 0);
+        fB[u] = rf[ii];
+        eB[u] = en[ii];
+      }
+      double zz = 0.0;
+#pragma unroll
+      for (int u = 0; u < kTwB; ++u) {
+        if (i0 - u >= 0) {  // uniform
+          zc = -eA[u] * zc * fA[u];
+          if (fabs(zc) > 1e150) {  // uniform; the stored part and this block's rescale with it
+            for (int q = i0 + 1 + lane; q <= r; q += 64) zs[q] *= 1e-150;
+            zz *= 1e-150;
+            zc *= 1e-150;
+            scale_pow += 1.0;
+          }
+          zz = put(zz, zc, u);
         }
+      }
+      if (lane < kTwB && i0 - lane >= 0) zs[i0 - lane] = zz;
+#pragma unroll
+      for (int u = 0; u < kTwB; ++u) {
+        fA[u] = fB[u];
+        eA[u] = eB[u];
       }
     }
   } else {
     double zc = 1.0;  // z_{i-1}
-    double ep = lane_read_f64(en[0], 0);
+    double bA[kTwB], eA[kTwB];
 #pragma unroll
-    for (int m = 0; m < NS; ++m)
-      if (m == rm) ep = lane_read_f64(en[m], rl);  // e_r
+    for (int u = 0; u < kTwB; ++u) {
+      const int ii = min(r + 1 + u, KM - 1);
+      bA[u] = rb[ii];
+      eA[u] = en[ii - 1];
+    }
+    for (int i0 = r + 1; i0 < k; i0 += kTwB) {
+      double bB[kTwB], eB[kTwB];
 #pragma unroll
-    for (int m = 0; m < NS; ++m) {
-      for (int j = 0; j < 64; ++j) {
-        const int i = 64 * m + j;
-        if (i <= r) continue;
-        if (i >= k) break;
-        const double ri = lane_read_f64(rp[m], j);
-        zc = -ep * zc * ri;
-        z[m] = (lane == j) ? zc : z[m];
-        ep = lane_read_f64(en[m], j);
-        if (fabs(zc) > 1e150) {  // uniform
+      for (int u = 0; u < kTwB; ++u) {
+        const int ii = min(i0 + kTwB + u, KM - 1);
+        bB[u] = rb[ii];
+        eB[u] = en[ii - 1];
+      }
+      double zz = 0.0;
 #pragma unroll
-          for (int q = 0; q < NS; ++q) z[q] *= 1e-150;
-          zc *= 1e-150;
-          scale_pow += 1.0;
+      for (int u = 0; u < kTwB; ++u) {
+        if (i0 + u < k) {  // uniform
+          zc = -eA[u] * zc * bA[u];
+          if (fabs(zc) > 1e150) {  // uniform
+            for (int q = r + 1 + lane; q < i0; q += 64) zs[q] *= 1e-150;
+            zz *= 1e-150;
+            zc *= 1e-150;
+            scale_pow += 1.0;
+          }
+          zz = put(zz, zc, u);
         }
+      }
+      if (lane < kTwB && i0 + lane < k) zs[i0 + lane] = zz;
+#pragma unroll
+      for (int u = 0; u < kTwB; ++u) {
+        bA[u] = bB[u];
+        eA[u] = eB[u];
       }
     }
   }
   // the two parts share z_r = 1; a part that was rescaled is scaled back
   // relative to the other before the norm
-  __shared__ double spow[2];
   if (lane == 0) spow[w] = scale_pow;
   __syncthreads();
   const double mine = spow[w], other = spow[1 - w];
   const double rel = (mine >= other) ? 1.0 : pow(1e-150, other - mine);
-#pragma unroll
-  for (int m = 0; m < NS; ++m) z[m] *= rel;
+  double z[NS];
   double sq = 0.0;
 #pragma unroll
-  for (int m = 0; m < NS; ++m) sq += z[m] * z[m];
+  for (int m = 0; m < NS; ++m) {
+    const int i = 64 * m + lane;
+    const bool mine_row = (w == 0) ? (i <= r) : (i > r);
+    z[m] = (i < k && mine_row) ? zs[i] * rel : 0.0;
+    sq += z[m] * z[m];
+  }
   sq = wave_sum_f64(sq);
   if (lane == 0) part2[w] = sq;
   __syncthreads();
