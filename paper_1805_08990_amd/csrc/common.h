@@ -320,10 +320,21 @@ inline int64_t rank_to_host(hipStream_t s, const int64_t* rank_dev) {
 // Symmetric eigen-decomposition of a k x k matrix (syev.hip).
 // Eigenvalues sorted by |lambda| descending; only those with |lambda| > tol*max|lambda|
 // (at most max_keep) get eigenvectors.  Writes kept count to *keep_dev.
+// A caller that finishes the vectors itself can leave the sign convention
+// (largest |entry| of each column positive, the first on ties) to its own
+// kernels (signs = false), and have the kept count sent to the host through
+// the bound auxiliary stream as soon as it is known (rank_seq set: the
+// sequence number for value_to_host_wait on the second stream; the value is
+// -1 when *rank_veto is nonzero).
+struct SyevPost {
+  bool signs = true;
+  const int64_t* rank_veto = nullptr;
+  int64_t* rank_seq = nullptr;
+};
 size_t syev_workspace(int64_t k);
 void syev_trunc_f64(hipStream_t s, int64_t k, const double* M, int64_t ldm, double tol,
                     int64_t max_keep, double* lam_out, double* V_out, int64_t ldv,
-                    int64_t* keep_dev, int* flag_dev, Arena& ws);
+                    int64_t* keep_dev, int* flag_dev, Arena& ws, const SyevPost& post = SyevPost());
 
 // Riccati subflow (riccati.hip): D (r x r) <- D - t D W (R + t W^T D W)^-1 W^T D, W = L^T B.
 // LQR feedback gain K (m x n, ld ldk) = R^-1 B^T L D L^T (riccati.hip).

@@ -369,16 +369,56 @@ __global__ void sym_kernel(int k, const double* G, double* S, int* flag) {
   if (bad) atomicOr(flag, 1);
 }
 
-// T(:, j) /= sqrt(lam_j) for j < *rank, T(:, j) = 0 for rank <= j < r (the
-// columns past the kept rank may hold anything); and the columns j < min(r,
-// rank) of D = diag(lam) (rank x rank, ld ldd, or the rank when ldd is 0).
-// The grid covers k >= rank rows.
-__global__ void scale_cols_kernel(int k, int r, const double* lam, const int64_t* rank, double* T, double* D,
-                                  int64_t ldd) {
+// T(:, j) *= s_j / sqrt(lam_j) for j < *rank, T(:, j) = 0 for rank <= j < r
+// (the columns past the kept rank may hold anything), where T = F V and s_j
+// is the sign that makes the largest |V(i, j)| (the first on ties) positive;
+// and the columns j < min(r, rank) of D = diag(lam) (rank x rank, ld ldd, or
+// the rank when ldd is 0).  256 threads a block; the grid covers k >= rank rows.
+__global__ __launch_bounds__(256) void scale_cols_kernel(int k, int r, const double* lam, const int64_t* rank,
+                                                         double* T, double* D, int64_t ldd, const double* V,
+                                                         int64_t ldv) {
+  __shared__ double sbest[4];
+  __shared__ int sidx[4];
   const int64_t rk = *rank;
   const int64_t ld = (ldd > 0) ? ldd : rk;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   for (int j = blockIdx.y; j < r; j += gridDim.y) {
-    const double f = (j < rk) ? 1.0 / sqrt(lam[j]) : 0.0;
+    double sgn = 1.0;
+    if (j < rk) {  // uniform in the block
+      const double* vj = V + (int64_t)j * ldv;
+      double best = -1.0;
+      int bi = k;
+      for (int i = threadIdx.x; i < k; i += 256) {
+        const double a = fabs(vj[i]);
+        if (a > best) {
+          best = a;
+          bi = i;
+        }
+      }
+      for (int off = 32; off > 0; off >>= 1) {
+        const double ob = __shfl_xor(best, off, 64);
+        const int oi = __shfl_xor(bi, off, 64);
+        if (ob > best || (ob == best && oi < bi)) {
+          best = ob;
+          bi = oi;
+        }
+      }
+      __syncthreads();  // the previous column's reads of sbest are done
+      if (lane == 0) {
+        sbest[wv] = best;
+        sidx[wv] = bi;
+      }
+      __syncthreads();
+      best = sbest[0];
+      bi = sidx[0];
+      for (int q = 1; q < 4; ++q)
+        if (sbest[q] > best || (sbest[q] == best && sidx[q] < bi)) {
+          best = sbest[q];
+          bi = sidx[q];
+        }
+      if (bi < k && vj[bi] < 0.0) sgn = -1.0;
+    }
+    const double f = (j < rk) ? sgn / sqrt(lam[j]) : 0.0;
     for (int i = blockIdx.x * 256 + threadIdx.x; i < k; i += gridDim.x * 256) {
       double* t = T + i + (int64_t)j * k;
       *t = (j < rk) ? *t * f : 0.0;
@@ -456,9 +496,15 @@ int64_t compress_gram_f64(hipStream_t s, int64_t n, int64_t k, const double* W, 
   hipLaunchKernelGGL(sym_kernel, dim3(blocks(k * k)), dim3(256), 0, s, (int)k, G, S, flag_dev);
   DME_HIP(hipGetLastError());
   ws.used = mark_g;
-  syev_trunc_f64(s, k, S, k, tol, std::min(max_rank, k), lam, V, k, rank_dev, flag_dev, ws);
+  // the kept rank travels to the host from the second stream as soon as it is
+  // known; the eigenvectors' signs are applied with the column scaling below
+  int64_t seq_rank = 0;
+  SyevPost post;
+  post.signs = false;
+  post.rank_veto = status;
+  post.rank_seq = &seq_rank;
+  syev_trunc_f64(s, k, S, k, tol, std::min(max_rank, k), lam, V, k, rank_dev, flag_dev, ws, post);
   ws.used = mark_g;
-  const int64_t seq_rank = value_to_host_launch(s, rank_dev, status);
   // L = W (F V_I Lam_I^-1/2), D = Lam_I: the products (and D) for a guessed
   // width go ahead of the rank's round trip to the host
   const int64_t kmax = std::min(max_rank, k);
@@ -467,13 +513,13 @@ int64_t compress_gram_f64(hipStream_t s, int64_t n, int64_t k, const double* W, 
     gemm_f64(s, 'N', 'N', k, w, k, 1.0, F, k, V, k, 0.0, T, k, &ws);
     ws.used = mark_g;
     const dim3 sg(cdiv(k, 256), (unsigned)std::min<int64_t>(w, 1024));
-    hipLaunchKernelGGL(scale_cols_kernel, sg, dim3(256), 0, s, (int)k, (int)w, lam, rank_dev, T, Dout, ldd);
+    hipLaunchKernelGGL(scale_cols_kernel, sg, dim3(256), 0, s, (int)k, (int)w, lam, rank_dev, T, Dout, ldd, V, k);
     DME_HIP(hipGetLastError());
     gemm_f64(s, 'N', 'N', n, w, k, 1.0, W, ldw, T, k, 0.0, L, ldl, &ws);
     ws.used = mark_g;
   };
   form_L(ks);
-  const int64_t rr = value_to_host_wait(s, seq_rank);
+  const int64_t rr = value_to_host_wait(aux_stream().s2, seq_rank);
   if (rr <= 0) {
     ws.used = mark;
     return rr < 0 ? -1 : 0;  // -1: Dhat is not positive definite

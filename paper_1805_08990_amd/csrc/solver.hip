@@ -615,12 +615,21 @@ void Solver::apply_T2(double t) {
 void Solver::apply_T12(double t, bool ext_product) {
   const QuadFactor& f = Q.at(t);
   double* Wd = W.as<double>();
+  const int64_t k = r + f.r;
+  // D-hat and the quadrature columns of W (they depend on neither the
+  // product nor its columns of W) on the second stream, beside the product
+  hipEvent_t w_ready = nullptr;
+  if (k > 0) {
+    AuxStream& ax = aux_stream();
+    DME_HIP(hipStreamWaitEvent(ax.s2, ax.record(s), 0));
+    blkdiag2_f64(ax.s2, Dc(), r, r, f.D.as<double>(), f.r, f.r, 1.0, Dhat.as<double>(), k);
+    if (f.r > 0) copy_f64(ax.s2, f.L.as<double>(), n, Wd + r * n, n, n, f.r);
+    w_ready = ax.record(ax.s2);
+  }
   if (r > 0 && !ext_product) apply_E(t, Lc(), r, Wd, n);
   if (r > 0) ++nprod;  // (a grouped product of the server counts the same)
-  const int64_t k = r + f.r;
   if (k == 0) return;
-  blkdiag2_f64(s, Dc(), r, r, f.D.as<double>(), f.r, f.r, 1.0, Dhat.as<double>(), k);
-  if (f.r > 0) copy_f64(s, f.L.as<double>(), n, Wd + r * n, n, n, f.r);
+  DME_HIP(hipStreamWaitEvent(s, w_ready, 0));
   compress_into(k);
 }
 

@@ -1541,10 +1541,11 @@ size_t syev_workspace(int64_t k) {
 
 void syev_trunc_f64(hipStream_t s, int64_t k, const double* M, int64_t ldm, double tol,
                     int64_t max_keep, double* lam_out, double* V_out, int64_t ldv,
-                    int64_t* keep_dev, int* flag_dev, Arena& ws) {
+                    int64_t* keep_dev, int* flag_dev, Arena& ws, const SyevPost& post) {
   DME_REQUIRE(k >= 0 && k <= 16384, DME_EINVAL, "syev: k out of range");
   if (k == 0) {
     fill_f64(s, reinterpret_cast<double*>(keep_dev), 1, 1, 1, 0.0);  // all-zero bits
+    if (post.rank_seq) *post.rank_seq = value_to_host_launch(s, keep_dev, post.rank_veto);
     return;
   }
   const int ki = (int)k;
@@ -1620,6 +1621,10 @@ void syev_trunc_f64(hipStream_t s, int64_t k, const double* M, int64_t ldm, doub
   hipLaunchKernelGGL(select_kernel, dim3(1), dim3(kSelT), 0, s, lam, ki, tol, max_keep, bounds, order,
                      pos_of, lam_out, clusters, cl_count, keep_dev, flag_dev, (int)nkeep_sel, cl_of, cl_fail);
   DME_HIP(hipGetLastError());
+  if (post.rank_seq) {  // the kept count to the host from the second stream, beside the vectors
+    DME_HIP(hipStreamWaitEvent(ax.s2, ax.record(s), 0));
+    *post.rank_seq = value_to_host_launch(ax.s2, keep_dev, post.rank_veto);
+  }
   // Z: k x (kept) column-major with ld = k (kept <= k)
   const unsigned nkeep = (unsigned)std::min<int64_t>(k, max_keep);
   // twisted factorisations for k <= 512, inverse iteration for ties (and larger k)
@@ -1674,8 +1679,10 @@ void syev_trunc_f64(hipStream_t s, int64_t k, const double* M, int64_t ldm, doub
   // V = Q Z with Q formed beside the eigenvalue work
   DME_HIP(hipStreamWaitEvent(s, q_done, 0));
   gemm_f64(s, 'N', 'N', k, (int64_t)nkeep, k, 1.0, Qm, k, Zf, k, 0.0, V_out, ldv, &ws);
-  hipLaunchKernelGGL(sign_columns_kernel, dim3(nkeep), dim3(64), 0, s, V_out, ldv, ki, keep_dev);
-  DME_HIP(hipGetLastError());
+  if (post.signs) {
+    hipLaunchKernelGGL(sign_columns_kernel, dim3(nkeep), dim3(64), 0, s, V_out, ldv, ki, keep_dev);
+    DME_HIP(hipGetLastError());
+  }
 }
 
 }  // namespace dme
