@@ -303,10 +303,20 @@ struct LowRankD {
   int ncopies;
 };
 size_t compress_gram_workspace(int64_t n, int64_t k);
+//
+// F_ready (optional, k x k, ld k): the factor of Dhat already formed on the
+// device by gram_factor_lowrank, ordered before the work s holds; its status
+// (0, or -1 when Dhat is not positive definite) in *status_ready.
 int64_t compress_gram_f64(hipStream_t s, int64_t n, int64_t k, const double* W, int64_t ldw,
                           const double* Dhat, int64_t lddh, bool dhat_diag, const LowRankD* lowrank,
                           double tol, int64_t max_rank, double* L, int64_t ldl, double* Dout, int64_t ldd,
-                          int64_t* rank_dev, int* flag_dev, Arena& ws, int64_t rank_hint = 0);
+                          int64_t* rank_dev, int* flag_dev, Arena& ws, int64_t rank_hint = 0,
+                          const double* F_ready = nullptr, const int64_t* status_ready = nullptr);
+// Launches the closed-form factor F (k x k, ld k) of a Dhat in the LowRankD
+// form on st, with its status in *status; returns false, launching nothing,
+// when the form's limits (m <= 8, r <= 256) do not hold.
+bool gram_factor_lowrank(hipStream_t st, int64_t k, const double* Dhat, int64_t lddh, const LowRankD& lr,
+                         double* F, int64_t* status);
 // A device int64 to the host through the bound auxiliary stream's pinned slot:
 // launch() enqueues the copy on s and returns its sequence number (the value
 // sent is -1 instead when *veto is nonzero), wait() polls for it (falling back

@@ -183,24 +183,6 @@ __global__ __launch_bounds__(kCT) void chol_lower_kernel(int k, double* A, int64
   if (tid == 0) *status = bad ? -1 : 0;
 }
 
-// F = diag(sqrt(Dhat_ii)) for a diagonal Dhat (zero elsewhere); a non-positive
-// entry makes *status = -1 (and F zero).
-__global__ void sqrt_diag_kernel(int k, const double* Dhat, int64_t ldd, double* F, int64_t* status) {
-  __shared__ int bad;
-  if (threadIdx.x == 0) bad = 0;
-  __syncthreads();
-  for (int i = threadIdx.x; i < k; i += blockDim.x) {
-    const double d = Dhat[i + (int64_t)i * ldd];
-    if (!(d > 0.0) || !isfinite(d)) bad = 1;
-  }
-  __syncthreads();
-  for (int64_t idx = threadIdx.x; idx < (int64_t)k * k; idx += blockDim.x) {
-    const int i = (int)(idx % k), j = (int)(idx / k);
-    F[idx] = (!bad && i == j) ? sqrt(Dhat[i + (int64_t)i * ldd]) : 0.0;
-  }
-  if (threadIdx.x == 0) *status = bad ? -1 : 0;
-}
-
 // F for a Dhat whose D blocks are diag(lam) - t Z Z^T (see LowRankD), one
 // workgroup: Zh = sqrt(t) Lam^-1/2 Z and G = Zh^T Zh (m x m, one lane per
 // entry) in LDS, G = U g U^T by cyclic Jacobi in registers of one thread
@@ -358,6 +340,35 @@ __global__ void copy_lower_kernel(int k, const double* Dhat, int64_t ldd, double
 }
 
 // S = (G + G^T) / 2; a non-finite entry sets bit 1 of *flag
+// S = F sym(G) F for a diagonal Dhat, F = diag(sqrt(Dhat_ii)): every block
+// checks the diagonal (k entries) so that a non-positive or non-finite entry
+// zeroes S everywhere, and block 0 writes *status (-1 then, else 0).
+__global__ void gram_scale_sym_kernel(int k, const double* G, const double* Dhat, int64_t lddh, double* S,
+                                      int64_t* status, int* flag) {
+  __shared__ int bad;
+  if (threadIdx.x == 0) bad = 0;
+  __syncthreads();
+  for (int i = threadIdx.x; i < k; i += blockDim.x) {
+    const double d = Dhat[i + (int64_t)i * lddh];
+    if (!(d > 0.0) || !isfinite(d)) bad = 1;
+  }
+  __syncthreads();
+  const bool ok = !bad;
+  if (blockIdx.x == 0 && threadIdx.x == 0) *status = ok ? 0 : -1;
+  bool nf = false;
+  for (int64_t idx = blockIdx.x * 256 + threadIdx.x; idx < (int64_t)k * k; idx += (int64_t)gridDim.x * 256) {
+    const int i = (int)(idx % k), j = (int)(idx / k);
+    double v = 0.0;
+    if (ok) {
+      const double fi = sqrt(Dhat[i + (int64_t)i * lddh]), fj = sqrt(Dhat[j + (int64_t)j * lddh]);
+      v = 0.5 * (G[idx] + G[j + (int64_t)i * k]) * (fi * fj);  // exactly symmetric
+    }
+    S[idx] = v;
+    if (!isfinite(v)) nf = true;
+  }
+  if (nf) atomicOr(flag, 1);
+}
+
 __global__ void sym_kernel(int k, const double* G, double* S, int* flag) {
   bool bad = false;
   for (int64_t idx = blockIdx.x * 256 + threadIdx.x; idx < (int64_t)k * k; idx += (int64_t)gridDim.x * 256) {
@@ -369,14 +380,16 @@ __global__ void sym_kernel(int k, const double* G, double* S, int* flag) {
   if (bad) atomicOr(flag, 1);
 }
 
-// T(:, j) *= s_j / sqrt(lam_j) for j < *rank, T(:, j) = 0 for rank <= j < r
-// (the columns past the kept rank may hold anything), where T = F V and s_j
-// is the sign that makes the largest |V(i, j)| (the first on ties) positive;
-// and the columns j < min(r, rank) of D = diag(lam) (rank x rank, ld ldd, or
-// the rank when ldd is 0).  256 threads a block; the grid covers k >= rank rows.
+// T(:, j) = X(:, j) s_j / sqrt(lam_j) for j < *rank, T(:, j) = 0 for
+// rank <= j < r (the columns past the kept rank may hold anything), where X
+// is T = F V itself (dh null) or diag(sqrt(dh_ii)) V (a diagonal Dhat, F V
+// without a product), and s_j is the sign that makes the largest |V(i, j)|
+// (the first on ties) positive; and the columns j < min(r, rank) of
+// D = diag(lam) (rank x rank, ld ldd, or the rank when ldd is 0).  256
+// threads a block; the grid covers k >= rank rows.
 __global__ __launch_bounds__(256) void scale_cols_kernel(int k, int r, const double* lam, const int64_t* rank,
                                                          double* T, double* D, int64_t ldd, const double* V,
-                                                         int64_t ldv) {
+                                                         int64_t ldv, const double* dh, int64_t lddh) {
   __shared__ double sbest[4];
   __shared__ int sidx[4];
   const int64_t rk = *rank;
@@ -421,7 +434,8 @@ __global__ __launch_bounds__(256) void scale_cols_kernel(int k, int r, const dou
     const double f = (j < rk) ? sgn / sqrt(lam[j]) : 0.0;
     for (int i = blockIdx.x * 256 + threadIdx.x; i < k; i += gridDim.x * 256) {
       double* t = T + i + (int64_t)j * k;
-      *t = (j < rk) ? *t * f : 0.0;
+      const double x = dh ? sqrt(dh[i + (int64_t)i * lddh]) * V[i + (int64_t)j * ldv] : *t;
+      *t = (j < rk) ? x * f : 0.0;
       if (j < rk && i < rk) D[i + j * ld] = (i == j) ? lam[j] : 0.0;
     }
   }
@@ -443,13 +457,31 @@ size_t compress_gram_workspace(int64_t n, int64_t k) {
   return b + 4096;
 }
 
+bool gram_factor_lowrank(hipStream_t st, int64_t k, const double* Dhat, int64_t lddh, const LowRankD& lr,
+                         double* F, int64_t* status) {
+  if (!(lr.m >= 1 && lr.m <= kLrMaxM && lr.r <= kLrMaxR && lr.ncopies * lr.r <= k)) return false;
+  switch (lr.m) {
+#define DME_LRF(MM)                                                                                       \
+  case MM:                                                                                                \
+    hipLaunchKernelGGL(lowrank_factor_kernel<MM>, dim3(1), dim3(kLrT), 0, st, (int)k, Dhat, lddh, lr.lam, \
+                       lr.Z, lr.t, (int)lr.r, lr.ncopies, F, status);                                     \
+    break;
+    DME_LRF(1) DME_LRF(2) DME_LRF(3) DME_LRF(4) DME_LRF(5) DME_LRF(6) DME_LRF(7) DME_LRF(8)
+#undef DME_LRF
+    default: return false;
+  }
+  DME_HIP(hipGetLastError());
+  return true;
+}
+
 int64_t compress_gram_f64(hipStream_t s, int64_t n, int64_t k, const double* W, int64_t ldw,
                           const double* Dhat, int64_t lddh, bool dhat_diag, const LowRankD* lowrank,
                           double tol, int64_t max_rank, double* L, int64_t ldl, double* Dout, int64_t ldd,
-                          int64_t* rank_dev, int* flag_dev, Arena& ws, int64_t rank_hint) {
+                          int64_t* rank_dev, int* flag_dev, Arena& ws, int64_t rank_hint,
+                          const double* F_ready, const int64_t* status_ready) {
   if (k <= 0 || n <= 0) return 0;
   const size_t mark = ws.used;
-  double* F = ws.get<double>((size_t)k * k);
+  double* Fw = ws.get<double>((size_t)k * k);
   double* G = ws.get<double>((size_t)k * k);
   double* T1 = ws.get<double>((size_t)k * k);
   double* S = ws.get<double>((size_t)k * k);
@@ -459,41 +491,42 @@ int64_t compress_gram_f64(hipStream_t s, int64_t n, int64_t k, const double* W, 
   int64_t* status = ws.get<int64_t>(8);
   const size_t mark_g = ws.used;
 
-  // Dhat = F F^T on the second stream, beside W^T W on s.  A factor that
-  // fails (Dhat not positive definite) leaves F = 0, so what follows sees a
-  // zero matrix; its status vetoes the rank on its way to the host, which
-  // then returns -1 for the caller to compress by Householder QR.
-  AuxStream& ax = aux_stream();
-  DME_HIP(hipStreamWaitEvent(ax.s2, ax.record(s), 0));
-  if (dhat_diag) {
-    hipLaunchKernelGGL(sqrt_diag_kernel, dim3(1), dim3(1024), 0, ax.s2, (int)k, Dhat, lddh, F, status);
-  } else if (lowrank && lowrank->m >= 1 && lowrank->m <= kLrMaxM && lowrank->r <= kLrMaxR && lowrank->ncopies * lowrank->r <= k) {
-    switch (lowrank->m) {
-#define DME_LRF(MM)                                                                                      \
-  case MM:                                                                                               \
-    hipLaunchKernelGGL(lowrank_factor_kernel<MM>, dim3(1), dim3(kLrT), 0, ax.s2, (int)k, Dhat, lddh,    \
-                       lowrank->lam, lowrank->Z, lowrank->t, (int)lowrank->r, lowrank->ncopies, F, status); \
-    break;
-      DME_LRF(1) DME_LRF(2) DME_LRF(3) DME_LRF(4) DME_LRF(5) DME_LRF(6) DME_LRF(7) DME_LRF(8)
-#undef DME_LRF
-      default: DME_REQUIRE(false, DME_EINTERNAL, "low-rank factor: m out of range");
+  // Dhat = F F^T.  A diagonal Dhat needs no F: its square roots scale the
+  // Gram matrix and V in the kernels that read them.  Otherwise F comes ready
+  // (formed by the caller on a stream s is already ordered after) or is
+  // formed here on the second stream, beside W^T W on s.  A factor that fails
+  // (Dhat not positive definite) leaves F = 0 (S = 0 when diagonal), so what
+  // follows sees a zero matrix; its status vetoes the rank on its way to the
+  // host, which then returns -1 for the caller to compress by Householder QR.
+  const bool diag = !F_ready && dhat_diag;
+  const double* F = F_ready ? F_ready : Fw;
+  const int64_t* fstatus = F_ready ? status_ready : status;
+  hipEvent_t f_done = nullptr;
+  if (!F_ready && !diag) {
+    AuxStream& ax = aux_stream();
+    DME_HIP(hipStreamWaitEvent(ax.s2, ax.record(s), 0));
+    if (!(lowrank && gram_factor_lowrank(ax.s2, k, Dhat, lddh, *lowrank, Fw, status))) {
+      hipLaunchKernelGGL(copy_lower_kernel, dim3(blocks(k * k)), dim3(256), 0, ax.s2, (int)k, Dhat, lddh, Fw);
+      DME_HIP(hipGetLastError());
+      hipLaunchKernelGGL(chol_lower_kernel, dim3(1), dim3(kCT), 0, ax.s2, (int)k, Fw, k, status);
+      DME_HIP(hipGetLastError());
     }
-  } else {
-    hipLaunchKernelGGL(copy_lower_kernel, dim3(blocks(k * k)), dim3(256), 0, ax.s2, (int)k, Dhat, lddh, F);
-    DME_HIP(hipGetLastError());
-    hipLaunchKernelGGL(chol_lower_kernel, dim3(1), dim3(kCT), 0, ax.s2, (int)k, F, k, status);
+    f_done = ax.record(ax.s2);
   }
-  DME_HIP(hipGetLastError());
-  const hipEvent_t f_done = ax.record(ax.s2);
   ws.used = mark_g;
   gemm_f64(s, 'T', 'N', k, k, n, 1.0, W, ldw, W, ldw, 0.0, G, k, &ws);
-  DME_HIP(hipStreamWaitEvent(s, f_done, 0));
-  // G <- F^T G F, symmetrised
   ws.used = mark_g;
-  gemm_f64(s, 'N', 'N', k, k, k, 1.0, G, k, F, k, 0.0, T1, k, &ws);
-  ws.used = mark_g;
-  gemm_f64(s, 'T', 'N', k, k, k, 1.0, F, k, T1, k, 0.0, G, k, &ws);
-  hipLaunchKernelGGL(sym_kernel, dim3(blocks(k * k)), dim3(256), 0, s, (int)k, G, S, flag_dev);
+  if (diag) {
+    hipLaunchKernelGGL(gram_scale_sym_kernel, dim3(blocks(k * k)), dim3(256), 0, s, (int)k, G, Dhat, lddh, S,
+                       status, flag_dev);
+  } else {
+    if (f_done) DME_HIP(hipStreamWaitEvent(s, f_done, 0));
+    // G <- F^T G F, symmetrised
+    gemm_f64(s, 'N', 'N', k, k, k, 1.0, G, k, F, k, 0.0, T1, k, &ws);
+    ws.used = mark_g;
+    gemm_f64(s, 'T', 'N', k, k, k, 1.0, F, k, T1, k, 0.0, G, k, &ws);
+    hipLaunchKernelGGL(sym_kernel, dim3(blocks(k * k)), dim3(256), 0, s, (int)k, G, S, flag_dev);
+  }
   DME_HIP(hipGetLastError());
   ws.used = mark_g;
   // the kept rank travels to the host from the second stream as soon as it is
@@ -501,7 +534,7 @@ int64_t compress_gram_f64(hipStream_t s, int64_t n, int64_t k, const double* W, 
   int64_t seq_rank = 0;
   SyevPost post;
   post.signs = false;
-  post.rank_veto = status;
+  post.rank_veto = fstatus;
   post.rank_seq = &seq_rank;
   syev_trunc_f64(s, k, S, k, tol, std::min(max_rank, k), lam, V, k, rank_dev, flag_dev, ws, post);
   ws.used = mark_g;
@@ -510,10 +543,11 @@ int64_t compress_gram_f64(hipStream_t s, int64_t n, int64_t k, const double* W, 
   const int64_t kmax = std::min(max_rank, k);
   const int64_t ks = (rank_hint > 0) ? std::min(kmax, rank_hint + 8) : kmax;
   auto form_L = [&](int64_t w) {
-    gemm_f64(s, 'N', 'N', k, w, k, 1.0, F, k, V, k, 0.0, T, k, &ws);
+    if (!diag) gemm_f64(s, 'N', 'N', k, w, k, 1.0, F, k, V, k, 0.0, T, k, &ws);
     ws.used = mark_g;
     const dim3 sg(cdiv(k, 256), (unsigned)std::min<int64_t>(w, 1024));
-    hipLaunchKernelGGL(scale_cols_kernel, sg, dim3(256), 0, s, (int)k, (int)w, lam, rank_dev, T, Dout, ldd, V, k);
+    hipLaunchKernelGGL(scale_cols_kernel, sg, dim3(256), 0, s, (int)k, (int)w, lam, rank_dev, T, Dout, ldd, V, k,
+                       diag ? Dhat : nullptr, lddh);
     DME_HIP(hipGetLastError());
     gemm_f64(s, 'N', 'N', n, w, k, 1.0, W, ldw, T, k, 0.0, L, ldl, &ws);
     ws.used = mark_g;

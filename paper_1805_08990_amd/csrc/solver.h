@@ -127,6 +127,10 @@ struct Solver {
   double t3 = 0.0;
   DevBuf lamT3, ZT3;
   DevBuf W, Dhat, WB, SL;
+  // the factor of a Dhat in that form, formed on the second stream beside
+  // the step product (kmax x kmax doubles, then its int64 status)
+  DevBuf Fpre;
+  bool f_ready = false;
   DevBuf flags;  // int flags[4]; int64 rank at offset 16
   Arena ws;
   AuxStream aux;  // second stream, event ring and rank slot of this solve

@@ -276,6 +276,7 @@ void Solver::setup(const dme_problem& prob, const dme_opts& o, bool dre,
   WB.ensure((size_t)max_rank * std::max<int64_t>(m, 1) * sizeof(double));
   lamT3.ensure((size_t)max_rank * sizeof(double));
   ZT3.ensure((size_t)max_rank * std::max<int64_t>(m, 1) * sizeof(double));
+  if (m >= 1 && m <= 8) Fpre.ensure((size_t)kmax * kmax * sizeof(double) + 64);
   if (has_S) SL.ensure((size_t)n * max_rank * sizeof(double));
   ws.reserve(workspace_bytes(n, m, max_rank, kmax, opts.precision) +
              leja_workspace(n, std::max<int64_t>(max_rank, (int64_t)opts.quad_nodes * p)));
@@ -402,6 +403,7 @@ size_t Solver::state_bytes(int64_t n, int64_t m, int64_t p, bool has_S, const dm
   add((size_t)n * km * 8 + (size_t)km * km * 8);                // W, Dhat
   add((size_t)mr * std::max<int64_t>(m, 1) * 8);                // W_B
   add((size_t)mr * (std::max<int64_t>(m, 1) + 1) * 8);          // lam and Z of a T3 update
+  if (m >= 1 && m <= 8) add((size_t)km * km * 8 + 64);          // its factor, formed ahead
   add(2 * ((size_t)n * Kp * 8 + (size_t)Kp * Kp * 8));          // quadrature factors (h and h/2)
   add(workspace_bytes(n, m, mr, km, o.precision));
   add(leja_workspace(n, std::max<int64_t>(mr, Kp)));
@@ -573,9 +575,12 @@ void Solver::compress_into(int64_t k, int ncopies) {
   // through the Gram matrix while Dhat is positive definite (every DLE / DRE
   // compression from a positive semidefinite P0), by Householder QR otherwise
   LowRankD lr{lamT3.as<double>(), ZT3.as<double>(), t3, r, m, ncopies};
+  const double* Fr = f_ready ? Fpre.as<double>() : nullptr;
+  const int64_t* Fs = f_ready ? reinterpret_cast<const int64_t*>(Fr + k * k) : nullptr;
+  f_ready = false;
   int64_t rn = compress_gram_f64(s, n, k, W.as<double>(), n, Dhat.as<double>(), k, d_diag,
                                  d_lowrank ? &lr : nullptr, opts.tol, max_rank, Ln(), n, Dn(), 0, rank_dev(),
-                                 flag_dev(), ws, r);  // the rank before: the guess for the new one
+                                 flag_dev(), ws, r, Fr, Fs);  // the rank before: the guess for the new one
   const double kk = (double)k;
   if (rn >= 0) {
     // W^T W 2 n k^2, L = W T 2 n k r', the k x k products and eigenproblem ~ 14 k^3
@@ -624,6 +629,13 @@ void Solver::apply_T12(double t, bool ext_product) {
     DME_HIP(hipStreamWaitEvent(ax.s2, ax.record(s), 0));
     blkdiag2_f64(ax.s2, Dc(), r, r, f.D.as<double>(), f.r, f.r, 1.0, Dhat.as<double>(), k);
     if (f.r > 0) copy_f64(ax.s2, f.L.as<double>(), n, Wd + r * n, n, n, f.r);
+    // after a T3 update the factor of Dhat too (the compression then waits
+    // for nothing more)
+    if (d_lowrank && Fpre.bytes > 0) {
+      const LowRankD lr{lamT3.as<double>(), ZT3.as<double>(), t3, r, m, 1};
+      double* F = Fpre.as<double>();
+      f_ready = gram_factor_lowrank(ax.s2, k, Dhat.as<double>(), k, lr, F, reinterpret_cast<int64_t*>(F + k * k));
+    }
     w_ready = ax.record(ax.s2);
   }
   if (r > 0 && !ext_product) apply_E(t, Lc(), r, Wd, n);
