@@ -21,8 +21,10 @@
 //      invit_kernel     : inverse iteration with a partially pivoted
 //                         tridiagonal LU for tied eigenvalues (and k > 512).
 //   5. polar steps      : clusters whose vectors are nearly orthonormal get
-//                         three Newton-Schulz steps Z <- Z (3I - Z^T Z) / 2 by
-//                         GEMMs (restricted to each cluster's block);
+//                         three Newton-Schulz steps Z <- Z (3I - Z^T Z) / 2
+//                         (restricted to each cluster's block), two MFMA
+//                         products a step: Z^T Z (the first one also checks
+//                         the clusters) and Z B with B formed as it is read;
 //      orth_kernel      : one workgroup per remaining cluster orthonormalises
 //                         its vectors (right-looking modified Gram-Schmidt,
 //                         two passes).
@@ -1314,30 +1316,71 @@ __global__ __launch_bounds__(128) void twist_kernel(const double* __restrict__ d
 constexpr double kPolarTol = 1e-2;
 constexpr int kPolarSteps = 3;
 
-// cl_fail[id] |= 1 when a cluster's Gram matrix is not close enough to I.
-__global__ void polar_check_kernel(const double* G, int ncol, const int* cl_of, const int* clusters,
-                                   int* cl_fail) {
-  const int64_t total = (int64_t)ncol * ncol;
-  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
-       idx += (int64_t)gridDim.x * blockDim.x) {
-    const int i = (int)(idx % ncol), j = (int)(idx / ncol);
-    const int ci = cl_of[i];
-    if (ci < 0 || ci != cl_of[j]) continue;
-    const double dev = fabs(G[idx] - (i == j ? 1.0 : 0.0));
-    if (!(dev * clusters[2 * ci + 1] < kPolarTol)) atomicOr(&cl_fail[ci], 1);
+// The products of a polar step on FP64 MFMA, one 16 x 16 tile of the result
+// a workgroup, the inner dimension over its four waves (as the small GEMMs):
+//   kPolarGram:  G = Z^T Z (ncol x ncol, Z k x ncol), and on the first step
+//                (check) cl_fail[c] |= 1 for a cluster c with an entry of
+//                len * |G - I| not below kPolarTol;
+//   kPolarApply: Zo = Z B, B = I + (i, j in one cluster that passed ?
+//                (I - G) / 2 : 0), B formed from G as it is read.
+typedef double pv4d __attribute__((ext_vector_type(4)));
+constexpr int kPolarGram = 0, kPolarApply = 1;
+template <int MODE>
+__global__ __launch_bounds__(256) void polar_gemm_kernel(int k, int ncol, const double* __restrict__ Z,
+                                                         const double* __restrict__ G, const int* cl_of,
+                                                         const int* clusters, int* cl_fail, bool check,
+                                                         double* __restrict__ out) {
+  __shared__ pv4d red[3][64];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int r16 = lane & 15, kq = lane >> 4;
+  const int M = (MODE == kPolarGram) ? ncol : k;  // rows of the result
+  const int K = (MODE == kPolarGram) ? k : ncol;  // inner dimension
+  const int m = blockIdx.x * 16 + r16, n = blockIdx.y * 16 + r16;
+  const bool min_ = m < M, nin = n < ncol;
+  const int cn = nin ? cl_of[n] : -1;
+  const bool nlive = (MODE == kPolarApply) && cn >= 0 && !cl_fail[cn];
+  auto opA = [&](int q) -> double {  // (m, q) of Z^T or of Z
+    if (!min_ || q >= K) return 0.0;
+    return (MODE == kPolarGram) ? Z[q + (int64_t)m * k] : Z[m + (int64_t)q * k];
+  };
+  auto opB = [&](int q) -> double {  // (q, n) of Z or of B
+    if (!nin || q >= K) return 0.0;
+    if (MODE == kPolarGram) return Z[q + (int64_t)n * k];
+    const double dl = (q == n) ? 1.0 : 0.0;
+    return (nlive && cl_of[q] == cn) ? dl + 0.5 * (dl - G[q + (int64_t)n * ncol]) : dl;
+  };
+  pv4d acc = pv4d{0.0, 0.0, 0.0, 0.0};
+  constexpr int U = 4;
+  for (int k0 = 4 * wave; k0 < K; k0 += 16 * U) {
+    double fa[U], fb[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int q = k0 + 16 * u + kq;
+      fa[u] = opB(q);
+      fb[u] = opA(q);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[u], fb[u], acc, 0, 0, 0);
   }
-}
-
-// B = I + (i, j in one cluster that passed ? (I - G) / 2 : 0)
-__global__ void polar_b_kernel(const double* G, int ncol, const int* cl_of, const int* cl_fail, double* B) {
-  const int64_t total = (int64_t)ncol * ncol;
-  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
-       idx += (int64_t)gridDim.x * blockDim.x) {
-    const int i = (int)(idx % ncol), j = (int)(idx / ncol);
-    const int ci = cl_of[i];
-    const double dl = (i == j) ? 1.0 : 0.0;
-    const bool live = ci >= 0 && ci == cl_of[j] && !cl_fail[ci];
-    B[idx] = live ? dl + 0.5 * (dl - G[idx]) : dl;
+  if (wave > 0) red[wave - 1][lane] = acc;
+  __syncthreads();
+  if (wave == 0) {
+#pragma unroll
+    for (int w = 0; w < 3; ++w) acc += red[w][lane];
+    const int cm = (MODE == kPolarGram && check && min_) ? cl_of[m] : -1;
+    bool bad = false;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int nn = blockIdx.y * 16 + v * 4 + kq;
+      if (min_ && nn < ncol) {
+        out[m + (int64_t)nn * M] = acc[v];
+        if (cm >= 0 && cl_of[nn] == cm) {
+          const double dev = fabs(acc[v] - (m == nn ? 1.0 : 0.0));
+          if (!(dev * clusters[2 * cm + 1] < kPolarTol)) bad = true;
+        }
+      }
+    }
+    if (bad) atomicOr(&cl_fail[cm], 1);
   }
 }
 
@@ -1532,7 +1575,7 @@ size_t syev_workspace(int64_t k) {
   b += (size_t)k * 2 * sizeof(int) + 256;
   b += (size_t)k * kInvitArrays * k * sizeof(double) + 256;  // inverse-iteration arrays
   b += (size_t)k * k * sizeof(double) + 256;      // Zt
-  b += 3 * ((size_t)k * k * sizeof(double) + 256);  // polar steps: G, B, Z1
+  b += 2 * ((size_t)k * k * sizeof(double) + 256);  // polar steps: G, Z1
   b += 2 * ((size_t)k * sizeof(int) + 256);          // cl_of, cl_fail
   b += gemm_f64_workspace(k, k, k);
   b += (size_t)k * k * sizeof(double) + 256;      // Q
@@ -1654,20 +1697,16 @@ void syev_trunc_f64(hipStream_t s, int64_t k, const double* M, int64_t ldm, doub
   {
     const int nc = (int)nkeep;
     double* G = ws.get<double>((size_t)nc * nc);
-    double* Bm = ws.get<double>((size_t)nc * nc);
     double* Z1 = ws.get<double>((size_t)k * nc);
-    const size_t mark = ws.used;
-    const unsigned gb = (unsigned)std::max<int64_t>(1, std::min<int64_t>(cdiv((int64_t)nc * nc, 256), 1024));
     double* Zo = Z1;  // Zf -> Zo each step
+    const dim3 gg((unsigned)cdiv(nc, 16), (unsigned)cdiv(nc, 16)), ga((unsigned)cdiv(k, 16), (unsigned)cdiv(nc, 16));
     for (int step = 0; step < kPolarSteps; ++step) {
-      gemm_f64(s, 'T', 'N', nc, nc, k, 1.0, Zf, k, Zf, k, 0.0, G, nc, &ws);
-      ws.used = mark;
-      if (step == 0)
-        hipLaunchKernelGGL(polar_check_kernel, dim3(gb), dim3(256), 0, s, G, nc, cl_of, clusters, cl_fail);
-      hipLaunchKernelGGL(polar_b_kernel, dim3(gb), dim3(256), 0, s, G, nc, cl_of, cl_fail, Bm);
+      hipLaunchKernelGGL(polar_gemm_kernel<kPolarGram>, gg, dim3(256), 0, s, ki, nc, Zf, (const double*)nullptr,
+                         cl_of, clusters, cl_fail, step == 0, G);
       DME_HIP(hipGetLastError());
-      gemm_f64(s, 'N', 'N', k, nc, nc, 1.0, Zf, k, Bm, nc, 0.0, Zo, k, &ws);
-      ws.used = mark;
+      hipLaunchKernelGGL(polar_gemm_kernel<kPolarApply>, ga, dim3(256), 0, s, ki, nc, Zf, G, cl_of, clusters,
+                         cl_fail, false, Zo);
+      DME_HIP(hipGetLastError());
       std::swap(Zf, Zo);
     }
     // cluster staging in LDS: up to 144 KiB, never more than the whole k x k set
