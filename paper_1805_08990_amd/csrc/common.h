@@ -8,6 +8,7 @@
 #include <cfloat>
 #include <cmath>
 #include <cstdint>
+#include <functional>
 #include <string>
 #include <vector>
 
@@ -175,6 +176,10 @@ void gemm_f64(hipStream_t s, char ta, char tb, int64_t M, int64_t N, int64_t K,
 // Workspace (bytes) gemm_f64 may need for a split-K launch of this shape.
 size_t gemm_f64_workspace(int64_t M, int64_t N, int64_t K);
 
+// Rows a workgroup of the split-BF16 step product takes, the unit a row
+// range of that product is cut in.
+constexpr int kRowBlock = 128;
+
 // Elementwise / small helpers (elementwise.hip)
 void fill_f64(hipStream_t s, double* X, int64_t rows, int64_t cols, int64_t ld, double v);
 void copy_f64(hipStream_t s, const double* X, int64_t ldx, double* Y, int64_t ldy,
@@ -307,11 +312,18 @@ size_t compress_gram_workspace(int64_t n, int64_t k);
 // F_ready (optional, k x k, ld k): the factor of Dhat already formed on the
 // device by gram_factor_lowrank, ordered before the work s holds; its status
 // (0, or -1 when Dhat is not positive definite) in *status_ready.
+// T_keep (optional, k x min(max_rank, k), ld k): receives T = F V_I
+// Lam_I^-1/2, so that L = W T (columns from the rank on zero).
+// beside (optional): called once, after the Gram matrix and before the
+// eigensolver are enqueued, with an event recorded on s there; work the
+// caller enqueues on another stream after that event runs beside the
+// eigensolver's one-workgroup tridiagonal reduction.
 int64_t compress_gram_f64(hipStream_t s, int64_t n, int64_t k, const double* W, int64_t ldw,
                           const double* Dhat, int64_t lddh, bool dhat_diag, const LowRankD* lowrank,
                           double tol, int64_t max_rank, double* L, int64_t ldl, double* Dout, int64_t ldd,
                           int64_t* rank_dev, int* flag_dev, Arena& ws, int64_t rank_hint = 0,
-                          const double* F_ready = nullptr, const int64_t* status_ready = nullptr);
+                          const double* F_ready = nullptr, const int64_t* status_ready = nullptr,
+                          double* T_keep = nullptr, const std::function<void(hipEvent_t)>* beside = nullptr);
 // Launches the closed-form factor F (k x k, ld k) of a Dhat in the LowRankD
 // form on st, with its status in *status; returns false, launching nothing,
 // when the form's limits (m <= 8, r <= 256) do not hold.

@@ -243,32 +243,35 @@ __global__ __launch_bounds__(256) void gemm_f64_small_kernel(int M, int N, int K
 }
 
 // Gram products C = alpha W^T W + beta C of a tall W (n x k, k <= 192, n >=
-// kSyMinK): the compression's W^T W.  A workgroup stages 64-row blocks of W in
-// LDS (each row block read from HBM once) and accumulates the upper 16 x 16
-// tiles of W_b^T W_b on FP64 MFMA, a wave taking every fourth tile pair, so
+// kSyMinK): the compression's W^T W.  A workgroup (eight waves) stages 64-row
+// blocks of W in LDS (each row block read from HBM once, every load of a
+// thread issued before its first LDS store) and accumulates the upper 16 x 16
+// tiles of W_b^T W_b on FP64 MFMA, a wave taking every eighth tile pair, so
 // that a tile's accumulator is updated once per 4-deep step with the other
-// pairs' MFMAs between (no dependent issue).  Workgroup b adds row blocks
-// b, b + grid, ... and writes its upper tiles to partial[b]; a second kernel
-// sums the partials in workgroup order and writes both triangles from the
-// upper one (C is exactly symmetric).
+// pairs' MFMAs between (no dependent issue), two waves per SIMD.  Workgroup b
+// adds row blocks b, b + grid, ... and writes its upper tiles to partial[b];
+// a second kernel sums the partials and writes both triangles from the upper
+// one (C is exactly symmetric).
 constexpr int kSyMaxT = 12;     // k <= 192
 constexpr int kSyRows = 64;     // rows of W per LDS stage
 constexpr int kSyMinK = 2048;   // rows of W from which this path is taken
 constexpr int kSyMaxGrid = 256;
+constexpr int kSyWaves = 8;
 
 template <int T>
-__global__ __launch_bounds__(256) void syrk_tn_kernel(int n, int k, const double* __restrict__ W, int64_t ldw,
-                                                      double* __restrict__ partial) {
-  constexpr int NP = T * (T + 1) / 2;  // upper tile pairs
-  constexpr int PW = (NP + 3) / 4;     // pairs per wave
-  constexpr int LD = 16 * T + 1;       // LDS row stride (doubles)
-  extern __shared__ double sW[];       // kSyRows x LD
+__global__ __launch_bounds__(64 * kSyWaves) void syrk_tn_kernel(int n, int k, const double* __restrict__ W,
+                                                                int64_t ldw, double* __restrict__ partial) {
+  constexpr int NP = T * (T + 1) / 2;                     // upper tile pairs
+  constexpr int PW = (NP + kSyWaves - 1) / kSyWaves;      // pairs per wave
+  constexpr int LD = 16 * T + 1;                          // LDS row stride (doubles)
+  constexpr int NL = kSyRows * 16 * T / (64 * kSyWaves);  // entries a thread stages per block
+  extern __shared__ double sW[];                          // kSyRows x LD
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int r16 = lane & 15, kq = lane >> 4;
   int ta[PW], tb[PW];
 #pragma unroll
   for (int q = 0; q < PW; ++q) {
-    int p = wave + 4 * q, b = 0;
+    int p = wave + kSyWaves * q, b = 0;
     while (p >= b + 1) {  // pair p = b (b + 1) / 2 + a, a <= b
       p -= b + 1;
       ++b;
@@ -281,18 +284,27 @@ __global__ __launch_bounds__(256) void syrk_tn_kernel(int n, int k, const double
   for (int q = 0; q < PW; ++q) acc[q] = v4d{0.0, 0.0, 0.0, 0.0};
   for (int blk = blockIdx.x; (int64_t)blk * kSyRows < n; blk += gridDim.x) {
     const int64_t r0 = (int64_t)blk * kSyRows;
-    __syncthreads();  // the previous stage is consumed
-    for (int idx = tid; idx < kSyRows * 16 * T; idx += 256) {
-      const int row = idx % kSyRows, col = idx / kSyRows;
-      sW[row * LD + col] = (r0 + row < n && col < k) ? W[r0 + row + (int64_t)col * ldw] : 0.0;
+    // row lane of the block, columns wave + 8 u (an entry out of range reads
+    // entry 0 and is zeroed, so that the loads need no branch)
+    const bool rok = r0 + lane < n;
+    double st[NL];
+#pragma unroll
+    for (int u = 0; u < NL; ++u) {
+      const int col = wave + kSyWaves * u;
+      const bool ok = rok && col < k;
+      st[u] = W[ok ? r0 + lane + (int64_t)col * ldw : 0];
+      st[u] = ok ? st[u] : 0.0;
     }
+    __syncthreads();  // the previous stage is consumed
+#pragma unroll
+    for (int u = 0; u < NL; ++u) sW[lane * LD + wave + kSyWaves * u] = st[u];
     __syncthreads();
 #pragma unroll 4
     for (int kk = 0; kk < kSyRows / 4; ++kk) {
       const double* rowp = sW + (4 * kk + kq) * LD + r16;
 #pragma unroll
       for (int q = 0; q < PW; ++q)
-        if (wave + 4 * q < NP)
+        if (wave + kSyWaves * q < NP)
           acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(rowp[16 * tb[q]], rowp[16 * ta[q]], acc[q], 0, 0, 0);
     }
   }
@@ -300,7 +312,7 @@ __global__ __launch_bounds__(256) void syrk_tn_kernel(int n, int k, const double
   double* out = partial + (int64_t)blockIdx.x * k * k;
 #pragma unroll
   for (int q = 0; q < PW; ++q)
-    if (wave + 4 * q < NP) {
+    if (wave + kSyWaves * q < NP) {
       const int m = 16 * ta[q] + r16;
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
@@ -310,39 +322,57 @@ __global__ __launch_bounds__(256) void syrk_tn_kernel(int n, int k, const double
     }
 }
 
-// C(m, n) = C(n, m) = alpha sum_b partial[b](min, max) (+ beta C): one thread
-// per upper-triangle entry, eight partials in flight over eight chains added
-// in a fixed order (deterministic).
-__global__ void syrk_reduce_kernel(int k, int nb, double alpha, const double* __restrict__ partial, double beta,
-                                   double* __restrict__ C, int64_t ldc) {
-  const int64_t kk = (int64_t)k * k;
-  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < kk;
-       idx += (int64_t)gridDim.x * blockDim.x) {
-    const int i = (int)(idx % k), j = (int)(idx / k);
-    if (i > j) continue;
+// C(i, j) = C(j, i) = alpha sum_b partial[b](i, j) (+ beta C) over the upper
+// triangle i <= j: a block takes 32 entries and its eight 32-thread groups
+// the partials b = g mod 8 (eight loads in flight each); the group sums are
+// added in a fixed order (deterministic).
+__global__ __launch_bounds__(256) void syrk_reduce_kernel(int k, int nb, double alpha,
+                                                          const double* __restrict__ partial, double beta,
+                                                          double* __restrict__ C, int64_t ldc) {
+  __shared__ double red[8][33];
+  const int64_t kk = (int64_t)k * k, nup = (int64_t)k * (k + 1) / 2;
+  const int e = threadIdx.x & 31, g = threadIdx.x >> 5;
+  for (int64_t base = (int64_t)blockIdx.x * 32; base < nup; base += (int64_t)gridDim.x * 32) {
+    const int64_t u = base + e;
+    int i = 0, j = 0;
+    if (u < nup) {  // u = j (j + 1) / 2 + i, i <= j
+      j = (int)((sqrt(8.0 * (double)u + 1.0) - 1.0) * 0.5);
+      while ((int64_t)j * (j + 1) / 2 > u) --j;
+      while ((int64_t)(j + 1) * (j + 2) / 2 <= u) ++j;
+      i = (int)(u - (int64_t)j * (j + 1) / 2);
+    }
+    const double* pp = partial + i + (int64_t)j * k;
     double sc[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-    int b = 0;
-    for (; b + 8 <= nb; b += 8) {
-      double v[8];
+    if (u < nup) {
+      int b = g;
+      for (; b + 56 < nb; b += 64) {
+        double v[8];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) v[u] = partial[(b + u) * kk + idx];
+        for (int q = 0; q < 8; ++q) v[q] = pp[(int64_t)(b + 8 * q) * kk];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) sc[u] += v[u];
+        for (int q = 0; q < 8; ++q) sc[q] += v[q];
+      }
+      for (; b < nb; b += 8) sc[0] += pp[(int64_t)b * kk];
     }
-    for (; b < nb; ++b) sc[0] += partial[b * kk + idx];
-    const double sum = ((sc[0] + sc[1]) + (sc[2] + sc[3])) + ((sc[4] + sc[5]) + (sc[6] + sc[7]));
-    const double out = alpha * sum;
-    double* c1 = C + i + (int64_t)j * ldc;
-    double* c2 = C + j + (int64_t)i * ldc;
-    if (beta == 0.0) {
-      *c1 = out;
-      *c2 = out;
-    } else {
-      const double v1 = out + beta * (*c1);
-      const double v2 = (i == j) ? v1 : out + beta * (*c2);
-      *c1 = v1;
-      *c2 = v2;
+    red[g][e] = ((sc[0] + sc[1]) + (sc[2] + sc[3])) + ((sc[4] + sc[5]) + (sc[6] + sc[7]));
+    __syncthreads();
+    if (g == 0 && u < nup) {
+      const double sum = ((red[0][e] + red[1][e]) + (red[2][e] + red[3][e])) +
+                         ((red[4][e] + red[5][e]) + (red[6][e] + red[7][e]));
+      const double out = alpha * sum;
+      double* c1 = C + i + (int64_t)j * ldc;
+      double* c2 = C + j + (int64_t)i * ldc;
+      if (beta == 0.0) {
+        *c1 = out;
+        *c2 = out;
+      } else {
+        const double v1 = out + beta * (*c1);
+        const double v2 = (i == j) ? v1 : out + beta * (*c2);
+        *c1 = v1;
+        *c2 = v2;
+      }
     }
+    __syncthreads();  // red is reused
   }
 }
 
@@ -656,7 +686,8 @@ void gemm_f64(hipStream_t s, char ta, char tb, int64_t M, int64_t N, int64_t K, 
     switch (T) {
 #define DME_SYRK(TT)                                                                                    \
   case TT:                                                                                              \
-    hipLaunchKernelGGL((syrk_tn_kernel<TT>), dim3(grid), dim3(256), lds, s, (int)K, (int)M, A, lda, partial); \
+    hipLaunchKernelGGL((syrk_tn_kernel<TT>), dim3(grid), dim3(64 * kSyWaves), lds, s, (int)K, (int)M, A, lda, \
+                       partial);                                                                      \
     break;
       DME_SYRK(1) DME_SYRK(2) DME_SYRK(3) DME_SYRK(4) DME_SYRK(5) DME_SYRK(6)
       DME_SYRK(7) DME_SYRK(8) DME_SYRK(9) DME_SYRK(10) DME_SYRK(11) DME_SYRK(12)
@@ -664,8 +695,8 @@ void gemm_f64(hipStream_t s, char ta, char tb, int64_t M, int64_t N, int64_t K, 
       default: fail(DME_EINTERNAL, "syrk: bad tile count");
     }
     DME_HIP(hipGetLastError());
-    hipLaunchKernelGGL(syrk_reduce_kernel, dim3((unsigned)std::min<int64_t>(cdiv(M * M, 256), 1024)), dim3(256), 0,
-                       s, (int)M, grid, alpha, partial, beta, C, ldc);
+    hipLaunchKernelGGL(syrk_reduce_kernel, dim3((unsigned)std::min<int64_t>(cdiv(M * (M + 1) / 2, 32), 4096)),
+                       dim3(256), 0, s, (int)M, grid, alpha, partial, beta, C, ldc);
     DME_HIP(hipGetLastError());
     return;
   }

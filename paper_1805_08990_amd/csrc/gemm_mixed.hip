@@ -387,14 +387,24 @@ size_t gemm_mixed_workspace(int64_t n, int64_t r) {
          (size_t)ns * n * std::min<int64_t>(r, 16 * kMaxTN) * sizeof(double) + 256;
 }
 
-// Y (n x r, ld ldy, FP64) = E X with X (n x r, ld ldx, FP64).
+static_assert(kMRows == kRowBlock, "row block of the split-BF16 product");
+
+int gemm_mixed_nsplit(int64_t n) { return nsplit_for(n); }
+
+// Rows [row0, row0 + rows) of Y (n x r, ld ldy, FP64) = E X with X (n x r,
+// ld ldx, FP64); rows < 0: all of them.  ns_force > 0 cuts the inner
+// dimension into that many chunks instead of the default.
 void gemm_mixed(hipStream_t s, const MixedOp& op, const double* X, int64_t ldx, int64_t r, double* Y,
-                int64_t ldy, Arena& ws) {
-  const int64_t n = op.n;
-  if (n <= 0 || r <= 0) return;
-  DME_REQUIRE(n < (1ll << 30), DME_EINVAL, "mixed gemm: n too large");
-  const int ns = nsplit_for(n);
-  const int kchunk = (int)(cdiv(cdiv(op.lde, ns), kMKGran) * kMKGran);
+                int64_t ldy, Arena& ws, int64_t row0, int64_t rows, int ns_force) {
+  const int64_t nk = op.n;  // inner dimension
+  if (rows < 0) rows = nk - row0;
+  if (nk <= 0 || r <= 0 || rows <= 0) return;
+  DME_REQUIRE(nk < (1ll << 30) && row0 >= 0 && row0 + rows <= nk, DME_EINVAL, "mixed gemm: bad rows");
+  const int64_t n = rows;  // rows of the result this call forms
+  const int ns0 = ns_force > 0 ? ns_force : nsplit_for(nk);
+  const int kchunk = (int)(cdiv(cdiv(op.lde, ns0), kMKGran) * kMKGran);
+  const int ns = (int)cdiv(op.lde, kchunk);  // no empty chunk
+  Y += row0;
   const size_t mark = ws.used;
   for (int64_t c0 = 0; c0 < r; c0 += 16 * kMaxTN) {
     const int64_t rc = std::min<int64_t>(r - c0, 16 * kMaxTN);
@@ -404,9 +414,9 @@ void gemm_mixed(hipStream_t s, const MixedOp& op, const double* X, int64_t ldx, 
     u16* Xs = ws.get<u16>((size_t)3 * op.lde * rpad);
     double* partial = ws.get<double>((size_t)ns * n * rc);
     hipLaunchKernelGGL(mixed_split_x_kernel, dim3((unsigned)std::min<int64_t>(cdiv(op.lde * rpad, 256), 8192)),
-                       dim3(256), 0, s, X + c0 * ldx, ldx, n, rc, op.lde, rpad, Xs);
+                       dim3(256), 0, s, X + c0 * ldx, ldx, nk, rc, op.lde, rpad, Xs);
     DME_HIP(hipGetLastError());
-    const float* Et = op.Et.as<float>();
+    const float* Et = op.Et.as<float>() + row0 * op.lde;
     KernelTimer* kt = kernel_timer();
     if (kt) kt->before(s);
     switch (tn) {
@@ -418,7 +428,7 @@ void gemm_mixed(hipStream_t s, const MixedOp& op, const double* X, int64_t ldx, 
       default: fail(DME_EINTERNAL, "mixed gemm: bad tile count");
     }
     DME_HIP(hipGetLastError());
-    if (kt) kt->after(s, n, rc, n, (int)sizeof(float));
+    if (kt) kt->after(s, n, rc, nk, (int)sizeof(float));
     hipLaunchKernelGGL(mixed_reduce_kernel, dim3((unsigned)std::min<int64_t>(cdiv(n * rc, 256), 8192)),
                        dim3(256), 0, s, partial, n, rc, ns, Y + c0 * ldy, ldy);
     DME_HIP(hipGetLastError());

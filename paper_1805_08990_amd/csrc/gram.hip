@@ -478,7 +478,8 @@ int64_t compress_gram_f64(hipStream_t s, int64_t n, int64_t k, const double* W, 
                           const double* Dhat, int64_t lddh, bool dhat_diag, const LowRankD* lowrank,
                           double tol, int64_t max_rank, double* L, int64_t ldl, double* Dout, int64_t ldd,
                           int64_t* rank_dev, int* flag_dev, Arena& ws, int64_t rank_hint,
-                          const double* F_ready, const int64_t* status_ready) {
+                          const double* F_ready, const int64_t* status_ready, double* T_keep,
+                          const std::function<void(hipEvent_t)>* beside) {
   if (k <= 0 || n <= 0) return 0;
   const size_t mark = ws.used;
   double* Fw = ws.get<double>((size_t)k * k);
@@ -486,7 +487,7 @@ int64_t compress_gram_f64(hipStream_t s, int64_t n, int64_t k, const double* W, 
   double* T1 = ws.get<double>((size_t)k * k);
   double* S = ws.get<double>((size_t)k * k);
   double* V = ws.get<double>((size_t)k * k);
-  double* T = ws.get<double>((size_t)k * k);
+  double* T = T_keep ? T_keep : ws.get<double>((size_t)k * k);
   double* lam = ws.get<double>(k);
   int64_t* status = ws.get<int64_t>(8);
   const size_t mark_g = ws.used;
@@ -529,6 +530,9 @@ int64_t compress_gram_f64(hipStream_t s, int64_t n, int64_t k, const double* W, 
   }
   DME_HIP(hipGetLastError());
   ws.used = mark_g;
+  // work the caller runs beside the eigensolver (which keeps one CU busy
+  // through the tridiagonal reduction), ordered after the Gram matrix
+  if (beside && *beside) (*beside)(aux_stream().record(s));
   // the kept rank travels to the host from the second stream as soon as it is
   // known; the eigenvectors' signs are applied with the column scaling below
   int64_t seq_rank = 0;

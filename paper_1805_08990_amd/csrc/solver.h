@@ -76,9 +76,13 @@ struct QuadFactor {
 void mixed_op_build(hipStream_t s, int64_t n, const double* E, MixedOp& op);
 std::shared_ptr<MixedOp> mixed_op_new();
 // Y (n x r, ld ldy) = E X on BF16 MFMA with three-piece splits, FP32 chunk
-// accumulation and an FP64 sum over chunks.
+// accumulation and an FP64 sum over chunks; or only the rows [row0, row0 +
+// rows) of Y, with the inner dimension cut into ns_force chunks (0: the
+// default split, gemm_mixed_nsplit).  One workgroup per kRowBlock rows and
+// chunk.
 void gemm_mixed(hipStream_t s, const MixedOp& op, const double* X, int64_t ldx, int64_t r, double* Y,
-                int64_t ldy, Arena& ws);
+                int64_t ldy, Arena& ws, int64_t row0 = 0, int64_t rows = -1, int ns_force = 0);
+int gemm_mixed_nsplit(int64_t n);
 size_t gemm_mixed_workspace(int64_t n, int64_t r);
 
 struct PhaseAcc {
@@ -131,6 +135,32 @@ struct Solver {
   // the step product (kmax x kmax doubles, then its int64 status)
   DevBuf Fpre;
   bool f_ready = false;
+
+  // Step products ahead of need (the split-BF16 mode with dense operators,
+  // every T12 of the step with the same t, driven by advance()).  A
+  // compression through the Gram matrix
+  // gives L = W T with W = [Y, L_I], so the next T12 needs
+  // e^{tA^T} L = [e^{tA^T} Y, e^{tA^T} L_I] T: the product e^{tA^T} Y can
+  // start before the compression ends.  Its first rows run on s3 beside the
+  // compression's one-workgroup tridiagonal reduction, the rest when the next
+  // T12 needs them; e^{tA^T} L_I is formed once per t.
+  //   EW (n x (max_rank + K p)): e^{tA^T} Y in the columns [max_rank - ey_cols,
+  //   max_rank), e^{tA^T} L_I from column max_rank on (so the two are one
+  //   n x k operand); Tk: T of the last such compression (tk_k x rank, ld tk_k).
+  DevBuf EW, Tk;
+  std::map<double, DevBuf> ELI;  // t -> e^{tA^T} L_I (n x its rank), FP64
+  double eli_t = -1.0;           // the t whose e^{tA^T} L_I is in EW
+  bool ahead = false;            // set by advance() (a server groups its products instead)
+  bool ahead_same_t = false;     // every T12 stage of the step has the same t
+  bool ey_ok = false;            // EW holds (rows [0, ey_rows) of) e^{ey_t A^T} W[:, 0:ey_cols]
+  double ey_t = 0.0;
+  int64_t ey_cols = 0, ey_rows = 0;
+  bool tk_ok = false;
+  int64_t tk_k = 0;
+  int cus = 0;                   // compute units of the device
+  hipStream_t s3 = nullptr;
+  hipEvent_t ey_done = nullptr;  // the rows formed on s3
+  Arena ws3;
   DevBuf flags;  // int flags[4]; int64 rank at offset 16
   Arena ws;
   AuxStream aux;  // second stream, event ring and rank slot of this solve
@@ -145,9 +175,11 @@ struct Solver {
   PhaseAcc phase[5];
   std::vector<PendingTiming> pending;
   std::vector<hipEvent_t> event_pool;
-  hipEvent_t mark_begin();
+  // events on st (the solve's stream when null)
+  hipEvent_t mark_begin(hipStream_t st = nullptr);
   // launches: how many launches of the phase's kernel the interval holds
-  void mark_end(int ph, hipEvent_t a, double flops, double bytes, int64_t launches = 1);
+  void mark_end(int ph, hipEvent_t a, double flops, double bytes, int64_t launches = 1,
+                hipStream_t st = nullptr);
   void flush_timings();
   ~Solver();
 
@@ -194,7 +226,28 @@ struct Solver {
   void apply_T4(double t);
   // W (n x k), Dhat (k x k) -> new (L, D); Dhat holds ncopies copies of D
   // (from row 0), the rest of it is diagonal
-  void compress_into(int64_t k, int ncopies = 1);
+  // ahead_t > 0: W[:, 0:r] is Y of a T12 with that t, and the next T12's
+  // product goes ahead beside this compression
+  void compress_into(int64_t k, int ncopies = 1, double ahead_t = 0.0);
+  // rows [row0, row0 + rows) of e^{tA^T} X (X n x cols) into EW's product
+  // columns, ns chunks of the inner dimension, on st with arena a
+  void product_rows(double t, const double* X, int64_t cols, int64_t row0, int64_t rows, int ns,
+                    hipStream_t st, Arena& a);
+  void drop_ahead() { ey_ok = false; tk_ok = false; }
+  // the solve's stream waits for rows still forming on s3 (they read
+  // W[:, 0:ey_cols]) before anything writes W again
+  bool beside_live = false;
+  void settle_beside() {
+    if (beside_live) DME_HIP(hipStreamWaitEvent(s, ey_done, 0));
+    beside_live = false;
+  }
+  // split of the inner dimension for `rows` rows of the split-BF16 step
+  // product in one wave of workgroups (beside: leaving one CU to the
+  // tridiagonal reduction)
+  int fill_split(int64_t rows, bool beside) const;
+  // rows of the next product to form beside a compression of width k (a
+  // multiple of kRowBlock, or n; 0: none) and their split
+  void plan_beside(int64_t k, int64_t* rows, int* ns) const;
   void apply_E(double t, const double* X, int64_t r, double* Y, int64_t ldy);
   void build_quadrature(double t);
   void apply_mass_matrix(const double* M);

@@ -114,7 +114,7 @@ void upload(hipStream_t s, DevBuf& dst, const double* src, size_t count) {
 
 }  // namespace
 
-hipEvent_t Solver::mark_begin() {
+hipEvent_t Solver::mark_begin(hipStream_t st) {
   if (!profiling) return nullptr;
   hipEvent_t e;
   if (!event_pool.empty()) {
@@ -123,19 +123,20 @@ hipEvent_t Solver::mark_begin() {
   } else {
     DME_HIP(hipEventCreate(&e));
   }
-  DME_HIP(hipEventRecord(e, s));
+  DME_HIP(hipEventRecord(e, st ? st : s));
   return e;
 }
 
-void Solver::mark_end(int ph, hipEvent_t a, double flops, double bytes, int64_t launches) {
+void Solver::mark_end(int ph, hipEvent_t a, double flops, double bytes, int64_t launches, hipStream_t st) {
   if (!profiling || a == nullptr) return;
-  hipEvent_t b = mark_begin();
+  hipEvent_t b = mark_begin(st);
   pending.push_back({ph, a, b, flops, bytes, launches});
 }
 
 void Solver::flush_timings() {
   if (pending.empty()) return;
   DME_HIP(hipStreamSynchronize(s));
+  if (s3) DME_HIP(hipStreamSynchronize(s3));
   for (const PendingTiming& t : pending) {
     float ms = 0.f;
     DME_HIP(hipEventElapsedTime(&ms, t.a, t.b));
@@ -154,6 +155,11 @@ Solver::~Solver() {
   // the solve's work on both of its streams ends before its events, rank slot
   // and device buffers go
   (void)hipStreamSynchronize(s);
+  if (s3) {
+    (void)hipStreamSynchronize(s3);
+    (void)hipStreamDestroy(s3);
+  }
+  if (ey_done) (void)hipEventDestroy(ey_done);
   aux.release();
   for (const PendingTiming& t : pending) {
     (void)hipEventDestroy(t.a);
@@ -226,10 +232,21 @@ void Solver::setup(const dme_problem& prob, const dme_opts& o, bool dre,
     m = 0;
   }
   seq = step_sequence(dre, has_S, opts.split, opts.scheme);
+  {
+    double t12 = -1.0;
+    ahead_same_t = true;
+    for (const Stage& st : seq)
+      if (st.sub == Sub::T12) {
+        if (t12 >= 0.0 && st.frac != t12) ahead_same_t = false;
+        t12 = st.frac;
+      }
+    if (t12 < 0.0) ahead_same_t = false;
+  }
   sizes_for(n, p, opts, &max_rank, &kmax);
   DME_REQUIRE(prob.r0 <= max_rank, DME_EINVAL, "r0 exceeds max_rank");
 
   DME_HIP(hipSetDevice(device));
+  DME_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device));
   flags.ensure(64);
   fill_f64(s, flags.as<double>(), 8, 1, 8, 0.0);
 
@@ -525,14 +542,33 @@ namespace {
 struct StepKernelTimer : KernelTimer {
   Solver* sv = nullptr;
   hipEvent_t a = nullptr;
-  void before(hipStream_t) override { a = sv->mark_begin(); }
-  void after(hipStream_t, int64_t m, int64_t ncols, int64_t k, int e_bytes) override {
+  void before(hipStream_t st) override { a = sv->mark_begin(st); }
+  void after(hipStream_t st, int64_t m, int64_t ncols, int64_t k, int e_bytes) override {
     sv->mark_end(DME_PHASE_STEP_KERNEL, a, 2.0 * m * k * ncols,
-                 (double)e_bytes * m * k + 8.0 * ((double)k * ncols + (double)m * ncols));
+                 (double)e_bytes * m * k + 8.0 * ((double)k * ncols + (double)m * ncols), 1, st);
     a = nullptr;
   }
 };
+// The split of the inner dimension (n) that gives `rows` rows of the
+// split-BF16 step product one wave of workgroups on `slots` CUs (one
+// workgroup per CU and per kRowBlock rows and chunk): the wave's time falls
+// with the chunk length (chunks of at least 1024).
+int fill_split_for(int64_t rows, int64_t slots, int64_t n) {
+  const int64_t rb = cdiv(rows, kRowBlock);
+  const int64_t cap = std::max<int64_t>(1, n / 1024);
+  return (int)std::max<int64_t>(1, std::min<int64_t>(slots / std::max<int64_t>(rb, 1), cap));
+}
+
 }  // namespace
+
+int Solver::fill_split(int64_t rows, bool beside) const {
+  return fill_split_for(rows, (int64_t)cus - (beside ? 1 : 0), n);
+}
+
+void Solver::product_rows(double t, const double* X, int64_t cols, int64_t row0, int64_t rows, int ns,
+                          hipStream_t st, Arena& a) {
+  gemm_mixed(st, *ops.at(t)->mix, X, n, cols, EW.as<double>() + (max_rank - cols) * n, n, a, row0, rows, ns);
+}
 
 void Solver::apply_E(double t, const double* X, int64_t rr, double* Y, int64_t ldy) {
   ws.reset();
@@ -569,7 +605,30 @@ void Solver::apply_E(double t, const double* X, int64_t rr, double* Y, int64_t l
   kernel_timer() = prev;
 }
 
-void Solver::compress_into(int64_t k, int ncopies) {
+void Solver::plan_beside(int64_t k, int64_t* rows_out, int* ns_out) const {
+  *rows_out = 0;
+  *ns_out = 0;
+  if (r <= 0 || n < kRowBlock || cus < 2) return;
+  // expected time of the tridiagonal reduction (one workgroup, about 1.9 us
+  // a step on gfx950), with a margin
+  const double tau = 0.85 * 1.9e-6 * (double)k;
+  // one wave of the whole product: the kernel reads the FP32 operator at
+  // about 2.8 TB/s
+  const double t_full = 4.0 * (double)n * n / 2.8e12;
+  const int ns_full = fill_split_for(n, cus, n);
+  // a workgroup of split ns takes about t_full ns_full / ns; one CU is left
+  // to the reduction
+  const int64_t cap = std::max<int64_t>(1, n / 1024);
+  int64_t ns = (int64_t)std::ceil(t_full * ns_full / tau);
+  ns = std::max<int64_t>(ns_full, std::min<int64_t>(ns, cap));
+  int64_t rows = (((int64_t)cus - 1) / ns) * kRowBlock;
+  if (rows >= n) rows = n;
+  if (rows < kRowBlock) return;
+  *rows_out = rows;
+  *ns_out = (int)ns;
+}
+
+void Solver::compress_into(int64_t k, int ncopies, double ahead_t) {
   ws.reset();
   hipEvent_t ev = mark_phase();
   // through the Gram matrix while Dhat is positive definite (every DLE / DRE
@@ -578,14 +637,53 @@ void Solver::compress_into(int64_t k, int ncopies) {
   const double* Fr = f_ready ? Fpre.as<double>() : nullptr;
   const int64_t* Fs = f_ready ? reinterpret_cast<const int64_t*>(Fr + k * k) : nullptr;
   f_ready = false;
+  // the next T12's product ahead: e^{tA^T} Y for Y = W[:, 0:r], its first
+  // rows on s3 beside the tridiagonal reduction
+  drop_ahead();
+  int64_t rows_b = 0;
+  int ns_b = 0;
+  if (ahead_t > 0.0) plan_beside(k, &rows_b, &ns_b);
+  std::function<void(hipEvent_t)> beside;
+  bool launched = false;
+  if (rows_b > 0) {
+    if (!s3) DME_HIP(hipStreamCreateWithFlags(&s3, hipStreamNonBlocking));
+    if (!ey_done) DME_HIP(hipEventCreateWithFlags(&ey_done, hipEventDisableTiming));
+    EW.ensure((size_t)n * (max_rank + (kmax - max_rank)) * sizeof(double));
+    Tk.ensure((size_t)kmax * max_rank * sizeof(double));
+    const size_t need = (size_t)ns_b * rows_b * kRowBlock * sizeof(double) +  // partial sums
+                        (size_t)3 * (n + kRowBlock) * kRowBlock * sizeof(uint16_t) + 4096;  // X pieces
+    if (ws3.buf.bytes < need) ws3.reserve(need);
+    const int64_t rY = r;
+    beside = [this, ahead_t, rows_b, ns_b, rY, &launched](hipEvent_t e) {
+      DME_HIP(hipStreamWaitEvent(s3, e, 0));
+      StepKernelTimer kt;
+      kt.sv = this;
+      KernelTimer* prev = kernel_timer();
+      if (profiling) kernel_timer() = &kt;
+      ws3.reset();
+      product_rows(ahead_t, W.as<double>(), rY, 0, rows_b, ns_b, s3, ws3);
+      kernel_timer() = prev;
+      DME_HIP(hipEventRecord(ey_done, s3));
+      launched = true;
+      beside_live = true;
+    };
+  }
   int64_t rn = compress_gram_f64(s, n, k, W.as<double>(), n, Dhat.as<double>(), k, d_diag,
                                  d_lowrank ? &lr : nullptr, opts.tol, max_rank, Ln(), n, Dn(), 0, rank_dev(),
-                                 flag_dev(), ws, r, Fr, Fs);  // the rank before: the guess for the new one
+                                 flag_dev(), ws, r, Fr, Fs,  // the rank before: the guess for the new one
+                                 rows_b > 0 ? Tk.as<double>() : nullptr, rows_b > 0 ? &beside : nullptr);
   const double kk = (double)k;
   if (rn >= 0) {
     // W^T W 2 n k^2, L = W T 2 n k r', the k x k products and eigenproblem ~ 14 k^3
     mark_end(1, ev, 2.0 * n * kk * kk + 2.0 * n * kk * rn + 14.0 * kk * kk * kk,
              8.0 * (2.0 * n * kk + n * rn));
+    if (launched && rn > 0) {  // L = W T: the next T12 takes [e^{tA^T} Y, e^{tA^T} L_I] T
+      ey_ok = tk_ok = true;
+      ey_t = ahead_t;
+      ey_cols = r;
+      ey_rows = rows_b;
+      tk_k = k;
+    }
   } else {
     ws.reset();
     rn = compress_f64(s, n, k, W.as<double>(), Dhat.as<double>(), opts.tol, max_rank, Ln(), n, Dn(), 0,
@@ -601,6 +699,8 @@ void Solver::compress_into(int64_t k, int ncopies) {
 }
 
 void Solver::apply_T1(double t) {
+  settle_beside();
+  drop_ahead();
   if (r == 0) return;
   apply_E(t, Lc(), r, Ln(), n);
   ++nprod;
@@ -609,6 +709,8 @@ void Solver::apply_T1(double t) {
 }
 
 void Solver::apply_T2(double t) {
+  settle_beside();
+  drop_ahead();
   double* Wd = W.as<double>();
   if (r > 0) copy_f64(s, Lc(), n, Wd, n, n, r);
   copy_f64(s, CT.as<double>(), n, Wd + r * n, n, n, p);
@@ -621,16 +723,22 @@ void Solver::apply_T12(double t, bool ext_product) {
   const QuadFactor& f = Q.at(t);
   double* Wd = W.as<double>();
   const int64_t k = r + f.r;
-  // D-hat and the quadrature columns of W (they depend on neither the
-  // product nor its columns of W) on the second stream, beside the product
+  const bool dense = !ops.at(t)->lop;
+  // (the split-BF16 mode only: beside an FP64 product the reduction runs at
+  // the clock the FP64 MFMA load leaves it, which costs more than it saves)
+  const bool can_ahead = ahead && ahead_same_t && !ext_product && dense && opts.precision == DME_MIXED;
+  // e^{tA^T} L = [e^{tA^T} Y, e^{tA^T} L_I] T from the product formed ahead
+  const bool from_ahead = can_ahead && r > 0 && ey_ok && tk_ok && ey_t == t && tk_k == ey_cols + f.r;
+  settle_beside();  // (the rows formed beside are complete before W changes)
+  // D-hat (and after a T3 update its factor; the quadrature columns of W too
+  // unless W still holds the Y of the product formed ahead) on the second
+  // stream, beside the product
   hipEvent_t w_ready = nullptr;
   if (k > 0) {
     AuxStream& ax = aux_stream();
     DME_HIP(hipStreamWaitEvent(ax.s2, ax.record(s), 0));
     blkdiag2_f64(ax.s2, Dc(), r, r, f.D.as<double>(), f.r, f.r, 1.0, Dhat.as<double>(), k);
-    if (f.r > 0) copy_f64(ax.s2, f.L.as<double>(), n, Wd + r * n, n, n, f.r);
-    // after a T3 update the factor of Dhat too (the compression then waits
-    // for nothing more)
+    if (f.r > 0 && !from_ahead) copy_f64(ax.s2, f.L.as<double>(), n, Wd + r * n, n, n, f.r);
     if (d_lowrank && Fpre.bytes > 0) {
       const LowRankD lr{lamT3.as<double>(), ZT3.as<double>(), t3, r, m, 1};
       double* F = Fpre.as<double>();
@@ -638,11 +746,46 @@ void Solver::apply_T12(double t, bool ext_product) {
     }
     w_ready = ax.record(ax.s2);
   }
-  if (r > 0 && !ext_product) apply_E(t, Lc(), r, Wd, n);
-  if (r > 0) ++nprod;  // (a grouped product of the server counts the same)
+  if (from_ahead) {
+    hipEvent_t ev = mark_phase();
+    StepKernelTimer kt;
+    kt.sv = this;
+    KernelTimer* prev = kernel_timer();
+    if (profiling) kernel_timer() = &kt;
+    // the rows not formed beside the last compression (W[:, 0:ey_cols] is
+    // still the Y they multiply)
+    const int64_t rest = n - ey_rows;
+    ws.reset();
+    if (rest > 0) product_rows(t, Wd, ey_cols, ey_rows, rest, fill_split(rest, false), s, ws);
+    kernel_timer() = prev;
+    if (eli_t != t) {  // e^{tA^T} L_I beside it, in FP64 (formed once per t)
+      DevBuf& e = ELI[t];
+      if (e.bytes == 0) {
+        e.ensure((size_t)n * std::max<int64_t>(f.r, 1) * sizeof(double));
+        ws.reset();
+        if (f.r > 0)
+          gemm_f64(s, 'N', 'N', n, f.r, n, 1.0, ops.at(t)->E.as<double>(), n, f.L.as<double>(), n, 0.0,
+                   e.as<double>(), n, &ws);
+      }
+      if (f.r > 0) copy_f64(s, e.as<double>(), n, EW.as<double>() + max_rank * n, n, n, f.r);
+      eli_t = t;
+    }
+    ws.reset();
+    gemm_f64(s, 'N', 'N', n, r, tk_k, 1.0, EW.as<double>() + (max_rank - ey_cols) * n, n, Tk.as<double>(),
+             tk_k, 0.0, Wd, n, &ws);
+    if (f.r > 0) copy_f64(s, f.L.as<double>(), n, Wd + r * n, n, n, f.r);
+    ++nprod;
+    mark_end(0, ev, 2.0 * rest * n * ey_cols + 2.0 * n * tk_k * r,
+             8.0 * ((double)rest * n + (double)n * (tk_k + r)));
+    drop_ahead();  // consumed
+  } else {
+    drop_ahead();
+    if (r > 0 && !ext_product) apply_E(t, Lc(), r, Wd, n);
+    if (r > 0) ++nprod;  // (a grouped product of the server counts the same)
+  }
   if (k == 0) return;
   DME_HIP(hipStreamWaitEvent(s, w_ready, 0));
-  compress_into(k);
+  compress_into(k, 1, (can_ahead && r > 0) ? t : 0.0);
 }
 
 void Solver::apply_T3(double t) {
@@ -664,6 +807,8 @@ void Solver::apply_T3(double t) {
 }
 
 void Solver::apply_T4(double t) {
+  settle_beside();
+  drop_ahead();
   if (r == 0) return;
   double* Wd = W.as<double>();
   hipEvent_t ev = mark_phase();
@@ -683,6 +828,8 @@ void Solver::apply_T4(double t) {
 }
 
 double Solver::err_estimate() {
+  settle_beside();
+  drop_ahead();  // W is scratch below
   const double u = std::ldexp(1.0, -53);
   double delta = 0.0;
   if (opts.precision == DME_MIXED && r > 0 && !ops.empty()) {
@@ -729,10 +876,18 @@ void Solver::run_stage(size_t i, bool ext_product) {
 
 void Solver::advance(int64_t nsteps) {
   AuxBinding bind(aux);
-  for (int64_t it = 0; it < nsteps; ++it) {
-    for (size_t i = 0; i < seq.size(); ++i) run_stage(i);
-    end_step();
+  ahead = true;
+  try {
+    for (int64_t it = 0; it < nsteps; ++it) {
+      for (size_t i = 0; i < seq.size(); ++i) run_stage(i);
+      end_step();
+    }
+  } catch (...) {
+    ahead = false;
+    drop_ahead();
+    throw;
   }
+  ahead = false;
   flush_timings();
   check_flags("step");
 }

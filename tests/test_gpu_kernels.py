@@ -38,7 +38,7 @@ def test_gemm_f64(ctx, M, N, K, ta, tb):
 
 
 @pytest.mark.parametrize("n,k,beta", [(2048, 178, 0.0), (16384, 192, 0.0), (5000, 33, -0.5), (3001, 1, 0.0),
-                                       (70000, 120, 0.0)])
+                                       (70000, 120, 0.0), (16384, 176, 0.5)])
 def test_gemm_gram(ctx, n, k, beta):
     """A^T A of a tall A (the compression's W^T W): the symmetric Gram path,
     ragged row blocks and tiles; the result is exactly symmetric."""

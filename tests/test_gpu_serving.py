@@ -93,7 +93,11 @@ def test_served_equals_direct_and_oracle(ctx, served):
         L, D, steps, info = solo[i]
         assert steps == nsteps and info["precision"] == prec and not info["fell_back"]
         Ld, Dd, _ = ctx.solve(kind, b.SolveOptions(T=T, h=h, tol=1e-10, precision=prec), A, C, B=B, R=R)
-        assert oracle.lowrank_rel_err(L, D, Ld, Dd) < 1e-12, i
+        # a direct solve forms each step product ahead of need, as
+        # [e^{tA^T} Y, e^{tA^T} L_I] T instead of e^{tA^T} (W T): the same
+        # products in another association, which agree to roundoff in FP64
+        # and to the split-BF16 product error in the mixed mode
+        assert oracle.lowrank_rel_err(L, D, Ld, Dd) < (1e-12 if prec == "fp64" else 1e-6), i
         Lo, Do, _ = oracle.solve(A, C, T, h, kind=kind, B=B, R=R, tol=1e-10)
         bound = 1e-10 if prec == "fp64" else 1e-6
         assert oracle.lowrank_rel_err(L, D, Lo, Do) < bound, i

@@ -131,6 +131,38 @@ def test_stepwise_equals_whole_solve(ctx):
     sv.close()
 
 
+def test_mixed_stepwise_ahead_products(ctx):
+    """The split-BF16 mode forms each step product ahead of need (its first
+    rows beside the compression's eigensolver, the rest at the next T12):
+    stepping in pieces repeats the whole solve's arithmetic exactly, and an
+    error estimate between the pieces (which uses W as scratch and so drops
+    the product formed ahead) changes only the association, within the
+    split-BF16 error of the oracle."""
+    p = wl.config_dre_quadrant(nx=32, T=1e-2, h=1e-3)
+    announce("mixed stepwise ahead", "n", p.A.shape[0])
+    opts = b.SolveOptions(T=p.T, h=p.h, tol=p.tol, scheme=p.scheme, split=p.split, quad_nodes=p.quad_nodes,
+                          precision="mixed")
+    L, D, _ = ctx.solve(p.kind, opts, p.A, p.C, B=p.B, R=p.R)
+    sv = ctx.solver("dre", opts, p.A, p.C, B=p.B, R=p.R)
+    sv.step(4)
+    sv.step(6)
+    L2, D2, _ = sv.result()
+    sv.close()
+    assert np.array_equal(L, L2) and np.array_equal(D, D2)
+    sv = ctx.solver("dre", opts, p.A, p.C, B=p.B, R=p.R)
+    sv.step(4)
+    _, _, _, est = sv.result(err_est=True)
+    sv.step(6)
+    L3, D3, _ = sv.result()
+    sv.close()
+    Lo, Do, _ = run_oracle(p)
+    e_whole = oracle.lowrank_rel_err(L, D, Lo, Do)
+    e_split = oracle.lowrank_rel_err(L3, D3, Lo, Do)
+    print(f"  rank {L.shape[1]} err whole {e_whole:.2e} split {e_split:.2e} est {est:.2e}", flush=True)
+    assert e_whole < 1e-6 and e_split < 1e-6
+    assert oracle.lowrank_rel_err(L3, D3, L, D) < 1e-6
+
+
 def test_profiling_levels(ctx):
     """Level 1 times every phase, level 2 the step product kernel alone; the
     timing does not change the result; other levels are rejected.  n = 1024,
