@@ -167,9 +167,12 @@ def kernel_source_hash(kernel):
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def measured_traffic(kernel):
-    """HBM bytes per launch of `kernel` from the committed counter summary, if
-    it was taken on the current source of the kernel (else None)."""
+def measured_traffic(kernel, alg_bytes_per_launch):
+    """HBM bytes per launch of `kernel`: the committed counter summary's
+    measured-over-algorithmic ratio (FETCH_SIZE + WRITE_SIZE of whole-product
+    launches, copy-calibrated) times this run's algorithmic bytes per launch
+    (the split-BF16 steps launch the product in two row ranges); None unless
+    the summary was taken on the current source of the kernel."""
     path = os.path.join(ROOT, "profiles", f"{kernel}_traffic.json")
     if not os.path.exists(path):
         return None
@@ -177,7 +180,7 @@ def measured_traffic(kernel):
         rec = json.load(f)
     if rec.get("source_sha256_16") != kernel_source_hash(kernel):
         return None
-    return rec.get("bytes_per_launch")
+    return int(round(rec["traffic_over_algorithmic"] * alg_bytes_per_launch))
 
 
 def roofline_from(prof, precision):
@@ -208,7 +211,7 @@ def roofline_from(prof, precision):
         executed = 6.0 * g["flops"] / g["count"] / avg_s / 1e12
         out["executed_bf16_tflops"] = round(executed, 1)
         out["executed_bf16_frac"] = round(executed / PEAK_BF16_TFLOPS, 4)
-    out["traffic"] = measured_traffic(kernel)
+    out["traffic"] = measured_traffic(kernel, g["bytes"] / g["count"])
     out.update({"kernel": kernel, "avg_launch_ms": round(avg_s * 1e3, 4), "launches": g["count"],
                 "algorithmic_per_launch": {"flops": g["flops"] / g["count"],
                                            "bytes": g["bytes"] / g["count"]}})

@@ -158,6 +158,7 @@ struct Solver {
   bool tk_ok = false;
   int64_t tk_k = 0;
   int cus = 0;                   // compute units of the device
+  int xccs = 1;                  // its compute dies (XCDs)
   hipStream_t s3 = nullptr;
   hipEvent_t ey_done = nullptr;  // the rows formed on s3
   Arena ws3;
@@ -242,9 +243,8 @@ struct Solver {
     beside_live = false;
   }
   // split of the inner dimension for `rows` rows of the split-BF16 step
-  // product in one wave of workgroups (beside: leaving one CU to the
-  // tridiagonal reduction)
-  int fill_split(int64_t rows, bool beside) const;
+  // product in one wave of workgroups
+  int fill_split(int64_t rows) const;
   // rows of the next product to form beside a compression of width k (a
   // multiple of kRowBlock, or n; 0: none) and their split
   void plan_beside(int64_t k, int64_t* rows, int* ns) const;

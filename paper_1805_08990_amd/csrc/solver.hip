@@ -247,6 +247,7 @@ void Solver::setup(const dme_problem& prob, const dme_opts& o, bool dre,
 
   DME_HIP(hipSetDevice(device));
   DME_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device));
+  if (hipDeviceGetAttribute(&xccs, hipDeviceAttributeNumberOfXccs, device) != hipSuccess || xccs < 1) xccs = 1;
   flags.ensure(64);
   fill_f64(s, flags.as<double>(), 8, 1, 8, 0.0);
 
@@ -561,9 +562,7 @@ int fill_split_for(int64_t rows, int64_t slots, int64_t n) {
 
 }  // namespace
 
-int Solver::fill_split(int64_t rows, bool beside) const {
-  return fill_split_for(rows, (int64_t)cus - (beside ? 1 : 0), n);
-}
+int Solver::fill_split(int64_t rows) const { return fill_split_for(rows, cus, n); }
 
 void Solver::product_rows(double t, const double* X, int64_t cols, int64_t row0, int64_t rows, int ns,
                           hipStream_t st, Arena& a) {
@@ -608,7 +607,7 @@ void Solver::apply_E(double t, const double* X, int64_t rr, double* Y, int64_t l
 void Solver::plan_beside(int64_t k, int64_t* rows_out, int* ns_out) const {
   *rows_out = 0;
   *ns_out = 0;
-  if (r <= 0 || n < kRowBlock || cus < 2) return;
+  if (r <= 0 || n < kRowBlock || cus <= xccs) return;
   // expected time of the tridiagonal reduction (one workgroup, about 1.9 us
   // a step on gfx950), with a margin
   const double tau = 0.85 * 1.9e-6 * (double)k;
@@ -616,12 +615,13 @@ void Solver::plan_beside(int64_t k, int64_t* rows_out, int* ns_out) const {
   // about 2.8 TB/s
   const double t_full = 4.0 * (double)n * n / 2.8e12;
   const int ns_full = fill_split_for(n, cus, n);
-  // a workgroup of split ns takes about t_full ns_full / ns; one CU is left
-  // to the reduction
+  // a workgroup of split ns takes about t_full ns_full / ns.  Workgroups go
+  // to the XCDs in turn, so one CU is left free in every XCD: the
+  // reduction's CU, wherever it is, then costs no workgroup a second turn.
   const int64_t cap = std::max<int64_t>(1, n / 1024);
   int64_t ns = (int64_t)std::ceil(t_full * ns_full / tau);
   ns = std::max<int64_t>(ns_full, std::min<int64_t>(ns, cap));
-  int64_t rows = (((int64_t)cus - 1) / ns) * kRowBlock;
+  int64_t rows = (((int64_t)cus - xccs) / ns) * kRowBlock;
   if (rows >= n) rows = n;
   if (rows < kRowBlock) return;
   *rows_out = rows;
@@ -756,7 +756,7 @@ void Solver::apply_T12(double t, bool ext_product) {
     // still the Y they multiply)
     const int64_t rest = n - ey_rows;
     ws.reset();
-    if (rest > 0) product_rows(t, Wd, ey_cols, ey_rows, rest, fill_split(rest, false), s, ws);
+    if (rest > 0) product_rows(t, Wd, ey_cols, ey_rows, rest, fill_split(rest), s, ws);
     kernel_timer() = prev;
     if (eli_t != t) {  // e^{tA^T} L_I beside it, in FP64 (formed once per t)
       DevBuf& e = ELI[t];
