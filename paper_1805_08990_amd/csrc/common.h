@@ -176,9 +176,15 @@ void gemm_f64(hipStream_t s, char ta, char tb, int64_t M, int64_t N, int64_t K,
 // Workspace (bytes) gemm_f64 may need for a split-K launch of this shape.
 size_t gemm_f64_workspace(int64_t M, int64_t N, int64_t K);
 
-// Rows a workgroup of the split-BF16 step product takes, the unit a row
-// range of that product is cut in.
+// Rows a workgroup of the step-product kernels takes (the FP64 skinny path
+// and the split-BF16 product), the unit a row range of a product is cut in.
 constexpr int kRowBlock = 128;
+// C (m x N) = A (m x K, ld lda) B (K x N, ld ldb) by the FP64 step-product
+// kernel with the inner dimension cut into ns chunks (a workgroup per
+// kRowBlock rows and chunk); N <= 256, K >= 16.  ws provides ns m N doubles
+// (+256 bytes).  A row range of a larger product is (A + row0, m).
+void gemm_f64_rows(hipStream_t s, int64_t m, int64_t N, int64_t K, const double* A, int64_t lda,
+                   const double* B, int64_t ldb, double* C, int64_t ldc, int ns, Arena& ws);
 
 // Elementwise / small helpers (elementwise.hip)
 void fill_f64(hipStream_t s, double* X, int64_t rows, int64_t cols, int64_t ld, double v);

@@ -579,9 +579,10 @@ void launch_skinny(hipStream_t s, int M, int N, int K, int ns, int kchunk, const
 
 void gemm_f64_skinny(hipStream_t s, int M, int N, int K, double alpha, const double* A, int64_t lda,
                      const double* B, int64_t ldb, double beta, double* C, int64_t ldc,
-                     double* partial) {
-  const int ns = skinny_nsplit(M, K);
-  const int kchunk = (int)(cdiv(cdiv(K, ns), kSkBK) * kSkBK);
+                     double* partial, int ns_force = 0) {
+  const int ns0 = ns_force > 0 ? ns_force : skinny_nsplit(M, K);
+  const int kchunk = (int)(cdiv(cdiv(K, ns0), kSkBK) * kSkBK);
+  const int ns = (int)cdiv(K, kchunk);  // no empty chunk
   const int tn = (int)cdiv(N, 16);
   KernelTimer* kt = kernel_timer();
   if (kt) kt->before(s);
@@ -660,6 +661,19 @@ size_t gemm_f64_workspace_tiled(int64_t M, int64_t N, int64_t K) {
   Plan p = plan_for(M, N, K);
   if (p.nsplit <= 1) return 0;
   return (size_t)p.nsplit * (size_t)M * (size_t)N * sizeof(double) + 256;
+}
+
+static_assert(kSkRows == kRowBlock, "row block of the skinny path");
+
+void gemm_f64_rows(hipStream_t s, int64_t m, int64_t N, int64_t K, const double* A, int64_t lda,
+                   const double* B, int64_t ldb, double* C, int64_t ldc, int ns, Arena& ws) {
+  if (m <= 0 || N <= 0) return;
+  DME_REQUIRE(m < (1ll << 31) && K >= kSkBK && K < (1ll << 31) && N <= kSkMaxN && ns >= 1, DME_EINVAL,
+              "row-range product: shape outside the skinny path");
+  const size_t mark = ws.used;
+  double* partial = ws.get<double>((size_t)ns * m * N);
+  gemm_f64_skinny(s, (int)m, (int)N, (int)K, 1.0, A, lda, B, ldb, 0.0, C, ldc, partial, ns);
+  ws.used = mark;
 }
 
 void gemm_f64(hipStream_t s, char ta, char tb, int64_t M, int64_t N, int64_t K, double alpha,

@@ -136,7 +136,7 @@ struct Solver {
   DevBuf Fpre;
   bool f_ready = false;
 
-  // Step products ahead of need (the split-BF16 mode with dense operators,
+  // Step products ahead of need (dense operators, FP64 up to 256 columns,
   // every T12 of the step with the same t, driven by advance()).  A
   // compression through the Gram matrix
   // gives L = W T with W = [Y, L_I], so the next T12 needs
@@ -242,8 +242,8 @@ struct Solver {
     if (beside_live) DME_HIP(hipStreamWaitEvent(s, ey_done, 0));
     beside_live = false;
   }
-  // split of the inner dimension for `rows` rows of the split-BF16 step
-  // product in one wave of workgroups
+  // split of the inner dimension for `rows` rows of a step product in one
+  // wave of workgroups
   int fill_split(int64_t rows) const;
   // rows of the next product to form beside a compression of width k (a
   // multiple of kRowBlock, or n; 0: none) and their split

@@ -550,23 +550,34 @@ struct StepKernelTimer : KernelTimer {
     a = nullptr;
   }
 };
-// The split of the inner dimension (n) that gives `rows` rows of the
-// split-BF16 step product one wave of workgroups on `slots` CUs (one
-// workgroup per CU and per kRowBlock rows and chunk): the wave's time falls
-// with the chunk length (chunks of at least 1024).
-int fill_split_for(int64_t rows, int64_t slots, int64_t n) {
+// Workgroups of a step-product kernel one CU holds at a time: two of the
+// FP64 kernel, one of the split-BF16 kernel.
+int per_cu(int precision) { return precision == DME_MIXED ? 1 : 2; }
+// Longest split of the inner dimension n (chunks of at least 1024 or 256).
+int64_t split_cap(int precision, int64_t n) { return std::max<int64_t>(1, n / (precision == DME_MIXED ? 1024 : 256)); }
+
+// The split of the inner dimension that gives `rows` rows of a step product
+// one wave of workgroups on `slots` workgroup slots (a workgroup per
+// kRowBlock rows and chunk): the wave's time falls with the chunk length.
+int fill_split_for(int64_t rows, int64_t slots, int64_t cap) {
   const int64_t rb = cdiv(rows, kRowBlock);
-  const int64_t cap = std::max<int64_t>(1, n / 1024);
   return (int)std::max<int64_t>(1, std::min<int64_t>(slots / std::max<int64_t>(rb, 1), cap));
 }
 
 }  // namespace
 
-int Solver::fill_split(int64_t rows) const { return fill_split_for(rows, cus, n); }
+int Solver::fill_split(int64_t rows) const {
+  return fill_split_for(rows, (int64_t)per_cu(opts.precision) * cus, split_cap(opts.precision, n));
+}
 
 void Solver::product_rows(double t, const double* X, int64_t cols, int64_t row0, int64_t rows, int ns,
                           hipStream_t st, Arena& a) {
-  gemm_mixed(st, *ops.at(t)->mix, X, n, cols, EW.as<double>() + (max_rank - cols) * n, n, a, row0, rows, ns);
+  double* Y = EW.as<double>() + (max_rank - cols) * n;
+  const OperatorSet& set = *ops.at(t);
+  if (opts.precision == DME_MIXED)
+    gemm_mixed(st, *set.mix, X, n, cols, Y, n, a, row0, rows, ns);
+  else
+    gemm_f64_rows(st, rows, cols, n, set.E.as<double>() + row0, n, X, n, Y + row0, n, ns, a);
 }
 
 void Solver::apply_E(double t, const double* X, int64_t rr, double* Y, int64_t ldy) {
@@ -608,24 +619,40 @@ void Solver::plan_beside(int64_t k, int64_t* rows_out, int* ns_out) const {
   *rows_out = 0;
   *ns_out = 0;
   if (r <= 0 || n < kRowBlock || cus <= xccs) return;
-  // expected time of the tridiagonal reduction (one workgroup, about 1.9 us
-  // a step on gfx950), with a margin
-  const double tau = 0.85 * 1.9e-6 * (double)k;
-  // one wave of the whole product: the kernel reads the FP32 operator at
-  // about 2.8 TB/s
-  const double t_full = 4.0 * (double)n * n / 2.8e12;
-  const int ns_full = fill_split_for(n, cus, n);
-  // a workgroup of split ns takes about t_full ns_full / ns.  Workgroups go
-  // to the XCDs in turn, so one CU is left free in every XCD: the
-  // reduction's CU, wherever it is, then costs no workgroup a second turn.
-  const int64_t cap = std::max<int64_t>(1, n / 1024);
-  int64_t ns = (int64_t)std::ceil(t_full * ns_full / tau);
-  ns = std::max<int64_t>(ns_full, std::min<int64_t>(ns, cap));
-  int64_t rows = (((int64_t)cus - xccs) / ns) * kRowBlock;
-  if (rows >= n) rows = n;
-  if (rows < kRowBlock) return;
-  *rows_out = rows;
-  *ns_out = (int)ns;
+  const bool mixed = opts.precision == DME_MIXED;
+  // Measured on gfx950 (n = 16384, k ~ 178): the tridiagonal reduction takes
+  // about 1.9 us a step; the whole product one wave of workgroups, the FP64
+  // kernel at ~50 TFLOP/s and the split-BF16 kernel reading the FP32
+  // operator at ~2.8 TB/s; beside the reduction the FP64 kernel's workgroups
+  // run ~1.6x slower than in a whole product (the split-BF16 ones at full
+  // speed); rows still running when the reduction ends hold the CUs the rest
+  // of the eigensolver needs, which waits about as long as they overrun.
+  const double tau = 1.9e-6 * (double)k;
+  const double t_full = mixed ? 4.0 * (double)n * n / 2.8e12 : 2.0 * (double)n * n * r / 50e12;
+  const double slow = mixed ? 1.0 : 1.6;
+  const int64_t cap = split_cap(opts.precision, n), rb_all = cdiv(n, kRowBlock);
+  const int64_t slots = (int64_t)per_cu(opts.precision) * cus;
+  // workgroups go to the XCDs in turn: one CU left free in every XCD keeps
+  // the reduction's CU, wherever it is, from costing a workgroup a second turn
+  const int64_t slots_b = (int64_t)per_cu(opts.precision) * (cus - xccs);
+  const double t_wg = t_full * fill_split_for(n, slots, cap);  // a workgroup's time at split 1
+  // c row blocks beside (the longest split that fits the slots): the
+  // shortest critical path, the remainder's wave plus the overrun's delay;
+  // the smallest c on ties
+  double best = t_full;
+  for (int64_t c = 1; c <= std::min(rb_all, slots_b); ++c) {
+    const int64_t ns_c = std::min<int64_t>(cap, slots_b / c);
+    if (ns_c < 1) break;
+    const double t_c = slow * t_wg / ns_c;
+    const int64_t rb_r = rb_all - c;
+    const double t_r = rb_r > 0 ? t_wg / fill_split_for(rb_r * kRowBlock, slots, cap) : 0.0;
+    const double path = t_r + std::max(0.0, t_c - tau);
+    if (path < best * (1.0 - 1e-3)) {
+      best = path;
+      *rows_out = std::min<int64_t>(n, c * kRowBlock);
+      *ns_out = (int)ns_c;
+    }
+  }
 }
 
 void Solver::compress_into(int64_t k, int ncopies, double ahead_t) {
@@ -650,8 +677,8 @@ void Solver::compress_into(int64_t k, int ncopies, double ahead_t) {
     if (!ey_done) DME_HIP(hipEventCreateWithFlags(&ey_done, hipEventDisableTiming));
     EW.ensure((size_t)n * (max_rank + (kmax - max_rank)) * sizeof(double));
     Tk.ensure((size_t)kmax * max_rank * sizeof(double));
-    const size_t need = (size_t)ns_b * rows_b * kRowBlock * sizeof(double) +  // partial sums
-                        (size_t)3 * (n + kRowBlock) * kRowBlock * sizeof(uint16_t) + 4096;  // X pieces
+    const size_t need = (size_t)ns_b * rows_b * std::max<int64_t>(r + 16, kRowBlock) * sizeof(double) +
+                        (size_t)3 * (n + kRowBlock) * kRowBlock * sizeof(uint16_t) + 4096;  // partials, X pieces
     if (ws3.buf.bytes < need) ws3.reserve(need);
     const int64_t rY = r;
     beside = [this, ahead_t, rows_b, ns_b, rY, &launched](hipEvent_t e) {
@@ -724,9 +751,8 @@ void Solver::apply_T12(double t, bool ext_product) {
   double* Wd = W.as<double>();
   const int64_t k = r + f.r;
   const bool dense = !ops.at(t)->lop;
-  // (the split-BF16 mode only: beside an FP64 product the reduction runs at
-  // the clock the FP64 MFMA load leaves it, which costs more than it saves)
-  const bool can_ahead = ahead && ahead_same_t && !ext_product && dense && opts.precision == DME_MIXED;
+  const bool can_ahead = ahead && ahead_same_t && !ext_product && dense &&
+                         (opts.precision == DME_MIXED || r <= 256);
   // e^{tA^T} L = [e^{tA^T} Y, e^{tA^T} L_I] T from the product formed ahead
   const bool from_ahead = can_ahead && r > 0 && ey_ok && tk_ok && ey_t == t && tk_k == ey_cols + f.r;
   settle_beside();  // (the rows formed beside are complete before W changes)
