@@ -246,13 +246,15 @@ def test_gdle_small(ctx, split, scheme):
     check(ctx, p)
 
 
-@pytest.mark.parametrize("split", ["F12", "F1F2"])
-def test_dle_indefinite_P0(ctx, split):
+@pytest.mark.parametrize("split,nx", [("F12", 10), ("F1F2", 10), ("F12", 12)])
+def test_dle_indefinite_P0(ctx, split, nx):
     """P0 = L0 D0 L0^T with an indefinite D0: the compressions see an
     indefinite Dhat, which the Gram-matrix route declines, so the Householder
-    route compresses; the P of both schemes matches the oracle."""
-    n = 100
-    A = wl.laplacian_2d(10)
+    route compresses; the P of both schemes matches the oracle.  At n = 144
+    the F12 steps also form their next product ahead beside the compression,
+    which a Householder compression then discards."""
+    n = nx * nx
+    A = wl.laplacian_2d(nx)
     C = wl.random_C(2, n, seed=8)
     L0, _ = wl.random_lowrank_P0(n, 4, seed=9)
     D0 = np.diag([1.0, -0.5, 0.25, -2.0])
