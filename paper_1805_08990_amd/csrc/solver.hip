@@ -675,8 +675,10 @@ void Solver::compress_into(int64_t k, int ncopies, double ahead_t) {
   if (rows_b > 0) {
     if (!s3) DME_HIP(hipStreamCreateWithFlags(&s3, hipStreamNonBlocking));
     if (!ey_done) DME_HIP(hipEventCreateWithFlags(&ey_done, hipEventDisableTiming));
-    EW.ensure((size_t)n * (max_rank + (kmax - max_rank)) * sizeof(double));
-    Tk.ensure((size_t)kmax * max_rank * sizeof(double));
+    // e^{tA^T} Y (at most max_rank columns) and e^{tA^T} L_I (at most K p)
+    const int64_t kq = std::max<int64_t>(1, (int64_t)opts.quad_nodes * p);
+    EW.ensure((size_t)n * (max_rank + kq) * sizeof(double));
+    Tk.ensure((size_t)(max_rank + kq) * max_rank * sizeof(double));
     const size_t need = (size_t)ns_b * rows_b * std::max<int64_t>(r + 16, kRowBlock) * sizeof(double) +
                         (size_t)3 * (n + kRowBlock) * kRowBlock * sizeof(uint16_t) + 4096;  // partials, X pieces
     if (ws3.buf.bytes < need) ws3.reserve(need);
