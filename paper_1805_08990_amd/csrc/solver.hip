@@ -554,7 +554,9 @@ struct StepKernelTimer : KernelTimer {
 // FP64 kernel, one of the split-BF16 kernel.
 int per_cu(int precision) { return precision == DME_MIXED ? 1 : 2; }
 // Longest split of the inner dimension n (chunks of at least 1024 or 256).
-int64_t split_cap(int precision, int64_t n) { return std::max<int64_t>(1, n / (precision == DME_MIXED ? 1024 : 256)); }
+int64_t split_cap(int precision, int64_t n) {
+  return std::max<int64_t>(1, n / (precision == DME_MIXED ? 1024 : 256));
+}
 
 // The split of the inner dimension that gives `rows` rows of a step product
 // one wave of workgroups on `slots` workgroup slots (a workgroup per
