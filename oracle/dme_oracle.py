@@ -34,7 +34,7 @@ itself uses a Leja-interpolation action instead (Sec. 3); the dense operator is
 the approach this project takes, and both sides of the parity comparison use
 the same (m, s) rule.
 
-Readings of points the paper leaves open (each is also listed in the design doc):
+Readings of points the paper leaves open:
   * Operators act right to left; lists below are in application order.
   * Alg. 3 as printed drops B^T; the formula of Sec. 2.2 is used.
   * Alg. 4 uses the pre-update L in S^2 L.
