@@ -426,8 +426,8 @@ def serve_sweep(ctx, count, parts=("0.5", "0.7", "0.9", "fifo"), capacity=None, 
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print(f"bench.py runs on one GPU; --gpus {args.gpus} is not supported (the design notes "
-              "describe how the path would shard across GPUs)", file=sys.stderr)
+        print(f"bench.py runs on one GPU; --gpus {args.gpus} is not supported (the path is built "
+              "for one GPU; sharding E by rows across GPUs is not built)", file=sys.stderr)
         sys.exit(2)
     import torch
     from paper_1805_08990_amd import _binding as b
