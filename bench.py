@@ -67,8 +67,9 @@ def parse():
     ap.add_argument("--product-only", type=int, default=0, metavar="R",
                     help="run only the step product E X (n x n times n x R, random E and X, 3 "
                          "launches) for hardware counters, and exit")
-    ap.add_argument("--product-precision", choices=["fp64", "mixed"], default="mixed",
-                    help="which step product --product-only runs")
+    ap.add_argument("--product-precision", choices=["fp64", "mixed", "leja"], default="mixed",
+                    help="which step product --product-only runs (leja: the Leja action "
+                         "e^{(h/2)A^T} X on the CSR Laplacian, its Newton terms at rank R)")
     ap.add_argument("--serve-sweep", type=int, default=0, metavar="COUNT",
                     help="instead of the steps/s line: serve COUNT requests at 0.5, 0.7 and 0.9 x "
                          "the measured capacity and the same stream one request at a time (FIFO)")
@@ -195,7 +196,8 @@ def roofline_from(prof, precision):
                "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP64_TFLOPS, 4)}
     elif precision == "leja":
         # one Newton term of the Leja action: the CSR operator, the basis block
-        # read and written, the accumulator read and written (HBM-bound form)
+        # read and written, the accumulator read and written by every second
+        # term (HBM-bound form, averaged over the terms)
         kernel = "leja_csr_term_kernel"
         achieved = g["bytes"] / g["count"] / avg_s / 1e9
         out = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
@@ -446,16 +448,34 @@ def main():
         # (its LU issues ~10^5 small launches, which counter collection does not bear)
         n, r = args.nx * args.nx, args.product_only
         g = torch.Generator(device="cuda").manual_seed(0)
-        E = torch.randn((n, n), dtype=torch.float64, device="cuda", generator=g) / math.sqrt(n)
-        X = torch.randn((n, r), dtype=torch.float64, device="cuda", generator=g)
-        for _ in range(3):
-            if args.product_precision == "mixed":
-                ctx.gemm_mixed(E, X)
-            else:
-                ctx.gemm(E, X)
-            torch.cuda.synchronize()
-        print(json.dumps({"product_only": {"n": n, "r": r, "launches": 3,
-                                           "precision": args.product_precision}}), flush=True)
+        info = {"n": n, "r": r, "launches": 3, "precision": args.product_precision}
+        if args.product_precision == "leja":
+            # three actions of the workload's half step; every Newton term is
+            # one leja_csr_term_kernel launch over the n x r block
+            import numpy as np
+            import scipy.sparse as sp
+            import workloads as wl
+            X = torch.randn((n, r), dtype=torch.float64, device="cuda", generator=g)
+            Ms = sp.csr_matrix(wl.laplacian_2d(args.nx))
+            A = (Ms.indptr.astype(np.int64), Ms.indices.astype(np.int64), Ms.data.astype(np.float64))
+            for _ in range(3):
+                _, S, m = ctx.expmv_leja(A, 0.5e-3, X)  # the workload's half step, h = 1e-3
+                torch.cuda.synchronize()
+            # per term the operator and the basis block read and written; the
+            # accumulator read and written by every second term
+            per_term = 12 * int(Ms.nnz) + 8 * n + 16 * n * r + 16 * n * r * ((m + 1) // 2) / m
+            info.update({"substeps": S, "degree": m, "term_launches": 3 * S * m, "nnz": int(Ms.nnz),
+                         "algorithmic_bytes_per_term": round(per_term)})
+        else:
+            E = torch.randn((n, n), dtype=torch.float64, device="cuda", generator=g) / math.sqrt(n)
+            X = torch.randn((n, r), dtype=torch.float64, device="cuda", generator=g)
+            for _ in range(3):
+                if args.product_precision == "mixed":
+                    ctx.gemm_mixed(E, X)
+                else:
+                    ctx.gemm(E, X)
+                torch.cuda.synchronize()
+        print(json.dumps({"product_only": info}), flush=True)
         return
     if args.serve_sweep > 0:
         parts = tuple(x.strip() for x in args.sweep_parts.split(","))

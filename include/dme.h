@@ -151,7 +151,8 @@ int dre_solve(dme_ctx *ctx, const dme_problem *prob, const dme_opts *opts, dme_r
  * (e^{tA^T}, quadrature factor), step = advance `nsteps` time steps with all
  * data resident in HBM, result = copy of the current (L, D).
  * is_dre: 0 -> DLE, 1 -> DRE.  A solver owns its device memory.
- * Stepping with the dense operators forms each step product ahead of need:
+ * Stepping with the dense operators, or with the Leja action on a CSR
+ * operator, forms each step product ahead of need:
  * after a compression L = W T with W = [Y, L_I], and e^{tA^T} L is taken as
  * [e^{tA^T} Y, e^{tA^T} L_I] T, most of it beside the compression.  Stepping in
  * pieces repeats one call's arithmetic exactly; a server's grouped products

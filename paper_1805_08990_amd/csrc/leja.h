@@ -31,6 +31,13 @@ struct LejaOp {
   const double* dense = nullptr;
   int64_t nnz = 0;
   DevBuf rowptr, colind, val;
+  // the same rows in fixed-width form when no row has more than kEllWidth
+  // entries: row i is a record of kEllRecord doubles at ell + i kEllRecord,
+  // its kEllWidth values, then their kEllWidth column indices (int), padded
+  // with zeros on the row itself; empty otherwise
+  static constexpr int kEllWidth = 8;
+  static constexpr int kEllRecord = kEllWidth + kEllWidth / 2;
+  DevBuf ell;
   double a = 0.0, b = 0.0;  // Gershgorin interval of the spectrum
   bool symmetric = false;   // CSR: A^T equals A entry for entry
   bool sparse() const { return dense == nullptr; }
@@ -74,5 +81,8 @@ void leja_apply(hipStream_t s, const LejaOp& op, const LejaPlan& plan, const dou
                 int64_t ncols, double* Y, int64_t ldy, Arena& ws);
 // Products with A^T one action makes (S * m), for the flop accounting.
 inline int64_t leja_products(const LejaPlan& p) { return (int64_t)p.S * p.m; }
+// Updates of the accumulator one action on a CSR operator makes (every second
+// term, S * ceil(m / 2)), for the byte accounting.
+inline int64_t leja_csr_p_updates(const LejaPlan& p) { return (int64_t)p.S * ((p.m + 1) / 2); }
 
 }  // namespace dme

@@ -13,6 +13,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstring>
 #include <mutex>
 
 namespace dme {
@@ -127,7 +128,8 @@ __global__ void symdiff_kernel(const double* __restrict__ X, int64_t n, int64_t 
 
 // ------------------------------------------------------------ Newton terms
 // Column q belongs to group q / gcols (a single group when gcols >= ncols).
-__device__ __forceinline__ int group_of(int64_t q, int64_t gcols) { return (int)(q / gcols); }
+// (column counts are far below 2^31: a 32-bit division)
+__device__ __forceinline__ int group_of(int64_t q, int64_t gcols) { return (int)q / (int)gcols; }
 
 // W <- X, P <- d_0 X
 __global__ void leja_init_kernel(int64_t n, int64_t ncols, const double* __restrict__ X, int64_t ldx,
@@ -161,17 +163,89 @@ __global__ void leja_dense_term_kernel(int64_t n, int64_t ncols, const double* _
 // even): one wave per row, each lane two adjacent columns (and further pairs
 // 128 columns apart), so every load and store of a wave is one contiguous run
 // of 16-byte pairs; the row's entries are wave-uniform (scalar loads).  Forms
-// (A^T W)(i, :), the next basis row W'(i, :) = (A^T W)(i, :) / g - shift
-// W(i, :), and P(i, :) += d_{j+1} W'(i, :).
+// (A^T W)(i, :) and the next basis row W'(i, :) = (A^T W)(i, :) / g - shift
+// W(i, :).  The accumulator is updated every second term: a launch reads the
+// basis row W = W_j it starts from anyway, so with pmode 2 it adds
+// d_j W + d_{j+1} W' (in that order, the order of one update per term) and the
+// launch before it (pmode 0) leaves P alone; pmode 1 adds d_{j+1} W' alone
+// (the last term of an odd count).  P is read and written by half the
+// launches.
 constexpr int kRowsPerBlock = 4;
+// Rows with at most this many entries (every row of a 5- or 7-point grid
+// operator) take their entries first, as wave-uniform values, and then issue
+// the loads of all the W rows they reach together: such a row waits for
+// three memory round trips (its extent, its entries, the W rows) instead of
+// two per entry.  The padding entries are zeros on the row itself, so the sum
+// runs over the same terms in the same order.
+constexpr int kFastNnz = 8;
 
+// W'(i, q:q+2) from the sum (A^T W)(i, q:q+2) = acc, and the accumulator update
+__device__ __forceinline__ void leja_csr_finish(int64_t o, int64_t q, int64_t ncols, double2 acc, double2 wi,
+                                                double* __restrict__ Wout, double* __restrict__ P, double inv_g,
+                                                double shift, const double* __restrict__ coef, int m1, int j1,
+                                                int64_t gcols, int pmode) {
+  double2 wn;
+  wn.x = acc.x * inv_g - shift * wi.x;
+  wn.y = acc.y * inv_g - shift * wi.y;
+  *reinterpret_cast<double2*>(Wout + o) = wn;
+  if (pmode != 0) {  // wave-uniform
+    double2 pp = *reinterpret_cast<const double2*>(P + o);
+    const double* cx = coef + group_of(q, gcols) * m1;
+    const double* cy = coef + group_of(q + 1, gcols) * m1;
+    if (pmode == 2) {
+      pp.x += cx[j1 - 1] * wi.x;
+      if (q + 1 < ncols) pp.y += cy[j1 - 1] * wi.y;
+    }
+    pp.x += cx[j1] * wn.x;
+    if (q + 1 < ncols) pp.y += cy[j1] * wn.y;
+    *reinterpret_cast<double2*>(P + o) = pp;
+  }
+}
+
+// The sum over a row's kFastNnz (padded) entries, all W rows loaded at once.
+__device__ __forceinline__ void leja_fixed_row(int64_t i, int64_t cp, int64_t ncols, int lane,
+                                               const int (&cu)[kFastNnz], const double (&au)[kFastNnz],
+                                               const double* __restrict__ Win, double* __restrict__ Wout,
+                                               double* __restrict__ P, double inv_g, double shift,
+                                               const double* __restrict__ coef, int m1, int j1, int64_t gcols,
+                                               int pmode) {
+  for (int64_t q = 2 * (int64_t)lane; q < ncols; q += 128) {
+    const int64_t o = i * cp + q;
+    double2 w[kFastNnz];
+#pragma unroll
+    for (int u = 0; u < kFastNnz; ++u) w[u] = *reinterpret_cast<const double2*>(Win + (int64_t)cu[u] * cp + q);
+    const double2 wi = *reinterpret_cast<const double2*>(Win + o);
+    double2 acc = make_double2(0.0, 0.0);
+#pragma unroll
+    for (int u = 0; u < kFastNnz; ++u) {
+      acc.x += au[u] * w[u].x;
+      acc.y += au[u] * w[u].y;
+    }
+    leja_csr_finish(o, q, ncols, acc, wi, Wout, P, inv_g, shift, coef, m1, j1, gcols, pmode);
+  }
+}
+
+// i is the wave's row (the same in every lane)
 __device__ __forceinline__ void leja_csr_row(int64_t i, int64_t cp, int64_t ncols, int lane,
                                              const int64_t* __restrict__ rowptr, const int* __restrict__ colind,
                                              const double* __restrict__ val, const double* __restrict__ Win,
                                              double* __restrict__ Wout, double* __restrict__ P, double inv_g,
                                              double shift, const double* __restrict__ coef, int m1, int j1,
-                                             int64_t gcols) {
+                                             int64_t gcols, int pmode) {
   const int64_t k0 = rowptr[i], k1 = rowptr[i + 1];
+  const int64_t nnz = k1 - k0;
+  if (nnz >= 1 && nnz <= kFastNnz) {  // wave-uniform
+    int cu[kFastNnz];
+    double au[kFastNnz];
+#pragma unroll
+    for (int u = 0; u < kFastNnz; ++u) {
+      const int64_t kk = k0 + min<int64_t>(u, nnz - 1);  // in [k0, k1)
+      cu[u] = (u < nnz) ? colind[kk] : (int)i;
+      au[u] = (u < nnz) ? val[kk] : 0.0;
+    }
+    leja_fixed_row(i, cp, ncols, lane, cu, au, Win, Wout, P, inv_g, shift, coef, m1, j1, gcols, pmode);
+    return;
+  }
   for (int64_t q = 2 * (int64_t)lane; q < ncols; q += 128) {
     double2 acc = make_double2(0.0, 0.0);
     for (int64_t kk = k0; kk < k1; ++kk) {
@@ -182,26 +256,48 @@ __device__ __forceinline__ void leja_csr_row(int64_t i, int64_t cp, int64_t ncol
     }
     const int64_t o = i * cp + q;
     const double2 wi = *reinterpret_cast<const double2*>(Win + o);
-    double2 wn;
-    wn.x = acc.x * inv_g - shift * wi.x;
-    wn.y = acc.y * inv_g - shift * wi.y;
-    *reinterpret_cast<double2*>(Wout + o) = wn;
-    double2 pp = *reinterpret_cast<const double2*>(P + o);
-    pp.x += coef[group_of(q, gcols) * m1 + j1] * wn.x;
-    if (q + 1 < ncols) pp.y += coef[group_of(q + 1, gcols) * m1 + j1] * wn.y;
-    *reinterpret_cast<double2*>(P + o) = pp;
+    leja_csr_finish(o, q, ncols, acc, wi, Wout, P, inv_g, shift, coef, m1, j1, gcols, pmode);
   }
+}
+
+// Workgroups go to the XCDs in turn (workgroup b to XCD b % 8, each XCD with
+// its own L2).  Workgroup b takes the row block that gives every XCD one
+// contiguous range of rows, so the rows a row's entries reach (for a grid
+// operator its neighbours one and one grid line away) are mostly in the
+// same XCD's range, and each row of W is fetched into about one L2 instead
+// of the L2s of both neighbouring blocks.  A bijection on [0, nb) for any
+// number of XCDs; 8 sets only the locality.
+__device__ __forceinline__ int64_t xcd_row_block(int64_t b, int64_t nb) {
+  constexpr int64_t kX = 8;
+  const int64_t x = b % kX, q = nb / kX, rem = nb % kX;
+  return x * q + min(x, rem) + b / kX;
 }
 
 __global__ __launch_bounds__(64 * kRowsPerBlock) void leja_csr_term_kernel(
     int64_t n, int64_t cp, int64_t ncols, const int64_t* __restrict__ rowptr, const int* __restrict__ colind,
-    const double* __restrict__ val, const double* __restrict__ Win, double* __restrict__ Wout,
-    double* __restrict__ P, double inv_g, double shift, const double* __restrict__ coef, int m1, int j1,
-    int64_t gcols) {
-  const int64_t i = (int64_t)blockIdx.x * kRowsPerBlock + (threadIdx.x >> 6);
+    const double* __restrict__ val, const double* __restrict__ ell, const double* __restrict__ Win, double* __restrict__ Wout, double* __restrict__ P, double inv_g,
+    double shift, const double* __restrict__ coef, int m1, int j1, int64_t gcols, int pmode) {
+  // the wave's row, as a wave-uniform (scalar) value: its extent and entries
+  // come by scalar loads
+  const int64_t i = xcd_row_block(blockIdx.x, gridDim.x) * kRowsPerBlock +
+                    __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   if (i >= n) return;
-  leja_csr_row(i, cp, ncols, threadIdx.x & 63, rowptr, colind, val, Win, Wout, P, inv_g, shift, coef, m1, j1,
-               gcols);
+  const int lane = threadIdx.x & 63;
+  if (ell) {  // fixed-width rows: the entries at a known place, one record
+    static_assert(LejaOp::kEllWidth == kFastNnz, "fixed-width rows hold kFastNnz entries");
+    const double* rv = ell + i * LejaOp::kEllRecord;
+    const int* rc = reinterpret_cast<const int*>(rv + kFastNnz);
+    int cu[kFastNnz];
+    double au[kFastNnz];
+#pragma unroll
+    for (int u = 0; u < kFastNnz; ++u) {
+      au[u] = rv[u];
+      cu[u] = rc[u];
+    }
+    leja_fixed_row(i, cp, ncols, lane, cu, au, Win, Wout, P, inv_g, shift, coef, m1, j1, gcols, pmode);
+    return;
+  }
+  leja_csr_row(i, cp, ncols, lane, rowptr, colind, val, Win, Wout, P, inv_g, shift, coef, m1, j1, gcols, pmode);
 }
 
 // Column-major X (ld ldx) -> row-major W (ld cp) and P = d_0 X, through 32 x 32
@@ -426,6 +522,29 @@ std::shared_ptr<LejaOp> leja_op_csr(hipStream_t s, int64_t n, const int64_t* row
       }
     }
   }
+  // fixed-width rows when every row of A^T fits: a row's entries are then at
+  // a known place and a term needs no row pointers
+  int64_t widest = 0;
+  for (int64_t i = 0; i < n; ++i) widest = std::max(widest, tp[i + 1] - tp[i]);
+  if (widest <= LejaOp::kEllWidth) {
+    constexpr int E = LejaOp::kEllWidth, Rd = LejaOp::kEllRecord;
+    static_assert(Rd * sizeof(double) == E * (sizeof(double) + sizeof(int)), "record layout");
+    std::vector<double> rec((size_t)n * Rd, 0.0);
+    for (int64_t i = 0; i < n; ++i) {
+      double* rv = rec.data() + (size_t)i * Rd;
+      int cols[E];
+      for (int u = 0; u < E; ++u) {
+        const int64_t k = tp[i] + u;
+        const bool real = k < tp[i + 1];
+        rv[u] = real ? tv[k] : 0.0;
+        cols[u] = real ? tc[k] : (int)i;
+      }
+      std::memcpy(rv + E, cols, sizeof(cols));
+    }
+    op->ell.ensure(rec.size() * sizeof(double));
+    DME_HIP(hipMemcpyAsync(op->ell.p, rec.data(), rec.size() * sizeof(double), hipMemcpyHostToDevice, s));
+    DME_HIP(hipStreamSynchronize(s));  // the host vector goes out of scope
+  }
   op->rowptr.ensure((size_t)(n + 1) * sizeof(int64_t));
   op->colind.ensure((size_t)std::max<int64_t>(nnz, 1) * sizeof(int));
   op->val.ensure((size_t)std::max<int64_t>(nnz, 1) * sizeof(double));
@@ -558,9 +677,14 @@ void leja_apply(hipStream_t s, const LejaOp& op, const LejaPlan& plan, const dou
     for (int sub = 0; sub < plan.S; ++sub) {
       for (int j = 0; j < plan.m; ++j) {
         const double shift = plan.c * inv_g + plan.xi[j];
+        // P takes d_j W_j + d_{j+1} W_{j+1} at odd j, d_m W_m at the last
+        // term of an odd count, nothing otherwise: every term of the substep
+        // is in P when the substep ends
+        const int pmode = (j & 1) ? 2 : (j + 1 == plan.m ? 1 : 0);
         hipLaunchKernelGGL(leja_csr_term_kernel, dim3(rgrid), dim3(64 * kRowsPerBlock), 0, s, n, cp, ncols,
-                           op.rowptr.as<int64_t>(), op.colind.as<int>(), op.val.as<double>(), W, W2, P, inv_g,
-                           shift, coef, m1, j + 1, gcols);
+                           op.rowptr.as<int64_t>(), op.colind.as<int>(), op.val.as<double>(),
+                           op.ell.bytes ? op.ell.as<double>() : nullptr, W, W2, P, inv_g, shift, coef, m1,
+                           j + 1, gcols, pmode);
         DME_HIP(hipGetLastError());
         std::swap(W, W2);
       }

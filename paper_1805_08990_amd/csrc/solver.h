@@ -137,13 +137,15 @@ struct Solver {
   bool f_ready = false;
 
   // Step products ahead of need (dense operators, FP64 up to 256 columns,
-  // every T12 of the step with the same t, driven by advance()).  A
-  // compression through the Gram matrix
+  // or the Leja action on a CSR operator; every T12 of the step with the same
+  // t, driven by advance()).  A compression through the Gram matrix
   // gives L = W T with W = [Y, L_I], so the next T12 needs
   // e^{tA^T} L = [e^{tA^T} Y, e^{tA^T} L_I] T: the product e^{tA^T} Y can
-  // start before the compression ends.  Its first rows run on s3 beside the
-  // compression's one-workgroup tridiagonal reduction, the rest when the next
-  // T12 needs them; e^{tA^T} L_I is formed once per t.
+  // start before the compression ends.  A dense product's first rows run on
+  // s3 beside the compression's one-workgroup tridiagonal reduction, the rest
+  // when the next T12 needs them; the Leja action (a chain of short launches
+  // that leave room for the compression's kernels) runs whole on s3 beside
+  // the compression.  e^{tA^T} L_I is formed once per t.
   //   EW (n x (max_rank + K p)): e^{tA^T} Y in the columns [max_rank - ey_cols,
   //   max_rank), e^{tA^T} L_I from column max_rank on (so the two are one
   //   n x k operand); Tk: T of the last such compression (tk_k x rank, ld tk_k).

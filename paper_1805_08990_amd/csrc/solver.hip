@@ -576,6 +576,22 @@ void Solver::product_rows(double t, const double* X, int64_t cols, int64_t row0,
                           hipStream_t st, Arena& a) {
   double* Y = EW.as<double>() + (max_rank - cols) * n;
   const OperatorSet& set = *ops.at(t);
+  if (set.lop) {
+    // the Leja action is formed for every row at once (its terms are short
+    // launches that leave room between them for the compression's kernels);
+    // profiling level 2 times it as its Newton-term launches
+    DME_REQUIRE(row0 == 0 && rows == n, DME_EINTERNAL, "Leja action ahead: all rows at once");
+    hipEvent_t ev = profiling == 2 ? mark_begin(st) : nullptr;
+    leja_apply(st, *set.lop, *set.plan, X, n, cols, Y, n, a);
+    const int64_t prods = leja_products(*set.plan);
+    // per term the operator and the basis block read and written; the
+    // accumulator read and written every second term
+    mark_end(DME_PHASE_STEP_KERNEL, ev, (double)prods * 2.0 * set.lop->nnz * cols,
+             (double)prods * (12.0 * set.lop->nnz + 8.0 * n + 16.0 * n * cols) +
+                 (double)leja_csr_p_updates(*set.plan) * 16.0 * n * cols,
+             prods, st);
+    return;
+  }
   if (opts.precision == DME_MIXED)
     gemm_mixed(st, *set.mix, X, n, cols, Y, n, a, row0, rows, ns);
   else
@@ -592,12 +608,15 @@ void Solver::apply_E(double t, const double* X, int64_t rr, double* Y, int64_t l
     hipEvent_t ev = profiling ? mark_begin() : nullptr;
     leja_apply(s, *set.lop, *set.plan, X, n, rr, Y, ldy, ws);
     // S m products with A^T (2 nnz r flops each for CSR, 2 n^2 r dense); per
-    // term the basis block is read and written and the accumulator updated
+    // term the basis block is read and written, and the accumulator is
+    // updated (every second term on a CSR operator)
     const int64_t prods = leja_products(*set.plan);
-    const double opf = set.lop->sparse() ? 2.0 * set.lop->nnz : 2.0 * (double)n * n;
-    const double opb = set.lop->sparse() ? 12.0 * set.lop->nnz + 8.0 * n : 8.0 * (double)n * n;
+    const bool csr = set.lop->sparse();
+    const double opf = csr ? 2.0 * set.lop->nnz : 2.0 * (double)n * n;
+    const double opb = csr ? 12.0 * set.lop->nnz + 8.0 * n : 8.0 * (double)n * n;
+    const double pupd = csr ? (double)leja_csr_p_updates(*set.plan) : (double)prods;
     mark_end(profiling == 2 ? DME_PHASE_STEP_KERNEL : DME_PHASE_STEP_GEMM, ev, (double)prods * opf * rr,
-             (double)prods * (opb + 32.0 * n * rr), prods);
+             (double)prods * (opb + 16.0 * n * rr) + pupd * 16.0 * n * rr, prods);
     return;
   }
   StepKernelTimer kt;
@@ -666,12 +685,17 @@ void Solver::compress_into(int64_t k, int ncopies, double ahead_t) {
   const double* Fr = f_ready ? Fpre.as<double>() : nullptr;
   const int64_t* Fs = f_ready ? reinterpret_cast<const int64_t*>(Fr + k * k) : nullptr;
   f_ready = false;
-  // the next T12's product ahead: e^{tA^T} Y for Y = W[:, 0:r], its first
-  // rows on s3 beside the tridiagonal reduction
+  // the next T12's product ahead: e^{tA^T} Y for Y = W[:, 0:r] on s3, its
+  // first rows beside the tridiagonal reduction (a Leja action: all of it)
   drop_ahead();
   int64_t rows_b = 0;
   int ns_b = 0;
-  if (ahead_t > 0.0) plan_beside(k, &rows_b, &ns_b);
+  const bool leja_ahead = ahead_t > 0.0 && ops.at(ahead_t)->lop != nullptr;
+  if (leja_ahead) {
+    if (r > 0) rows_b = n;  // the whole action beside the compression
+  } else if (ahead_t > 0.0) {
+    plan_beside(k, &rows_b, &ns_b);
+  }
   std::function<void(hipEvent_t)> beside;
   bool launched = false;
   if (rows_b > 0) {
@@ -681,8 +705,10 @@ void Solver::compress_into(int64_t k, int ncopies, double ahead_t) {
     const int64_t kq = std::max<int64_t>(1, (int64_t)opts.quad_nodes * p);
     EW.ensure((size_t)n * (max_rank + kq) * sizeof(double));
     Tk.ensure((size_t)(max_rank + kq) * max_rank * sizeof(double));
-    const size_t need = (size_t)ns_b * rows_b * std::max<int64_t>(r + 16, kRowBlock) * sizeof(double) +
-                        (size_t)3 * (n + kRowBlock) * kRowBlock * sizeof(uint16_t) + 4096;  // partials, X pieces
+    const size_t need = leja_ahead ? leja_workspace(n, r) + 4096
+                                   : (size_t)ns_b * rows_b * std::max<int64_t>(r + 16, kRowBlock) * sizeof(double) +
+                                         (size_t)3 * (n + kRowBlock) * kRowBlock * sizeof(uint16_t) +
+                                         4096;  // partials, X pieces
     if (ws3.buf.bytes < need) ws3.reserve(need);
     const int64_t rY = r;
     beside = [this, ahead_t, rows_b, ns_b, rY, &launched](hipEvent_t e) {
@@ -754,9 +780,11 @@ void Solver::apply_T12(double t, bool ext_product) {
   const QuadFactor& f = Q.at(t);
   double* Wd = W.as<double>();
   const int64_t k = r + f.r;
-  const bool dense = !ops.at(t)->lop;
-  const bool can_ahead = ahead && ahead_same_t && !ext_product && dense &&
-                         (opts.precision == DME_MIXED || r <= 256);
+  const OperatorSet& set = *ops.at(t);
+  // dense products (FP64 up to 256 columns), or the Leja action on a CSR operator
+  const bool leja = set.lop && set.lop->sparse();
+  const bool can_ahead = ahead && ahead_same_t && !ext_product && (!set.lop || leja) &&
+                         (leja || opts.precision == DME_MIXED || r <= 256);
   // e^{tA^T} L = [e^{tA^T} Y, e^{tA^T} L_I] T from the product formed ahead
   const bool from_ahead = can_ahead && r > 0 && ey_ok && tk_ok && ey_t == t && tk_k == ey_cols + f.r;
   settle_beside();  // (the rows formed beside are complete before W changes)
@@ -793,8 +821,10 @@ void Solver::apply_T12(double t, bool ext_product) {
       if (e.bytes == 0) {
         e.ensure((size_t)n * std::max<int64_t>(f.r, 1) * sizeof(double));
         ws.reset();
-        if (f.r > 0)
-          gemm_f64(s, 'N', 'N', n, f.r, n, 1.0, ops.at(t)->E.as<double>(), n, f.L.as<double>(), n, 0.0,
+        if (f.r > 0 && leja)
+          leja_apply(s, *set.lop, *set.plan, f.L.as<double>(), n, f.r, e.as<double>(), n, ws);
+        else if (f.r > 0)
+          gemm_f64(s, 'N', 'N', n, f.r, n, 1.0, set.E.as<double>(), n, f.L.as<double>(), n, 0.0,
                    e.as<double>(), n, &ws);
       }
       if (f.r > 0) copy_f64(s, e.as<double>(), n, EW.as<double>() + max_rank * n, n, n, f.r);

@@ -39,6 +39,35 @@ def test_expmv_leja_matches_exact_action(ctx, nx, t, c, form):
         assert np.linalg.norm(to_np(Y) - ref_o) <= 1e-12 * np.linalg.norm(X)
 
 
+@pytest.mark.parametrize("t,c", [(5e-4, 7), (1e-2, 3)])
+def test_expmv_leja_csr_wide_rows(ctx, t, c):
+    """A symmetric CSR operator whose rows hold 3 to 9 entries (the 24 x 24
+    Laplacian with symmetric couplings i <-> i + {37, 53, 71, 97} on every
+    fifth row): rows of more than 8 entries rule out the fixed-width form, so
+    the rows of up to 8 entries and the wider ones take the two CSR-walking
+    paths of the term kernel.  Against the exact action from the
+    eigendecomposition of A and against the oracle's action."""
+    announce("expmv_leja wide rows", t, c)
+    nx = 24
+    n = nx * nx
+    A = wl.laplacian_2d(nx).copy()
+    for i in range(0, n, 5):
+        for d in (37, 53, 71, 97):
+            if i + d < n:
+                A[i, i + d] = A[i + d, i] = 40.0
+    widths = np.count_nonzero(A, axis=1)
+    assert widths.max() > 8 and widths.min() <= 8
+    X = np.random.default_rng(11 + c).standard_normal((n, c))
+    Y, S, m = ctx.expmv_leja(csr(A), t, X)
+    lam, U = np.linalg.eigh(A)
+    ref = U @ (np.exp(t * lam)[:, None] * (U.T @ X))
+    err = np.linalg.norm(to_np(Y) - ref) / np.linalg.norm(ref)
+    print(f"  S {S} m {m} err {err:.2e}", flush=True)
+    assert err < 1e-12
+    ref_o = oracle.leja_expmv(A, t, X)
+    assert np.linalg.norm(to_np(Y) - ref_o) <= 1e-12 * np.linalg.norm(ref)
+
+
 def test_expmv_leja_rejects_nonsymmetric(ctx):
     A = wl.random_nonsymmetric(30, seed=4)
     X = np.ones((30, 2))
